@@ -1,0 +1,22 @@
+"""CPU reference implementations (test infrastructure only).
+
+Nothing in the product path may import, call or link anything in this
+package: only the tests, the package's smoke check and the benchmark's CPU
+baseline leg use it.  Everything here is plain NumPy/SciPy in float64,
+written from the paper's definitions, and shares no code with the HIP
+library.
+
+Modules
+  dense    O1: textbook CP-ALS on the explicitly formed order-4 tensor
+           (tiny sizes only).  Fit by dense reconstruction.
+  matfree  O2: the matrix-free THC-based CP-ALS of the paper (eq. lossF),
+           in the same step order as the GPU path, any size.
+  lt       Laplace-transform row scaling of the THC factors (eq. mp1_t and
+           the THC-LT amplitude that follows it).
+  mlp      Warm-start network: features, forward, manual backward, Adam.
+
+Pins: every function is checked by ``tests/test_oracle_*.py`` against
+brute-force loops, closed forms, planted decompositions, special cases and
+invariances (see each module's header).  The paper prints no numeric
+example for the CP-ALS itself, so there is no golden value from the paper.
+"""
