@@ -1,0 +1,201 @@
+"""Benchmark: CP-ALS time-to-fit and MTTKRP TFLOP/s, split-BF16 vs FP64, on one MI355X.
+
+Workload (default): the mixed-precision configuration -- THC input with
+N = 800 orbitals, R_thc = 4000, R_cp = 4000, from the seeded generator
+(synthetic stand-in for the paper's water clusters).
+
+Protocol
+  1. Reference (untimed): plain FP64 CP-ALS for --ref-sweeps sweeps with the
+     stopping rule off; f_ref = its best fit, target f* = f_ref (1 + 1e-4).
+  2. Warm-up (untimed): --warmup mixed runs to the target.
+  3. Timed: --steps runs of the mixed-precision path, each from cpd_init
+     (inputs already in HBM) to the end of the first sweep whose fit --
+     evaluated in FP64 -- is <= f*.  value = mean seconds per run.
+     One timed FP64 run to the same target gives the FP64 time-to-fit.
+  4. Kernel times (hipEvents on the plan's stream) of the projection, core
+     product, back-projection, Gram and solve at this shape give MTTKRP
+     TFLOP/s for both precisions and the roofline of the dominant kernel.
+  5. CPU baseline: the matrix-free NumPy oracle on the host, a bounded
+     sample of sweeps, extrapolated to the FP64 sweep count.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MFMA_PEAK = {"bf16": 2.5e15, "f64": 78.6e12, "f32": 157.3e12}
+HBM_PEAK = 8.0e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def mttkrp_flops(n, r_thc, r_cp):
+    return 4.0 * r_thc * r_cp * sum(n) + 4.0 * r_thc * r_thc * r_cp
+
+
+def run_to_target(make, target, max_sweeps, chunk=1):
+    """Wall time (s) from plan creation to the sweep that reaches target."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cpd = make()
+    sweeps, reached, last = 0, False, None
+    while sweeps < max_sweeps:
+        fits = cpd.sweep(chunk)
+        if not fits:
+            break
+        sweeps += len(fits)
+        evaluated = [f for f in fits if f >= 0]
+        if evaluated:
+            last = evaluated[-1]
+            if last <= target:
+                reached = True
+                break
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    cpd.close()
+    return t, sweeps, reached, last
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=800)
+    ap.add_argument("--r-thc", type=int, default=4000)
+    ap.add_argument("--r-cp", type=int, default=4000)
+    ap.add_argument("--ref-sweeps", type=int, default=60)
+    ap.add_argument("--max-sweeps", type=int, default=400)
+    ap.add_argument("--fit-every", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2502_17683_amd import CPD
+    from synth import make_thc, init_factors
+
+    N, Rt, Rc = args.n, args.r_thc, args.r_cp
+    dev = torch.device("cuda:0")
+    log(f"[bench] generating THC input N={N} R_thc={Rt} R_cp={Rc} seed={args.seed}")
+    X, Z = make_thc(N, Rt, args.seed)
+    init = init_factors([N] * 4, Rc, args.seed + 1000)
+    Xd = torch.as_tensor(X, device=dev)
+    Zd = torch.as_tensor(Z, device=dev)
+    Id = [torch.as_tensor(f, device=dev) for f in init]
+
+    def make(prec, tol=0.0, fit_every=1):
+        return CPD(Xd, Zd, Rc, Id, precision=prec, tol=tol, fit_floor=0.0, fit_every=fit_every)
+
+    # 1. FP64 reference trajectory
+    log(f"[bench] FP64 reference: {args.ref_sweeps} sweeps")
+    ref = make("fp64")
+    ref_fits = ref.sweep(args.ref_sweeps)
+    ref.close()
+    f_ref = float(min(ref_fits))
+    target = f_ref * (1.0 + 1e-4)
+    log(f"[bench] f_ref={f_ref:.8f} target={target:.8f} (first fit {ref_fits[0]:.6f})")
+
+    # 2./3. time-to-fit
+    for w in range(args.warmup):
+        t, s, ok, last = run_to_target(lambda: make("mixed", fit_every=args.fit_every), target,
+                                       args.max_sweeps, args.fit_every)
+        log(f"[bench] warmup {w}: mixed {t:.3f}s sweeps={s} reached={ok} last_fit={last}")
+    times, sweeps_m, reached_m, last_m = [], [], [], []
+    for k in range(args.steps):
+        t, s, ok, last = run_to_target(lambda: make("mixed", fit_every=args.fit_every), target,
+                                       args.max_sweeps, args.fit_every)
+        times.append(t)
+        sweeps_m.append(s)
+        reached_m.append(ok)
+        last_m.append(last)
+        log(f"[bench] step {k}: mixed {t:.3f}s sweeps={s} reached={ok} last_fit={last}")
+    t64, s64, ok64, last64 = run_to_target(lambda: make("fp64"), target, args.max_sweeps, 1)
+    log(f"[bench] fp64 run: {t64:.3f}s sweeps={s64} reached={ok64} last_fit={last64}")
+
+    # 4. kernel times
+    kt = {}
+    for prec in ("mixed", "fp64"):
+        c = make(prec)
+        kt[prec] = c.kernel_times(reps=5)
+        c.close()
+        log(f"[bench] kernel ms ({prec}): {kt[prec]}")
+    fl_proj = 2.0 * N * Rt * Rc
+    fl_core = 2.0 * Rt * Rt * Rc
+    fl_back = 2.0 * N * Rt * Rc
+    def mttkrp_ms(k):
+        return 4 * k["projection"] + 2 * k["core"] + 4 * k["backprojection"]
+    mtt = mttkrp_flops([N] * 4, Rt, Rc)
+    tflops = {p: mtt / (mttkrp_ms(kt[p]) * 1e-3) / 1e12 for p in kt}
+    core_ms = kt["mixed"]["core"]
+    achieved = fl_core / (core_ms * 1e-3)
+
+    # 5. CPU oracle baseline
+    cpu = None
+    if not args.no_cpu:
+        from oracle import matfree
+        import multiprocessing
+        cores = int(os.environ.get("OMP_NUM_THREADS", multiprocessing.cpu_count()))
+        log(f"[bench] CPU oracle: {args.cpu_sweeps} sweeps on {cores} threads")
+        st = matfree.MatFreeCPALS([X] * 4, Z, init)
+        t0 = time.perf_counter()
+        for _ in range(args.cpu_sweeps):
+            st.sweep()
+        dt = (time.perf_counter() - t0) / args.cpu_sweeps
+        cpu = {"value": dt * s64, "unit": "s", "cores": cores, "kind": "oracle",
+               "sample": f"{args.cpu_sweeps} matrix-free FP64 NumPy sweeps at N={N}, R_thc={Rt}, "
+                         f"R_cp={Rc} ({dt:.2f} s/sweep, set-up excluded), extrapolated to the "
+                         f"{s64} sweeps the FP64 GPU run needed"}
+
+    value = float(np.mean(times))
+    out = {
+        "metric": "CP-ALS time-to-fit 1e-4 (s) and MTTKRP TFLOP/s, mixed vs FP64, 1 MI355X",
+        "value": value,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": value * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-split(fp32 acc)+f64",
+        "data": "synthetic",
+        "config": {"workload": f"mixed-precision THC CP-ALS, N={N}, R_thc={Rt}, R_cp={Rc}, "
+                               f"seed {args.seed}, target fit = FP64 best over "
+                               f"{args.ref_sweeps} sweeps x (1+1e-4)",
+                   "n": N, "r_thc": Rt, "r_cp": Rc, "fit_every": args.fit_every},
+        "fp64_time_to_fit_s": t64,
+        "speedup_vs_fp64": t64 / value if value > 0 else None,
+        "sweeps_to_fit": {"mixed": sweeps_m, "fp64": s64},
+        "reached": {"mixed": reached_m, "fp64": ok64},
+        "f_ref": f_ref, "target_fit": target,
+        "mttkrp_tflops": tflops,
+        "kernel_ms": kt,
+        "roofline": {"bound": "mfma", "kernel": "core product Z (W o W), split BF16",
+                     "achieved": achieved / 1e12, "peak": MFMA_PEAK["bf16"] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK["bf16"], "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

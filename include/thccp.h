@@ -1,0 +1,194 @@
+/*
+ * thccp.h -- C-ABI of libthccp.so: matrix-free, THC-based CP-ALS of an
+ * order-4 two-electron-integral tensor on one MI355X (gfx950).
+ *
+ * The tensor is never formed.  It is given in tensor-hypercontraction form
+ * (Pierce & Morales, Section 2.1, eq. THC), in chemists' index order:
+ *
+ *   G[p,q,r,s] = sum_{P,Q} X0[p,P] X1[q,P] Z[P,Q] X2[r,Q] X3[s,Q]
+ *
+ * and fitted by a rank-R_cp canonical polyadic decomposition with column
+ * weights (eq. cp4), G ~ sum_k lambda_k F0[:,k] o F1[:,k] o F2[:,k] o F3[:,k],
+ * by alternating least squares on the THC-approximated loss (eq. lossF).
+ * Each mode update needs only the projections W_m = X_m^T F_m, Hadamard
+ * products, one core product Z (W o W) (reused by the partner mode) and a
+ * back-projection X_n (W o Y) -- O(n R_thc R_cp + R_thc^2 R_cp) work and
+ * O(R^2) storage -- followed by the FP64 normal-equation solve with the
+ * Gram-Hadamard matrix V_n = o_{m != n} F_m^T F_m.  The fit is the paper's
+ * ||T - T~|| / ||T|| (Computational Details), evaluated matrix-free.
+ *
+ * Conventions
+ *   - All matrices are row-major, densely packed (leading dimension = number
+ *     of columns), float64, in DEVICE memory unless stated otherwise.
+ *   - Pointers passed in are borrowed: the library never frees them and
+ *     they must stay valid for the life of the plan.
+ *   - The library allocates no device memory: all state lives in the
+ *     caller's workspace (size from cpd_workspace_size).  It creates one
+ *     private HIP stream per plan for graph capture.
+ *   - Work is enqueued on desc.stream; calls return without synchronising
+ *     unless their comment says otherwise.
+ *   - Errors are returned as negative cpd_status codes; nothing aborts and
+ *     no C++ exception crosses the ABI.  Arguments are validated before any
+ *     launch.  Device-side conditions (non-SPD normal matrix, non-finite
+ *     fit) are latched in device flags and reported by the next call that
+ *     synchronises (cpd_sweep with outputs, cpd_fit, cpd_stats).
+ */
+#ifndef THCCP_H
+#define THCCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cpd_status;
+enum {
+  CPD_OK = 0,
+  CPD_ERR_INVALID_ARG = -1, /* bad sizes, null pointers, unsupported option  */
+  CPD_ERR_HIP = -2,         /* a HIP runtime call failed                      */
+  CPD_ERR_NOT_SPD = -3,     /* normal matrix not positive definite (after the
+                               damped retry, if enabled)                      */
+  CPD_ERR_NONFINITE = -4,   /* NaN/Inf reached the fit or ||G||^2 <= 0        */
+  CPD_ERR_WORKSPACE = -5,   /* workspace missing or smaller than required     */
+  CPD_ERR_UNSUPPORTED = -6  /* option not available in this build             */
+};
+
+typedef enum {
+  CPD_FP64 = 0,       /* every step in FP64 (matrix cores, 16x16x4 f64)        */
+  CPD_FP32 = 1,       /* every step, including the Cholesky, in FP32;
+                         scalar fit terms accumulate in FP64                  */
+  CPD_MIXED_BF16 = 2  /* projection, core and back-projection products in
+                         split BF16 (hi + lo, one correction pass) with FP32
+                         accumulation; Gram, Cholesky, solve and fit in FP64  */
+} cpd_precision;
+
+typedef struct cpd_plan_s* cpd_plan;
+
+typedef struct {
+  int32_t n[4];           /* mode sizes n_m (> 0)                                  */
+  int32_t r_thc;          /* THC rank R_thc (> 0)                                  */
+  int32_t r_cp;           /* CP rank R_cp (> 0)                                    */
+  const double* X[4];     /* DEVICE n[m] x r_thc THC factors; may alias each other */
+  const double* Z;        /* DEVICE r_thc x r_thc THC core (general; Z^T is used
+                             for modes 2 and 3)                                   */
+  const double* init[4];  /* DEVICE n[m] x r_cp initial factors (required); their
+                             columns are normalised to unit 2-norm at init        */
+  int32_t precision;      /* cpd_precision                                        */
+  double tol;             /* stop when |f_k - f_{k-1}| <= tol f_{k-1}             */
+  double fit_floor;       /* ... or when f_k <= fit_floor (0 disables)            */
+  int32_t chol_fallback;  /* 1: one damped retry V + mu I, mu = 1e-12 tr(V)/R_cp,
+                             on a non-positive pivot; 0: fail with NOT_SPD       */
+  int32_t use_graph;      /* 1: replay each sweep as a captured hipGraph          */
+  int32_t fit_every;      /* CPD_MIXED_BF16 only: evaluate the fit (in FP64, with
+                             an FP64 mode-3 MTTKRP) and the stopping rule every
+                             fit_every sweeps (<= 1: every sweep); other
+                             precisions evaluate it every sweep               */
+  void* stream;           /* hipStream_t the work is ordered on (0 = null stream) */
+  void* workspace;        /* DEVICE memory owned by the caller                    */
+  size_t workspace_bytes;
+} cpd_desc;
+
+typedef struct {
+  int32_t sweeps;         /* sweeps completed since init / set_factors            */
+  int32_t converged;      /* the stopping rule fired                              */
+  int32_t fallbacks;      /* damped Cholesky retries so far                       */
+  int32_t flags;          /* device status bits (1 = not SPD, 2 = non-finite)     */
+  double fit;             /* last fit (relative residual), -1 before any sweep    */
+  double norm2;           /* ||G||^2                                              */
+  double inner;           /* <G, G~> of the last sweep                            */
+  double model2;          /* ||G~||^2 of the last sweep                           */
+  double cond_est;        /* (max_i L_ii / min_i L_ii)^2 of the last factor       */
+} cpd_stats_t;
+
+/* Bytes of device workspace cpd_init needs for this descriptor (0 on
+ * invalid arguments).  Host-only; launches nothing. */
+size_t cpd_workspace_size(const cpd_desc* d);
+
+/* Set-up (eq. lossF and the fit of Computational Details): validates d,
+ * carves the workspace, computes S_m = X_m^T X_m and ||G||^2 =
+ * <Z, (S0 o S1) Z (S2 o S3)>, copies and normalises the initial factors,
+ * forms the projections W_m and the Gram matrices, and (use_graph) captures
+ * one sweep as a hipGraph.  Asynchronous on d->stream.  *out receives a
+ * host-side plan to be released with cpd_destroy. */
+cpd_status cpd_init(const cpd_desc* d, cpd_plan* out);
+
+/* Runs up to nsweeps ALS sweeps (modes 0,1,2,3 in order, then the fit and
+ * the stopping rule).  Sweeps after convergence are no-ops on the device.
+ * If fits_host or n_run is non-NULL the call synchronises after every sweep,
+ * stops at convergence, writes the fit of each sweep run to fits_host
+ * (length >= nsweeps) and the number of sweeps run to *n_run; otherwise it
+ * only enqueues the work. */
+cpd_status cpd_sweep(cpd_plan p, int32_t nsweeps, double* fits_host, int32_t* n_run);
+
+/* Synchronises the plan's stream and returns the last fit (-1 if none). */
+cpd_status cpd_fit(cpd_plan p, double* fit_host);
+
+/* Copies the current factors (DEVICE n[m] x r_cp each, dense) and the
+ * weights lambda (DEVICE r_cp) out; async.  Any pointer may be NULL. */
+cpd_status cpd_get_factors(cpd_plan p, double* const F_dev[4], double* lambda_dev);
+
+/* Restores factors and weights written by cpd_get_factors (checkpoint
+ * resume): recomputes the projections and Grams from them and sets the
+ * previous fit used by the stopping rule to prev_fit (< 0: none) and the
+ * sweep counter to sweeps.  Async. */
+cpd_status cpd_set_factors(cpd_plan p, const double* const F_dev[4], const double* lambda_dev,
+                           double prev_fit, int32_t sweeps);
+
+/* Synchronises and fills *out. */
+cpd_status cpd_stats(cpd_plan p, cpd_stats_t* out);
+
+/* Test hook: the matrix-free MTTKRP of `mode` from the current factors,
+ * M = G_(mode) (Khatri-Rao of the other factors), into DEVICE
+ * n[mode] x r_cp (dense).  Async. */
+cpd_status cpd_mttkrp(cpd_plan p, int32_t mode, double* M_dev);
+
+/* Measurement hook: average device time (ms, hipEvents on the plan's
+ * stream, `reps` back-to-back launches after one warm-up) of one launch of
+ * each kernel family of the sweep at the plan's shapes, for mode 0:
+ *   ms_out[0] projection X^T F,  ms_out[1] core product Z (W o W),
+ *   ms_out[2] back-projection X (W o Y),  ms_out[3] Gram F^T F,
+ *   ms_out[4] normal-equation solve (V, Cholesky + retry pass, triangular
+ *   solves, normalisation).
+ * Overwrites the plan's intermediate buffers and resets its stopping state:
+ * re-initialise the plan before using it again.  Synchronises. */
+cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out);
+
+/* Releases the host plan and its private stream/graph (not the workspace). */
+cpd_status cpd_destroy(cpd_plan p);
+
+const char* cpd_status_string(cpd_status s);
+
+/* ---- kernel-level test hooks (all pointers DEVICE, dense row-major) ----
+ * cpd_test_gemm: C (M x N) = op(A) op(B1 [o B2]) on the FP64 (fp32 = 0) or
+ *   FP32 (fp32 = 1) matrix cores.  a_t: A is stored K x M (lda); b_t: B is
+ *   stored N x K (ldb); B2 (same layout as B1, b_t = 0 only) multiplies B1
+ *   element-wise.  Async on stream. */
+cpd_status cpd_test_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, const void* A, int32_t lda,
+                         int32_t a_t, const void* B1, const void* B2, int32_t ldb, int32_t b_t, void* C,
+                         int32_t ldc, void* stream);
+/* cpd_test_solve: F (n x R) = M V^{-1} for SPD V (R x R) by the blocked
+ *   Cholesky and triangular solves of the sweep (no damped retry).  Sync;
+ *   returns CPD_ERR_NOT_SPD (and *failed = 1) on a non-positive pivot. */
+size_t cpd_test_solve_workspace(int32_t fp32, int32_t R, int32_t n);
+cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, const void* M, void* F,
+                          void* workspace, size_t ws_bytes, void* stream, int32_t* failed);
+/* cpd_test_gemm_split: C (M x N, FP64) = A B^T from FP64 A (M x K) and
+ *   B (N x K) through the split-BF16 product (hi*hi + hi*lo + lo*hi, FP32
+ *   accumulation).  With A2 != NULL the A operand is the FP32 product
+ *   A o A2, split on the fly.  Async on stream. */
+size_t cpd_test_split_workspace(int32_t M, int32_t N, int32_t K);
+cpd_status cpd_test_gemm_split(int32_t M, int32_t N, int32_t K, const double* A, const double* A2,
+                               const double* B, double* C, void* workspace, size_t ws_bytes, void* stream);
+/* cpd_test_mfma_probe: lane-layout probe of the 16x16x4 FP64 (fp32 = 0) or
+ *   FP32 matrix instruction.  Probe p (of nprobe) feeds a[64p + lane] and
+ *   b[64p + lane] to one wave with a zero accumulator and writes the four
+ *   result registers to d[256p + 4 lane + r].  Async on stream. */
+cpd_status cpd_test_mfma_probe(int32_t fp32, int32_t nprobe, const void* a, const void* b, void* d,
+                               void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* THCCP_H */

@@ -1,0 +1,9 @@
+"""Matrix-free THC-based CP-ALS on MI355X (gfx950).
+
+The CP-ALS of an order-4 tensor given in THC form,
+G[p,q,r,s] = sum_PQ X0[p,P] X1[q,P] Z[P,Q] X2[r,Q] X3[s,Q], runs entirely in
+the HIP library libthccp.so (include/thccp.h); this package only marshals
+arguments and owns the torch tensors that back the library's workspace.
+"""
+from ._lib import CpdError, load, LIB_PATH  # noqa: F401
+from .cpd import CPD, test_gemm, test_solve, test_gemm_split  # noqa: F401

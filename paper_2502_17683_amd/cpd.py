@@ -1,0 +1,185 @@
+"""Python face of the C-ABI: the ``CPD`` plan object and the kernel test hooks.
+
+PyTorch supplies device memory (the workspace and the input/output
+tensors) and the current HIP stream; nothing here computes.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import CpdDesc, CpdStats, check, PRECISIONS
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(dev):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _dev_f64(t, device):
+    t = torch.as_tensor(t, dtype=torch.float64, device=device)
+    return t.contiguous()
+
+
+class CPD:
+    """One CP-ALS run of the THC tensor (X[0..3], Z) at CP rank r_cp.
+
+    X: one tensor (used for all four modes) or a list of four n_m x r_thc
+    tensors; Z: r_thc x r_thc; init: four n_m x r_cp initial factors.
+    Inputs are copied to the device as float64 if needed and kept alive by
+    the object (the library borrows them).
+    """
+
+    def __init__(self, X, Z, r_cp, init, precision="fp64", tol=1e-4, fit_floor=1e-7,
+                 chol_fallback=True, use_graph=True, fit_every=1, device="cuda"):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        if not isinstance(X, (list, tuple)):
+            X = [X] * 4
+        xs, seen = [], {}
+        for x in X:
+            key = id(x)
+            if key not in seen:
+                seen[key] = _dev_f64(x, self.device)
+            xs.append(seen[key])
+        self.X = xs
+        self.Z = _dev_f64(Z, self.device)
+        self.init = [_dev_f64(f, self.device) for f in init]
+        self.n = [int(x.shape[0]) for x in self.X]
+        self.r_thc = int(self.Z.shape[0])
+        self.r_cp = int(r_cp)
+        d = CpdDesc()
+        for m in range(4):
+            d.n[m] = self.n[m]
+            d.X[m] = self.X[m].data_ptr()
+            d.init[m] = self.init[m].data_ptr()
+        d.r_thc = self.r_thc
+        d.r_cp = self.r_cp
+        d.Z = self.Z.data_ptr()
+        d.precision = PRECISIONS[precision]
+        d.tol = float(tol)
+        d.fit_floor = float(fit_floor)
+        d.chol_fallback = int(bool(chol_fallback))
+        d.use_graph = int(bool(use_graph))
+        d.fit_every = int(fit_every)
+        d.stream = _stream(self.device).value
+        need = self.lib.cpd_workspace_size(ctypes.byref(d))
+        if need == 0:
+            raise _lib.CpdError(_lib.CPD_ERR_INVALID_ARG, "cpd_workspace_size")
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        d.workspace = self.workspace.data_ptr()
+        d.workspace_bytes = need
+        self.desc = d
+        plan = ctypes.c_void_p()
+        check(self.lib.cpd_init(ctypes.byref(d), ctypes.byref(plan)), "cpd_init")
+        self.plan = plan
+
+    @property
+    def workspace_bytes(self):
+        return self.desc.workspace_bytes
+
+    def sweep(self, n=1, sync=True):
+        """Run up to n sweeps; with sync, returns the list of fits (-1 for
+        sweeps whose fit was not evaluated) and stops at convergence."""
+        if not sync:
+            check(self.lib.cpd_sweep(self.plan, int(n), None, None), "cpd_sweep")
+            return None
+        fits = (ctypes.c_double * max(int(n), 1))()
+        ran = ctypes.c_int32(0)
+        check(self.lib.cpd_sweep(self.plan, int(n), fits, ctypes.byref(ran)), "cpd_sweep")
+        return list(fits[: ran.value])
+
+    def fit(self):
+        f = ctypes.c_double()
+        check(self.lib.cpd_fit(self.plan, ctypes.byref(f)), "cpd_fit")
+        return f.value
+
+    def factors(self):
+        F = [torch.empty(n, self.r_cp, dtype=torch.float64, device=self.device) for n in self.n]
+        lam = torch.empty(self.r_cp, dtype=torch.float64, device=self.device)
+        arr = (ctypes.c_void_p * 4)(*[f.data_ptr() for f in F])
+        check(self.lib.cpd_get_factors(self.plan, arr, _ptr(lam)), "cpd_get_factors")
+        torch.cuda.current_stream(self.device).synchronize()
+        return F, lam
+
+    def set_factors(self, F, lam, prev_fit=-1.0, sweeps=0):
+        F = [_dev_f64(f, self.device) for f in F]
+        lam = _dev_f64(lam, self.device)
+        arr = (ctypes.c_void_p * 4)(*[f.data_ptr() for f in F])
+        check(self.lib.cpd_set_factors(self.plan, arr, _ptr(lam), float(prev_fit), int(sweeps)),
+              "cpd_set_factors")
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def stats(self):
+        s = CpdStats()
+        check(self.lib.cpd_stats(self.plan, ctypes.byref(s)), "cpd_stats")
+        return {k: getattr(s, k) for k, _ in CpdStats._fields_}
+
+    def mttkrp(self, mode):
+        M = torch.empty(self.n[mode], self.r_cp, dtype=torch.float64, device=self.device)
+        check(self.lib.cpd_mttkrp(self.plan, int(mode), _ptr(M)), "cpd_mttkrp")
+        torch.cuda.current_stream(self.device).synchronize()
+        return M
+
+    def kernel_times(self, reps=5):
+        """Average ms per launch of (projection, core product, back-projection,
+        Gram, solve) at this plan's shapes.  Invalidates the plan's state."""
+        out = (ctypes.c_double * 5)()
+        check(self.lib.cpd_kernel_times(self.plan, int(reps), out), "cpd_kernel_times")
+        return dict(zip(("projection", "core", "backprojection", "gram", "solve"), list(out)))
+
+    def close(self):
+        if getattr(self, "plan", None) is not None and self.plan.value:
+            self.lib.cpd_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def test_gemm(A, B1, B2=None, a_t=False, b_t=False):
+    """C = op(A) op(B1 [o B2]) through the library's FP64/FP32 GEMM."""
+    lib = _lib.load()
+    fp32 = A.dtype == torch.float32
+    M = A.shape[1] if a_t else A.shape[0]
+    K = A.shape[0] if a_t else A.shape[1]
+    N = B1.shape[0] if b_t else B1.shape[1]
+    C = torch.empty(M, N, dtype=A.dtype, device=A.device)
+    check(lib.cpd_test_gemm(int(fp32), M, N, K, _ptr(A), A.shape[1], int(a_t), _ptr(B1), _ptr(B2),
+                            B1.shape[1], int(b_t), _ptr(C), N, _stream(A.device)), "cpd_test_gemm")
+    torch.cuda.current_stream(A.device).synchronize()
+    return C
+
+
+def test_solve(V, M):
+    """F = M V^{-1} through the library's blocked Cholesky and solves."""
+    lib = _lib.load()
+    fp32 = V.dtype == torch.float32
+    R, n = V.shape[0], M.shape[0]
+    ws = torch.empty(lib.cpd_test_solve_workspace(int(fp32), R, n), dtype=torch.uint8, device=V.device)
+    F = torch.empty_like(M)
+    failed = ctypes.c_int32(0)
+    code = lib.cpd_test_solve(int(fp32), R, n, _ptr(V), _ptr(M), _ptr(F), _ptr(ws), ws.numel(),
+                              _stream(V.device), ctypes.byref(failed))
+    if code not in (_lib.CPD_OK, _lib.CPD_ERR_NOT_SPD):
+        check(code, "cpd_test_solve")
+    return F, bool(failed.value)
+
+
+def test_gemm_split(A, B, A2=None):
+    """C = A B^T (or (A o A2) B^T) through the split-BF16 GEMM."""
+    lib = _lib.load()
+    M, K = A.shape
+    N = B.shape[0]
+    ws = torch.empty(lib.cpd_test_split_workspace(M, N, K), dtype=torch.uint8, device=A.device)
+    C = torch.empty(M, N, dtype=torch.float64, device=A.device)
+    check(lib.cpd_test_gemm_split(M, N, K, _ptr(A), _ptr(A2), _ptr(B), _ptr(C), _ptr(ws), ws.numel(),
+                                  _stream(A.device)), "cpd_test_gemm_split")
+    torch.cuda.current_stream(A.device).synchronize()
+    return C

@@ -1,0 +1,47 @@
+// Shared device-side definitions for the THC CP-ALS kernels (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+#define WAVE 64
+
+// Device-side status flags written by kernels and read back by the host
+// at synchronisation points.
+enum {
+  FLAG_NOT_SPD = 1,      // a Cholesky pivot was <= 0 or not finite
+  FLAG_NONFINITE = 2,    // a non-finite value reached the fit
+};
+
+// Per-plan device state (lives in the caller's workspace).
+struct DevState {
+  double norm2;          // ||G||^2
+  double fit_prev;       // fit of the previous sweep (-1 before the first)
+  double inner;          // <G, G~> of the last sweep
+  double model2;         // ||G~||^2 of the last sweep
+  double mu;             // damping shift used by the retry (diagnostic)
+  int32_t done;          // set once the stopping rule fired: sweeps become no-ops
+  int32_t sweeps;        // sweeps completed
+  int32_t flags;         // sticky FLAG_* bits
+  int32_t chol_fail;     // current factorisation hit a bad pivot
+  int32_t fallbacks;     // number of damped retries
+  int32_t retry_active;  // retry pass armed for the current mode
+  int32_t pad[2];
+};
+
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous range of tiles so neighbouring tiles share its L2.
+  const int nx = 8;
+  if (nblocks < 2 * nx) return bid;
+  int per = nblocks / nx;
+  int rem = nblocks - per * nx;
+  int x = bid % nx;
+  int j = bid / nx;
+  if (j >= per) return per * nx + x;  // tail: blocks beyond the even split
+  (void)rem;
+  return x * per + j;
+}

@@ -1,0 +1,179 @@
+// Dense GEMM on the 16x16x4 FP64 / FP32 matrix cores, with the Hadamard
+// product of two B operands fused into the operand load.
+//
+// This one kernel family carries every contraction of the matrix-free
+// MTTKRP (projection X^T F, core product Z (W o W), back-projection
+// X (W o Y)), the Gram matrices F^T F and the set-up products.
+//
+// Tiling: 256 threads = 2 x 2 waves; block tile BM x BN, k-step 16 staged
+// through LDS in k-major form (conflict-free fragment reads), next k-tile
+// prefetched into registers while the current one is multiplied.
+#include "kernels.h"
+#include "mfma.h"
+
+namespace thccp {
+
+template <typename T>
+struct GemmArgs {
+  int M, N, K;
+  const T* A; int lda;
+  const T* B1; const T* B2; int ldb;
+  T* C; int ldc; T* C2;
+  T alpha, beta;
+  const int32_t* done;
+};
+
+template <typename T, int BM, int BN, bool AT, bool BT, bool HAD>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> p) {
+  constexpr int BK = 16;
+  constexpr int WTM = BM / 2, WTN = BN / 2;
+  constexpr int TI = WTM / 16, TJ = WTN / 16;
+  constexpr int PAD = 4;
+  constexpr int AE = BM * BK / 256, BE = BN * BK / 256;
+  typedef typename Acc4<T>::type acc_t;
+  __shared__ T As[BK][BM + PAD];
+  __shared__ T Bs[BK][BN + PAD];
+
+  if (p.done && *p.done) return;
+  const int tiles_n = (p.N + BN - 1) / BN;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int m0 = (bid / tiles_n) * BM, n0 = (bid % tiles_n) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+
+  T ra[AE], rb[BE];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      const int idx = tid + e * 256;
+      int i, k;
+      if (AT) { i = idx % BM; k = idx / BM; } else { k = idx % BK; i = idx / BK; }
+      const int gi = m0 + i, gk = k0 + k;
+      T v = T(0);
+      if (gi < p.M && gk < p.K)
+        v = AT ? p.A[(size_t)gk * p.lda + gi] : p.A[(size_t)gi * p.lda + gk];
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      const int idx = tid + e * 256;
+      int j, k;
+      if (BT) { k = idx % BK; j = idx / BK; } else { j = idx % BN; k = idx / BN; }
+      const int gj = n0 + j, gk = k0 + k;
+      T v = T(0);
+      if (gj < p.N && gk < p.K) {
+        const size_t off = BT ? (size_t)gj * p.ldb + gk : (size_t)gk * p.ldb + gj;
+        v = p.B1[off];
+        if (HAD) v *= p.B2[off];
+      }
+      rb[e] = v;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      const int idx = tid + e * 256;
+      int i, k;
+      if (AT) { i = idx % BM; k = idx / BM; } else { k = idx % BK; i = idx / BK; }
+      As[k][i] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      const int idx = tid + e * 256;
+      int j, k;
+      if (BT) { k = idx % BK; j = idx / BK; } else { j = idx % BN; k = idx / BN; }
+      Bs[k][j] = rb[e];
+    }
+  };
+
+  acc_t acc[TI][TJ];
+#pragma unroll
+  for (int a = 0; a < TI; ++a)
+#pragma unroll
+    for (int b = 0; b < TJ; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+  const int nk = (p.K + BK - 1) / BK;
+  load(0);
+  store();
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int k = kk + (lane >> 4);
+      T af[TI], bf[TJ];
+#pragma unroll
+      for (int a = 0; a < TI; ++a) af[a] = As[k][wm * WTM + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < TJ; ++b) bf[b] = Bs[k][wn * WTN + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < TI; ++a)
+#pragma unroll
+        for (int b = 0; b < TJ; ++b) acc[a][b] = mfma4(af[a], bf[b], acc[a][b]);
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      store();
+      __syncthreads();
+    }
+  }
+
+#pragma unroll
+  for (int a = 0; a < TI; ++a)
+#pragma unroll
+    for (int b = 0; b < TJ; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WTM + a * 16 + dsub_row<T>(lane, r);
+        const int col = n0 + wn * WTN + b * 16 + (lane & 15);
+        if (row < p.M && col < p.N) {
+          const size_t off = (size_t)row * p.ldc + col;
+          T v = p.alpha * acc[a][b][r];
+          if (p.beta != T(0)) v += p.beta * p.C[off];
+          p.C[off] = v;
+          if (p.C2) p.C2[off] = v;
+        }
+      }
+}
+
+template <typename T, int BM, int BN>
+static void launch_tile(hipStream_t s, const GemmArgs<T>& a, bool at, bool bt, bool had) {
+  const int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+  dim3 grid(tiles), block(256);
+#define THCCP_GEMM_CASE(AT_, BT_, HAD_)                                           \
+  if (at == AT_ && bt == BT_ && had == HAD_) {                                    \
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, AT_, BT_, HAD_>), grid, block, 0, s, a); \
+    return;                                                                       \
+  }
+  THCCP_GEMM_CASE(false, false, false)
+  THCCP_GEMM_CASE(true, false, false)
+  THCCP_GEMM_CASE(false, false, true)
+  THCCP_GEMM_CASE(true, false, true)
+  THCCP_GEMM_CASE(false, true, false)
+  THCCP_GEMM_CASE(true, true, false)
+#undef THCCP_GEMM_CASE
+}
+
+template <typename T>
+static void gemm_dispatch(hipStream_t s, const GemmArgs<T>& a, bool at, bool bt, bool had) {
+  if (a.M <= 0 || a.N <= 0) return;
+  // 128x128 tiles when there are enough of them to cover the 256 compute
+  // units, 64x64 otherwise.
+  const long t128 = (long)((a.M + 127) / 128) * ((a.N + 127) / 128);
+  if (t128 >= 256) launch_tile<T, 128, 128>(s, a, at, bt, had);
+  else launch_tile<T, 64, 64>(s, a, at, bt, had);
+}
+
+void gemm_f64(hipStream_t s, const GemmF64& g) {
+  GemmArgs<double> a{g.M, g.N, g.K, g.A, g.lda, g.B1, g.B2, g.ldb, g.C, g.ldc, g.C2,
+                     g.alpha, g.beta, g.done};
+  gemm_dispatch<double>(s, a, g.a_t, g.b_t, g.B2 != nullptr);
+}
+
+void gemm_f32(hipStream_t s, const GemmF32& g) {
+  GemmArgs<float> a{g.M, g.N, g.K, g.A, g.lda, g.B1, g.B2, g.ldb, g.C, g.ldc, g.C2,
+                    g.alpha, g.beta, g.done};
+  gemm_dispatch<float>(s, a, g.a_t, g.b_t, g.B2 != nullptr);
+}
+
+}  // namespace thccp

@@ -1,0 +1,182 @@
+// Kernel-level entry points used by the unit tests: one GEMM, one
+// normal-equation solve, one split-BF16 GEMM, each on caller memory.
+#include <string.h>
+
+#include "../../include/thccp.h"
+#include "kernels.h"
+#include "common.h"
+#include "mixed.h"
+
+using namespace thccp;
+
+namespace {
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <typename T>
+__global__ void pad_square(const T* V, int R, int Tp, T* Vp) {
+  const size_t total = (size_t)Tp * Tp;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    const int i = (int)(e / Tp), j = (int)(e % Tp);
+    Vp[e] = (i < R && j < R) ? V[(size_t)i * R + j] : (i == j ? T(1) : T(0));
+  }
+}
+template <typename T>
+__global__ void pad_rows(const T* M, int n, int R, int Tp, T* Mp) {
+  const size_t total = (size_t)n * Tp;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    const int i = (int)(e / Tp), j = (int)(e % Tp);
+    Mp[e] = j < R ? M[(size_t)i * R + j] : T(0);
+  }
+}
+template <typename T>
+__global__ void unpad_rows(const T* Mp, int n, int R, int Tp, T* M) {
+  const size_t total = (size_t)n * R;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    const int i = (int)(e / R), j = (int)(e % R);
+    M[e] = Mp[(size_t)i * Tp + j];
+  }
+}
+__global__ void init_state(DevState* st) {
+  if (threadIdx.x == 0) memset(st, 0, sizeof(DevState));
+}
+__global__ void to_f32_padded(const double* a, int rows, int cols, float* b, int ldb) {
+  const size_t total = (size_t)rows * ldb;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    const int i = (int)(e / ldb), j = (int)(e % ldb);
+    b[e] = j < cols ? (float)a[(size_t)i * cols + j] : 0.f;
+  }
+}
+int grid_of(size_t n) {
+  size_t g = (n + 255) / 256;
+  return (int)(g > 8192 ? 8192 : (g < 1 ? 1 : g));
+}
+
+template <typename T>
+size_t solve_ws(int R, int n) {
+  const int nblk = (R + 63) / 64, Tp = nblk * 64;
+  return al(sizeof(DevState)) + al(sizeof(T) * (size_t)Tp * Tp) + al(sizeof(T) * (size_t)nblk * 4096) +
+         al(sizeof(T) * Tp) + al(sizeof(T) * (size_t)n * Tp);
+}
+
+template <typename T>
+cpd_status solve_impl(int R, int n, const T* V, const T* M, T* F, void* ws, hipStream_t s,
+                      int32_t* failed) {
+  const int nblk = (R + 63) / 64, Tp = nblk * 64;
+  char* b = (char*)ws;
+  DevState* st = (DevState*)b; b += al(sizeof(DevState));
+  T* Vp = (T*)b; b += al(sizeof(T) * (size_t)Tp * Tp);
+  T* linv = (T*)b; b += al(sizeof(T) * (size_t)nblk * 4096);
+  T* diagL = (T*)b; b += al(sizeof(T) * Tp);
+  T* Mp = (T*)b;
+  hipLaunchKernelGGL(init_state, dim3(1), dim3(64), 0, s, st);
+  hipLaunchKernelGGL((pad_square<T>), dim3(grid_of((size_t)Tp * Tp)), dim3(256), 0, s, V, R, Tp, Vp);
+  hipLaunchKernelGGL((pad_rows<T>), dim3(grid_of((size_t)n * Tp)), dim3(256), 0, s, M, n, R, Tp, Mp);
+  chol_factor<T>(s, Vp, nblk, linv, diagL, st, 0);
+  chol_solve_rows<T>(s, Vp, nblk, linv, Mp, n, st);
+  hipLaunchKernelGGL((unpad_rows<T>), dim3(grid_of((size_t)n * R)), dim3(256), 0, s, Mp, n, R, Tp, F);
+  DevState h;
+  if (hipMemcpyAsync(&h, st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess) return CPD_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return CPD_ERR_HIP;
+  if (failed) *failed = h.chol_fail;
+  return h.chol_fail ? CPD_ERR_NOT_SPD : CPD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+cpd_status cpd_test_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, const void* A, int32_t lda,
+                         int32_t a_t, const void* B1, const void* B2, int32_t ldb, int32_t b_t, void* C,
+                         int32_t ldc, void* stream) {
+  if (M < 0 || N < 0 || K < 0 || !A || !B1 || !C) return CPD_ERR_INVALID_ARG;
+  if (B2 && b_t) return CPD_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (fp32) {
+    GemmF32 g{M, N, K, (const float*)A, lda, a_t != 0, (const float*)B1, (const float*)B2, ldb, b_t != 0,
+              (float*)C, ldc, nullptr, 1.f, 0.f, nullptr};
+    gemm_f32(s, g);
+  } else {
+    GemmF64 g{M, N, K, (const double*)A, lda, a_t != 0, (const double*)B1, (const double*)B2, ldb,
+              b_t != 0, (double*)C, ldc, nullptr, 1.0, 0.0, nullptr};
+    gemm_f64(s, g);
+  }
+  return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
+}
+
+size_t cpd_test_solve_workspace(int32_t fp32, int32_t R, int32_t n) {
+  if (R <= 0 || n <= 0) return 0;
+  return fp32 ? solve_ws<float>(R, n) : solve_ws<double>(R, n);
+}
+
+cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, const void* M, void* F,
+                          void* workspace, size_t ws_bytes, void* stream, int32_t* failed) {
+  if (R <= 0 || n <= 0 || !V || !M || !F) return CPD_ERR_INVALID_ARG;
+  if (!workspace || ws_bytes < cpd_test_solve_workspace(fp32, R, n)) return CPD_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (fp32) return solve_impl<float>(R, n, (const float*)V, (const float*)M, (float*)F, workspace, s, failed);
+  return solve_impl<double>(R, n, (const double*)V, (const double*)M, (double*)F, workspace, s, failed);
+}
+
+size_t cpd_test_split_workspace(int32_t M, int32_t N, int32_t K) {
+  if (M <= 0 || N <= 0 || K <= 0) return 0;
+  const size_t Kp = (K + 31) / 32 * 32;
+  return 4 * al(2 * (size_t)M * Kp) + 4 * al(2 * (size_t)N * Kp) + 2 * al(4 * (size_t)M * Kp);
+}
+
+// C (M x N, dense) = A B^T with A (M x K), B (N x K) dense FP64; when A2 is
+// non-null the A operand is the FP32 element-wise product A o A2 (split on
+// the fly), as in the fused core product.
+cpd_status cpd_test_gemm_split(int32_t M, int32_t N, int32_t K, const double* A, const double* A2,
+                               const double* B, double* C, void* workspace, size_t ws_bytes, void* stream) {
+  if (M <= 0 || N <= 0 || K <= 0 || !A || !B || !C) return CPD_ERR_INVALID_ARG;
+  if (!workspace || ws_bytes < cpd_test_split_workspace(M, N, K)) return CPD_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const int Kp = (K + 31) / 32 * 32;
+  char* b = (char*)workspace;
+  __bf16* Ah = (__bf16*)b; b += al(2 * (size_t)M * Kp);
+  __bf16* Al = (__bf16*)b; b += al(2 * (size_t)M * Kp);
+  b += 2 * al(2 * (size_t)M * Kp);
+  __bf16* Bh = (__bf16*)b; b += al(2 * (size_t)N * Kp);
+  __bf16* Bl = (__bf16*)b; b += al(2 * (size_t)N * Kp);
+  b += 2 * al(2 * (size_t)N * Kp);
+  float* Ap = (float*)b; b += al(4 * (size_t)M * Kp);
+  float* Aq = (float*)b;
+  split_rows_f64(s, B, N, K, K, Bh, Bl, Kp, Kp);
+  SplitOperand opB{Bh, Bl, nullptr, nullptr, Kp};
+  SplitOperand opA;
+  if (A2) {
+    hipLaunchKernelGGL(to_f32_padded, dim3(grid_of((size_t)M * Kp)), dim3(256), 0, s, A, M, K, Ap, Kp);
+    hipLaunchKernelGGL(to_f32_padded, dim3(grid_of((size_t)M * Kp)), dim3(256), 0, s, A2, M, K, Aq, Kp);
+    opA = SplitOperand{nullptr, nullptr, Ap, Aq, Kp};
+  } else {
+    split_rows_f64(s, A, M, K, K, Ah, Al, Kp, Kp);
+    opA = SplitOperand{Ah, Al, nullptr, nullptr, Kp};
+  }
+  gemm_split_launch(s, M, N, Kp, opA, opB, nullptr, C, nullptr, N, nullptr);
+  return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
+}
+
+}  // extern "C"
+
+// Lane-layout probe of the 16x16x4 FP64 / FP32 matrix instructions: probe
+// p feeds a[p*64 + lane], b[p*64 + lane] to one wave with a zero
+// accumulator and writes the 4 result registers to d[p*256 + lane*4 + r].
+__global__ void mfma_probe_f64(const double* a, const double* b, double* d) {
+  const int p = blockIdx.x, l = threadIdx.x;
+  d4_t acc = {0, 0, 0, 0};
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p * 64 + l], b[p * 64 + l], acc, 0, 0, 0);
+  for (int r = 0; r < 4; ++r) d[p * 256 + l * 4 + r] = acc[r];
+}
+__global__ void mfma_probe_f32(const float* a, const float* b, float* d) {
+  const int p = blockIdx.x, l = threadIdx.x;
+  f4_t acc = {0, 0, 0, 0};
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[p * 64 + l], b[p * 64 + l], acc, 0, 0, 0);
+  for (int r = 0; r < 4; ++r) d[p * 256 + l * 4 + r] = acc[r];
+}
+extern "C" cpd_status cpd_test_mfma_probe(int32_t fp32, int32_t nprobe, const void* a, const void* b, void* d,
+                                          void* stream) {
+  if (nprobe <= 0 || !a || !b || !d) return CPD_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (fp32) hipLaunchKernelGGL(mfma_probe_f32, dim3(nprobe), dim3(64), 0, s, (const float*)a, (const float*)b, (float*)d);
+  else hipLaunchKernelGGL(mfma_probe_f64, dim3(nprobe), dim3(64), 0, s, (const double*)a, (const double*)b, (double*)d);
+  return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
+}

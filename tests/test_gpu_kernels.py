@@ -1,0 +1,132 @@
+"""Kernel-level parity on the GPU: GEMM (FP64/FP32 matrix cores, fused
+Hadamard), the blocked Cholesky + triangular solves, and the split-BF16
+GEMM, each against NumPy FP64 on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from gpu_util import need_gpu, say, to_dev, rel_err, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+GEMM_CASES = [
+    # (M, N, K, a_t, b_t, had)
+    (13, 7, 5, False, False, False),
+    (131, 77, 45, False, False, False),
+    (131, 77, 45, True, False, False),
+    (131, 77, 45, False, False, True),
+    (131, 77, 45, True, False, True),
+    (64, 200, 33, False, True, False),
+    (70, 70, 19, True, True, False),
+    (2100, 2080, 40, False, False, True),   # 128x128 tiles, ragged edges
+    (2100, 2080, 40, True, False, False),
+]
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("case", GEMM_CASES)
+def test_gemm(case, fp32):
+    from paper_2502_17683_amd import test_gemm
+    M, N, K, a_t, b_t, had = case
+    say(f"gemm M={M} N={N} K={K} a_t={a_t} b_t={b_t} had={had} fp32={fp32}")
+    rng = np.random.default_rng(M * 7 + N + K)
+    A = rng.standard_normal((K, M) if a_t else (M, K))
+    B1 = rng.standard_normal((N, K) if b_t else (K, N))
+    B2 = rng.standard_normal(B1.shape) if had else None
+    dt = torch.float32 if fp32 else torch.float64
+    C = test_gemm(to_dev(A, dt), to_dev(B1, dt), to_dev(B2, dt) if had else None, a_t, b_t).cpu().numpy()
+    opA = A.T if a_t else A
+    opB = B1.T if b_t else B1
+    if had:
+        opB = opB * B2
+    ref = opA @ opB
+    scale = np.abs(opA) @ np.abs(opB)
+    tol = (4e-6 if fp32 else 1e-14) * np.sqrt(K)
+    assert np.all(np.abs(C - ref) <= tol * scale + 1e-300)
+
+
+@pytest.mark.parametrize("R,n", [(60, 20), (64, 64), (150, 45), (300, 200), (1000, 130)])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_spd_solve(R, n, fp32):
+    from paper_2502_17683_amd import test_solve
+    say(f"solve R={R} n={n} fp32={fp32}")
+    rng = np.random.default_rng(R + n)
+    A = rng.standard_normal((R, R + 5))
+    V = A @ A.T / R + 0.5 * np.eye(R)
+    M = rng.standard_normal((n, R))
+    dt = torch.float32 if fp32 else torch.float64
+    F, failed = test_solve(to_dev(V, dt), to_dev(M, dt))
+    assert not failed
+    F = F.cpu().numpy()
+    ref = np.linalg.solve(V, M.T).T
+    cond = np.linalg.cond(V)
+    eps = 6e-8 if fp32 else 1.1e-16
+    assert rel_err(F, ref) <= 50 * R * cond * eps
+
+
+def test_spd_solve_detects_indefinite():
+    from paper_2502_17683_amd import test_solve
+    R = 100
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((R, R))
+    V = A @ A.T
+    V[70, 70] = -5.0  # not positive definite
+    _, failed = test_solve(to_dev(V), to_dev(rng.standard_normal((8, R))))
+    assert failed
+
+
+@pytest.mark.parametrize("M,N,K", [(37, 29, 50), (256, 130, 300), (800, 1000, 1024)])
+@pytest.mark.parametrize("pair", [False, True])
+def test_gemm_split_error_bound(M, N, K, pair):
+    """Split-BF16 product: every element within the bound of one correction
+    pass (dropped lo*lo term and the two bf16 roundings, ~3 * 2^-16 of
+    sum |a||b|) plus FP32 accumulation (K * 2^-24 of sum |a||b|)."""
+    from paper_2502_17683_amd import test_gemm_split
+    say(f"split M={M} N={N} K={K} pair={pair}")
+    rng = np.random.default_rng(M + N + K)
+    A = rng.standard_normal((M, K))
+    A2 = rng.standard_normal((M, K)) if pair else None
+    B = rng.standard_normal((N, K))
+    C = test_gemm_split(to_dev(A), to_dev(B), to_dev(A2) if pair else None).cpu().numpy()
+    Aop = (A.astype(np.float32) * A2.astype(np.float32)).astype(np.float64) if pair else A
+    ref = Aop @ B.T
+    scale = np.abs(Aop) @ np.abs(B).T
+    bound = (3 * 2.0 ** -16 + K * 2.0 ** -24) * scale
+    assert np.all(np.abs(C - ref) <= bound)
+    # and it really is better than a single bf16 pass
+    assert np.abs(C - ref).max() < 2.0 ** -9 * scale.max()
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_mfma_result_layout(fp32):
+    """The result-register layout the kernels assume (csrc/mfma.h): FP32
+    row 4*(l/16)+r, FP64 row l/16+4*r, column l%16 for both."""
+    import ctypes
+    from paper_2502_17683_amd import _lib
+    lib = _lib.load()
+    dt = torch.float32 if fp32 else torch.float64
+    rng = np.random.default_rng(11)
+    A = rng.integers(-3, 4, (16, 4)).astype(np.float64)
+    B = rng.integers(-3, 4, (4, 16)).astype(np.float64)
+    a = np.zeros(64)
+    b = np.zeros(64)
+    for l in range(64):
+        a[l] = A[l % 16, l // 16]
+        b[l] = B[l // 16, l % 16]
+    ad, bd = to_dev(a, dt), to_dev(b, dt)
+    d = torch.zeros(256, dtype=dt, device="cuda")
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert lib.cpd_test_mfma_probe(int(fp32), 1, ctypes.c_void_p(ad.data_ptr()), ctypes.c_void_p(bd.data_ptr()),
+                                   ctypes.c_void_p(d.data_ptr()), s) == 0
+    torch.cuda.synchronize()
+    D = d.cpu().numpy().reshape(64, 4)
+    ref = A @ B
+    for l in range(64):
+        for r in range(4):
+            row = 4 * (l // 16) + r if fp32 else l // 16 + 4 * r
+            assert D[l, r] == ref[row, l % 16]
