@@ -3,13 +3,20 @@
 //
 // V is Tp x Tp row-major (Tp = 64 nblk; padding rows/columns hold the
 // identity).  Right-looking, 64-wide blocks, ONE launch per block step:
-// step j updates every trailing tile (i, k), k >= j+1, with panel j and,
-// for the tiles of column j+1, immediately factors the (updated) diagonal
-// block in LDS -- every workgroup of that column does so redundantly, so
-// no workgroup ever waits on another -- and solves its own panel tile.
-// The diagonal blocks of L are never written back to V (other workgroups
-// of the same launch still read the unfactored block); their inverses go
-// to `linv` and feed the triangular solves as small GEMMs.
+// step j updates every trailing tile (i, k), k >= j+1, with panel j on the
+// matrix cores and, for the tiles of column j+1, immediately factors the
+// updated diagonal block -- every workgroup of that column does so
+// redundantly, so no workgroup ever waits on another -- and solves its own
+// panel tile.  The diagonal blocks of L are never written back to V (other
+// workgroups of the same launch still read the unfactored block); they go
+// to `ldiag` and feed the triangular solves.
+//
+// The sequential parts (diagonal factorisation, triangular solves of a
+// 64-wide strip) use the "strip" thread layout: thread t owns row t / 4 and
+// the 16 columns (t % 4) + 4u of a 64 x 64 tile in registers; the value of
+// column c is broadcast inside each 4-lane quad with a DPP move, and L is
+// read from LDS.  A strip solve needs no barrier at all; the diagonal
+// factorisation needs one barrier per column.
 #include <math.h>
 
 #include "kernels.h"
@@ -17,70 +24,193 @@
 
 namespace thccp {
 
-// Unblocked Cholesky of the 64x64 block in LDS (row-major, stride LDT),
-// outer-product form with deferred column scaling: one barrier per column.
-// Returns false if a pivot was not positive (the block is then garbage
-// but finite).
+// ---------------------------------------------------------- quad broadcast
+template <int K>
+__device__ __forceinline__ int qb_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, K * 0x55, 0xF, 0xF, false);
+}
+template <int K>
+__device__ __forceinline__ double qb(double v) {
+  union { double d; int i[2]; } a, b;
+  a.d = v;
+  b.i[0] = qb_int<K>(a.i[0]);
+  b.i[1] = qb_int<K>(a.i[1]);
+  return b.d;
+}
+template <int K>
+__device__ __forceinline__ float qb(float v) {
+  return __int_as_float(qb_int<K>(__float_as_int(v)));
+}
+// Value of lane (quad base + k) for every lane of the quad.
 template <typename T>
-__device__ bool lds_potrf64(T* D, int tid) {
-  bool ok = true;
-  const int r = tid >> 2, q0 = tid & 3;
+__device__ __forceinline__ T quad_bcast(T v, int k) {
+  switch (k) {
+    case 0: return qb<0>(v);
+    case 1: return qb<1>(v);
+    case 2: return qb<2>(v);
+    default: return qb<3>(v);
+  }
+}
+
+// 1/x to working precision: hardware reciprocal estimate refined by two
+// Newton steps (keeps the long FP64 division sequence off the pivot chain).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x) { return 1.0f / x; }
+
+// ----------------------------------------------------------- strip solves
+// s holds columns q0 + 4u of one row of a 64-wide strip S.
+// Forward:  S <- S L^{-T}   (solve X L^T = S, column by column, left to right)
+template <typename T>
+__device__ __forceinline__ void strip_fwd(T s[16], const T* L, const T* invd, int q0) {
+#pragma unroll
   for (int c = 0; c < TB; ++c) {
-    T piv = D[c * LDT + c];
-    if (!(piv > T(0)) || !isfinite((double)piv)) { ok = false; piv = T(1); }
-    const T inv = T(1) / piv;
-    if (r > c) {
-      const T lrc = D[r * LDT + c] * inv;
-      for (int q = c + 1 + q0; q <= r; q += 4) D[r * LDT + q] -= lrc * D[q * LDT + c];
+    const int uc = c >> 2, oc = c & 3;
+    const T x = quad_bcast<T>(s[uc] * invd[c], oc);
+    if (q0 == oc) s[uc] = x;
+#pragma unroll
+    for (int u = uc; u < 16; ++u) {
+      if (u > uc || q0 > oc) s[u] -= x * L[(q0 + 4 * u) * LDT + c];
+    }
+  }
+}
+// Backward: S <- S L^{-1}   (solve X L = S, column by column, right to left)
+template <typename T>
+__device__ __forceinline__ void strip_bwd(T s[16], const T* L, const T* invd, int q0) {
+#pragma unroll
+  for (int c = TB - 1; c >= 0; --c) {
+    const int uc = c >> 2, oc = c & 3;
+    const T x = quad_bcast<T>(s[uc] * invd[c], oc);
+    if (q0 == oc) s[uc] = x;
+#pragma unroll
+    for (int u = 0; u <= uc; ++u) {
+      if (u < uc || q0 < oc) s[u] -= x * L[c * LDT + q0 + 4 * u];
+    }
+  }
+}
+
+// Cholesky of the 64 x 64 block held in strip layout d (lower part used).
+// Right-looking with deferred scaling: column c (unscaled) and its pivot
+// are published through LDS, one barrier per column.  On return L is in
+// LDS (row-major, stride LDT, upper part zero) and invd[c] = 1 / L[c][c].
+// Returns false if a pivot was not positive (the factor is then finite
+// garbage).
+template <typename T>
+__device__ __forceinline__ bool strip_potrf(T d[16], T* L, T* invd, T* colbuf /* 2 x 64 */, T* pivs, int r, int q0) {
+  bool ok = true;
+  if (q0 == 0) colbuf[r] = d[0];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < TB; ++c) {
+    const int uc = c >> 2, oc = c & 3;
+    const T* col = colbuf + (c & 1) * TB;
+    T piv = col[c];
+    if (!(piv > T(0)) || !isfinite((double)piv)) {
+      ok = false;
+      piv = T(1);
+    }
+    const T f = col[r] * recip(piv);
+#pragma unroll
+    for (int u = uc; u < 16; ++u) {
+      if (u > uc || q0 > oc) d[u] -= f * col[q0 + 4 * u];
+    }
+    if (r == 0 && q0 == 0) pivs[c] = piv;
+    if (c + 1 < TB) {
+      const int un = (c + 1) >> 2, on = (c + 1) & 3;
+      if (q0 == on) colbuf[((c + 1) & 1) * TB + r] = d[un];
     }
     __syncthreads();
   }
-  // D[c][c] still holds pivot c; scale the columns, clear the upper part.
-  for (int e = tid; e < TB * TB; e += 256) {
-    const int rr = e >> 6, cc = e & 63;
-    if (cc < rr) {
-      T pv = D[cc * LDT + cc];
-      if (!(pv > T(0))) pv = T(1);
-      D[rr * LDT + cc] /= sqrt(pv);
-    }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int q = q0 + 4 * u;
+    const T sq = sqrt(pivs[q]);
+    T v;
+    if (q < r) v = d[u] / sq;
+    else if (q == r) v = sq;
+    else v = T(0);
+    L[r * LDT + q] = v;
   }
-  __syncthreads();
-  for (int e = tid; e < TB * TB; e += 256) {
-    const int rr = e >> 6, cc = e & 63;
-    if (cc > rr) D[rr * LDT + cc] = T(0);
-    else if (cc == rr) {
-      T pv = D[rr * LDT + rr];
-      D[rr * LDT + rr] = sqrt(pv > T(0) ? pv : T(1));
-    }
-  }
+  if (q0 == 0) invd[r] = T(1) / sqrt(pivs[r]);
   __syncthreads();
   return ok;
 }
 
-// Inverse of the lower-triangular 64x64 block L (LDS, row-major) written
-// TRANSPOSED into XT (XT[c][r] = inv(L)[r][c]).  Forward substitution on
-// the identity, outer-product form, one barrier per row.
+// ------------------------------------------------------- layout transfers
 template <typename T>
-__device__ void lds_trtri64_t(const T* L, T* X, T* XT, int tid) {
-  for (int e = tid; e < TB * TB; e += 256) {
-    const int rr = e >> 6, cc = e & 63;
-    X[rr * LDT + cc] = (rr == cc) ? T(1) : T(0);
-  }
-  __syncthreads();
-  const int r = tid >> 2, q0 = tid & 3;
-  for (int k = 0; k < TB; ++k) {
-    // rows r > k: X[r][:] -= L[r][k] / L[k][k] * X[k][:]   (columns <= k)
-    if (r > k) {
-      const T f = L[r * LDT + k] / L[k * LDT + k];
-      for (int q = q0; q <= k; q += 4) X[r * LDT + q] -= f * X[k * LDT + q];
+__device__ __forceinline__ void acc_to_lds(const typename Acc4<T>::type acc[4], T* S, int lane, int w) {
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S[acc_row<T>(lane, w, r) * LDT + acc_col(lane, tj)] = acc[tj][r];
+}
+template <typename T>
+__device__ __forceinline__ void lds_to_strip(const T* S, T s[16], int r, int q0) {
+#pragma unroll
+  for (int u = 0; u < 16; ++u) s[u] = S[r * LDT + q0 + 4 * u];
+}
+template <typename T>
+__device__ __forceinline__ void load_acc(typename Acc4<T>::type acc[4], const T* g, size_t ld, int nrows,
+                                         int lane, int w) {
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = acc_row<T>(lane, w, r);
+      acc[tj][r] = row < nrows ? g[(size_t)row * ld + acc_col(lane, tj)] : T(0);
     }
-    __syncthreads();
+}
+template <typename T>
+__device__ __forceinline__ void store_acc(const typename Acc4<T>::type acc[4], T* g, size_t ld, int nrows,
+                                          int lane, int w) {
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = acc_row<T>(lane, w, r);
+      if (row < nrows) g[(size_t)row * ld + acc_col(lane, tj)] = acc[tj][r];
+    }
+}
+template <typename T>
+__device__ __forceinline__ void store_strip(const T s[16], T* g, size_t ld, int nrows, int r, int q0) {
+  if (r < nrows) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) g[(size_t)r * ld + q0 + 4 * u] = s[u];
   }
-  for (int e = tid; e < TB * TB; e += 256) {
-    const int rr = e >> 6, cc = e & 63;
-    XT[cc * LDT + rr] = X[rr * LDT + cc] / L[rr * LDT + rr];
+}
+template <typename T>
+__device__ __forceinline__ void load_block_lds(T* S, const T* g, size_t ld, int tid) {
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int idx = tid + 256 * e;
+    S[(idx >> 6) * LDT + (idx & 63)] = g[(size_t)(idx >> 6) * ld + (idx & 63)];
   }
-  __syncthreads();
+}
+
+// Register prefetch of a 64 x 64 row-major block (16 values per thread,
+// element idx = tid + 256 e at (idx / 64, idx % 64)); rows >= nrows read 0.
+template <typename T>
+__device__ __forceinline__ void fetch_block(T v[16], const T* g, size_t ld, int nrows, int tid) {
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int idx = tid + 256 * e;
+    v[e] = (idx >> 6) < nrows ? g[(size_t)(idx >> 6) * ld + (idx & 63)] : T(0);
+  }
+}
+// ... written to LDS transposed (S[c][r]) or as is (S[r][c]).
+template <typename T, bool TRANSPOSE>
+__device__ __forceinline__ void put_block(T* S, const T v[16], int tid) {
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int idx = tid + 256 * e;
+    if (TRANSPOSE) S[(idx & 63) * LDT + (idx >> 6)] = v[e];
+    else S[(idx >> 6) * LDT + (idx & 63)] = v[e];
+  }
 }
 
 // Maps a linear block id onto the lower-triangular tile (i, k) of the
@@ -88,256 +218,220 @@ __device__ void lds_trtri64_t(const T* L, T* X, T* XT, int tid) {
 __device__ __forceinline__ void tri_tile(int bid, int k0, int nblk, int& i, int& k) {
   k = k0;
   int len = nblk - k0;
-  while (bid >= len) { bid -= len; ++k; --len; }
+  while (bid >= len) {
+    bid -= len;
+    ++k;
+    --len;
+  }
   i = k + bid;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void chol_step_kernel(T* V, int nblk, int j, T* linv,
-                                                         T* diagL, DevState* st, int retry_pass) {
+// Tiles launched by each step.
+__host__ __device__ inline int chol_tiles(int nblk, int j) {
+  if (j > nblk - 2) return 0;
+  const int t = nblk - 1 - j;
+  return (j < 0) ? nblk : t * (t + 1) / 2;  // step -1: column 0 only
+}
+__host__ __device__ inline int fwd_tiles(int nblk, int nrt, int j) {
+  if (j < -1 || j > nblk - 2) return 0;
+  return nrt * ((j < 0) ? 1 : nblk - 1 - j);
+}
+
+enum StepMode { STEP_CHOL = 0, STEP_FWD = 1, STEP_BWD = 2, STEP_CHOL_FWD = 3 };
+
+// One launch of the blocked factorisation / solve.
+//   STEP_CHOL:     Cholesky step j (tiles of the trailing lower triangle).
+//   STEP_FWD/BWD:  triangular-solve step j over (row tile, column block).
+//                  Forward: G L^T = M; step j subtracts G_j L_kj^T from every
+//                  block k > j, the blocks of column j+1 then solve with
+//                  L_{j+1,j+1}.  Backward: F L = G, mirrored from the last
+//                  column block down.
+//   STEP_CHOL_FWD: Cholesky step j and forward step j-1 in one launch (the
+//                  latter needs only panel columns <= j-1 and diagonal block
+//                  j, all from earlier launches); no damped retry.
+// (The bodies are written inline in the kernel: moving them into device
+// functions doubles the register use and spills.)
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void step_kernel(T* V, int nblk, int j, T* ldiag, T* diagL, T* M, int n,
+                                                    DevState* st, int retry_pass) {
   typedef typename Acc4<T>::type acc_t;
   __shared__ T S0[TB * LDT];
   __shared__ T S1[TB * LDT];
   __shared__ T S2[TB * LDT];
+  __shared__ T colbuf[2 * TB];
+  __shared__ T invd[TB];
+  __shared__ T pivs[TB];
   if (st->done) return;
-  if (retry_pass ? !st->retry_active : st->chol_fail) return;
-
   const int Tp = nblk * TB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  int i, k;
-  tri_tile(blockIdx.x, j + 1, nblk, i, k);
-  T* tile = V + (size_t)i * TB * Tp + (size_t)k * TB;
+  const int sr = tid >> 2, q0 = tid & 3;
+  int bid = blockIdx.x;
 
-  acc_t acc[4];
+  if constexpr (MODE == STEP_CHOL || MODE == STEP_CHOL_FWD) {
+    if (MODE == STEP_CHOL_FWD ? st->chol_fail : (retry_pass ? !st->retry_active : st->chol_fail)) return;
+    const int nc = MODE == STEP_CHOL ? 1 << 30 : chol_tiles(nblk, j);
+    if (bid < nc) {
+      int i, k;
+      tri_tile(bid, j + 1, nblk, i, k);
+      T* tile = V + (size_t)i * TB * Tp + (size_t)k * TB;
+      // every global load of the step is issued up front
+      acc_t acc[4];
+      T ra[16], rb[16];
+      load_acc<T>(acc, tile, Tp, TB, lane, w);
+      if (j >= 0) {
+        fetch_block<T>(ra, V + (size_t)i * TB * Tp + (size_t)j * TB, Tp, TB, tid);
+        fetch_block<T>(rb, V + (size_t)k * TB * Tp + (size_t)j * TB, Tp, TB, tid);
+      }
+      acc_t dd[4];
+      const bool need_d = (k == j + 1) && (i != k);
+      if (need_d) load_acc<T>(dd, V + (size_t)k * TB * Tp + (size_t)k * TB, Tp, TB, lane, w);
+      if (j >= 0) {
+        // tile -= L_ij L_kj^T
+        put_block<T, true>(S0, ra, tid);
+        put_block<T, true>(S1, rb, tid);
+        __syncthreads();
+        acc_t p[4];
 #pragma unroll
-  for (int tj = 0; tj < 4; ++tj)
+        for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
+        tile_mma64<T>(p, S0, S1, lane, w);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      acc[tj][r] = tile[(size_t)acc_row<T>(lane, w, r) * Tp + acc_col(lane, tj)];
-
-  if (j >= 0) {
-    // tile -= L_ij L_kj^T
-    block_to_lds<T, true>(S0, V + (size_t)i * TB * Tp + (size_t)j * TB, Tp, TB, tid);
-    block_to_lds<T, true>(S1, V + (size_t)k * TB * Tp + (size_t)j * TB, Tp, TB, tid);
-    __syncthreads();
-    acc_t p[4];
+        for (int tj = 0; tj < 4; ++tj) acc[tj] -= p[tj];
+        if (k != j + 1) {
+          store_acc<T>(acc, tile, Tp, TB, lane, w);
+          return;
+        }
+      }
+      // Column k = j + 1.  Updated diagonal block D = A_kk - L_kj L_kj^T.
+      T d[16];
+      if (i == k) {
+        acc_to_lds<T>(acc, S2, lane, w);
+      } else {
+        if (j >= 0) {
+          acc_t p[4];
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
-    tile_mma64<T>(p, S0, S1, lane, w);
+          for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
+          tile_mma64<T>(p, S1, S1, lane, w);
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj) acc[tj] -= p[tj];
-    if (k != j + 1) {
+          for (int tj = 0; tj < 4; ++tj) dd[tj] -= p[tj];
+        }
+        acc_to_lds<T>(dd, S2, lane, w);
+        // own updated tile into S0 (free once every wave is past the MMAs)
+        __syncthreads();
+        acc_to_lds<T>(acc, S0, lane, w);
+      }
+      __syncthreads();
+      lds_to_strip<T>(S2, d, sr, q0);
+      // S1 receives L_kk (every wave is past its last read of S1 here).
+      const bool ok = strip_potrf<T>(d, S1, invd, colbuf, pivs, sr, q0);
+      if (i == k) {
+        if (!ok && tid == 0) {
+          if (retry_pass) atomicOr(&st->flags, (int)FLAG_NOT_SPD);
+          else atomicExch(&st->chol_fail, 1);
+        }
+        T* out = ldiag + (size_t)k * TB * TB;
 #pragma unroll
-      for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          tile[(size_t)acc_row<T>(lane, w, r) * Tp + acc_col(lane, tj)] = acc[tj][r];
+        for (int e = 0; e < 16; ++e) {
+          const int idx = tid + 256 * e;
+          out[idx] = S1[(idx >> 6) * LDT + (idx & 63)];
+        }
+        if (tid < TB) diagL[k * TB + tid] = S1[tid * LDT + tid];
+        return;
+      }
+      // Panel tile: L_ik = A'_ik L_kk^{-T}
+      T s[16];
+      lds_to_strip<T>(S0, s, sr, q0);
+      strip_fwd<T>(s, S1, invd, q0);
+      store_strip<T>(s, tile, Tp, TB, sr, q0);
       return;
     }
+    bid -= nc;
   }
-  // Column k = j + 1: updated diagonal block D = A_kk - L_kj L_kj^T into S2.
-  if (i == k) {
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) S2[acc_row<T>(lane, w, r) * LDT + acc_col(lane, tj)] = acc[tj][r];
-  } else {
-    const T* dblk = V + (size_t)k * TB * Tp + (size_t)k * TB;
-    acc_t d[4];
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) d[tj][r] = dblk[(size_t)acc_row<T>(lane, w, r) * Tp + acc_col(lane, tj)];
-    if (j >= 0) {
+  if constexpr (MODE != STEP_CHOL) {
+    constexpr bool FWD = MODE != STEP_BWD;
+    const int js = MODE == STEP_CHOL_FWD ? j - 1 : j;  // solve step
+    const int nrt = (n + TB - 1) / TB;
+    const int rt = bid % nrt;
+    const int k = FWD ? js + 1 + bid / nrt : js - 1 - bid / nrt;
+    const int r0 = rt * TB;
+    const int nrows = min(TB, n - r0);
+    T* tile = M + (size_t)r0 * Tp + (size_t)k * TB;
+    const bool has_update = FWD ? (js >= 0) : (js < nblk);
+    const bool solve = FWD ? (k == js + 1) : (k == js - 1);
+    // every global load of the step is issued up front
+    acc_t acc[4];
+    T ra[16], rb[16], rl[16];
+    load_acc<T>(acc, tile, Tp, nrows, lane, w);
+    if (has_update) {
+      fetch_block<T>(ra, M + (size_t)r0 * Tp + (size_t)js * TB, Tp, nrows, tid);
+      if (FWD) fetch_block<T>(rb, V + (size_t)k * TB * Tp + (size_t)js * TB, Tp, TB, tid);  // L_kj
+      else fetch_block<T>(rb, V + (size_t)js * TB * Tp + (size_t)k * TB, Tp, TB, tid);     // L_jk
+    }
+    if (solve) fetch_block<T>(rl, ldiag + (size_t)k * TB * TB, TB, TB, tid);
+    if (has_update) {
+      put_block<T, true>(S0, ra, tid);
+      if (FWD) put_block<T, true>(S1, rb, tid);   // B = L_kj^T
+      else put_block<T, false>(S1, rb, tid);      // B = L_jk
+      __syncthreads();
       acc_t p[4];
 #pragma unroll
       for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
-      tile_mma64<T>(p, S1, S1, lane, w);
+      tile_mma64<T>(p, S0, S1, lane, w);
 #pragma unroll
-      for (int tj = 0; tj < 4; ++tj) d[tj] -= p[tj];
+      for (int tj = 0; tj < 4; ++tj) acc[tj] -= p[tj];
     }
-    __syncthreads();  // S0 is reused below
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) S2[acc_row<T>(lane, w, r) * LDT + acc_col(lane, tj)] = d[tj][r];
+    if (!solve) {
+      store_acc<T>(acc, tile, Tp, nrows, lane, w);
+      return;
+    }
+    __syncthreads();
+    acc_to_lds<T>(acc, S0, lane, w);
+    put_block<T, false>(S1, rl, tid);
+    __syncthreads();
+    if (tid < TB) invd[tid] = recip(S1[tid * LDT + tid]);
+    T s[16];
+    lds_to_strip<T>(S0, s, sr, q0);
+    __syncthreads();
+    if (FWD) strip_fwd<T>(s, S1, invd, q0);
+    else strip_bwd<T>(s, S1, invd, q0);
+    store_strip<T>(s, tile, Tp, nrows, sr, q0);
   }
-  __syncthreads();
-  const bool ok = lds_potrf64<T>(S2, tid);
-  // inverse of L_kk, transposed, into S1 (S0 is scratch)
-  lds_trtri64_t<T>(S2, S0, S1, tid);
-  if (i == k) {
-    if (!ok && tid == 0) {
-      if (retry_pass) atomicOr(&st->flags, (int)FLAG_NOT_SPD);
-      else atomicExch(&st->chol_fail, 1);
-    }
-    T* out = linv + (size_t)k * TB * TB;
-    for (int e = tid; e < TB * TB; e += 256) {
-      const int rr = e >> 6, cc = e & 63;
-      out[rr * TB + cc] = S1[cc * LDT + rr];
-    }
-    if (tid < TB) diagL[k * TB + tid] = S2[tid * LDT + tid];
-    return;
-  }
-  // Panel tile: L_ik = A'_ik inv(L_kk)^T.  A operand from acc via LDS.
-#pragma unroll
-  for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) S0[acc_col(lane, tj) * LDT + acc_row<T>(lane, w, r)] = acc[tj][r];
-  __syncthreads();
-  // B[kk][c] = inv(L)[c][kk] = XT[kk][c]... S1 holds XT[c][r] = inv[r][c];
-  // we need B[kk][c] = inv[c][kk] = S1[kk][c].
-  acc_t o[4];
-#pragma unroll
-  for (int tj = 0; tj < 4; ++tj) o[tj] = acc_t{0, 0, 0, 0};
-  tile_mma64<T>(o, S0, S1, lane, w);
-#pragma unroll
-  for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) tile[(size_t)acc_row<T>(lane, w, r) * Tp + acc_col(lane, tj)] = o[tj][r];
 }
 
 template <typename T>
-void chol_factor(hipStream_t s, T* V, int nblk, T* linv, T* diagL, DevState* st, int retry_pass) {
-  for (int j = -1; j <= nblk - 2; ++j) {
-    const int t = nblk - 1 - j;
-    const int tiles = (j < 0) ? nblk : t * (t + 1) / 2;  // step -1: column 0 only
-    hipLaunchKernelGGL((chol_step_kernel<T>), dim3(tiles), dim3(256), 0, s, V, nblk, j, linv,
-                       diagL, st, retry_pass);
-  }
-}
-
-// ------------------------------------------------------------------ solves
-// Row tiles of 64 rows of M (n x Tp).  Forward: G L^T = M; backward: F L = G.
-template <typename T>
-__global__ __launch_bounds__(256) void trsm_fwd_kernel(const T* V, int nblk, const T* linv, T* M,
-                                                        int n, int j, DevState* st) {
-  typedef typename Acc4<T>::type acc_t;
-  __shared__ T S0[TB * LDT];
-  __shared__ T S1[TB * LDT];
-  if (st->done) return;
-  const int Tp = nblk * TB;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int nrt = (n + TB - 1) / TB;
-  const int rt = blockIdx.x % nrt;
-  const int k = j + 1 + blockIdx.x / nrt;
-  const int r0 = rt * TB;
-  const int nrows = min(TB, n - r0);
-  T* tile = M + (size_t)r0 * Tp + (size_t)k * TB;
-
-  acc_t acc[4];
-#pragma unroll
-  for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = acc_row<T>(lane, w, r);
-      acc[tj][r] = row < nrows ? tile[(size_t)row * Tp + acc_col(lane, tj)] : T(0);
-    }
-  if (j >= 0) {
-    // M_k -= G_j L_kj^T : A = G_j (rows x 64), B[kk][c] = L_kj[c][kk]
-    block_to_lds<T, true>(S0, M + (size_t)r0 * Tp + (size_t)j * TB, Tp, nrows, tid);
-    block_to_lds<T, true>(S1, V + (size_t)k * TB * Tp + (size_t)j * TB, Tp, TB, tid);
-    __syncthreads();
-    acc_t p[4];
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
-    tile_mma64<T>(p, S0, S1, lane, w);
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj) acc[tj] -= p[tj];
-  }
-  if (k == j + 1) {
-    // G_k = M'_k inv(L_kk)^T : B[kk][c] = inv[c][kk]
-    __syncthreads();
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) S0[acc_col(lane, tj) * LDT + acc_row<T>(lane, w, r)] = acc[tj][r];
-    block_to_lds<T, true>(S1, linv + (size_t)k * TB * TB, TB, TB, tid);
-    __syncthreads();
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj) acc[tj] = acc_t{0, 0, 0, 0};
-    tile_mma64<T>(acc, S0, S1, lane, w);
-  }
-#pragma unroll
-  for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = acc_row<T>(lane, w, r);
-      if (row < nrows) tile[(size_t)row * Tp + acc_col(lane, tj)] = acc[tj][r];
-    }
+void chol_factor(hipStream_t s, T* V, int nblk, T* ldiag, T* diagL, DevState* st, int retry_pass) {
+  for (int j = -1; j <= nblk - 2; ++j)
+    hipLaunchKernelGGL((step_kernel<T, STEP_CHOL>), dim3(chol_tiles(nblk, j)), dim3(256), 0, s, V, nblk, j,
+                       ldiag, diagL, (T*)nullptr, 0, st, retry_pass);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void trsm_bwd_kernel(const T* V, int nblk, const T* linv, T* M,
-                                                        int n, int j, DevState* st) {
-  typedef typename Acc4<T>::type acc_t;
-  __shared__ T S0[TB * LDT];
-  __shared__ T S1[TB * LDT];
-  if (st->done) return;
-  const int Tp = nblk * TB;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int nrt = (n + TB - 1) / TB;
-  const int rt = blockIdx.x % nrt;
-  const int k = j - 1 - blockIdx.x / nrt;  // k = j-1, j-2, ..., 0
-  const int r0 = rt * TB;
-  const int nrows = min(TB, n - r0);
-  T* tile = M + (size_t)r0 * Tp + (size_t)k * TB;
-
-  acc_t acc[4];
-#pragma unroll
-  for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = acc_row<T>(lane, w, r);
-      acc[tj][r] = row < nrows ? tile[(size_t)row * Tp + acc_col(lane, tj)] : T(0);
-    }
-  if (j < nblk) {
-    // G_k -= F_j L_jk : A = F_j, B[kk][c] = L_jk[kk][c]
-    block_to_lds<T, true>(S0, M + (size_t)r0 * Tp + (size_t)j * TB, Tp, nrows, tid);
-    block_to_lds<T, false>(S1, V + (size_t)j * TB * Tp + (size_t)k * TB, Tp, TB, tid);
-    __syncthreads();
-    acc_t p[4];
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
-    tile_mma64<T>(p, S0, S1, lane, w);
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj) acc[tj] -= p[tj];
-  }
-  if (k == j - 1) {
-    // F_k = G'_k inv(L_kk) : B[kk][c] = inv[kk][c]
-    __syncthreads();
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) S0[acc_col(lane, tj) * LDT + acc_row<T>(lane, w, r)] = acc[tj][r];
-    block_to_lds<T, false>(S1, linv + (size_t)k * TB * TB, TB, TB, tid);
-    __syncthreads();
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj) acc[tj] = acc_t{0, 0, 0, 0};
-    tile_mma64<T>(acc, S0, S1, lane, w);
-  }
-#pragma unroll
-  for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = acc_row<T>(lane, w, r);
-      if (row < nrows) tile[(size_t)row * Tp + acc_col(lane, tj)] = acc[tj][r];
-    }
-}
-
-template <typename T>
-void chol_solve_rows(hipStream_t s, const T* V, int nblk, const T* linv, T* M, int n, DevState* st) {
+void chol_solve_rows(hipStream_t s, const T* V, int nblk, const T* ldiag, T* M, int n, DevState* st) {
   if (n <= 0) return;
   const int nrt = (n + TB - 1) / TB;
-  for (int j = -1; j <= nblk - 2; ++j) {
-    const int cols = (j < 0) ? 1 : nblk - 1 - j;
-    hipLaunchKernelGGL((trsm_fwd_kernel<T>), dim3(nrt * cols), dim3(256), 0, s, V, nblk, linv, M, n,
-                       j, st);
-  }
+  for (int j = -1; j <= nblk - 2; ++j)
+    hipLaunchKernelGGL((step_kernel<T, STEP_FWD>), dim3(fwd_tiles(nblk, nrt, j)), dim3(256), 0, s, (T*)V,
+                       nblk, j, (T*)ldiag, (T*)nullptr, M, n, st, 0);
+  chol_solve_bwd<T>(s, V, nblk, ldiag, M, n, st);
+}
+
+template <typename T>
+void chol_solve_bwd(hipStream_t s, const T* V, int nblk, const T* ldiag, T* M, int n, DevState* st) {
+  if (n <= 0) return;
+  const int nrt = (n + TB - 1) / TB;
   for (int j = nblk; j >= 1; --j) {
     const int cols = (j == nblk) ? 1 : j;
-    hipLaunchKernelGGL((trsm_bwd_kernel<T>), dim3(nrt * cols), dim3(256), 0, s, V, nblk, linv, M, n,
-                       j, st);
+    hipLaunchKernelGGL((step_kernel<T, STEP_BWD>), dim3(nrt * cols), dim3(256), 0, s, (T*)V, nblk, j,
+                       (T*)ldiag, (T*)nullptr, M, n, st, 0);
+  }
+}
+
+template <typename T>
+void chol_factor_fwd(hipStream_t s, T* V, int nblk, T* ldiag, T* diagL, T* M, int n, DevState* st) {
+  const int nrt = (n + TB - 1) / TB;
+  for (int t = -1; t <= nblk - 1; ++t) {
+    const int tiles = chol_tiles(nblk, t) + fwd_tiles(nblk, nrt, t - 1);
+    hipLaunchKernelGGL((step_kernel<T, STEP_CHOL_FWD>), dim3(tiles), dim3(256), 0, s, V, nblk, t, ldiag, diagL,
+                       M, n, st, 0);
   }
 }
 
@@ -347,5 +441,9 @@ template void chol_solve_rows<double>(hipStream_t, const double*, int, const dou
                                       DevState*);
 template void chol_solve_rows<float>(hipStream_t, const float*, int, const float*, float*, int,
                                      DevState*);
+template void chol_solve_bwd<double>(hipStream_t, const double*, int, const double*, double*, int, DevState*);
+template void chol_solve_bwd<float>(hipStream_t, const float*, int, const float*, float*, int, DevState*);
+template void chol_factor_fwd<double>(hipStream_t, double*, int, double*, double*, double*, int, DevState*);
+template void chol_factor_fwd<float>(hipStream_t, float*, int, float*, float*, float*, int, DevState*);
 
 }  // namespace thccp

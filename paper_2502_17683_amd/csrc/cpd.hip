@@ -26,6 +26,7 @@ struct Bufs {
   T* Msol;
   T* Msave;
   T* F[4];
+  T* Fsave[4];  // factors at the start of the sweep (fast-path checkpoint)
   T* G[4];
   T* V;
   T* linv;
@@ -52,8 +53,11 @@ struct cpd_plan_s {
   cpd_desc d;
   hipStream_t stream;
   hipStream_t cap;
-  hipGraph_t graph, graph_nofit;
-  hipGraphExec_t exec, exec_nofit;
+  // [fast][fit]: fast = checkpoint + factorisation fused with the forward
+  // solve and no retry pass (a failed pivot is replayed by the host through
+  // the safe graph); safe = damped retry pass inside the graph.
+  hipGraph_t graph[2][2];
+  hipGraphExec_t exec[2][2];
   bool have_graph;
   int fit_every;     // mixed precision: the fit (FP64) is evaluated every fit_every sweeps
   long launched;     // sweeps enqueued since init / set_factors
@@ -63,6 +67,7 @@ struct cpd_plan_s {
   Bufs<float> b32;
   MixedBufs mx;
   DevState* st;
+  DevState* st_save;
   double* fit_hist;
   double* inner_part;
   double* row_part;
@@ -107,6 +112,7 @@ void carve_typed(Layout& L, cpd_plan_s* p, Bufs<T>& b, bool own_inputs) {
   b.Msol = (T*)L.take(sizeof(T) * (size_t)p->nmax * Tp);
   b.Msave = (T*)L.take(sizeof(T) * (size_t)p->n[3] * Tp);
   for (int m = 0; m < 4; ++m) b.F[m] = (T*)L.take(sizeof(T) * (size_t)p->n[m] * Tp);
+  for (int m = 0; m < 4; ++m) b.Fsave[m] = (T*)L.take(sizeof(T) * (size_t)p->n[m] * Tp);
   for (int m = 0; m < 4; ++m) b.G[m] = (T*)L.take(sizeof(T) * (size_t)Tp * Tp);
   b.V = (T*)L.take(sizeof(T) * (size_t)Tp * Tp);
   b.linv = (T*)L.take(sizeof(T) * (size_t)p->nblk * 64 * 64);
@@ -119,6 +125,7 @@ size_t carve(cpd_plan_s* p, char* base) {
   L.base = base;
   const int Rt = p->Rt, Tp = p->Tp;
   p->st = (DevState*)L.take(sizeof(DevState));
+  p->st_save = (DevState*)L.take(sizeof(DevState));
   p->fit_hist = (double*)L.take(sizeof(double) * HIST_CAP);
   p->inner_part = (double*)L.take(sizeof(double) * Tp);
   p->row_part = (double*)L.take(sizeof(double) * Tp);
@@ -234,7 +241,7 @@ void mttkrp_into(cpd_plan_s* p, Bufs<T>& b, int n, bool fresh_core, T* out, T* o
 // Normal-equation solve of mode n, in place in Msol, then normalisation,
 // Gram and projection of the new factor.
 template <typename T>
-void solve_mode(cpd_plan_s* p, Bufs<T>& b, int n, hipStream_t s, bool with_inner) {
+void solve_mode(cpd_plan_s* p, Bufs<T>& b, int n, hipStream_t s, bool with_inner, bool fast) {
   const int Rc = p->Rc, Tp = p->Tp;
   DevState* st = p->st;
   const T* g[3];
@@ -242,21 +249,65 @@ void solve_mode(cpd_plan_s* p, Bufs<T>& b, int n, hipStream_t s, bool with_inner
   for (int m = 0; m < 4; ++m)
     if (m != n) g[q++] = b.G[m];
   form_normal_matrix<T>(s, b.V, Tp, Rc, g[0], g[1], g[2], st, 0);
-  chol_factor<T>(s, b.V, p->nblk, b.linv, b.diagL, st, 0);
-  retry_prepare_launch<T>(s, st, p->d.chol_fallback, g[0], g[1], g[2], Rc, Tp);
-  form_normal_matrix<T>(s, b.V, Tp, Rc, g[0], g[1], g[2], st, 1);
-  chol_factor<T>(s, b.V, p->nblk, b.linv, b.diagL, st, 1);
-  chol_solve_rows<T>(s, b.V, p->nblk, b.linv, b.Msol, p->n[n], st);
+  if (fast) {
+    chol_factor_fwd<T>(s, b.V, p->nblk, b.linv, b.diagL, b.Msol, p->n[n], st);
+    chol_solve_bwd<T>(s, b.V, p->nblk, b.linv, b.Msol, p->n[n], st);
+  } else {
+    chol_factor<T>(s, b.V, p->nblk, b.linv, b.diagL, st, 0);
+    retry_prepare_launch<T>(s, st, p->d.chol_fallback, g[0], g[1], g[2], Rc, Tp);
+    form_normal_matrix<T>(s, b.V, Tp, Rc, g[0], g[1], g[2], st, 1);
+    chol_factor<T>(s, b.V, p->nblk, b.linv, b.diagL, st, 1);
+    chol_solve_rows<T>(s, b.V, p->nblk, b.linv, b.Msol, p->n[n], st);
+  }
   normalise_columns<T>(s, b.Msol, p->n[n], Rc, Tp, b.F[n], b.lam, with_inner ? b.Msave : nullptr,
                        with_inner ? p->inner_part : nullptr, st);
 }
 
+// Copies the factors and the device state to (dir = 0) or from (dir = 1)
+// the sweep checkpoint.
+struct CkptArgs {
+  void* a[4];
+  void* b[4];
+  size_t bytes[4];
+  DevState* st;
+  DevState* st_save;
+  int dir;
+};
+__global__ void checkpoint_kernel(CkptArgs c) {
+  for (int m = 0; m < 4; ++m) {
+    const uint32_t* src = (const uint32_t*)(c.dir ? c.b[m] : c.a[m]);
+    uint32_t* dst = (uint32_t*)(c.dir ? c.a[m] : c.b[m]);
+    const size_t words = c.bytes[m] / 4;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < words; e += (size_t)gridDim.x * 256)
+      dst[e] = src[e];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (c.dir) *c.st = *c.st_save;
+    else *c.st_save = *c.st;
+  }
+}
+
 template <typename T>
-void enqueue_sweep_typed(cpd_plan_s* p, Bufs<T>& b, hipStream_t s) {
+void checkpoint(cpd_plan_s* p, Bufs<T>& b, hipStream_t s, int dir) {
+  CkptArgs c;
+  for (int m = 0; m < 4; ++m) {
+    c.a[m] = b.F[m];
+    c.b[m] = b.Fsave[m];
+    c.bytes[m] = sizeof(T) * (size_t)p->n[m] * p->Tp;
+  }
+  c.st = p->st;
+  c.st_save = p->st_save;
+  c.dir = dir;
+  hipLaunchKernelGGL(checkpoint_kernel, dim3(512), dim3(256), 0, s, c);
+}
+
+template <typename T>
+void enqueue_sweep_typed(cpd_plan_s* p, Bufs<T>& b, hipStream_t s, bool fast) {
   const int32_t* done = &p->st->done;
+  if (fast) checkpoint<T>(p, b, s, 0);
   for (int n = 0; n < 4; ++n) {
     mttkrp_into<T>(p, b, n, n == 0 || n == 2, b.Msol, n == 3 ? b.Msave : nullptr, s, done);
-    solve_mode<T>(p, b, n, s, n == 3);
+    solve_mode<T>(p, b, n, s, n == 3, fast);
     refresh_mode<T>(p, b, n, s, done);
   }
   const T* g[4] = {b.G[0], b.G[1], b.G[2], b.G[3]};
@@ -272,10 +323,11 @@ __global__ void sweep_tick_kernel(DevState* st) {
 // else in FP64.  On fit sweeps the mode-3 MTTKRP is ALSO formed in FP64
 // (from the FP64 factors) for <G, G~>: the residual is first-order
 // sensitive to that inner product, which split BF16 cannot deliver.
-void enqueue_sweep_mixed(cpd_plan_s* p, hipStream_t s, bool fit_sweep) {
+void enqueue_sweep_mixed(cpd_plan_s* p, hipStream_t s, bool fit_sweep, bool fast) {
   Bufs<double>& b = p->b64;
   const int32_t* done = &p->st->done;
   const int Rt = p->Rt, Rc = p->Rc, Tp = p->Tp;
+  if (fast) checkpoint<double>(p, b, s, 0);
   for (int n = 0; n < 4; ++n) {
     mixed_mttkrp(s, p->mx, n, n == 0 || n == 2, p->n, Rt, Rc, Tp, b.Msol, nullptr, done);
     if (n == 3 && fit_sweep) {
@@ -284,7 +336,7 @@ void enqueue_sweep_mixed(cpd_plan_s* p, hipStream_t s, bool fit_sweep) {
                        done);
       mttkrp_into<double>(p, b, 3, true, b.Msave, nullptr, s, done);
     }
-    solve_mode<double>(p, b, n, s, n == 3 && fit_sweep);
+    solve_mode<double>(p, b, n, s, n == 3 && fit_sweep, fast);
     gemm_t<double>(s, Rc, Rc, p->n[n], b.F[n], Tp, true, b.F[n], nullptr, Tp, b.G[n], Tp, nullptr,
                    done);
     mixed_refresh(s, p->mx, n, b.F[n], p->n, Rt, Rc, Tp, done);
@@ -298,19 +350,19 @@ void enqueue_sweep_mixed(cpd_plan_s* p, hipStream_t s, bool fit_sweep) {
   }
 }
 
-void enqueue_sweep(cpd_plan_s* p, hipStream_t s, bool fit_sweep) {
-  if (p->prec == CPD_FP64) enqueue_sweep_typed<double>(p, p->b64, s);
-  else if (p->prec == CPD_FP32) enqueue_sweep_typed<float>(p, p->b32, s);
-  else enqueue_sweep_mixed(p, s, fit_sweep);
+void enqueue_sweep(cpd_plan_s* p, hipStream_t s, bool fit_sweep, bool fast) {
+  if (p->prec == CPD_FP64) enqueue_sweep_typed<double>(p, p->b64, s, fast);
+  else if (p->prec == CPD_FP32) enqueue_sweep_typed<float>(p, p->b32, s, fast);
+  else enqueue_sweep_mixed(p, s, fit_sweep, fast);
 }
 
 bool is_fit_sweep(const cpd_plan_s* p, long index1) {
   return p->prec != CPD_MIXED_BF16 || p->fit_every <= 1 || index1 % p->fit_every == 0;
 }
 
-int capture(cpd_plan_s* p, bool fit_sweep, hipGraph_t* g, hipGraphExec_t* e) {
+int capture(cpd_plan_s* p, bool fit_sweep, bool fast, hipGraph_t* g, hipGraphExec_t* e) {
   if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return CPD_ERR_HIP;
-  enqueue_sweep(p, p->cap, fit_sweep);
+  enqueue_sweep(p, p->cap, fit_sweep, fast);
   if (hipStreamEndCapture(p->cap, g) != hipSuccess) return CPD_ERR_HIP;
   if (hipGraphInstantiate(e, *g, nullptr, nullptr, 0) != hipSuccess) return CPD_ERR_HIP;
   return CPD_OK;
@@ -397,6 +449,25 @@ int status_from_flags(int flags) {
   return CPD_OK;
 }
 
+int launch_sweep(cpd_plan_s* p, bool fit, bool fast) {
+  if (p->have_graph) {
+    HIPCHK(hipGraphLaunch(p->exec[fast ? 1 : 0][fit ? 1 : 0], p->stream));
+  } else {
+    enqueue_sweep(p, p->stream, fit, fast);
+    HIPCHK(hipGetLastError());
+  }
+  return CPD_OK;
+}
+
+// Rewinds to the checkpoint taken at the start of the last fast sweep and
+// recomputes the projections / Grams from the restored factors.
+int rewind_sweep(cpd_plan_s* p) {
+  if (p->prec == CPD_FP32) checkpoint<float>(p, p->b32, p->stream, 1);
+  else checkpoint<double>(p, p->b64, p->stream, 1);
+  HIPCHK(hipGetLastError());
+  return refresh_all(p, p->stream);
+}
+
 }  // namespace
 
 extern "C" {
@@ -462,9 +533,10 @@ cpd_status cpd_init(const cpd_desc* d, cpd_plan* out) {
     if (hipGetLastError() != hipSuccess) rc = CPD_ERR_HIP;
   }
   if (rc == CPD_OK && d->use_graph) {
-    rc = capture(p, true, &p->graph, &p->exec);
-    if (rc == CPD_OK && p->prec == CPD_MIXED_BF16 && p->fit_every > 1)
-      rc = capture(p, false, &p->graph_nofit, &p->exec_nofit);
+    const bool nofit = p->prec == CPD_MIXED_BF16 && p->fit_every > 1;
+    for (int fast = 0; fast < 2 && rc == CPD_OK; ++fast)
+      for (int fit = nofit ? 0 : 1; fit < 2 && rc == CPD_OK; ++fit)
+        rc = capture(p, fit == 1, fast == 1, &p->graph[fast][fit], &p->exec[fast][fit]);
     if (rc == CPD_OK) p->have_graph = true;
   }
   if (rc != CPD_OK) {
@@ -474,6 +546,7 @@ cpd_status cpd_init(const cpd_desc* d, cpd_plan* out) {
   *out = p;
   return CPD_OK;
 }
+
 
 cpd_status cpd_sweep(cpd_plan p, int32_t nsweeps, double* fits_host, int32_t* n_run) {
   if (!p || nsweeps < 0) return CPD_ERR_INVALID_ARG;
@@ -487,37 +560,34 @@ cpd_status cpd_sweep(cpd_plan p, int32_t nsweeps, double* fits_host, int32_t* n_
       return status_from_flags(p->host_state->flags);
     }
   }
-  bool need_final_read = false;
   for (int i = 0; i < nsweeps; ++i) {
     const bool fit = is_fit_sweep(p, p->launched + 1);
-    if (p->have_graph) {
-      HIPCHK(hipGraphLaunch(fit ? p->exec : p->exec_nofit, p->stream));
-    } else {
-      enqueue_sweep(p, p->stream, fit);
-      HIPCHK(hipGetLastError());
+    int rc;
+    if (!sync) {
+      // asynchronous: the damped retry must live inside the graph
+      rc = launch_sweep(p, fit, false);
+      if (rc != CPD_OK) return rc;
+      p->launched += 1;
+      ++ran;
+      continue;
+    }
+    rc = launch_sweep(p, fit, true);
+    if (rc == CPD_OK) rc = read_state(p);
+    if (rc != CPD_OK) return rc;
+    if (p->host_state->chol_fail) {
+      // a pivot failed: replay this sweep with the damped-retry graph
+      rc = rewind_sweep(p);
+      if (rc == CPD_OK) rc = launch_sweep(p, fit, false);
+      if (rc == CPD_OK) rc = read_state(p);
+      if (rc != CPD_OK) return rc;
     }
     p->launched += 1;
     ++ran;
-    if (!sync) continue;
-    if (fit) {
-      int rc = read_state(p);
-      if (rc != CPD_OK) return rc;
-      if (fits_host) fits_host[ran - 1] = p->host_state->fit_prev;
-      need_final_read = false;
-      if (p->host_state->done) break;
-    } else {
-      if (fits_host) fits_host[ran - 1] = -1.0;
-      need_final_read = true;
-    }
+    if (fits_host) fits_host[ran - 1] = fit ? p->host_state->fit_prev : -1.0;
+    if (p->host_state->done) break;
   }
   if (n_run) *n_run = ran;
-  if (sync) {
-    if (need_final_read) {
-      int rc = read_state(p);
-      if (rc != CPD_OK) return rc;
-    }
-    return status_from_flags(p->host_state->flags);
-  }
+  if (sync) return status_from_flags(p->host_state->flags);
   return CPD_OK;
 }
 
@@ -617,10 +687,11 @@ cpd_status cpd_mttkrp(cpd_plan p, int32_t mode, double* M_dev) {
 
 cpd_status cpd_destroy(cpd_plan p) {
   if (!p) return CPD_ERR_INVALID_ARG;
-  if (p->exec) (void)hipGraphExecDestroy(p->exec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
-  if (p->exec_nofit) (void)hipGraphExecDestroy(p->exec_nofit);
-  if (p->graph_nofit) (void)hipGraphDestroy(p->graph_nofit);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      if (p->exec[a][b]) (void)hipGraphExecDestroy(p->exec[a][b]);
+      if (p->graph[a][b]) (void)hipGraphDestroy(p->graph[a][b]);
+    }
   if (p->cap) (void)hipStreamDestroy(p->cap);
   if (p->host_state) (void)hipHostFree(p->host_state);
   delete p;
@@ -647,7 +718,7 @@ cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out) {
         } else if (which == 3) {
           gemm_t<double>(s, Rc, Rc, n0, b.F[0], Tp, true, b.F[0], nullptr, Tp, b.G[0], Tp, nullptr, nullptr);
         } else {
-          solve_mode<double>(p, b, 0, s, false);
+          solve_mode<double>(p, b, 0, s, false, true);
         }
       } else if (p->prec == CPD_FP64) {
         Bufs<double>& b = p->b64;
@@ -655,14 +726,14 @@ cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out) {
         else if (which == 1) gemm_t<double>(s, Rt, Rc, Rt, b.Z, Rt, false, b.W[2], b.W[3], Tp, b.Y, Tp, nullptr, nullptr);
         else if (which == 2) gemm_t<double>(s, n0, Rc, Rt, b.X[0], Rt, false, b.W[1], b.Y, Tp, b.Msol, Tp, nullptr, nullptr);
         else if (which == 3) gemm_t<double>(s, Rc, Rc, n0, b.F[0], Tp, true, b.F[0], nullptr, Tp, b.G[0], Tp, nullptr, nullptr);
-        else solve_mode<double>(p, b, 0, s, false);
+        else solve_mode<double>(p, b, 0, s, false, true);
       } else {
         Bufs<float>& b = p->b32;
         if (which == 0) gemm_t<float>(s, Rt, Rc, n0, b.X[0], Rt, true, b.F[0], nullptr, Tp, b.W[0], Tp, nullptr, nullptr);
         else if (which == 1) gemm_t<float>(s, Rt, Rc, Rt, b.Z, Rt, false, b.W[2], b.W[3], Tp, b.Y, Tp, nullptr, nullptr);
         else if (which == 2) gemm_t<float>(s, n0, Rc, Rt, b.X[0], Rt, false, b.W[1], b.Y, Tp, b.Msol, Tp, nullptr, nullptr);
         else if (which == 3) gemm_t<float>(s, Rc, Rc, n0, b.F[0], Tp, true, b.F[0], nullptr, Tp, b.G[0], Tp, nullptr, nullptr);
-        else solve_mode<float>(p, b, 0, s, false);
+        else solve_mode<float>(p, b, 0, s, false, true);
       }
     };
     body();  // warm-up

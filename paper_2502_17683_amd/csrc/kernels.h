@@ -46,13 +46,20 @@ void gemm_split(hipStream_t s, const GemmSplit& g);
 
 // -------------------------------------------------- Cholesky / triangular solve
 // V: Tp x Tp row-major (Tp = 64 * nblk), lower triangle factorised in place
-// (off-diagonal blocks); inverses of the diagonal blocks go to linv
-// (nblk blocks of 64 x 64, row-major), the diagonal of L to diagL (Tp).
+// (off-diagonal blocks); the diagonal blocks of L go to ldiag (nblk blocks
+// of 64 x 64, row-major), the diagonal of L to diagL (Tp).
 template <typename T>
-void chol_factor(hipStream_t s, T* V, int nblk, T* linv, T* diagL, DevState* st, int retry_pass);
+void chol_factor(hipStream_t s, T* V, int nblk, T* ldiag, T* diagL, DevState* st, int retry_pass);
 // Solve F V = M in place (M: n x Tp, ld Tp) given the factor above.
 template <typename T>
-void chol_solve_rows(hipStream_t s, const T* V, int nblk, const T* linv, T* M, int n, DevState* st);
+void chol_solve_rows(hipStream_t s, const T* V, int nblk, const T* ldiag, T* M, int n, DevState* st);
+// Backward half of the solve only (F L = G, in place).
+template <typename T>
+void chol_solve_bwd(hipStream_t s, const T* V, int nblk, const T* ldiag, T* M, int n, DevState* st);
+// Factorisation fused with the forward half of the solve (G L^T = M, in
+// place), no damped retry: a failed pivot leaves st->chol_fail set.
+template <typename T>
+void chol_factor_fwd(hipStream_t s, T* V, int nblk, T* ldiag, T* diagL, T* M, int n, DevState* st);
 
 // ------------------------------------------------------------- element-wise
 template <typename T>

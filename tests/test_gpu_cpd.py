@@ -242,3 +242,32 @@ def test_workspace_too_small_is_rejected():
     d.workspace_bytes = need - 1
     plan = ctypes.c_void_p()
     assert lib.cpd_init(ctypes.byref(d), ctypes.byref(plan)) == _lib.CPD_ERR_WORKSPACE
+
+
+def test_async_sweeps_match_synchronised_sweeps():
+    """Asynchronous sweeps (damped retry inside the graph) and synchronised
+    sweeps (fused factorisation + forward solve, host replay on a failed
+    pivot) compute the same iterates bit for bit."""
+    X, Z = make_thc(40, 160, 7)
+    init = init_factors([40] * 4, 130, 1007)
+    a = _plan(X, Z, init, 130, tol=0.0)
+    fa = a.sweep(7)
+    b = _plan(X, Z, init, 130, tol=0.0)
+    b.sweep(7, sync=False)
+    assert b.fit() == fa[-1]
+    Fa, _ = a.factors()
+    Fb, _ = b.factors()
+    for m in range(4):
+        assert torch.equal(Fa[m], Fb[m])
+
+
+def test_async_fallback_matches_replay():
+    X, Z = make_thc(20, 80, 6)
+    init = init_factors([20] * 4, 60, 1006)
+    init[2][:, 3] = 0.0
+    a = _plan(X, Z, init, 60, tol=0.0)
+    fa = a.sweep(4)
+    b = _plan(X, Z, init, 60, tol=0.0)
+    b.sweep(4, sync=False)
+    assert b.fit() == fa[-1]
+    assert a.stats()["fallbacks"] == b.stats()["fallbacks"] > 0
