@@ -145,12 +145,15 @@ cpd_status cpd_stats(cpd_plan p, cpd_stats_t* out);
 cpd_status cpd_mttkrp(cpd_plan p, int32_t mode, double* M_dev);
 
 /* Measurement hook: average device time (ms, hipEvents on the plan's
- * stream, `reps` back-to-back launches after one warm-up) of one launch of
- * each kernel family of the sweep at the plan's shapes, for mode 0:
- *   ms_out[0] projection X^T F,  ms_out[1] core product Z (W o W),
- *   ms_out[2] back-projection X (W o Y),  ms_out[3] Gram F^T F,
- *   ms_out[4] normal-equation solve (V, Cholesky + retry pass, triangular
- *   solves, normalisation).
+ * stream, `reps` back-to-back repetitions after one warm-up) of each kernel
+ * family of the sweep at the plan's shapes, for mode 0 (ms_out: 7 doubles):
+ *   [0] projection X^T F,  [1] core product Z (W o W),
+ *   [2] back-projection X (W o Y),  [3] Gram F^T F,
+ *   [4] whole normal-equation solve (V, factorisation fused with the
+ *       forward triangular solve, backward solve, normalisation),
+ *   [5] V + factorisation/forward solve (nblk + 1 launches of the fused
+ *       step kernel), [6] backward solve (nblk launches),
+ *   with nblk = ceil(r_cp / 64).
  * Overwrites the plan's intermediate buffers and resets its stopping state:
  * re-initialise the plan before using it again.  Synchronises. */
 cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out);

@@ -125,11 +125,13 @@ class CPD:
         return M
 
     def kernel_times(self, reps=5):
-        """Average ms per launch of (projection, core product, back-projection,
-        Gram, solve) at this plan's shapes.  Invalidates the plan's state."""
-        out = (ctypes.c_double * 5)()
+        """Average ms of (projection, core product, back-projection, Gram,
+        solve, factorisation + forward solve, backward solve) at this plan's
+        shapes.  Invalidates the plan's state."""
+        out = (ctypes.c_double * 7)()
         check(self.lib.cpd_kernel_times(self.plan, int(reps), out), "cpd_kernel_times")
-        return dict(zip(("projection", "core", "backprojection", "gram", "solve"), list(out)))
+        return dict(zip(("projection", "core", "backprojection", "gram", "solve", "factor_fwd",
+                         "solve_bwd"), list(out)))
 
     def close(self):
         if getattr(self, "plan", None) is not None and self.plan.value:

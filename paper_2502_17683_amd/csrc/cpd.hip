@@ -707,33 +707,49 @@ cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out) {
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   const int Rt = p->Rt, Rc = p->Rc, Tp = p->Tp, n0 = p->n[0];
-  for (int which = 0; which < 5; ++which) {
+  const bool f32 = p->prec == CPD_FP32;
+  for (int which = 0; which < 7; ++which) {
     auto body = [&]() {
+      if (which == 4 || which == 5 || which == 6) {
+        // normal-equation solve of mode 0: V, factorisation fused with the
+        // forward solve, backward solve, normalisation
+        if (f32) {
+          Bufs<float>& b = p->b32;
+          if (which != 6) form_normal_matrix<float>(s, b.V, Tp, Rc, b.G[1], b.G[2], b.G[3], p->st, 0);
+          if (which != 6) chol_factor_fwd<float>(s, b.V, p->nblk, b.linv, b.diagL, b.Msol, n0, p->st);
+          if (which != 5) chol_solve_bwd<float>(s, b.V, p->nblk, b.linv, b.Msol, n0, p->st);
+          if (which == 4) normalise_columns<float>(s, b.Msol, n0, Rc, Tp, b.F[0], b.lam, nullptr, nullptr, p->st);
+        } else {
+          Bufs<double>& b = p->b64;
+          if (which != 6) form_normal_matrix<double>(s, b.V, Tp, Rc, b.G[1], b.G[2], b.G[3], p->st, 0);
+          if (which != 6) chol_factor_fwd<double>(s, b.V, p->nblk, b.linv, b.diagL, b.Msol, n0, p->st);
+          if (which != 5) chol_solve_bwd<double>(s, b.V, p->nblk, b.linv, b.Msol, n0, p->st);
+          if (which == 4) normalise_columns<double>(s, b.Msol, n0, Rc, Tp, b.F[0], b.lam, nullptr, nullptr, p->st);
+        }
+        return;
+      }
       if (p->prec == CPD_MIXED_BF16) {
         Bufs<double>& b = p->b64;
         if (which == 0) mixed_refresh(s, p->mx, 0, b.F[0], p->n, Rt, Rc, Tp, nullptr);
         else if (which == 1 || which == 2) {
-          // core product only (which == 1), or core + back-projection (2)
-          mixed_mttkrp(s, p->mx, 0, which == 1, p->n, Rt, Rc, Tp, b.Msol, nullptr, nullptr);
-        } else if (which == 3) {
-          gemm_t<double>(s, Rc, Rc, n0, b.F[0], Tp, true, b.F[0], nullptr, Tp, b.G[0], Tp, nullptr, nullptr);
+          // core product only (which == 1), or back-projection only (2)
+          if (which == 1) mixed_mttkrp(s, p->mx, 0, true, p->n, Rt, Rc, Tp, b.Msol, nullptr, nullptr);
+          else mixed_mttkrp(s, p->mx, 0, false, p->n, Rt, Rc, Tp, b.Msol, nullptr, nullptr);
         } else {
-          solve_mode<double>(p, b, 0, s, false, true);
+          gemm_t<double>(s, Rc, Rc, n0, b.F[0], Tp, true, b.F[0], nullptr, Tp, b.G[0], Tp, nullptr, nullptr);
         }
       } else if (p->prec == CPD_FP64) {
         Bufs<double>& b = p->b64;
         if (which == 0) gemm_t<double>(s, Rt, Rc, n0, b.X[0], Rt, true, b.F[0], nullptr, Tp, b.W[0], Tp, nullptr, nullptr);
         else if (which == 1) gemm_t<double>(s, Rt, Rc, Rt, b.Z, Rt, false, b.W[2], b.W[3], Tp, b.Y, Tp, nullptr, nullptr);
         else if (which == 2) gemm_t<double>(s, n0, Rc, Rt, b.X[0], Rt, false, b.W[1], b.Y, Tp, b.Msol, Tp, nullptr, nullptr);
-        else if (which == 3) gemm_t<double>(s, Rc, Rc, n0, b.F[0], Tp, true, b.F[0], nullptr, Tp, b.G[0], Tp, nullptr, nullptr);
-        else solve_mode<double>(p, b, 0, s, false, true);
+        else gemm_t<double>(s, Rc, Rc, n0, b.F[0], Tp, true, b.F[0], nullptr, Tp, b.G[0], Tp, nullptr, nullptr);
       } else {
         Bufs<float>& b = p->b32;
         if (which == 0) gemm_t<float>(s, Rt, Rc, n0, b.X[0], Rt, true, b.F[0], nullptr, Tp, b.W[0], Tp, nullptr, nullptr);
         else if (which == 1) gemm_t<float>(s, Rt, Rc, Rt, b.Z, Rt, false, b.W[2], b.W[3], Tp, b.Y, Tp, nullptr, nullptr);
         else if (which == 2) gemm_t<float>(s, n0, Rc, Rt, b.X[0], Rt, false, b.W[1], b.Y, Tp, b.Msol, Tp, nullptr, nullptr);
-        else if (which == 3) gemm_t<float>(s, Rc, Rc, n0, b.F[0], Tp, true, b.F[0], nullptr, Tp, b.G[0], Tp, nullptr, nullptr);
-        else solve_mode<float>(p, b, 0, s, false, true);
+        else gemm_t<float>(s, Rc, Rc, n0, b.F[0], Tp, true, b.F[0], nullptr, Tp, b.G[0], Tp, nullptr, nullptr);
       }
     };
     body();  // warm-up
@@ -745,7 +761,6 @@ cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out) {
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     ms_out[which] = (double)ms / reps;
   }
-  if (p->prec == CPD_MIXED_BF16) ms_out[2] -= ms_out[1];  // back-projection alone
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return CPD_OK;
