@@ -61,7 +61,10 @@ typedef enum {
                          scalar fit terms accumulate in FP64                  */
   CPD_MIXED_BF16 = 2  /* projection, core and back-projection products in
                          split BF16 (hi + lo, one correction pass) with FP32
-                         accumulation; Gram, Cholesky, solve and fit in FP64  */
+                         accumulation; Gram, Cholesky, solve and fit in FP64.
+                         A precision guard moves a problem to FP64 products
+                         when its normal matrices become ill-conditioned;
+                         synchronised sweeps that promote are replayed     */
 } cpd_precision;
 
 typedef struct cpd_plan_s* cpd_plan;
@@ -85,6 +88,9 @@ typedef struct {
                              an FP64 mode-3 MTTKRP) and the stopping rule every
                              fit_every sweeps (<= 1: every sweep); other
                              precisions evaluate it every sweep               */
+  int32_t autotune;       /* 1: time both GEMM tile shapes of every grouped
+                             FP64/FP32 product at init and keep the faster
+                             (cached per process by shape); 0: heuristic      */
   void* stream;           /* hipStream_t the work is ordered on (0 = null stream) */
   void* workspace;        /* DEVICE memory owned by the caller                    */
   size_t workspace_bytes;
@@ -100,6 +106,10 @@ typedef struct {
   double inner;           /* <G, G~> of the last sweep                            */
   double model2;          /* ||G~||^2 of the last sweep                           */
   double cond_est;        /* (max_i L_ii / min_i L_ii)^2 of the last factor       */
+  int32_t fp64_path;      /* CPD_MIXED_BF16: 1 once the precision guard moved the
+                             problem to the FP64 MTTKRP (cond estimate > 1e5, a
+                             damped retry, or a rising fit)                   */
+  int32_t reserved;
 } cpd_stats_t;
 
 /* Bytes of device workspace cpd_init needs for this descriptor (0 on
@@ -141,7 +151,8 @@ cpd_status cpd_stats(cpd_plan p, cpd_stats_t* out);
 
 /* Test hook: the matrix-free MTTKRP of `mode` from the current factors,
  * M = G_(mode) (Khatri-Rao of the other factors), into DEVICE
- * n[mode] x r_cp (dense).  Async. */
+ * n[mode] x r_cp (dense).  Needs a plan that has not converged (the
+ * grouped kernels skip converged problems).  Async. */
 cpd_status cpd_mttkrp(cpd_plan p, int32_t mode, double* M_dev);
 
 /* Measurement hook: average device time (ms, hipEvents on the plan's
@@ -157,6 +168,37 @@ cpd_status cpd_mttkrp(cpd_plan p, int32_t mode, double* M_dev);
  * Overwrites the plan's intermediate buffers and resets its stopping state:
  * re-initialise the plan before using it again.  Synchronises. */
 cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out);
+
+/* ---- batched form (many independent CPDs of uneven size, e.g. one per
+ * Laplace-transform point, Section 2.2: the LT-MP2 energy is a sum of
+ * independent terms over the quadrature points) ----
+ * All problems must use the same precision; tol, fit_floor, chol_fallback,
+ * use_graph, fit_every, autotune and stream are taken from descs[0]; the
+ * workspace is passed separately (descs[i].workspace is ignored).  Every
+ * step of a sweep is one grouped launch over all problems, and a sweep is
+ * one hipGraph launch.  Converged problems become no-ops while the others
+ * continue. */
+size_t cpd_batch_workspace_size(const cpd_desc* descs, int32_t count);
+cpd_status cpd_batch_init(const cpd_desc* descs, int32_t count, void* workspace, size_t workspace_bytes,
+                          cpd_plan* out);
+/* Like cpd_sweep; fits_host (if non-NULL) is count x nsweeps, row-major by
+ * problem (-1 where a fit was not evaluated or the problem had stopped);
+ * stops early once every problem has converged. */
+cpd_status cpd_batch_sweep(cpd_plan p, int32_t nsweeps, double* fits_host, int32_t* n_run);
+/* Synchronises; per problem: last fit, converged flag, sweeps (any may be NULL). */
+cpd_status cpd_batch_states(cpd_plan p, double* fits_host, int32_t* converged_host, int32_t* sweeps_host);
+int32_t cpd_batch_count(cpd_plan p);
+cpd_status cpd_batch_get_factors(cpd_plan p, int32_t idx, double* const F_dev[4], double* lambda_dev);
+cpd_status cpd_batch_stats(cpd_plan p, int32_t idx, cpd_stats_t* out);
+/* Autotuner decisions of the plan as "kind,M,N,K,...=tile" lines into buf
+ * (NUL-terminated, truncated to len); returns the full length. */
+int32_t cpd_autotune_log(cpd_plan p, char* buf, int32_t len);
+/* Laplace-transform row scaling of THC factors (eq. mp1_t and the THC-LT
+ * amplitude after it): out[p, :] = exp(sign * eps[p] * t) * X[p, :] for
+ * X DEVICE n x r (row-major), eps DEVICE n; sign = +1 for occupied rows,
+ * -1 for virtual rows.  Async on stream. */
+cpd_status cpd_lt_scale_rows(const double* X, const double* eps, int32_t n, int32_t r, double t, double sign,
+                             double* out, void* stream);
 
 /* Releases the host plan and its private stream/graph (not the workspace). */
 cpd_status cpd_destroy(cpd_plan p);
@@ -180,7 +222,8 @@ cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, con
 /* cpd_test_gemm_split: C (M x N, FP64) = A B^T from FP64 A (M x K) and
  *   B (N x K) through the split-BF16 product (hi*hi + hi*lo + lo*hi, FP32
  *   accumulation).  With A2 != NULL the A operand is the FP32 product
- *   A o A2, split on the fly.  Async on stream. */
+ *   A o A2, split on the fly.  Uploads a one-entry argument table and
+ *   synchronises before the launch. */
 size_t cpd_test_split_workspace(int32_t M, int32_t N, int32_t K);
 cpd_status cpd_test_gemm_split(int32_t M, int32_t N, int32_t K, const double* A, const double* A2,
                                const double* B, double* C, void* workspace, size_t ws_bytes, void* stream);

@@ -6,4 +6,5 @@ the HIP library libthccp.so (include/thccp.h); this package only marshals
 arguments and owns the torch tensors that back the library's workspace.
 """
 from ._lib import CpdError, load, LIB_PATH  # noqa: F401
-from .cpd import CPD, test_gemm, test_solve, test_gemm_split  # noqa: F401
+from .cpd import CPD, CPDBatch, lt_scale_rows, test_gemm, test_solve, test_gemm_split  # noqa: F401
+from .lt import lt_batch_problems  # noqa: F401

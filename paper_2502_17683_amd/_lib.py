@@ -34,6 +34,7 @@ class CpdDesc(ctypes.Structure):
         ("chol_fallback", i32),
         ("use_graph", i32),
         ("fit_every", i32),
+        ("autotune", i32),
         ("stream", vp),
         ("workspace", vp),
         ("workspace_bytes", ctypes.c_size_t),
@@ -51,6 +52,8 @@ class CpdStats(ctypes.Structure):
         ("inner", ctypes.c_double),
         ("model2", ctypes.c_double),
         ("cond_est", ctypes.c_double),
+        ("fp64_path", i32),
+        ("reserved", i32),
     ]
 
 
@@ -73,6 +76,15 @@ EXPORTS = {
     "cpd_stats": (i32, [vp, ctypes.POINTER(CpdStats)]),
     "cpd_mttkrp": (i32, [vp, i32, vp]),
     "cpd_kernel_times": (i32, [vp, i32, ctypes.POINTER(ctypes.c_double)]),
+    "cpd_batch_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(CpdDesc), i32]),
+    "cpd_batch_init": (i32, [ctypes.POINTER(CpdDesc), i32, vp, ctypes.c_size_t, ctypes.POINTER(vp)]),
+    "cpd_batch_sweep": (i32, [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]),
+    "cpd_batch_states": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+    "cpd_batch_count": (i32, [vp]),
+    "cpd_batch_get_factors": (i32, [vp, i32, vp * 4, vp]),
+    "cpd_batch_stats": (i32, [vp, i32, ctypes.POINTER(CpdStats)]),
+    "cpd_autotune_log": (i32, [vp, ctypes.c_char_p, i32]),
+    "cpd_lt_scale_rows": (i32, [vp, vp, i32, i32, ctypes.c_double, ctypes.c_double, vp, vp]),
     "cpd_destroy": (i32, [vp]),
     "cpd_status_string": (ctypes.c_char_p, [i32]),
     "cpd_test_gemm": (i32, [i32, i32, i32, i32, vp, i32, i32, vp, vp, i32, i32, vp, i32, vp]),

@@ -34,7 +34,7 @@ class CPD:
     """
 
     def __init__(self, X, Z, r_cp, init, precision="fp64", tol=1e-4, fit_floor=1e-7,
-                 chol_fallback=True, use_graph=True, fit_every=1, device="cuda"):
+                 chol_fallback=True, use_graph=True, fit_every=1, autotune=False, device="cuda"):
         self.lib = _lib.load()
         self.device = torch.device(device)
         if not isinstance(X, (list, tuple)):
@@ -65,6 +65,7 @@ class CPD:
         d.chol_fallback = int(bool(chol_fallback))
         d.use_graph = int(bool(use_graph))
         d.fit_every = int(fit_every)
+        d.autotune = int(bool(autotune))
         d.stream = _stream(self.device).value
         need = self.lib.cpd_workspace_size(ctypes.byref(d))
         if need == 0:
@@ -143,6 +144,134 @@ class CPD:
             self.close()
         except Exception:
             pass
+
+
+class CPDBatch:
+    """Many independent CP-ALS problems of uneven size run as one grouped
+    sweep (one launch per step for all problems, one hipGraph per sweep).
+
+    problems: list of dicts with keys X (tensor or list of 4), Z, r_cp, init
+    (list of 4).  Options are shared by all problems.
+    """
+
+    def __init__(self, problems, precision="mixed", tol=1e-4, fit_floor=1e-7, chol_fallback=True,
+                 use_graph=True, fit_every=1, autotune=False, device="cuda"):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.count = len(problems)
+        self._keep = []
+        descs = (CpdDesc * self.count)()
+        self.shapes = []
+        cache = {}
+
+        def dev(t):
+            key = id(t)
+            if key not in cache:
+                cache[key] = _dev_f64(t, self.device)
+                self._keep.append(cache[key])
+            return cache[key]
+
+        for i, pr in enumerate(problems):
+            X = pr["X"] if isinstance(pr["X"], (list, tuple)) else [pr["X"]] * 4
+            Xs = [dev(x) for x in X]
+            Zd = dev(pr["Z"])
+            init = [_dev_f64(f, self.device) for f in pr["init"]]
+            self._keep.extend(init)
+            d = descs[i]
+            for m in range(4):
+                d.n[m] = int(Xs[m].shape[0])
+                d.X[m] = Xs[m].data_ptr()
+                d.init[m] = init[m].data_ptr()
+            d.r_thc = int(Zd.shape[0])
+            d.r_cp = int(pr["r_cp"])
+            d.Z = Zd.data_ptr()
+            d.precision = PRECISIONS[precision]
+            d.tol = float(tol)
+            d.fit_floor = float(fit_floor)
+            d.chol_fallback = int(bool(chol_fallback))
+            d.use_graph = int(bool(use_graph))
+            d.fit_every = int(fit_every)
+            d.autotune = int(bool(autotune))
+            d.stream = _stream(self.device).value
+            self.shapes.append(([d.n[m] for m in range(4)], d.r_thc, d.r_cp))
+        need = self.lib.cpd_batch_workspace_size(descs, self.count)
+        if need == 0:
+            raise _lib.CpdError(_lib.CPD_ERR_INVALID_ARG, "cpd_batch_workspace_size")
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        self.descs = descs
+        plan = ctypes.c_void_p()
+        check(self.lib.cpd_batch_init(descs, self.count, ctypes.c_void_p(self.workspace.data_ptr()), need,
+                                      ctypes.byref(plan)), "cpd_batch_init")
+        self.plan = plan
+
+    def sweep(self, n=1, sync=True):
+        """Run up to n batched sweeps.  With sync, returns one list of fits
+        per problem, covering the sweeps that problem actually ran (-1 where
+        the fit was not evaluated)."""
+        if not sync:
+            check(self.lib.cpd_batch_sweep(self.plan, int(n), None, None), "cpd_batch_sweep")
+            return None
+        _, _, before = self.states()
+        fits = (ctypes.c_double * (self.count * max(int(n), 1)))()
+        ran = ctypes.c_int32(0)
+        check(self.lib.cpd_batch_sweep(self.plan, int(n), fits, ctypes.byref(ran)), "cpd_batch_sweep")
+        _, _, after = self.states()
+        return [list(fits[i * n: i * n + min(ran.value, after[i] - before[i])]) for i in range(self.count)]
+
+    def states(self):
+        f = (ctypes.c_double * self.count)()
+        c = (ctypes.c_int32 * self.count)()
+        s = (ctypes.c_int32 * self.count)()
+        check(self.lib.cpd_batch_states(self.plan, f, c, s), "cpd_batch_states")
+        return list(f), list(c), list(s)
+
+    def factors(self, idx):
+        n, _, r_cp = self.shapes[idx]
+        F = [torch.empty(k, r_cp, dtype=torch.float64, device=self.device) for k in n]
+        lam = torch.empty(r_cp, dtype=torch.float64, device=self.device)
+        arr = (ctypes.c_void_p * 4)(*[f.data_ptr() for f in F])
+        check(self.lib.cpd_batch_get_factors(self.plan, int(idx), arr, _ptr(lam)), "cpd_batch_get_factors")
+        torch.cuda.current_stream(self.device).synchronize()
+        return F, lam
+
+    def stats(self, idx):
+        st = CpdStats()
+        check(self.lib.cpd_batch_stats(self.plan, int(idx), ctypes.byref(st)), "cpd_batch_stats")
+        return {k: getattr(st, k) for k, _ in CpdStats._fields_}
+
+    def kernel_times(self, reps=5):
+        out = (ctypes.c_double * 7)()
+        check(self.lib.cpd_kernel_times(self.plan, int(reps), out), "cpd_kernel_times")
+        return dict(zip(("projection", "core", "backprojection", "gram", "solve", "factor_fwd",
+                         "solve_bwd"), list(out)))
+
+    def autotune_log(self):
+        n = self.lib.cpd_autotune_log(self.plan, None, 0)
+        buf = ctypes.create_string_buffer(max(n, 0) + 1)
+        self.lib.cpd_autotune_log(self.plan, buf, len(buf))
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "plan", None) is not None and self.plan.value:
+            self.lib.cpd_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lt_scale_rows(X, eps, t, sign):
+    """exp(sign * eps_p * t) * X[p, :] on the GPU (Laplace-transform row scaling)."""
+    lib = _lib.load()
+    X = X.contiguous()
+    eps = eps.contiguous()
+    out = torch.empty_like(X)
+    check(lib.cpd_lt_scale_rows(_ptr(X), _ptr(eps), X.shape[0], X.shape[1], float(t), float(sign), _ptr(out),
+                                _stream(X.device)), "cpd_lt_scale_rows")
+    return out
 
 
 def test_gemm(A, B1, B2=None, a_t=False, b_t=False):

@@ -237,7 +237,6 @@ __host__ __device__ inline int fwd_tiles(int nblk, int nrt, int j) {
   return nrt * ((j < 0) ? 1 : nblk - 1 - j);
 }
 
-enum StepMode { STEP_CHOL = 0, STEP_FWD = 1, STEP_BWD = 2, STEP_CHOL_FWD = 3 };
 
 // One launch of the blocked factorisation / solve.
 //   STEP_CHOL:     Cholesky step j (tiles of the trailing lower triangle).
@@ -252,8 +251,8 @@ enum StepMode { STEP_CHOL = 0, STEP_FWD = 1, STEP_BWD = 2, STEP_CHOL_FWD = 3 };
 // (The bodies are written inline in the kernel: moving them into device
 // functions doubles the register use and spills.)
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void step_kernel(T* V, int nblk, int j, T* ldiag, T* diagL, T* M, int n,
-                                                    DevState* st, int retry_pass) {
+__global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, const int* offs, int nprob,
+                                                    int step, int retry_pass) {
   typedef typename Acc4<T>::type acc_t;
   __shared__ T S0[TB * LDT];
   __shared__ T S1[TB * LDT];
@@ -261,11 +260,21 @@ __global__ __launch_bounds__(256) void step_kernel(T* V, int nblk, int j, T* ldi
   __shared__ T colbuf[2 * TB];
   __shared__ T invd[TB];
   __shared__ T pivs[TB];
+  int pid = 0;
+  while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
+  T* const V = probs[pid].V;
+  T* const ldiag = probs[pid].ldiag;
+  T* const diagL = probs[pid].diagL;
+  T* const M = probs[pid].M;
+  DevState* const st = probs[pid].st;
+  const int nblk = probs[pid].nblk;
+  const int n = probs[pid].n;
+  const int j = MODE == STEP_BWD ? nblk - step : step;
+  int bid = blockIdx.x - offs[pid];
   if (st->done) return;
   const int Tp = nblk * TB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int sr = tid >> 2, q0 = tid & 3;
-  int bid = blockIdx.x;
 
   if constexpr (MODE == STEP_CHOL || MODE == STEP_CHOL_FWD) {
     if (MODE == STEP_CHOL_FWD ? st->chol_fail : (retry_pass ? !st->retry_active : st->chol_fail)) return;
@@ -397,53 +406,51 @@ __global__ __launch_bounds__(256) void step_kernel(T* V, int nblk, int j, T* ldi
   }
 }
 
-template <typename T>
-void chol_factor(hipStream_t s, T* V, int nblk, T* ldiag, T* diagL, DevState* st, int retry_pass) {
-  for (int j = -1; j <= nblk - 2; ++j)
-    hipLaunchKernelGGL((step_kernel<T, STEP_CHOL>), dim3(chol_tiles(nblk, j)), dim3(256), 0, s, V, nblk, j,
-                       ldiag, diagL, (T*)nullptr, 0, st, retry_pass);
-}
-
-template <typename T>
-void chol_solve_rows(hipStream_t s, const T* V, int nblk, const T* ldiag, T* M, int n, DevState* st) {
-  if (n <= 0) return;
+int step_tiles(int mode, int nblk, int n, int step) {
   const int nrt = (n + TB - 1) / TB;
-  for (int j = -1; j <= nblk - 2; ++j)
-    hipLaunchKernelGGL((step_kernel<T, STEP_FWD>), dim3(fwd_tiles(nblk, nrt, j)), dim3(256), 0, s, (T*)V,
-                       nblk, j, (T*)ldiag, (T*)nullptr, M, n, st, 0);
-  chol_solve_bwd<T>(s, V, nblk, ldiag, M, n, st);
+  switch (mode) {
+    case STEP_CHOL: return chol_tiles(nblk, step);
+    case STEP_FWD: return fwd_tiles(nblk, nrt, step);
+    case STEP_CHOL_FWD: return chol_tiles(nblk, step) + fwd_tiles(nblk, nrt, step - 1);
+    default: {
+      const int j = nblk - step;
+      if (j < 1) return 0;
+      return nrt * (j == nblk ? 1 : j);
+    }
+  }
 }
-
-template <typename T>
-void chol_solve_bwd(hipStream_t s, const T* V, int nblk, const T* ldiag, T* M, int n, DevState* st) {
-  if (n <= 0) return;
-  const int nrt = (n + TB - 1) / TB;
-  for (int j = nblk; j >= 1; --j) {
-    const int cols = (j == nblk) ? 1 : j;
-    hipLaunchKernelGGL((step_kernel<T, STEP_BWD>), dim3(nrt * cols), dim3(256), 0, s, (T*)V, nblk, j,
-                       (T*)ldiag, (T*)nullptr, M, n, st, 0);
+int step_first(int mode) { return mode == STEP_BWD ? 0 : -1; }
+int step_count(int mode, int max_nblk) {
+  switch (mode) {
+    case STEP_CHOL:
+    case STEP_FWD: return max_nblk;       // j = -1 .. nblk-2
+    case STEP_CHOL_FWD: return max_nblk + 1;  // t = -1 .. nblk-1
+    default: return max_nblk;              // s = 0 .. nblk-1
   }
 }
 
 template <typename T>
-void chol_factor_fwd(hipStream_t s, T* V, int nblk, T* ldiag, T* diagL, T* M, int n, DevState* st) {
-  const int nrt = (n + TB - 1) / TB;
-  for (int t = -1; t <= nblk - 1; ++t) {
-    const int tiles = chol_tiles(nblk, t) + fwd_tiles(nblk, nrt, t - 1);
-    hipLaunchKernelGGL((step_kernel<T, STEP_CHOL_FWD>), dim3(tiles), dim3(256), 0, s, V, nblk, t, ldiag, diagL,
-                       M, n, st, 0);
+void step_group(hipStream_t s, int mode, const StepProb<T>* probs, const int* offs, int nprob, int total_tiles,
+                int step, int retry_pass) {
+  if (total_tiles <= 0) return;
+  dim3 grid(total_tiles), block(256);
+  switch (mode) {
+    case STEP_CHOL:
+      hipLaunchKernelGGL((step_kernel<T, STEP_CHOL>), grid, block, 0, s, probs, offs, nprob, step, retry_pass);
+      break;
+    case STEP_FWD:
+      hipLaunchKernelGGL((step_kernel<T, STEP_FWD>), grid, block, 0, s, probs, offs, nprob, step, retry_pass);
+      break;
+    case STEP_BWD:
+      hipLaunchKernelGGL((step_kernel<T, STEP_BWD>), grid, block, 0, s, probs, offs, nprob, step, retry_pass);
+      break;
+    default:
+      hipLaunchKernelGGL((step_kernel<T, STEP_CHOL_FWD>), grid, block, 0, s, probs, offs, nprob, step,
+                         retry_pass);
   }
 }
 
-template void chol_factor<double>(hipStream_t, double*, int, double*, double*, DevState*, int);
-template void chol_factor<float>(hipStream_t, float*, int, float*, float*, DevState*, int);
-template void chol_solve_rows<double>(hipStream_t, const double*, int, const double*, double*, int,
-                                      DevState*);
-template void chol_solve_rows<float>(hipStream_t, const float*, int, const float*, float*, int,
-                                     DevState*);
-template void chol_solve_bwd<double>(hipStream_t, const double*, int, const double*, double*, int, DevState*);
-template void chol_solve_bwd<float>(hipStream_t, const float*, int, const float*, float*, int, DevState*);
-template void chol_factor_fwd<double>(hipStream_t, double*, int, double*, double*, double*, int, DevState*);
-template void chol_factor_fwd<float>(hipStream_t, float*, int, float*, float*, float*, int, DevState*);
+template void step_group<double>(hipStream_t, int, const StepProb<double>*, const int*, int, int, int, int);
+template void step_group<float>(hipStream_t, int, const StepProb<float>*, const int*, int, int, int, int);
 
 }  // namespace thccp

@@ -29,7 +29,10 @@ struct DevState {
   int32_t chol_fail;     // current factorisation hit a bad pivot
   int32_t fallbacks;     // number of damped retries
   int32_t retry_active;  // retry pass armed for the current mode
-  int32_t pad[2];
+  int32_t path;          // split-BF16 plans: 0 = split-BF16 MTTKRP, 1 = promoted to FP64
+  int32_t promote;       // set by the precision guard in the sweep that promoted
+  int32_t fallbacks_start;  // fallbacks at the start of the sweep
+  double cond_max;       // largest (max L_ii / min L_ii)^2 seen in the sweep
 };
 
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {

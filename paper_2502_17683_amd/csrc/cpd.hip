@@ -1,10 +1,18 @@
 // C-ABI of libthccp.so: plan set-up, the matrix-free ALS sweep, fit,
-// checkpointing and statistics.  See include/thccp.h for the contract.
+// checkpointing, statistics, and the batched (grouped) form.
+//
+// A plan holds `count` independent CP-ALS problems (a single CPD is a
+// batch of one).  Every step of a sweep is ONE grouped launch over all
+// problems, driven by argument tables that live in the plan's workspace,
+// and a whole sweep is captured once as a hipGraph and replayed.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/thccp.h"
@@ -16,6 +24,17 @@ namespace thccp {
 static const int HIST_CAP = 4096;
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Carves a region; with base == nullptr only computes the size.
+struct Layout {
+  size_t off = 0;
+  char* base = nullptr;
+  void* take(size_t bytes) {
+    void* p = base ? (void*)(base + off) : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  }
+};
 
 template <typename T>
 struct Bufs {
@@ -29,40 +48,14 @@ struct Bufs {
   T* Fsave[4];  // factors at the start of the sweep (fast-path checkpoint)
   T* G[4];
   T* V;
-  T* linv;
+  T* ldiag;
   T* diagL;
   T* lam;
 };
 
-// Carves the workspace; with base == nullptr only computes the size.
-struct Layout {
-  size_t off = 0;
-  char* base = nullptr;
-  void* take(size_t bytes) {
-    void* p = base ? (void*)(base + off) : nullptr;
-    off = align_up(off + bytes);
-    return p;
-  }
-};
-
-}  // namespace thccp
-
-using namespace thccp;
-
-struct cpd_plan_s {
+struct Prob {
   cpd_desc d;
-  hipStream_t stream;
-  hipStream_t cap;
-  // [fast][fit]: fast = checkpoint + factorisation fused with the forward
-  // solve and no retry pass (a failed pivot is replayed by the host through
-  // the safe graph); safe = damped retry pass inside the graph.
-  hipGraph_t graph[2][2];
-  hipGraphExec_t exec[2][2];
-  bool have_graph;
-  int fit_every;     // mixed precision: the fit (FP64) is evaluated every fit_every sweeps
-  long launched;     // sweeps enqueued since init / set_factors
   int n[4], Rt, Rc, Tp, nblk, nmax;
-  int prec;
   Bufs<double> b64;
   Bufs<float> b32;
   MixedBufs mx;
@@ -74,11 +67,79 @@ struct cpd_plan_s {
   double* setup[3];
   double* partials;
   double* norm2;
-  double* scratch64;  // n_max x Tp doubles (FP32 conversions)
-  DevState* host_state;  // pinned
+  double* scratch64;
+};
+
+// One grouped launch: device table + workgroup prefix sums.
+struct GroupOp {
+  void* tab = nullptr;   // device: GemmArgs<T>[] / SplitArgs[]
+  int* offs = nullptr;   // device: nprob + 1 prefix sums
+  int total = 0;
+  int bm = 64;
+  bool a_t = false, b_t = false, had = false, apair = false, bpair = false;
+};
+
+// Step launches of the factorisation / solves of one mode.
+struct StepOps {
+  void* probs = nullptr;                // StepProb<T>[nprob]
+  std::vector<int*> offs[4];            // per step-mode: per launch, nprob + 1 ints (device)
+  std::vector<int> total[4];            // per step-mode: per launch, workgroups
+};
+
+// Process-wide autotune cache: (kind, shapes) -> tile edge.
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune;
+
+}  // namespace thccp
+
+using namespace thccp;
+
+struct cpd_plan_s {
+  int count = 0;
+  std::vector<Prob> P;
+  int prec = 0;
+  int fit_every = 1;
+  int allow_fallback = 1;
+  int use_graph = 0;
+  int autotune = 0;
+  double tol = 0.0, fit_floor = 0.0;
+  long launched = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  bool have_graph = false;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t tables_off = 0;
+  int maxR = 0, maxTp = 0, maxNblk = 0, maxN = 0;
+  GroupOp core[4], back[4], gram[4], proj[4];  // FP64 / FP32 MTTKRP, Gram, projection
+  GroupOp score[4], sback[4], sproj[4];         // split-BF16 core / back / projection
+  void* ftt[4] = {nullptr, nullptr, nullptr, nullptr};  // SplitTArgs per mode
+  GroupOp fproj[3], fcore, fback;               // mixed: FP64 mode-3 MTTKRP of fit sweeps
+  GroupOp cproj[4];                             // mixed: FP64 projections of just-promoted problems
+  void* cond = nullptr;                         // CondArgs<T>[nprob] (precision guard)
+  int32_t* forced_dev = nullptr;                // nprob flags: problems promoted to the FP64 path
+  std::vector<int32_t> forced;                  // host copy (sticky)
+  double cond_limit = 1e5;
+  StepOps steps[4];
+  void* formv[4] = {nullptr, nullptr, nullptr, nullptr};
+  void* norm[4] = {nullptr, nullptr, nullptr, nullptr};
+  void* norm_inner = nullptr;                   // mode 3 with the inner-product partials
+  void* fit = nullptr;
+  void* ckpt = nullptr;
+  void* sts = nullptr;                          // DevState*[nprob]
+  DevState* host_states = nullptr;              // pinned, nprob
+  std::vector<std::pair<std::string, int>> tune_log;
 };
 
 namespace {
+
+#define HIPCHK(x)                             \
+  do {                                        \
+    hipError_t e_ = (x);                      \
+    if (e_ != hipSuccess) return CPD_ERR_HIP; \
+  } while (0)
 
 int check_desc(const cpd_desc* d) {
   if (!d) return CPD_ERR_INVALID_ARG;
@@ -95,269 +156,560 @@ int check_desc(const cpd_desc* d) {
   return CPD_OK;
 }
 
+void fill_prob(Prob& q, const cpd_desc* d) {
+  memset(&q, 0, sizeof(q));
+  q.d = *d;
+  for (int m = 0; m < 4; ++m) q.n[m] = d->n[m];
+  q.Rt = d->r_thc;
+  q.Rc = d->r_cp;
+  q.nblk = (d->r_cp + 63) / 64;
+  q.Tp = q.nblk * 64;
+  q.nmax = 0;
+  for (int m = 0; m < 4; ++m)
+    if (q.n[m] > q.nmax) q.nmax = q.n[m];
+}
+
 template <typename T>
-void carve_typed(Layout& L, cpd_plan_s* p, Bufs<T>& b, bool own_inputs) {
-  const int Rt = p->Rt, Tp = p->Tp;
+void carve_typed(Layout& L, Prob& q, Bufs<T>& b, bool own_inputs) {
+  const int Rt = q.Rt, Tp = q.Tp;
   if (own_inputs) {
     for (int m = 0; m < 4; ++m) {
       int alias = -1;
-      for (int q = 0; q < m; ++q)
-        if (p->d.X[q] == p->d.X[m]) alias = q;
-      b.X[m] = alias >= 0 ? b.X[alias] : (const T*)L.take(sizeof(T) * (size_t)p->n[m] * Rt);
+      for (int r = 0; r < m; ++r)
+        if (q.d.X[r] == q.d.X[m]) alias = r;
+      b.X[m] = alias >= 0 ? b.X[alias] : (const T*)L.take(sizeof(T) * (size_t)q.n[m] * Rt);
     }
     b.Z = (const T*)L.take(sizeof(T) * (size_t)Rt * Rt);
   }
   for (int m = 0; m < 4; ++m) b.W[m] = (T*)L.take(sizeof(T) * (size_t)Rt * Tp);
   b.Y = (T*)L.take(sizeof(T) * (size_t)Rt * Tp);
-  b.Msol = (T*)L.take(sizeof(T) * (size_t)p->nmax * Tp);
-  b.Msave = (T*)L.take(sizeof(T) * (size_t)p->n[3] * Tp);
-  for (int m = 0; m < 4; ++m) b.F[m] = (T*)L.take(sizeof(T) * (size_t)p->n[m] * Tp);
-  for (int m = 0; m < 4; ++m) b.Fsave[m] = (T*)L.take(sizeof(T) * (size_t)p->n[m] * Tp);
+  b.Msol = (T*)L.take(sizeof(T) * (size_t)q.nmax * Tp);
+  b.Msave = (T*)L.take(sizeof(T) * (size_t)q.n[3] * Tp);
+  for (int m = 0; m < 4; ++m) b.F[m] = (T*)L.take(sizeof(T) * (size_t)q.n[m] * Tp);
+  for (int m = 0; m < 4; ++m) b.Fsave[m] = (T*)L.take(sizeof(T) * (size_t)q.n[m] * Tp);
   for (int m = 0; m < 4; ++m) b.G[m] = (T*)L.take(sizeof(T) * (size_t)Tp * Tp);
   b.V = (T*)L.take(sizeof(T) * (size_t)Tp * Tp);
-  b.linv = (T*)L.take(sizeof(T) * (size_t)p->nblk * 64 * 64);
+  b.ldiag = (T*)L.take(sizeof(T) * (size_t)q.nblk * 64 * 64);
   b.diagL = (T*)L.take(sizeof(T) * (size_t)Tp);
   b.lam = (T*)L.take(sizeof(T) * (size_t)Tp);
 }
 
-size_t carve(cpd_plan_s* p, char* base) {
+// Split-BF16 buffers; X and Z splits are shared between problems (and
+// modes) that pass the same input pointer.
+typedef std::map<const double*, std::pair<__bf16*, __bf16*>> SplitMap;
+struct SplitShare {
+  SplitMap x, xt, z, zt;
+};
+
+void carve_mixed(Layout& L, Prob& q, SplitShare& sh) {
+  MixedBufs& mx = q.mx;
+  const int Rt = q.Rt, Rc = q.Rc;
+  mx.Rtp = (Rt + 31) / 32 * 32;
+  mx.npad_max = 0;
+  for (int m = 0; m < 4; ++m) {
+    mx.npad[m] = (q.n[m] + 31) / 32 * 32;
+    if (mx.npad[m] > mx.npad_max) mx.npad_max = mx.npad[m];
+  }
+  auto pair_for = [&](SplitMap& mp, const double* key, size_t elems) {
+    auto it = mp.find(key);
+    if (it != mp.end()) return it->second;
+    std::pair<__bf16*, __bf16*> v((__bf16*)L.take(2 * elems), (__bf16*)L.take(2 * elems));
+    mp[key] = v;
+    return v;
+  };
+  for (int m = 0; m < 4; ++m) {
+    auto a = pair_for(sh.x, q.d.X[m], (size_t)q.n[m] * mx.Rtp);
+    auto b = pair_for(sh.xt, q.d.X[m], (size_t)Rt * mx.npad[m]);
+    mx.Xh[m] = a.first;
+    mx.Xl[m] = a.second;
+    mx.XTh[m] = b.first;
+    mx.XTl[m] = b.second;
+  }
+  auto z = pair_for(sh.z, q.d.Z, (size_t)Rt * mx.Rtp);
+  auto zt = pair_for(sh.zt, q.d.Z, (size_t)Rt * mx.Rtp);
+  mx.Zh = z.first;
+  mx.Zl = z.second;
+  mx.ZTh = zt.first;
+  mx.ZTl = zt.second;
+  for (int m = 0; m < 4; ++m) mx.WT[m] = (float*)L.take(4 * (size_t)Rc * mx.Rtp);
+  mx.YT = (float*)L.take(4 * (size_t)Rc * mx.Rtp);
+  mx.FTh = (__bf16*)L.take(2 * (size_t)Rc * mx.npad_max);
+  mx.FTl = (__bf16*)L.take(2 * (size_t)Rc * mx.npad_max);
+}
+
+void carve_prob(Layout& L, Prob& q, int prec, SplitShare& sh) {
+  const int Rt = q.Rt, Tp = q.Tp;
+  q.st = (DevState*)L.take(sizeof(DevState));
+  q.st_save = (DevState*)L.take(sizeof(DevState));
+  q.fit_hist = (double*)L.take(sizeof(double) * HIST_CAP);
+  q.inner_part = (double*)L.take(sizeof(double) * Tp);
+  q.row_part = (double*)L.take(sizeof(double) * Tp);
+  q.norm2 = (double*)L.take(sizeof(double) * 8);
+  const size_t nt = (size_t)((Rt + 63) / 64);
+  q.partials = (double*)L.take(sizeof(double) * nt * nt);
+  size_t setup_elems = (size_t)Rt * Rt;
+  if ((size_t)q.nmax * Tp > setup_elems) setup_elems = (size_t)q.nmax * Tp;
+  for (int i = 0; i < 3; ++i) q.setup[i] = (double*)L.take(sizeof(double) * setup_elems);
+  q.scratch64 = (double*)L.take(sizeof(double) * (size_t)q.nmax * Tp);
+  if (prec == CPD_FP32) {
+    carve_typed<float>(L, q, q.b32, true);
+  } else {
+    carve_typed<double>(L, q, q.b64, false);
+    for (int m = 0; m < 4; ++m) q.b64.X[m] = q.d.X[m];
+    q.b64.Z = q.d.Z;
+    if (prec == CPD_MIXED_BF16) carve_mixed(L, q, sh);
+  }
+}
+
+// ---------------------------------------------------------- table building
+// Tables are built on the host, laid out in the table region and uploaded
+// once.  With base == nullptr only the sizes are accumulated.
+struct TableBuilder {
+  Layout L;
+  std::vector<char> host;
+  template <typename X>
+  void* put(const std::vector<X>& v) {
+    const size_t bytes = sizeof(X) * v.size();
+    const size_t at = L.off;
+    void* dev = L.take(bytes);
+    if (L.base) {
+      if (host.size() < L.off) host.resize(L.off);
+      memcpy(host.data() + at, v.data(), bytes);
+    }
+    return dev;
+  }
+};
+
+std::string tune_key(const std::string& kind, const std::vector<int>& dims) {
+  std::string k(kind);
+  for (int d : dims) k += "," + std::to_string(d);
+  return k;
+}
+
+template <typename T>
+GroupOp gemm_op(TableBuilder& tb, const std::vector<GemmArgs<T>>& v, bool at, bool had, const std::string& kind) {
+  GroupOp op;
+  op.a_t = at;
+  op.had = had;
+  // tile edge: autotune cache, else heuristic (128 when the 128-tiles of the
+  // group cover the 256 compute units)
+  std::vector<int> dims;
+  long t128 = 0;
+  for (auto& g : v) {
+    dims.push_back(g.M);
+    dims.push_back(g.N);
+    dims.push_back(g.K);
+    t128 += gemm_tile_count(g.M, g.N, 128);
+  }
+  op.bm = t128 >= 256 ? 128 : 64;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(kind, dims));
+    if (it != g_tune.end()) op.bm = it->second;
+  }
+  std::vector<int> offs(1, 0);
+  for (auto& g : v) offs.push_back(offs.back() + gemm_tile_count(g.M, g.N, op.bm));
+  op.total = offs.back();
+  op.tab = tb.put(v);
+  op.offs = (int*)tb.put(offs);
+  return op;
+}
+
+GroupOp split_op(TableBuilder& tb, const std::vector<SplitArgs>& v, bool apair, bool bpair) {
+  GroupOp op;
+  op.apair = apair;
+  op.bpair = bpair;
+  std::vector<int> offs(1, 0);
+  for (auto& g : v) offs.push_back(offs.back() + split_tile_count(g.M, g.N));
+  op.total = offs.back();
+  op.tab = tb.put(v);
+  op.offs = (int*)tb.put(offs);
+  return op;
+}
+
+const int partner_of[4] = {1, 0, 3, 2};
+
+template <typename T>
+void build_typed(TableBuilder& tb, cpd_plan_s* p, Bufs<T> Prob::*bufs, bool gated) {
+  const int np = p->count;
+  const std::string kind = sizeof(T) == 8 ? "f64" : "f32";
+  for (int n = 0; n < 4; ++n) {
+    std::vector<GemmArgs<T>> core, back, gram, proj;
+    std::vector<StepProb<T>> sp;
+    std::vector<FormVArgs<T>> fv;
+    std::vector<NormArgs<T>> nm;
+    for (int i = 0; i < np; ++i) {
+      Prob& q = p->P[i];
+      Bufs<T>& b = q.*bufs;
+      const int32_t* done = &q.st->done;
+      const int Rt = q.Rt, Rc = q.Rc, Tp = q.Tp;
+      if (n == 0) core.push_back({Rt, Rc, Rt, b.Z, Rt, b.W[2], b.W[3], Tp, b.Y, Tp, nullptr, T(1), T(0), done});
+      if (n == 2) core.push_back({Rt, Rc, Rt, b.Z, Rt, b.W[0], b.W[1], Tp, b.Y, Tp, nullptr, T(1), T(0), done});
+      back.push_back({q.n[n], Rc, Rt, b.X[n], Rt, b.W[partner_of[n]], b.Y, Tp, b.Msol, Tp,
+                      n == 3 ? b.Msave : nullptr, T(1), T(0), done});
+      gram.push_back({Rc, Rc, q.n[n], b.F[n], Tp, b.F[n], nullptr, Tp, b.G[n], Tp, nullptr, T(1), T(0), done});
+      proj.push_back({Rt, Rc, q.n[n], b.X[n], Rt, b.F[n], nullptr, Tp, b.W[n], Tp, nullptr, T(1), T(0), done});
+      if (gated) {
+        // split-BF16 plans: these FP64 products serve only problems promoted
+        // to the FP64 path (the Gram always runs in FP64)
+        for (auto* v : {&core, &back, &proj})
+          if (!v->empty()) {
+            v->back().gate = &q.st->path;
+            v->back().want = 1;
+          }
+      }
+      sp.push_back({b.V, b.ldiag, b.diagL, b.Msol, q.st, q.nblk, q.n[n]});
+      const T* g[3];
+      int c = 0;
+      for (int m = 0; m < 4; ++m)
+        if (m != n) g[c++] = b.G[m];
+      fv.push_back({b.V, g[0], g[1], g[2], q.st, Tp, Rc});
+      nm.push_back({b.Msol, b.F[n], b.lam, nullptr, nullptr, q.st, q.n[n], Rc, Tp});
+    }
+    if (n == 0 || n == 2) p->core[n] = gemm_op<T>(tb, core, n == 2, true, kind + "core");
+    p->back[n] = gemm_op<T>(tb, back, false, true, kind + "back");
+    p->gram[n] = gemm_op<T>(tb, gram, true, false, kind + "gram");
+    p->proj[n] = gemm_op<T>(tb, proj, true, false, kind + "proj");
+    StepOps& so = p->steps[n];
+    so.probs = tb.put(sp);
+    for (int mode = 0; mode < 4; ++mode) {
+      so.offs[mode].clear();
+      so.total[mode].clear();
+      const int first = step_first(mode), cnt = step_count(mode, p->maxNblk);
+      for (int k = 0; k < cnt; ++k) {
+        std::vector<int> offs(1, 0);
+        for (int i = 0; i < np; ++i)
+          offs.push_back(offs.back() + step_tiles(mode, p->P[i].nblk, p->P[i].n[n], first + k));
+        so.total[mode].push_back(offs.back());
+        so.offs[mode].push_back((int*)tb.put(offs));
+      }
+    }
+    p->formv[n] = tb.put(fv);
+    p->norm[n] = tb.put(nm);
+    if (n == 3) {
+      for (int i = 0; i < np; ++i) {
+        Bufs<T>& b = p->P[i].*bufs;
+        nm[i].Msave = b.Msave;
+        nm[i].inner_part = p->P[i].inner_part;
+      }
+      p->norm_inner = tb.put(nm);
+    }
+  }
+  std::vector<FitArgs<T>> ft;
+  std::vector<CkptArgs> ck;
+  std::vector<CondArgs<T>> cd;
+  for (int i = 0; i < np; ++i) {
+    Prob& q = p->P[i];
+    Bufs<T>& b = q.*bufs;
+    cd.push_back({b.diagL, q.st, q.Rc});
+    FitArgs<T> f;
+    for (int m = 0; m < 4; ++m) f.g[m] = b.G[m];
+    f.lam = b.lam;
+    f.inner_part = q.inner_part;
+    f.row_part = q.row_part;
+    f.fit_hist = q.fit_hist;
+    f.st = q.st;
+    f.R = q.Rc;
+    f.ld = q.Tp;
+    ft.push_back(f);
+    CkptArgs c;
+    for (int m = 0; m < 4; ++m) {
+      c.a[m] = b.F[m];
+      c.b[m] = b.Fsave[m];
+      c.bytes[m] = sizeof(T) * (size_t)q.n[m] * q.Tp;
+    }
+    c.st = q.st;
+    c.st_save = q.st_save;
+    ck.push_back(c);
+  }
+  p->fit = tb.put(ft);
+  p->ckpt = tb.put(ck);
+  p->cond = tb.put(cd);
+}
+
+void build_mixed(TableBuilder& tb, cpd_plan_s* p) {
+  const int np = p->count;
+  for (int n = 0; n < 4; ++n) {
+    std::vector<SplitArgs> core, back, proj;
+    std::vector<SplitTArgs> ftt;
+    for (int i = 0; i < np; ++i) {
+      Prob& q = p->P[i];
+      MixedBufs& mx = q.mx;
+      const int32_t* done = &q.st->done;
+      const int Rt = q.Rt, Rc = q.Rc;
+      if (n == 0 || n == 2) {
+        const int a = n == 0 ? 2 : 0, b = n == 0 ? 3 : 1;
+        SplitOperand A{nullptr, nullptr, mx.WT[a], mx.WT[b], mx.Rtp};
+        SplitOperand B = n == 0 ? SplitOperand{mx.Zh, mx.Zl, nullptr, nullptr, mx.Rtp}
+                                : SplitOperand{mx.ZTh, mx.ZTl, nullptr, nullptr, mx.Rtp};
+        core.push_back({Rc, Rt, mx.Rtp, A, B, mx.YT, nullptr, nullptr, mx.Rtp, done, &q.st->path, 0});
+      }
+      SplitOperand A{mx.Xh[n], mx.Xl[n], nullptr, nullptr, mx.Rtp};
+      SplitOperand B{nullptr, nullptr, mx.WT[partner_of[n]], mx.YT, mx.Rtp};
+      back.push_back({q.n[n], Rc, mx.Rtp, A, B, nullptr, q.b64.Msol, nullptr, q.Tp, done, &q.st->path, 0});
+      SplitOperand PA{mx.FTh, mx.FTl, nullptr, nullptr, mx.npad_max};
+      SplitOperand PB{mx.XTh[n], mx.XTl[n], nullptr, nullptr, mx.npad[n]};
+      proj.push_back({Rc, Rt, mx.npad[n], PA, PB, mx.WT[n], nullptr, nullptr, mx.Rtp, done, &q.st->path, 0});
+      ftt.push_back({q.b64.F[n], mx.FTh, mx.FTl, done, &q.st->path, q.n[n], Rc, q.Tp, mx.npad_max, mx.npad[n]});
+    }
+    if (n == 0 || n == 2) p->score[n] = split_op(tb, core, true, false);
+    p->sback[n] = split_op(tb, back, false, true);
+    p->sproj[n] = split_op(tb, proj, false, false);
+    p->ftt[n] = tb.put(ftt);
+  }
+  // FP64 mode-3 MTTKRP for the fit of fit sweeps (split-path problems; a
+  // promoted problem's FP64 back-projection already fills Msave), and the
+  // FP64 projections that catch up a problem promoted in an asynchronous
+  // sweep
+  std::vector<GemmArgs<double>> fp[3], fc, fb, cp[4];
+  for (int i = 0; i < np; ++i) {
+    Prob& q = p->P[i];
+    Bufs<double>& b = q.b64;
+    const int32_t* done = &q.st->done;
+    const int32_t* path = &q.st->path;
+    const int Rt = q.Rt, Rc = q.Rc, Tp = q.Tp;
+    for (int m = 0; m < 3; ++m)
+      fp[m].push_back({Rt, Rc, q.n[m], b.X[m], Rt, b.F[m], nullptr, Tp, b.W[m], Tp, nullptr, 1.0, 0.0, done, path, 0});
+    fc.push_back({Rt, Rc, Rt, b.Z, Rt, b.W[0], b.W[1], Tp, b.Y, Tp, nullptr, 1.0, 0.0, done, path, 0});
+    fb.push_back({q.n[3], Rc, Rt, b.X[3], Rt, b.W[2], b.Y, Tp, b.Msave, Tp, nullptr, 1.0, 0.0, done, path, 0});
+    for (int m = 0; m < 4; ++m)
+      cp[m].push_back({Rt, Rc, q.n[m], b.X[m], Rt, b.F[m], nullptr, Tp, b.W[m], Tp, nullptr, 1.0, 0.0, done,
+                       &q.st->promote, 1});
+  }
+  for (int m = 0; m < 3; ++m) p->fproj[m] = gemm_op<double>(tb, fp[m], true, false, "f64proj");
+  p->fcore = gemm_op<double>(tb, fc, true, true, "f64core");
+  p->fback = gemm_op<double>(tb, fb, false, true, "f64back");
+  for (int m = 0; m < 4; ++m) p->cproj[m] = gemm_op<double>(tb, cp[m], true, false, "f64proj");
+}
+
+size_t build_tables(cpd_plan_s* p, char* base, std::vector<char>* host) {
+  TableBuilder tb;
+  tb.L.base = base;
+  if (p->prec == CPD_FP32) build_typed<float>(tb, p, &Prob::b32, false);
+  else build_typed<double>(tb, p, &Prob::b64, p->prec == CPD_MIXED_BF16);
+  if (p->prec == CPD_MIXED_BF16) build_mixed(tb, p);
+  std::vector<DevState*> sts;
+  for (auto& q : p->P) sts.push_back(q.st);
+  p->sts = tb.put(sts);
+  std::vector<int32_t> forced(p->count, 0);
+  p->forced_dev = (int32_t*)tb.put(forced);
+  if (host) {
+    tb.host.resize(tb.L.off);
+    *host = tb.host;
+  }
+  return tb.L.off;
+}
+
+// Carves all problems and sizes the table region; returns total bytes
+// (the last 4 KiB are autotuning scratch).
+size_t layout_plan(cpd_plan_s* p, char* base) {
   Layout L;
   L.base = base;
-  const int Rt = p->Rt, Tp = p->Tp;
-  p->st = (DevState*)L.take(sizeof(DevState));
-  p->st_save = (DevState*)L.take(sizeof(DevState));
-  p->fit_hist = (double*)L.take(sizeof(double) * HIST_CAP);
-  p->inner_part = (double*)L.take(sizeof(double) * Tp);
-  p->row_part = (double*)L.take(sizeof(double) * Tp);
-  p->norm2 = (double*)L.take(sizeof(double) * 8);
-  const size_t nt = (size_t)((Rt + 63) / 64);
-  p->partials = (double*)L.take(sizeof(double) * nt * nt);
-  size_t setup_elems = (size_t)Rt * Rt;
-  if ((size_t)p->nmax * Tp > setup_elems) setup_elems = (size_t)p->nmax * Tp;
-  for (int i = 0; i < 3; ++i) p->setup[i] = (double*)L.take(sizeof(double) * setup_elems);
-  p->scratch64 = (double*)L.take(sizeof(double) * (size_t)p->nmax * Tp);
-  if (p->prec == CPD_FP64) {
-    carve_typed<double>(L, p, p->b64, false);
-    for (int m = 0; m < 4; ++m) p->b64.X[m] = p->d.X[m];
-    p->b64.Z = p->d.Z;
-  } else if (p->prec == CPD_FP32) {
-    carve_typed<float>(L, p, p->b32, true);
-  } else {
-    // mixed: FP64 factors / Grams / solve, split-BF16 operand copies
-    carve_typed<double>(L, p, p->b64, false);
-    for (int m = 0; m < 4; ++m) p->b64.X[m] = p->d.X[m];
-    p->b64.Z = p->d.Z;
-    mixed_carve(L.base, &L.off, p->mx, p->n, Rt, p->Rc, p->d.X);
+  SplitShare sh;
+  for (auto& q : p->P) carve_prob(L, q, p->prec, sh);
+  p->tables_off = L.off;
+  const size_t tables = build_tables(p, nullptr, nullptr);
+  return L.off + align_up(tables) + 4096;
+}
+
+int init_shape(cpd_plan_s* p, const cpd_desc* descs, int count) {
+  if (count <= 0 || count > 4096 || !descs) return CPD_ERR_INVALID_ARG;
+  p->count = count;
+  p->P.resize(count);
+  for (int i = 0; i < count; ++i) {
+    const int rc = check_desc(&descs[i]);
+    if (rc != CPD_OK) return rc;
+    if (descs[i].precision != descs[0].precision) return CPD_ERR_INVALID_ARG;
+    fill_prob(p->P[i], &descs[i]);
   }
-  return L.off;
-}
-
-void fill_shape(cpd_plan_s* p, const cpd_desc* d) {
-  p->d = *d;
-  for (int m = 0; m < 4; ++m) p->n[m] = d->n[m];
-  p->Rt = d->r_thc;
-  p->Rc = d->r_cp;
-  p->nblk = (d->r_cp + 63) / 64;
-  p->Tp = p->nblk * 64;
-  p->nmax = 0;
-  for (int m = 0; m < 4; ++m)
-    if (p->n[m] > p->nmax) p->nmax = p->n[m];
-  p->prec = d->precision;
-  p->fit_every = d->fit_every > 0 ? d->fit_every : 1;
+  p->prec = descs[0].precision;
+  p->fit_every = descs[0].fit_every > 0 ? descs[0].fit_every : 1;
+  p->allow_fallback = descs[0].chol_fallback;
+  p->use_graph = descs[0].use_graph;
+  p->autotune = descs[0].autotune;
+  p->tol = descs[0].tol;
+  p->fit_floor = descs[0].fit_floor;
   p->launched = 0;
+  p->maxR = p->maxTp = p->maxNblk = p->maxN = 0;
+  for (auto& q : p->P) {
+    if (q.Rc > p->maxR) p->maxR = q.Rc;
+    if (q.Tp > p->maxTp) p->maxTp = q.Tp;
+    if (q.nblk > p->maxNblk) p->maxNblk = q.nblk;
+    if (q.nmax > p->maxN) p->maxN = q.nmax;
+  }
+  return CPD_OK;
 }
-
-#define HIPCHK(x)                                    \
-  do {                                               \
-    hipError_t e_ = (x);                             \
-    if (e_ != hipSuccess) return CPD_ERR_HIP;        \
-  } while (0)
 
 // ------------------------------------------------------------------ set-up
-int setup_norm2(cpd_plan_s* p, hipStream_t s) {
-  const int Rt = p->Rt;
-  double *A = p->setup[0], *B = p->setup[1], *C = p->setup[2];
-  const double* const* X = p->d.X;
+int setup_norm2(Prob& q, hipStream_t s) {
+  const int Rt = q.Rt;
+  double *A = q.setup[0], *B = q.setup[1], *C = q.setup[2];
+  const double* const* X = q.d.X;
   auto syrk = [&](const double* x, int n, double* out) {
     GemmF64 g{Rt, Rt, n, x, Rt, true, x, nullptr, Rt, false, out, Rt, nullptr, 1.0, 0.0, nullptr};
     gemm_f64(s, g);
   };
   const size_t cnt = (size_t)Rt * Rt;
-  syrk(X[0], p->n[0], A);
+  syrk(X[0], q.n[0], A);
   if (X[1] == X[0]) hadamard_inplace_f64(s, A, A, cnt);
-  else { syrk(X[1], p->n[1], B); hadamard_inplace_f64(s, A, B, cnt); }
-  // P = Z^T (S0 o S1)
-  { GemmF64 g{Rt, Rt, Rt, p->d.Z, Rt, true, A, nullptr, Rt, false, C, Rt, nullptr, 1.0, 0.0, nullptr}; gemm_f64(s, g); }
-  if (!(X[2] == X[0] && X[3] == X[1])) {
-    syrk(X[2], p->n[2], A);
-    if (X[3] == X[2]) hadamard_inplace_f64(s, A, A, cnt);
-    else { syrk(X[3], p->n[3], B); hadamard_inplace_f64(s, A, B, cnt); }
+  else {
+    syrk(X[1], q.n[1], B);
+    hadamard_inplace_f64(s, A, B, cnt);
   }
-  // Q = Z (S2 o S3)
-  { GemmF64 g{Rt, Rt, Rt, p->d.Z, Rt, false, A, nullptr, Rt, false, B, Rt, nullptr, 1.0, 0.0, nullptr}; gemm_f64(s, g); }
-  transposed_dot_f64(s, C, B, Rt, Rt, p->partials, p->norm2);
+  {
+    GemmF64 g{Rt, Rt, Rt, q.d.Z, Rt, true, A, nullptr, Rt, false, C, Rt, nullptr, 1.0, 0.0, nullptr};
+    gemm_f64(s, g);
+  }
+  if (!(X[2] == X[0] && X[3] == X[1])) {
+    syrk(X[2], q.n[2], A);
+    if (X[3] == X[2]) hadamard_inplace_f64(s, A, A, cnt);
+    else {
+      syrk(X[3], q.n[3], B);
+      hadamard_inplace_f64(s, A, B, cnt);
+    }
+  }
+  {
+    GemmF64 g{Rt, Rt, Rt, q.d.Z, Rt, false, A, nullptr, Rt, false, B, Rt, nullptr, 1.0, 0.0, nullptr};
+    gemm_f64(s, g);
+  }
+  transposed_dot_f64(s, C, B, Rt, Rt, q.partials, q.norm2);
   return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
 }
 
-template <typename T>
-void gemm_t(hipStream_t s, int M, int N, int K, const T* A, int lda, bool at, const T* B1,
-            const T* B2, int ldb, T* C, int ldc, T* C2, const int32_t* done);
-template <>
-void gemm_t<double>(hipStream_t s, int M, int N, int K, const double* A, int lda, bool at,
-                    const double* B1, const double* B2, int ldb, double* C, int ldc, double* C2,
-                    const int32_t* done) {
-  GemmF64 g{M, N, K, A, lda, at, B1, B2, ldb, false, C, ldc, C2, 1.0, 0.0, done};
-  gemm_f64(s, g);
-}
-template <>
-void gemm_t<float>(hipStream_t s, int M, int N, int K, const float* A, int lda, bool at,
-                   const float* B1, const float* B2, int ldb, float* C, int ldc, float* C2,
-                   const int32_t* done) {
-  GemmF32 g{M, N, K, A, lda, at, B1, B2, ldb, false, C, ldc, C2, 1.0f, 0.0f, done};
-  gemm_f32(s, g);
-}
-
-// Projection W_m = X_m^T F_m and Gram F_m^T F_m of one mode.
-template <typename T>
-void refresh_mode(cpd_plan_s* p, Bufs<T>& b, int m, hipStream_t s, const int32_t* done) {
-  const int Rt = p->Rt, Rc = p->Rc, Tp = p->Tp;
-  gemm_t<T>(s, Rc, Rc, p->n[m], b.F[m], Tp, true, b.F[m], nullptr, Tp, b.G[m], Tp, nullptr, done);
-  gemm_t<T>(s, Rt, Rc, p->n[m], b.X[m], Rt, true, b.F[m], nullptr, Tp, b.W[m], Tp, nullptr, done);
-}
-
-// Core product Y and back-projection M of mode n into `out` (ld Tp).
-template <typename T>
-void mttkrp_into(cpd_plan_s* p, Bufs<T>& b, int n, bool fresh_core, T* out, T* out2, hipStream_t s,
-                 const int32_t* done) {
-  const int Rt = p->Rt, Rc = p->Rc, Tp = p->Tp;
-  if (fresh_core) {
-    if (n < 2) gemm_t<T>(s, Rt, Rc, Rt, b.Z, Rt, false, b.W[2], b.W[3], Tp, b.Y, Tp, nullptr, done);
-    else gemm_t<T>(s, Rt, Rc, Rt, b.Z, Rt, true, b.W[0], b.W[1], Tp, b.Y, Tp, nullptr, done);
+void split_inputs(Prob& q, hipStream_t s, std::map<const void*, int>& done_split) {
+  MixedBufs& mx = q.mx;
+  for (int m = 0; m < 4; ++m) {
+    if (done_split.count(mx.Xh[m])) continue;
+    done_split[mx.Xh[m]] = 1;
+    split_rows_f64(s, q.d.X[m], q.n[m], q.Rt, q.Rt, mx.Xh[m], mx.Xl[m], mx.Rtp, mx.Rtp);
+    split_transpose_f64(s, q.d.X[m], q.n[m], q.Rt, q.Rt, mx.XTh[m], mx.XTl[m], mx.npad[m], mx.npad[m]);
   }
-  static const int partner[4] = {1, 0, 3, 2};
-  gemm_t<T>(s, p->n[n], Rc, Rt, b.X[n], Rt, false, b.W[partner[n]], b.Y, Tp, out, Tp, out2, done);
+  if (!done_split.count(mx.Zh)) {
+    done_split[mx.Zh] = 1;
+    split_rows_f64(s, q.d.Z, q.Rt, q.Rt, q.Rt, mx.Zh, mx.Zl, mx.Rtp, mx.Rtp);
+    split_transpose_f64(s, q.d.Z, q.Rt, q.Rt, q.Rt, mx.ZTh, mx.ZTl, mx.Rtp, mx.Rtp);
+  }
 }
 
-// Normal-equation solve of mode n, in place in Msol, then normalisation,
-// Gram and projection of the new factor.
+// --------------------------------------------------------- grouped launches
 template <typename T>
-void solve_mode(cpd_plan_s* p, Bufs<T>& b, int n, hipStream_t s, bool with_inner, bool fast) {
-  const int Rc = p->Rc, Tp = p->Tp;
-  DevState* st = p->st;
-  const T* g[3];
-  int q = 0;
-  for (int m = 0; m < 4; ++m)
-    if (m != n) g[q++] = b.G[m];
-  form_normal_matrix<T>(s, b.V, Tp, Rc, g[0], g[1], g[2], st, 0);
+void run_gemm(cpd_plan_s* p, hipStream_t s, const GroupOp& op) {
+  gemm_group<T>(s, (const GemmArgs<T>*)op.tab, op.offs, p->count, op.total, op.a_t, op.b_t, op.had, op.bm);
+}
+void run_split(cpd_plan_s* p, hipStream_t s, const GroupOp& op) {
+  gemm_split_group(s, (const SplitArgs*)op.tab, op.offs, p->count, op.total, op.apair, op.bpair);
+}
+template <typename T>
+void run_steps(cpd_plan_s* p, hipStream_t s, int n, int mode, int retry_pass) {
+  StepOps& so = p->steps[n];
+  const int first = step_first(mode);
+  for (size_t k = 0; k < so.offs[mode].size(); ++k)
+    step_group<T>(s, mode, (const StepProb<T>*)so.probs, so.offs[mode][k], p->count, so.total[mode][k],
+                  first + (int)k, retry_pass);
+}
+
+template <typename T>
+void solve_mode(cpd_plan_s* p, int n, hipStream_t s, bool with_inner, bool fast) {
+  const FormVArgs<T>* fv = (const FormVArgs<T>*)p->formv[n];
+  form_v_group<T>(s, fv, p->count, p->maxTp, 0);
   if (fast) {
-    chol_factor_fwd<T>(s, b.V, p->nblk, b.linv, b.diagL, b.Msol, p->n[n], st);
-    chol_solve_bwd<T>(s, b.V, p->nblk, b.linv, b.Msol, p->n[n], st);
+    run_steps<T>(p, s, n, STEP_CHOL_FWD, 0);
+    run_steps<T>(p, s, n, STEP_BWD, 0);
   } else {
-    chol_factor<T>(s, b.V, p->nblk, b.linv, b.diagL, st, 0);
-    retry_prepare_launch<T>(s, st, p->d.chol_fallback, g[0], g[1], g[2], Rc, Tp);
-    form_normal_matrix<T>(s, b.V, Tp, Rc, g[0], g[1], g[2], st, 1);
-    chol_factor<T>(s, b.V, p->nblk, b.linv, b.diagL, st, 1);
-    chol_solve_rows<T>(s, b.V, p->nblk, b.linv, b.Msol, p->n[n], st);
+    run_steps<T>(p, s, n, STEP_CHOL, 0);
+    retry_prepare_group<T>(s, fv, p->count, p->allow_fallback);
+    form_v_group<T>(s, fv, p->count, p->maxTp, 1);
+    run_steps<T>(p, s, n, STEP_CHOL, 1);
+    run_steps<T>(p, s, n, STEP_FWD, 0);
+    run_steps<T>(p, s, n, STEP_BWD, 0);
   }
-  normalise_columns<T>(s, b.Msol, p->n[n], Rc, Tp, b.F[n], b.lam, with_inner ? b.Msave : nullptr,
-                       with_inner ? p->inner_part : nullptr, st);
-}
-
-// Copies the factors and the device state to (dir = 0) or from (dir = 1)
-// the sweep checkpoint.
-struct CkptArgs {
-  void* a[4];
-  void* b[4];
-  size_t bytes[4];
-  DevState* st;
-  DevState* st_save;
-  int dir;
-};
-__global__ void checkpoint_kernel(CkptArgs c) {
-  for (int m = 0; m < 4; ++m) {
-    const uint32_t* src = (const uint32_t*)(c.dir ? c.b[m] : c.a[m]);
-    uint32_t* dst = (uint32_t*)(c.dir ? c.a[m] : c.b[m]);
-    const size_t words = c.bytes[m] / 4;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < words; e += (size_t)gridDim.x * 256)
-      dst[e] = src[e];
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (c.dir) *c.st = *c.st_save;
-    else *c.st_save = *c.st;
-  }
+  normalise_group<T>(s, (const NormArgs<T>*)(with_inner ? p->norm_inner : p->norm[n]), p->count, p->maxR);
 }
 
 template <typename T>
-void checkpoint(cpd_plan_s* p, Bufs<T>& b, hipStream_t s, int dir) {
-  CkptArgs c;
-  for (int m = 0; m < 4; ++m) {
-    c.a[m] = b.F[m];
-    c.b[m] = b.Fsave[m];
-    c.bytes[m] = sizeof(T) * (size_t)p->n[m] * p->Tp;
-  }
-  c.st = p->st;
-  c.st_save = p->st_save;
-  c.dir = dir;
-  hipLaunchKernelGGL(checkpoint_kernel, dim3(512), dim3(256), 0, s, c);
-}
-
-template <typename T>
-void enqueue_sweep_typed(cpd_plan_s* p, Bufs<T>& b, hipStream_t s, bool fast) {
-  const int32_t* done = &p->st->done;
-  if (fast) checkpoint<T>(p, b, s, 0);
+void enqueue_sweep_typed(cpd_plan_s* p, hipStream_t s, bool fast) {
+  if (fast) checkpoint_group(s, (const CkptArgs*)p->ckpt, p->count, 0);
   for (int n = 0; n < 4; ++n) {
-    mttkrp_into<T>(p, b, n, n == 0 || n == 2, b.Msol, n == 3 ? b.Msave : nullptr, s, done);
-    solve_mode<T>(p, b, n, s, n == 3, fast);
-    refresh_mode<T>(p, b, n, s, done);
+    if (n == 0 || n == 2) run_gemm<T>(p, s, p->core[n]);
+    run_gemm<T>(p, s, p->back[n]);
+    solve_mode<T>(p, n, s, n == 3, fast);
+    run_gemm<T>(p, s, p->gram[n]);
+    run_gemm<T>(p, s, p->proj[n]);
   }
-  const T* g[4] = {b.G[0], b.G[1], b.G[2], b.G[3]};
-  fit_update<T>(s, g, b.lam, p->Rc, p->Tp, p->inner_part, p->row_part, p->fit_hist, HIST_CAP,
-                p->d.tol, p->d.fit_floor, p->st);
-}
-
-__global__ void sweep_tick_kernel(DevState* st) {
-  if (threadIdx.x == 0 && !st->done) st->sweeps += 1;
+  fit_group<T>(s, (const FitArgs<T>*)p->fit, p->count, p->maxR, HIST_CAP, p->tol, p->fit_floor, 0, 0.0);
 }
 
 // Mixed precision: the three MTTKRP products in split BF16, everything
 // else in FP64.  On fit sweeps the mode-3 MTTKRP is ALSO formed in FP64
 // (from the FP64 factors) for <G, G~>: the residual is first-order
 // sensitive to that inner product, which split BF16 cannot deliver.
+void mixed_refresh_mode(cpd_plan_s* p, hipStream_t s, int n) {
+  run_gemm<double>(p, s, p->gram[n]);
+  run_gemm<double>(p, s, p->proj[n]);  // FP64-path problems only (gated)
+  int maxc = 0, maxd = 0;
+  for (auto& q : p->P) {
+    if (q.Rc > maxc) maxc = q.Rc;
+    if (q.mx.npad[n] > maxd) maxd = q.mx.npad[n];
+  }
+  split_transpose_group(s, (const SplitTArgs*)p->ftt[n], p->count, maxc, maxd);
+  run_split(p, s, p->sproj[n]);
+}
+
+// Precision guard: each problem runs either the split-BF16 MTTKRP (path 0)
+// or the FP64 one (path 1); both grouped products are enqueued and every
+// problem takes exactly one of them.  A problem is promoted to FP64 when
+// its normal matrices get too ill-conditioned, it needs a damped retry, or
+// its fit rises (see fit_final / sweep_tick).
 void enqueue_sweep_mixed(cpd_plan_s* p, hipStream_t s, bool fit_sweep, bool fast) {
-  Bufs<double>& b = p->b64;
-  const int32_t* done = &p->st->done;
-  const int Rt = p->Rt, Rc = p->Rc, Tp = p->Tp;
-  if (fast) checkpoint<double>(p, b, s, 0);
+  if (fast) checkpoint_group(s, (const CkptArgs*)p->ckpt, p->count, 0);
+  for (int m = 0; m < 4; ++m) run_gemm<double>(p, s, p->cproj[m]);  // promoted last sweep (async)
+  guard_begin_group(s, (DevState* const*)p->sts, p->count);
   for (int n = 0; n < 4; ++n) {
-    mixed_mttkrp(s, p->mx, n, n == 0 || n == 2, p->n, Rt, Rc, Tp, b.Msol, nullptr, done);
-    if (n == 3 && fit_sweep) {
-      for (int m = 0; m < 3; ++m)
-        gemm_t<double>(s, Rt, Rc, p->n[m], b.X[m], Rt, true, b.F[m], nullptr, Tp, b.W[m], Tp, nullptr,
-                       done);
-      mttkrp_into<double>(p, b, 3, true, b.Msave, nullptr, s, done);
+    if (n == 0 || n == 2) {
+      run_split(p, s, p->score[n]);
+      run_gemm<double>(p, s, p->core[n]);
     }
-    solve_mode<double>(p, b, n, s, n == 3 && fit_sweep, fast);
-    gemm_t<double>(s, Rc, Rc, p->n[n], b.F[n], Tp, true, b.F[n], nullptr, Tp, b.G[n], Tp, nullptr,
-                   done);
-    mixed_refresh(s, p->mx, n, b.F[n], p->n, Rt, Rc, Tp, done);
+    run_split(p, s, p->sback[n]);
+    run_gemm<double>(p, s, p->back[n]);
+    if (n == 3 && fit_sweep) {
+      for (int m = 0; m < 3; ++m) run_gemm<double>(p, s, p->fproj[m]);
+      run_gemm<double>(p, s, p->fcore);
+      run_gemm<double>(p, s, p->fback);
+    }
+    solve_mode<double>(p, n, s, n == 3 && fit_sweep, fast);
+    cond_track_group<double>(s, (const CondArgs<double>*)p->cond, p->count);
+    mixed_refresh_mode(p, s, n);
   }
-  if (fit_sweep) {
-    const double* g[4] = {b.G[0], b.G[1], b.G[2], b.G[3]};
-    fit_update<double>(s, g, b.lam, Rc, Tp, p->inner_part, p->row_part, p->fit_hist, HIST_CAP, p->d.tol,
-                       p->d.fit_floor, p->st);
-  } else {
-    hipLaunchKernelGGL(sweep_tick_kernel, dim3(1), dim3(64), 0, s, p->st);
-  }
+  if (fit_sweep)
+    fit_group<double>(s, (const FitArgs<double>*)p->fit, p->count, p->maxR, HIST_CAP, p->tol, p->fit_floor, 1,
+                      p->cond_limit);
+  else
+    sweep_tick_group(s, (DevState* const*)p->sts, p->count, 1, p->cond_limit);
 }
 
 void enqueue_sweep(cpd_plan_s* p, hipStream_t s, bool fit_sweep, bool fast) {
-  if (p->prec == CPD_FP64) enqueue_sweep_typed<double>(p, p->b64, s, fast);
-  else if (p->prec == CPD_FP32) enqueue_sweep_typed<float>(p, p->b32, s, fast);
+  if (p->prec == CPD_FP64) enqueue_sweep_typed<double>(p, s, fast);
+  else if (p->prec == CPD_FP32) enqueue_sweep_typed<float>(p, s, fast);
   else enqueue_sweep_mixed(p, s, fit_sweep, fast);
 }
 
 bool is_fit_sweep(const cpd_plan_s* p, long index1) {
   return p->prec != CPD_MIXED_BF16 || p->fit_every <= 1 || index1 % p->fit_every == 0;
+}
+
+int refresh_all(cpd_plan_s* p, hipStream_t s) {
+  for (int m = 0; m < 4; ++m) {
+    if (p->prec == CPD_FP64) {
+      run_gemm<double>(p, s, p->gram[m]);
+      run_gemm<double>(p, s, p->proj[m]);
+    } else if (p->prec == CPD_FP32) {
+      run_gemm<float>(p, s, p->gram[m]);
+      run_gemm<float>(p, s, p->proj[m]);
+    } else {
+      mixed_refresh_mode(p, s, m);
+    }
+  }
+  return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
 }
 
 int capture(cpd_plan_s* p, bool fit_sweep, bool fast, hipGraph_t* g, hipGraphExec_t* e) {
@@ -400,53 +752,62 @@ int grid_for(size_t n) {
   return (int)g;
 }
 
-int copy_out(cpd_plan_s* p, const void* src_typed, int rows, int cols, double* dst, hipStream_t s) {
+int copy_out(cpd_plan_s* p, const Prob& q, const void* src_typed, int rows, int cols, double* dst,
+             hipStream_t s) {
   if (p->prec == CPD_FP32) {
     hipLaunchKernelGGL(strided_to_dense_f32, dim3(grid_for((size_t)rows * cols)), dim3(256), 0, s,
-                       (const float*)src_typed, rows, cols, p->Tp, dst);
+                       (const float*)src_typed, rows, cols, q.Tp, dst);
     HIPCHK(hipGetLastError());
   } else {
-    HIPCHK(hipMemcpy2DAsync(dst, sizeof(double) * cols, src_typed, sizeof(double) * p->Tp,
-                            sizeof(double) * cols, rows, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpy2DAsync(dst, sizeof(double) * cols, src_typed, sizeof(double) * q.Tp, sizeof(double) * cols,
+                            rows, hipMemcpyDeviceToDevice, s));
   }
   return CPD_OK;
 }
 
-int copy_in(cpd_plan_s* p, const double* src, int rows, int cols, void* dst_typed, hipStream_t s) {
+int copy_in(cpd_plan_s* p, const Prob& q, const double* src, int rows, int cols, void* dst_typed, hipStream_t s) {
   if (p->prec == CPD_FP32) {
-    hipLaunchKernelGGL(dense_to_strided_f32, dim3(grid_for((size_t)rows * cols)), dim3(256), 0, s,
-                       src, rows, cols, p->Tp, (float*)dst_typed);
+    hipLaunchKernelGGL(dense_to_strided_f32, dim3(grid_for((size_t)rows * cols)), dim3(256), 0, s, src, rows,
+                       cols, q.Tp, (float*)dst_typed);
     HIPCHK(hipGetLastError());
   } else {
-    HIPCHK(hipMemcpy2DAsync(dst_typed, sizeof(double) * p->Tp, src, sizeof(double) * cols,
-                            sizeof(double) * cols, rows, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpy2DAsync(dst_typed, sizeof(double) * q.Tp, src, sizeof(double) * cols, sizeof(double) * cols,
+                            rows, hipMemcpyDeviceToDevice, s));
   }
   return CPD_OK;
 }
 
-int refresh_all(cpd_plan_s* p, hipStream_t s) {
-  for (int m = 0; m < 4; ++m) {
-    if (p->prec == CPD_FP64) refresh_mode<double>(p, p->b64, m, s, nullptr);
-    else if (p->prec == CPD_FP32) refresh_mode<float>(p, p->b32, m, s, nullptr);
-    else {
-      gemm_t<double>(s, p->Rc, p->Rc, p->n[m], p->b64.F[m], p->Tp, true, p->b64.F[m], nullptr,
-                     p->Tp, p->b64.G[m], p->Tp, nullptr, nullptr);
-      mixed_refresh(s, p->mx, m, p->b64.F[m], p->n, p->Rt, p->Rc, p->Tp, nullptr);
-    }
-  }
-  return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
-}
-
-int read_state(cpd_plan_s* p) {
-  HIPCHK(hipMemcpyAsync(p->host_state, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->stream));
+int read_states(cpd_plan_s* p) {
+  for (int i = 0; i < p->count; ++i)
+    HIPCHK(hipMemcpyAsync(&p->host_states[i], p->P[i].st, sizeof(DevState), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   return CPD_OK;
 }
 
+bool all_done(const cpd_plan_s* p) {
+  for (int i = 0; i < p->count; ++i)
+    if (!p->host_states[i].done) return false;
+  return true;
+}
+bool any_chol_fail(const cpd_plan_s* p) {
+  for (int i = 0; i < p->count; ++i)
+    if (p->host_states[i].chol_fail) return true;
+  return false;
+}
+bool any_promote(const cpd_plan_s* p) {
+  for (int i = 0; i < p->count; ++i)
+    if (p->host_states[i].promote) return true;
+  return false;
+}
 int status_from_flags(int flags) {
   if (flags & FLAG_NOT_SPD) return CPD_ERR_NOT_SPD;
   if (flags & FLAG_NONFINITE) return CPD_ERR_NONFINITE;
   return CPD_OK;
+}
+int batch_status(const cpd_plan_s* p) {
+  int f = 0;
+  for (int i = 0; i < p->count; ++i) f |= p->host_states[i].flags;
+  return status_from_flags(f);
 }
 
 int launch_sweep(cpd_plan_s* p, bool fit, bool fast) {
@@ -459,80 +820,165 @@ int launch_sweep(cpd_plan_s* p, bool fit, bool fast) {
   return CPD_OK;
 }
 
-// Rewinds to the checkpoint taken at the start of the last fast sweep and
-// recomputes the projections / Grams from the restored factors.
+// Rewinds every problem to the checkpoint taken at the start of the last
+// fast sweep and recomputes the projections / Grams from the restored
+// factors (deterministic, so problems that did not fail are unchanged).
 int rewind_sweep(cpd_plan_s* p) {
-  if (p->prec == CPD_FP32) checkpoint<float>(p, p->b32, p->stream, 1);
-  else checkpoint<double>(p, p->b64, p->stream, 1);
+  checkpoint_group(p->stream, (const CkptArgs*)p->ckpt, p->count, 1);
   HIPCHK(hipGetLastError());
+  if (p->prec == CPD_MIXED_BF16) {
+    // the restored states predate any promotion: re-apply the sticky ones
+    HIPCHK(hipMemcpyAsync(p->forced_dev, p->forced.data(), sizeof(int32_t) * p->count, hipMemcpyHostToDevice,
+                          p->stream));
+    set_path_group(p->stream, (DevState* const*)p->sts, p->count, p->forced_dev);
+    HIPCHK(hipStreamSynchronize(p->stream));  // the host vector may change before the copy ran
+  }
   return refresh_all(p, p->stream);
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t cpd_workspace_size(const cpd_desc* d) {
-  if (check_desc(d) != CPD_OK) return 0;
-  cpd_plan_s tmp;
-  memset(&tmp, 0, sizeof(tmp));
-  fill_shape(&tmp, d);
-  return carve(&tmp, nullptr);
+// Tile-size autotuning of the grouped FP64/FP32 GEMMs: times both tile
+// edges of every group once and records the faster in the process cache
+// (keyed by kind and shapes), which later table builds read.
+template <typename T>
+void autotune_ops(cpd_plan_s* p, hipStream_t s) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return;
+  }
+  int* doffs = (int*)(p->ws + p->ws_bytes - 4096);
+  auto tune = [&](GroupOp& op, const std::string& kind) {
+    if (op.total == 0 || !op.tab || (size_t)(p->count + 1) * sizeof(int) > 4096) return;
+    std::vector<GemmArgs<T>> host(p->count);
+    if (hipMemcpy(host.data(), op.tab, sizeof(GemmArgs<T>) * p->count, hipMemcpyDeviceToHost) != hipSuccess)
+      return;
+    std::vector<int> dims;
+    for (auto& g : host) {
+      dims.push_back(g.M);
+      dims.push_back(g.N);
+      dims.push_back(g.K);
+    }
+    const std::string key = tune_key(kind, dims);
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) {
+        p->tune_log.push_back({key, it->second});
+        return;
+      }
+    }
+    float best = 1e30f;
+    int best_bm = op.bm;
+    for (int bm : {64, 128}) {
+      std::vector<int> offs(1, 0);
+      for (auto& g : host) offs.push_back(offs.back() + gemm_tile_count(g.M, g.N, bm));
+      if (hipMemcpy(doffs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice) != hipSuccess) return;
+      float ms = 0.f;
+      for (int w = 0; w < 2; ++w) {  // second pass is the timed one
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < 3; ++r)
+          gemm_group<T>(s, (const GemmArgs<T>*)op.tab, doffs, p->count, offs.back(), op.a_t, op.b_t, op.had, bm);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
+      }
+      if (ms < best) {
+        best = ms;
+        best_bm = bm;
+      }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best_bm;
+    p->tune_log.push_back({key, best_bm});
+  };
+  const std::string kind = sizeof(T) == 8 ? "f64" : "f32";
+  for (int n = 0; n < 4; ++n) {
+    if (n == 0 || n == 2) tune(p->core[n], kind + "core");
+    tune(p->back[n], kind + "back");
+    tune(p->gram[n], kind + "gram");
+    tune(p->proj[n], kind + "proj");
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
 }
 
-cpd_status cpd_init(const cpd_desc* d, cpd_plan* out) {
+int upload_tables(cpd_plan_s* p, hipStream_t s) {
+  std::vector<char> host;
+  build_tables(p, p->ws + p->tables_off, &host);
+  if (host.empty()) return CPD_OK;
+  HIPCHK(hipMemcpyAsync(p->ws + p->tables_off, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  // the host vector goes out of scope: wait for the copy
+  HIPCHK(hipStreamSynchronize(s));
+  return CPD_OK;
+}
+
+int plan_create(const cpd_desc* descs, int count, void* workspace, size_t ws_bytes, cpd_plan* out) {
   if (!out) return CPD_ERR_INVALID_ARG;
   *out = nullptr;
-  int rc = check_desc(d);
-  if (rc != CPD_OK) return rc;
-  cpd_plan_s* p = new (std::nothrow) cpd_plan_s;
+  cpd_plan_s* p = new (std::nothrow) cpd_plan_s();
   if (!p) return CPD_ERR_INVALID_ARG;
-  memset(p, 0, sizeof(*p));
-  fill_shape(p, d);
-  const size_t need = carve(p, nullptr);
-  if (!d->workspace || d->workspace_bytes < need) {
+  int rc = init_shape(p, descs, count);
+  if (rc != CPD_OK) {
+    delete p;
+    return rc;
+  }
+  const size_t need = layout_plan(p, nullptr);
+  if (!workspace || ws_bytes < need) {
     delete p;
     return CPD_ERR_WORKSPACE;
   }
-  carve(p, (char*)d->workspace);
-  p->stream = (hipStream_t)d->stream;
-  if (hipHostMalloc((void**)&p->host_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+  p->ws = (char*)workspace;
+  p->ws_bytes = ws_bytes;
+  p->stream = (hipStream_t)descs[0].stream;
+  p->forced.assign(count, 0);
+  layout_plan(p, (char*)workspace);
+  if (hipHostMalloc((void**)&p->host_states, sizeof(DevState) * count, hipHostMallocDefault) != hipSuccess) {
     delete p;
     return CPD_ERR_HIP;
   }
   if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
-    (void)hipHostFree(p->host_state);
+    (void)hipHostFree(p->host_states);
     delete p;
     return CPD_ERR_HIP;
   }
   hipStream_t s = p->stream;
-  fill_bytes(s, d->workspace, need);
-  rc = setup_norm2(p, s);
-  if (rc == CPD_OK) {
+  fill_bytes(s, workspace, p->tables_off);
+  rc = upload_tables(p, s);
+  if (rc == CPD_OK && p->autotune && p->prec != CPD_MIXED_BF16) {
+    // tuning launches write the plan's intermediate buffers; they are
+    // cleared again below and recomputed by the set-up
+    if (p->prec == CPD_FP64) autotune_ops<double>(p, s);
+    else autotune_ops<float>(p, s);
+    rc = upload_tables(p, s);
+    fill_bytes(s, workspace, p->tables_off);
+  }
+  std::map<const void*, int> split_done;
+  for (int i = 0; i < count && rc == CPD_OK; ++i) {
+    Prob& q = p->P[i];
+    rc = setup_norm2(q, s);
+    if (rc != CPD_OK) break;
     if (p->prec == CPD_FP32) {
       for (int m = 0; m < 4; ++m) {
         bool first = true;
-        for (int q = 0; q < m; ++q)
-          if (d->X[q] == d->X[m]) first = false;
-        if (first) cast_f64_to_f32(s, d->X[m], (float*)p->b32.X[m], (size_t)p->n[m] * p->Rt);
+        for (int r = 0; r < m; ++r)
+          if (q.d.X[r] == q.d.X[m]) first = false;
+        if (first) cast_f64_to_f32(s, q.d.X[m], (float*)q.b32.X[m], (size_t)q.n[m] * q.Rt);
       }
-      cast_f64_to_f32(s, d->Z, (float*)p->b32.Z, (size_t)p->Rt * p->Rt);
+      cast_f64_to_f32(s, q.d.Z, (float*)q.b32.Z, (size_t)q.Rt * q.Rt);
       for (int m = 0; m < 4; ++m) {
-        copy_normalised_init(s, d->init[m], p->n[m], p->Rc, p->Tp, p->scratch64);
-        cast_f64_to_f32(s, p->scratch64, p->b32.F[m], (size_t)p->n[m] * p->Tp);
+        copy_normalised_init(s, q.d.init[m], q.n[m], q.Rc, q.Tp, q.scratch64);
+        cast_f64_to_f32(s, q.scratch64, q.b32.F[m], (size_t)q.n[m] * q.Tp);
       }
     } else {
-      if (p->prec == CPD_MIXED_BF16) mixed_setup_inputs(s, p->mx, d->X, d->Z, p->n, p->Rt);
-      for (int m = 0; m < 4; ++m)
-        copy_normalised_init(s, d->init[m], p->n[m], p->Rc, p->Tp, p->b64.F[m]);
+      if (p->prec == CPD_MIXED_BF16) split_inputs(q, s, split_done);
+      for (int m = 0; m < 4; ++m) copy_normalised_init(s, q.d.init[m], q.n[m], q.Rc, q.Tp, q.b64.F[m]);
     }
-    rc = refresh_all(p, s);
+    state_reset(s, q.st, q.norm2);
   }
-  if (rc == CPD_OK) {
-    state_reset(s, p->st, p->norm2);
-    if (hipGetLastError() != hipSuccess) rc = CPD_ERR_HIP;
-  }
-  if (rc == CPD_OK && d->use_graph) {
+  if (rc == CPD_OK) rc = refresh_all(p, s);
+  if (rc == CPD_OK && hipGetLastError() != hipSuccess) rc = CPD_ERR_HIP;
+  if (rc == CPD_OK && p->use_graph) {
     const bool nofit = p->prec == CPD_MIXED_BF16 && p->fit_every > 1;
     for (int fast = 0; fast < 2 && rc == CPD_OK; ++fast)
       for (int fit = nofit ? 0 : 1; fit < 2 && rc == CPD_OK; ++fit)
@@ -547,17 +993,17 @@ cpd_status cpd_init(const cpd_desc* d, cpd_plan* out) {
   return CPD_OK;
 }
 
-
-cpd_status cpd_sweep(cpd_plan p, int32_t nsweeps, double* fits_host, int32_t* n_run) {
-  if (!p || nsweeps < 0) return CPD_ERR_INVALID_ARG;
+// Runs up to nsweeps batched sweeps (see cpd_batch_sweep).
+int batch_sweep(cpd_plan_s* p, int nsweeps, double* fits_host, int32_t* n_run) {
+  if (nsweeps < 0) return CPD_ERR_INVALID_ARG;
   const bool sync = fits_host || n_run;
   int ran = 0;
   if (sync) {
-    int rc = read_state(p);
+    int rc = read_states(p);
     if (rc != CPD_OK) return rc;
-    if (p->host_state->done) {
+    if (all_done(p)) {
       if (n_run) *n_run = 0;
-      return status_from_flags(p->host_state->flags);
+      return batch_status(p);
     }
   }
   for (int i = 0; i < nsweeps; ++i) {
@@ -572,79 +1018,43 @@ cpd_status cpd_sweep(cpd_plan p, int32_t nsweeps, double* fits_host, int32_t* n_
       continue;
     }
     rc = launch_sweep(p, fit, true);
-    if (rc == CPD_OK) rc = read_state(p);
+    if (rc == CPD_OK) rc = read_states(p);
     if (rc != CPD_OK) return rc;
-    if (p->host_state->chol_fail) {
-      // a pivot failed: replay this sweep with the damped-retry graph
+    // Replays: a failed pivot reruns the sweep with the damped-retry graph;
+    // a precision promotion reruns it with the promoted problems on the
+    // FP64 path.  Each problem can be promoted once, so this terminates.
+    for (int attempt = 0; attempt < 2 * p->count + 2; ++attempt) {
+      if (any_chol_fail(p)) {
+        rc = rewind_sweep(p);
+        if (rc == CPD_OK) rc = launch_sweep(p, fit, false);
+        if (rc == CPD_OK) rc = read_states(p);
+        if (rc != CPD_OK) return rc;
+      }
+      if (!any_promote(p)) break;
+      for (int q = 0; q < p->count; ++q)
+        if (p->host_states[q].promote) p->forced[q] = 1;
       rc = rewind_sweep(p);
-      if (rc == CPD_OK) rc = launch_sweep(p, fit, false);
-      if (rc == CPD_OK) rc = read_state(p);
+      if (rc == CPD_OK) rc = launch_sweep(p, fit, true);
+      if (rc == CPD_OK) rc = read_states(p);
       if (rc != CPD_OK) return rc;
     }
     p->launched += 1;
     ++ran;
-    if (fits_host) fits_host[ran - 1] = fit ? p->host_state->fit_prev : -1.0;
-    if (p->host_state->done) break;
+    if (fits_host)
+      for (int q = 0; q < p->count; ++q)
+        fits_host[(size_t)q * nsweeps + (ran - 1)] = fit ? p->host_states[q].fit_prev : -1.0;
+    if (all_done(p)) break;
   }
   if (n_run) *n_run = ran;
-  if (sync) return status_from_flags(p->host_state->flags);
+  if (sync) return batch_status(p);
   return CPD_OK;
 }
 
-cpd_status cpd_fit(cpd_plan p, double* fit_host) {
-  if (!p || !fit_host) return CPD_ERR_INVALID_ARG;
-  int rc = read_state(p);
+int stats_of(cpd_plan_s* p, int idx, cpd_stats_t* out) {
+  int rc = read_states(p);
   if (rc != CPD_OK) return rc;
-  *fit_host = p->host_state->sweeps > 0 ? p->host_state->fit_prev : -1.0;
-  return status_from_flags(p->host_state->flags);
-}
-
-cpd_status cpd_get_factors(cpd_plan p, double* const F_dev[4], double* lambda_dev) {
-  if (!p) return CPD_ERR_INVALID_ARG;
-  hipStream_t s = p->stream;
-  for (int m = 0; m < 4; ++m) {
-    if (!F_dev || !F_dev[m]) continue;
-    const void* src = p->prec == CPD_FP32 ? (const void*)p->b32.F[m] : (const void*)p->b64.F[m];
-    int rc = copy_out(p, src, p->n[m], p->Rc, F_dev[m], s);
-    if (rc != CPD_OK) return rc;
-  }
-  if (lambda_dev) {
-    const void* src = p->prec == CPD_FP32 ? (const void*)p->b32.lam : (const void*)p->b64.lam;
-    int rc = copy_out(p, src, 1, p->Rc, lambda_dev, s);
-    if (rc != CPD_OK) return rc;
-  }
-  return CPD_OK;
-}
-
-cpd_status cpd_set_factors(cpd_plan p, const double* const F_dev[4], const double* lambda_dev,
-                           double prev_fit, int32_t sweeps) {
-  if (!p || !F_dev || sweeps < 0) return CPD_ERR_INVALID_ARG;
-  for (int m = 0; m < 4; ++m)
-    if (!F_dev[m]) return CPD_ERR_INVALID_ARG;
-  hipStream_t s = p->stream;
-  for (int m = 0; m < 4; ++m) {
-    void* dst = p->prec == CPD_FP32 ? (void*)p->b32.F[m] : (void*)p->b64.F[m];
-    int rc = copy_in(p, F_dev[m], p->n[m], p->Rc, dst, s);
-    if (rc != CPD_OK) return rc;
-  }
-  if (lambda_dev) {
-    void* dst = p->prec == CPD_FP32 ? (void*)p->b32.lam : (void*)p->b64.lam;
-    int rc = copy_in(p, lambda_dev, 1, p->Rc, dst, s);
-    if (rc != CPD_OK) return rc;
-  }
-  int rc = refresh_all(p, s);
-  if (rc != CPD_OK) return rc;
-  hipLaunchKernelGGL(state_set_kernel, dim3(1), dim3(64), 0, s, p->st, prev_fit, (int)sweeps);
-  HIPCHK(hipGetLastError());
-  p->launched = sweeps;
-  return CPD_OK;
-}
-
-cpd_status cpd_stats(cpd_plan p, cpd_stats_t* out) {
-  if (!p || !out) return CPD_ERR_INVALID_ARG;
-  int rc = read_state(p);
-  if (rc != CPD_OK) return rc;
-  const DevState& h = *p->host_state;
+  const DevState& h = p->host_states[idx];
+  const Prob& q = p->P[idx];
   out->sweeps = h.sweeps;
   out->converged = h.done;
   out->fallbacks = h.fallbacks;
@@ -653,103 +1063,203 @@ cpd_status cpd_stats(cpd_plan p, cpd_stats_t* out) {
   out->norm2 = h.norm2;
   out->inner = h.inner;
   out->model2 = h.model2;
-  std::vector<double> dg(p->Rc);
+  std::vector<double> dg(q.Rc);
   if (p->prec == CPD_FP32) {
-    std::vector<float> df(p->Rc);
-    HIPCHK(hipMemcpy(df.data(), p->b32.diagL, sizeof(float) * p->Rc, hipMemcpyDeviceToHost));
-    for (int i = 0; i < p->Rc; ++i) dg[i] = df[i];
+    std::vector<float> df(q.Rc);
+    HIPCHK(hipMemcpy(df.data(), q.b32.diagL, sizeof(float) * q.Rc, hipMemcpyDeviceToHost));
+    for (int i = 0; i < q.Rc; ++i) dg[i] = df[i];
   } else {
-    HIPCHK(hipMemcpy(dg.data(), p->b64.diagL, sizeof(double) * p->Rc, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(dg.data(), q.b64.diagL, sizeof(double) * q.Rc, hipMemcpyDeviceToHost));
   }
   double lo = INFINITY, hi = 0.0;
-  for (int i = 0; i < p->Rc; ++i) {
+  for (int i = 0; i < q.Rc; ++i) {
     const double v = fabs(dg[i]);
     if (v < lo) lo = v;
     if (v > hi) hi = v;
   }
   out->cond_est = (lo > 0.0 && h.sweeps > 0) ? (hi / lo) * (hi / lo) : -1.0;
+  out->fp64_path = h.path;
+  out->reserved = 0;
   return CPD_OK;
+}
+
+int get_factors_of(cpd_plan_s* p, int idx, double* const F_dev[4], double* lambda_dev) {
+  hipStream_t s = p->stream;
+  const Prob& q = p->P[idx];
+  for (int m = 0; m < 4; ++m) {
+    if (!F_dev || !F_dev[m]) continue;
+    const void* src = p->prec == CPD_FP32 ? (const void*)q.b32.F[m] : (const void*)q.b64.F[m];
+    int rc = copy_out(p, q, src, q.n[m], q.Rc, F_dev[m], s);
+    if (rc != CPD_OK) return rc;
+  }
+  if (lambda_dev) {
+    const void* src = p->prec == CPD_FP32 ? (const void*)q.b32.lam : (const void*)q.b64.lam;
+    int rc = copy_out(p, q, src, 1, q.Rc, lambda_dev, s);
+    if (rc != CPD_OK) return rc;
+  }
+  return CPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t cpd_batch_workspace_size(const cpd_desc* descs, int32_t count) {
+  cpd_plan_s tmp;
+  if (init_shape(&tmp, descs, count) != CPD_OK) return 0;
+  return layout_plan(&tmp, nullptr);
+}
+
+size_t cpd_workspace_size(const cpd_desc* d) { return cpd_batch_workspace_size(d, 1); }
+
+cpd_status cpd_init(const cpd_desc* d, cpd_plan* out) {
+  if (!d) return CPD_ERR_INVALID_ARG;
+  return plan_create(d, 1, d->workspace, d->workspace_bytes, out);
+}
+
+cpd_status cpd_batch_init(const cpd_desc* descs, int32_t count, void* workspace, size_t workspace_bytes,
+                          cpd_plan* out) {
+  return plan_create(descs, count, workspace, workspace_bytes, out);
+}
+
+cpd_status cpd_sweep(cpd_plan p, int32_t nsweeps, double* fits_host, int32_t* n_run) {
+  if (!p) return CPD_ERR_INVALID_ARG;
+  if (p->count == 1) return batch_sweep(p, nsweeps, fits_host, n_run);
+  std::vector<double> all(fits_host ? (size_t)p->count * (nsweeps > 0 ? nsweeps : 1) : 0);
+  int rc = batch_sweep(p, nsweeps, fits_host ? all.data() : nullptr, n_run);
+  if (fits_host)
+    for (int i = 0; i < nsweeps; ++i) fits_host[i] = all[i];
+  return rc;
+}
+
+cpd_status cpd_batch_sweep(cpd_plan p, int32_t nsweeps, double* fits_host, int32_t* n_run) {
+  if (!p) return CPD_ERR_INVALID_ARG;
+  return batch_sweep(p, nsweeps, fits_host, n_run);
+}
+
+cpd_status cpd_batch_states(cpd_plan p, double* fits_host, int32_t* converged_host, int32_t* sweeps_host) {
+  if (!p) return CPD_ERR_INVALID_ARG;
+  int rc = read_states(p);
+  if (rc != CPD_OK) return rc;
+  for (int i = 0; i < p->count; ++i) {
+    const DevState& h = p->host_states[i];
+    if (fits_host) fits_host[i] = h.sweeps > 0 ? h.fit_prev : -1.0;
+    if (converged_host) converged_host[i] = h.done;
+    if (sweeps_host) sweeps_host[i] = h.sweeps;
+  }
+  return batch_status(p);
+}
+
+int32_t cpd_batch_count(cpd_plan p) { return p ? p->count : 0; }
+
+cpd_status cpd_fit(cpd_plan p, double* fit_host) {
+  if (!p || !fit_host) return CPD_ERR_INVALID_ARG;
+  int rc = read_states(p);
+  if (rc != CPD_OK) return rc;
+  *fit_host = p->host_states[0].sweeps > 0 ? p->host_states[0].fit_prev : -1.0;
+  return status_from_flags(p->host_states[0].flags);
+}
+
+cpd_status cpd_get_factors(cpd_plan p, double* const F_dev[4], double* lambda_dev) {
+  if (!p) return CPD_ERR_INVALID_ARG;
+  return get_factors_of(p, 0, F_dev, lambda_dev);
+}
+
+cpd_status cpd_batch_get_factors(cpd_plan p, int32_t idx, double* const F_dev[4], double* lambda_dev) {
+  if (!p || idx < 0 || idx >= p->count) return CPD_ERR_INVALID_ARG;
+  return get_factors_of(p, idx, F_dev, lambda_dev);
+}
+
+cpd_status cpd_set_factors(cpd_plan p, const double* const F_dev[4], const double* lambda_dev, double prev_fit,
+                           int32_t sweeps) {
+  if (!p || !F_dev || sweeps < 0 || p->count != 1) return CPD_ERR_INVALID_ARG;
+  for (int m = 0; m < 4; ++m)
+    if (!F_dev[m]) return CPD_ERR_INVALID_ARG;
+  hipStream_t s = p->stream;
+  Prob& q = p->P[0];
+  for (int m = 0; m < 4; ++m) {
+    void* dst = p->prec == CPD_FP32 ? (void*)q.b32.F[m] : (void*)q.b64.F[m];
+    int rc = copy_in(p, q, F_dev[m], q.n[m], q.Rc, dst, s);
+    if (rc != CPD_OK) return rc;
+  }
+  if (lambda_dev) {
+    void* dst = p->prec == CPD_FP32 ? (void*)q.b32.lam : (void*)q.b64.lam;
+    int rc = copy_in(p, q, lambda_dev, 1, q.Rc, dst, s);
+    if (rc != CPD_OK) return rc;
+  }
+  hipLaunchKernelGGL(state_set_kernel, dim3(1), dim3(64), 0, s, q.st, prev_fit, (int)sweeps);
+  HIPCHK(hipGetLastError());
+  int rc = refresh_all(p, s);
+  if (rc != CPD_OK) return rc;
+  p->launched = sweeps;
+  return CPD_OK;
+}
+
+cpd_status cpd_stats(cpd_plan p, cpd_stats_t* out) {
+  if (!p || !out) return CPD_ERR_INVALID_ARG;
+  return stats_of(p, 0, out);
+}
+
+cpd_status cpd_batch_stats(cpd_plan p, int32_t idx, cpd_stats_t* out) {
+  if (!p || !out || idx < 0 || idx >= p->count) return CPD_ERR_INVALID_ARG;
+  return stats_of(p, idx, out);
 }
 
 cpd_status cpd_mttkrp(cpd_plan p, int32_t mode, double* M_dev) {
   if (!p || mode < 0 || mode > 3 || !M_dev) return CPD_ERR_INVALID_ARG;
   hipStream_t s = p->stream;
+  const int core = mode < 2 ? 0 : 2;
+  Prob& q = p->P[0];
   if (p->prec == CPD_FP64) {
-    mttkrp_into<double>(p, p->b64, mode, true, p->b64.Msol, nullptr, s, nullptr);
-    return copy_out(p, p->b64.Msol, p->n[mode], p->Rc, M_dev, s);
+    run_gemm<double>(p, s, p->core[core]);
+    run_gemm<double>(p, s, p->back[mode]);
+    return copy_out(p, q, q.b64.Msol, q.n[mode], q.Rc, M_dev, s);
   } else if (p->prec == CPD_FP32) {
-    mttkrp_into<float>(p, p->b32, mode, true, p->b32.Msol, nullptr, s, nullptr);
-    return copy_out(p, p->b32.Msol, p->n[mode], p->Rc, M_dev, s);
+    run_gemm<float>(p, s, p->core[core]);
+    run_gemm<float>(p, s, p->back[mode]);
+    return copy_out(p, q, q.b32.Msol, q.n[mode], q.Rc, M_dev, s);
   }
-  mixed_mttkrp(s, p->mx, mode, true, p->n, p->Rt, p->Rc, p->Tp, p->b64.Msol, nullptr, nullptr);
-  return copy_out(p, p->b64.Msol, p->n[mode], p->Rc, M_dev, s);
-}
-
-cpd_status cpd_destroy(cpd_plan p) {
-  if (!p) return CPD_ERR_INVALID_ARG;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      if (p->exec[a][b]) (void)hipGraphExecDestroy(p->exec[a][b]);
-      if (p->graph[a][b]) (void)hipGraphDestroy(p->graph[a][b]);
-    }
-  if (p->cap) (void)hipStreamDestroy(p->cap);
-  if (p->host_state) (void)hipHostFree(p->host_state);
-  delete p;
-  return CPD_OK;
+  run_split(p, s, p->score[core]);
+  run_split(p, s, p->sback[mode]);
+  return copy_out(p, q, q.b64.Msol, q.n[mode], q.Rc, M_dev, s);
 }
 
 cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out) {
   if (!p || reps <= 0 || !ms_out) return CPD_ERR_INVALID_ARG;
   hipStream_t s = p->stream;
-  hipLaunchKernelGGL(state_set_kernel, dim3(1), dim3(64), 0, s, p->st, -1.0, 0);
+  for (auto& q : p->P) hipLaunchKernelGGL(state_set_kernel, dim3(1), dim3(64), 0, s, q.st, -1.0, 0);
   HIPCHK(hipGetLastError());
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  const int Rt = p->Rt, Rc = p->Rc, Tp = p->Tp, n0 = p->n[0];
   const bool f32 = p->prec == CPD_FP32;
   for (int which = 0; which < 7; ++which) {
     auto body = [&]() {
-      if (which == 4 || which == 5 || which == 6) {
+      if (which >= 4) {
         // normal-equation solve of mode 0: V, factorisation fused with the
         // forward solve, backward solve, normalisation
         if (f32) {
-          Bufs<float>& b = p->b32;
-          if (which != 6) form_normal_matrix<float>(s, b.V, Tp, Rc, b.G[1], b.G[2], b.G[3], p->st, 0);
-          if (which != 6) chol_factor_fwd<float>(s, b.V, p->nblk, b.linv, b.diagL, b.Msol, n0, p->st);
-          if (which != 5) chol_solve_bwd<float>(s, b.V, p->nblk, b.linv, b.Msol, n0, p->st);
-          if (which == 4) normalise_columns<float>(s, b.Msol, n0, Rc, Tp, b.F[0], b.lam, nullptr, nullptr, p->st);
+          if (which != 6) form_v_group<float>(s, (const FormVArgs<float>*)p->formv[0], p->count, p->maxTp, 0);
+          if (which != 6) run_steps<float>(p, s, 0, STEP_CHOL_FWD, 0);
+          if (which != 5) run_steps<float>(p, s, 0, STEP_BWD, 0);
+          if (which == 4) normalise_group<float>(s, (const NormArgs<float>*)p->norm[0], p->count, p->maxR);
         } else {
-          Bufs<double>& b = p->b64;
-          if (which != 6) form_normal_matrix<double>(s, b.V, Tp, Rc, b.G[1], b.G[2], b.G[3], p->st, 0);
-          if (which != 6) chol_factor_fwd<double>(s, b.V, p->nblk, b.linv, b.diagL, b.Msol, n0, p->st);
-          if (which != 5) chol_solve_bwd<double>(s, b.V, p->nblk, b.linv, b.Msol, n0, p->st);
-          if (which == 4) normalise_columns<double>(s, b.Msol, n0, Rc, Tp, b.F[0], b.lam, nullptr, nullptr, p->st);
+          if (which != 6) form_v_group<double>(s, (const FormVArgs<double>*)p->formv[0], p->count, p->maxTp, 0);
+          if (which != 6) run_steps<double>(p, s, 0, STEP_CHOL_FWD, 0);
+          if (which != 5) run_steps<double>(p, s, 0, STEP_BWD, 0);
+          if (which == 4) normalise_group<double>(s, (const NormArgs<double>*)p->norm[0], p->count, p->maxR);
         }
         return;
       }
       if (p->prec == CPD_MIXED_BF16) {
-        Bufs<double>& b = p->b64;
-        if (which == 0) mixed_refresh(s, p->mx, 0, b.F[0], p->n, Rt, Rc, Tp, nullptr);
-        else if (which == 1 || which == 2) {
-          // core product only (which == 1), or back-projection only (2)
-          if (which == 1) mixed_mttkrp(s, p->mx, 0, true, p->n, Rt, Rc, Tp, b.Msol, nullptr, nullptr);
-          else mixed_mttkrp(s, p->mx, 0, false, p->n, Rt, Rc, Tp, b.Msol, nullptr, nullptr);
-        } else {
-          gemm_t<double>(s, Rc, Rc, n0, b.F[0], Tp, true, b.F[0], nullptr, Tp, b.G[0], Tp, nullptr, nullptr);
-        }
-      } else if (p->prec == CPD_FP64) {
-        Bufs<double>& b = p->b64;
-        if (which == 0) gemm_t<double>(s, Rt, Rc, n0, b.X[0], Rt, true, b.F[0], nullptr, Tp, b.W[0], Tp, nullptr, nullptr);
-        else if (which == 1) gemm_t<double>(s, Rt, Rc, Rt, b.Z, Rt, false, b.W[2], b.W[3], Tp, b.Y, Tp, nullptr, nullptr);
-        else if (which == 2) gemm_t<double>(s, n0, Rc, Rt, b.X[0], Rt, false, b.W[1], b.Y, Tp, b.Msol, Tp, nullptr, nullptr);
-        else gemm_t<double>(s, Rc, Rc, n0, b.F[0], Tp, true, b.F[0], nullptr, Tp, b.G[0], Tp, nullptr, nullptr);
+        if (which == 0) mixed_refresh_mode(p, s, 0);
+        else if (which == 1) run_split(p, s, p->score[0]);
+        else if (which == 2) run_split(p, s, p->sback[0]);
+        else run_gemm<double>(p, s, p->gram[0]);
       } else {
-        Bufs<float>& b = p->b32;
-        if (which == 0) gemm_t<float>(s, Rt, Rc, n0, b.X[0], Rt, true, b.F[0], nullptr, Tp, b.W[0], Tp, nullptr, nullptr);
-        else if (which == 1) gemm_t<float>(s, Rt, Rc, Rt, b.Z, Rt, false, b.W[2], b.W[3], Tp, b.Y, Tp, nullptr, nullptr);
-        else if (which == 2) gemm_t<float>(s, n0, Rc, Rt, b.X[0], Rt, false, b.W[1], b.Y, Tp, b.Msol, Tp, nullptr, nullptr);
-        else gemm_t<float>(s, Rc, Rc, n0, b.F[0], Tp, true, b.F[0], nullptr, Tp, b.G[0], Tp, nullptr, nullptr);
+        const GroupOp& op = which == 0 ? p->proj[0] : which == 1 ? p->core[0] : which == 2 ? p->back[0] : p->gram[0];
+        if (f32) run_gemm<float>(p, s, op);
+        else run_gemm<double>(p, s, op);
       }
     };
     body();  // warm-up
@@ -763,6 +1273,38 @@ cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  return CPD_OK;
+}
+
+int32_t cpd_autotune_log(cpd_plan p, char* buf, int32_t len) {
+  if (!p) return -1;
+  std::string out;
+  for (auto& kv : p->tune_log) out += kv.first + "=" + std::to_string(kv.second) + "\n";
+  if (buf && len > 0) {
+    const size_t n = out.size() < (size_t)(len - 1) ? out.size() : (size_t)(len - 1);
+    memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  return (int32_t)out.size();
+}
+
+cpd_status cpd_lt_scale_rows(const double* X, const double* eps, int32_t n, int32_t r, double t, double sign,
+                             double* out, void* stream) {
+  if (!X || !eps || !out || n <= 0 || r <= 0) return CPD_ERR_INVALID_ARG;
+  lt_scale_rows((hipStream_t)stream, X, eps, n, r, t, sign, out);
+  return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
+}
+
+cpd_status cpd_destroy(cpd_plan p) {
+  if (!p) return CPD_ERR_INVALID_ARG;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      if (p->exec[a][b]) (void)hipGraphExecDestroy(p->exec[a][b]);
+      if (p->graph[a][b]) (void)hipGraphDestroy(p->graph[a][b]);
+    }
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->host_states) (void)hipHostFree(p->host_states);
+  delete p;
   return CPD_OK;
 }
 

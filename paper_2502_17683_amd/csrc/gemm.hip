@@ -13,18 +13,8 @@
 
 namespace thccp {
 
-template <typename T>
-struct GemmArgs {
-  int M, N, K;
-  const T* A; int lda;
-  const T* B1; const T* B2; int ldb;
-  T* C; int ldc; T* C2;
-  T alpha, beta;
-  const int32_t* done;
-};
-
 template <typename T, int BM, int BN, bool AT, bool BT, bool HAD>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> p) {
+__device__ __forceinline__ void gemm_body(const GemmArgs<T>& p, int bid_in, int nblocks) {
   constexpr int BK = 16;
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int TI = WTM / 16, TJ = WTN / 16;
@@ -35,8 +25,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> p) {
   __shared__ T Bs[BK][BN + PAD];
 
   if (p.done && *p.done) return;
+  if (p.gate && *p.gate != p.want) return;
   const int tiles_n = (p.N + BN - 1) / BN;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int bid = xcd_remap(bid_in, nblocks);
   const int m0 = (bid / tiles_n) * BM, n0 = (bid % tiles_n) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
@@ -136,6 +127,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> p) {
       }
 }
 
+template <typename T, int BM, int BN, bool AT, bool BT, bool HAD>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> p) {
+  gemm_body<T, BM, BN, AT, BT, HAD>(p, blockIdx.x, gridDim.x);
+}
+
+// Grouped form: workgroup -> (problem, local tile) through the prefix sums.
+template <typename T, int BM, int BN, bool AT, bool BT, bool HAD>
+__global__ __launch_bounds__(256) void gemm_group_kernel(const GemmArgs<T>* tab, const int* offs, int nprob) {
+  int pid = 0;
+  while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
+  const GemmArgs<T> p = tab[pid];
+  gemm_body<T, BM, BN, AT, BT, HAD>(p, blockIdx.x - offs[pid], offs[pid + 1] - offs[pid]);
+}
+
 template <typename T, int BM, int BN>
 static void launch_tile(hipStream_t s, const GemmArgs<T>& a, bool at, bool bt, bool had) {
   const int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
@@ -154,25 +159,55 @@ static void launch_tile(hipStream_t s, const GemmArgs<T>& a, bool at, bool bt, b
 #undef THCCP_GEMM_CASE
 }
 
+int gemm_default_tile(int M, int N) {
+  // 128x128 tiles when there are enough of them to cover the 256 compute
+  // units, 64x64 otherwise.
+  const long t128 = (long)((M + 127) / 128) * ((N + 127) / 128);
+  return t128 >= 256 ? 128 : 64;
+}
+
 template <typename T>
 static void gemm_dispatch(hipStream_t s, const GemmArgs<T>& a, bool at, bool bt, bool had) {
   if (a.M <= 0 || a.N <= 0) return;
-  // 128x128 tiles when there are enough of them to cover the 256 compute
-  // units, 64x64 otherwise.
-  const long t128 = (long)((a.M + 127) / 128) * ((a.N + 127) / 128);
-  if (t128 >= 256) launch_tile<T, 128, 128>(s, a, at, bt, had);
+  if (gemm_default_tile(a.M, a.N) == 128) launch_tile<T, 128, 128>(s, a, at, bt, had);
   else launch_tile<T, 64, 64>(s, a, at, bt, had);
 }
 
+template <typename T, int BM>
+static void launch_group_tile(hipStream_t s, const GemmArgs<T>* tab, const int* offs, int nprob, int tiles,
+                              bool at, bool bt, bool had) {
+  dim3 grid(tiles), block(256);
+#define THCCP_GEMM_GCASE(AT_, BT_, HAD_)                                                              \
+  if (at == AT_ && bt == BT_ && had == HAD_) {                                                       \
+    hipLaunchKernelGGL((gemm_group_kernel<T, BM, BM, AT_, BT_, HAD_>), grid, block, 0, s, tab, offs, nprob); \
+    return;                                                                                          \
+  }
+  THCCP_GEMM_GCASE(false, false, false)
+  THCCP_GEMM_GCASE(true, false, false)
+  THCCP_GEMM_GCASE(false, false, true)
+  THCCP_GEMM_GCASE(true, false, true)
+#undef THCCP_GEMM_GCASE
+}
+
+template <typename T>
+void gemm_group(hipStream_t s, const GemmArgs<T>* tab, const int* offs, int nprob, int total_tiles, bool a_t,
+                bool b_t, bool had, int bm) {
+  if (total_tiles <= 0) return;
+  if (bm == 128) launch_group_tile<T, 128>(s, tab, offs, nprob, total_tiles, a_t, b_t, had);
+  else launch_group_tile<T, 64>(s, tab, offs, nprob, total_tiles, a_t, b_t, had);
+}
+template void gemm_group<double>(hipStream_t, const GemmArgs<double>*, const int*, int, int, bool, bool, bool, int);
+template void gemm_group<float>(hipStream_t, const GemmArgs<float>*, const int*, int, int, bool, bool, bool, int);
+
 void gemm_f64(hipStream_t s, const GemmF64& g) {
   GemmArgs<double> a{g.M, g.N, g.K, g.A, g.lda, g.B1, g.B2, g.ldb, g.C, g.ldc, g.C2,
-                     g.alpha, g.beta, g.done};
+                     g.alpha, g.beta, g.done, nullptr, 0};
   gemm_dispatch<double>(s, a, g.a_t, g.b_t, g.B2 != nullptr);
 }
 
 void gemm_f32(hipStream_t s, const GemmF32& g) {
   GemmArgs<float> a{g.M, g.N, g.K, g.A, g.lda, g.B1, g.B2, g.ldb, g.C, g.ldc, g.C2,
-                    g.alpha, g.beta, g.done};
+                    g.alpha, g.beta, g.done, nullptr, 0};
   gemm_dispatch<float>(s, a, g.a_t, g.b_t, g.B2 != nullptr);
 }
 

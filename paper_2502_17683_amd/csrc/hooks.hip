@@ -55,24 +55,39 @@ template <typename T>
 size_t solve_ws(int R, int n) {
   const int nblk = (R + 63) / 64, Tp = nblk * 64;
   return al(sizeof(DevState)) + al(sizeof(T) * (size_t)Tp * Tp) + al(sizeof(T) * (size_t)nblk * 4096) +
-         al(sizeof(T) * Tp) + al(sizeof(T) * (size_t)n * Tp);
+         al(sizeof(T) * Tp) + al(sizeof(T) * (size_t)n * Tp) + al(sizeof(StepProb<T>)) + al(sizeof(int) * 2);
 }
 
+// One-problem run of the grouped factorisation (STEP_CHOL), forward and
+// backward solves -- the launches of a sweep with the damped retry left out.
 template <typename T>
-cpd_status solve_impl(int R, int n, const T* V, const T* M, T* F, void* ws, hipStream_t s,
-                      int32_t* failed) {
+cpd_status solve_impl(int R, int n, const T* V, const T* M, T* F, void* ws, hipStream_t s, int32_t* failed) {
   const int nblk = (R + 63) / 64, Tp = nblk * 64;
   char* b = (char*)ws;
   DevState* st = (DevState*)b; b += al(sizeof(DevState));
   T* Vp = (T*)b; b += al(sizeof(T) * (size_t)Tp * Tp);
-  T* linv = (T*)b; b += al(sizeof(T) * (size_t)nblk * 4096);
+  T* ldiag = (T*)b; b += al(sizeof(T) * (size_t)nblk * 4096);
   T* diagL = (T*)b; b += al(sizeof(T) * Tp);
-  T* Mp = (T*)b;
+  T* Mp = (T*)b; b += al(sizeof(T) * (size_t)n * Tp);
+  StepProb<T>* prob = (StepProb<T>*)b; b += al(sizeof(StepProb<T>));
+  int* offs = (int*)b;
   hipLaunchKernelGGL(init_state, dim3(1), dim3(64), 0, s, st);
   hipLaunchKernelGGL((pad_square<T>), dim3(grid_of((size_t)Tp * Tp)), dim3(256), 0, s, V, R, Tp, Vp);
   hipLaunchKernelGGL((pad_rows<T>), dim3(grid_of((size_t)n * Tp)), dim3(256), 0, s, M, n, R, Tp, Mp);
-  chol_factor<T>(s, Vp, nblk, linv, diagL, st, 0);
-  chol_solve_rows<T>(s, Vp, nblk, linv, Mp, n, st);
+  StepProb<T> hp{Vp, ldiag, diagL, Mp, st, nblk, n};
+  if (hipMemcpyAsync(prob, &hp, sizeof(hp), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
+  const int modes[3] = {STEP_CHOL, STEP_FWD, STEP_BWD};
+  for (int mode : modes) {
+    const int first = step_first(mode), cnt = step_count(mode, nblk);
+    for (int k = 0; k < cnt; ++k) {
+      int ho[2] = {0, step_tiles(mode, nblk, n, first + k)};
+      // offsets are passed by value through a tiny per-launch upload (this
+      // hook is not performance-critical)
+      if (hipMemcpyAsync(offs, ho, sizeof(ho), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
+      if (hipStreamSynchronize(s) != hipSuccess) return CPD_ERR_HIP;
+      step_group<T>(s, mode, prob, offs, 1, ho[1], first + k, 0);
+    }
+  }
   hipLaunchKernelGGL((unpad_rows<T>), dim3(grid_of((size_t)n * R)), dim3(256), 0, s, Mp, n, R, Tp, F);
   DevState h;
   if (hipMemcpyAsync(&h, st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess) return CPD_ERR_HIP;
@@ -119,7 +134,8 @@ cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, con
 size_t cpd_test_split_workspace(int32_t M, int32_t N, int32_t K) {
   if (M <= 0 || N <= 0 || K <= 0) return 0;
   const size_t Kp = (K + 31) / 32 * 32;
-  return 4 * al(2 * (size_t)M * Kp) + 4 * al(2 * (size_t)N * Kp) + 2 * al(4 * (size_t)M * Kp);
+  return 4 * al(2 * (size_t)M * Kp) + 4 * al(2 * (size_t)N * Kp) + 2 * al(4 * (size_t)M * Kp) +
+         al(sizeof(SplitArgs)) + al(2 * sizeof(int));
 }
 
 // C (M x N, dense) = A B^T with A (M x K), B (N x K) dense FP64; when A2 is
@@ -139,7 +155,9 @@ cpd_status cpd_test_gemm_split(int32_t M, int32_t N, int32_t K, const double* A,
   __bf16* Bl = (__bf16*)b; b += al(2 * (size_t)N * Kp);
   b += 2 * al(2 * (size_t)N * Kp);
   float* Ap = (float*)b; b += al(4 * (size_t)M * Kp);
-  float* Aq = (float*)b;
+  float* Aq = (float*)b; b += al(4 * (size_t)M * Kp);
+  SplitArgs* tab = (SplitArgs*)b; b += al(sizeof(SplitArgs));
+  int* offs = (int*)b;
   split_rows_f64(s, B, N, K, K, Bh, Bl, Kp, Kp);
   SplitOperand opB{Bh, Bl, nullptr, nullptr, Kp};
   SplitOperand opA;
@@ -151,7 +169,12 @@ cpd_status cpd_test_gemm_split(int32_t M, int32_t N, int32_t K, const double* A,
     split_rows_f64(s, A, M, K, K, Ah, Al, Kp, Kp);
     opA = SplitOperand{Ah, Al, nullptr, nullptr, Kp};
   }
-  gemm_split_launch(s, M, N, Kp, opA, opB, nullptr, C, nullptr, N, nullptr);
+  const SplitArgs ha{M, N, Kp, opA, opB, nullptr, C, nullptr, N, nullptr, nullptr, 0};
+  const int ho[2] = {0, split_tile_count(M, N)};
+  if (hipMemcpyAsync(tab, &ha, sizeof(ha), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
+  if (hipMemcpyAsync(offs, ho, sizeof(ho), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return CPD_ERR_HIP;  // host copies of ha/ho go out of scope
+  gemm_split_group(s, tab, offs, 1, ho[1], opA.p != nullptr, false);
   return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
 }
 

@@ -1,5 +1,10 @@
 // Internal launchers shared by the translation units of libthccp.so.
 // Not part of the public C-ABI (include/thccp.h).
+//
+// Every kernel of the sweep is "grouped": one launch serves a table of
+// independent problems (the CPDs of a batch; a single CPD is a group of
+// one).  Argument tables live in device memory (the plan's workspace);
+// `offs` tables hold the prefix sums of each problem's workgroup count.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -9,14 +14,27 @@
 
 namespace thccp {
 
-// ---------------------------------------------------------------- GEMM (FP64)
+// ---------------------------------------------------------------- GEMM
 // C[M x N] = alpha * op(A)[M x K] * op(B)[K x N] + beta * C, row-major C.
 //   a_t = false: A[i*lda + k];  a_t = true: A[k*lda + i]   (A stored K x M)
 //   b_t = false: B[k*ldb + j];  b_t = true: B[j*ldb + k]   (B stored N x K)
 //   B2 != nullptr: every B element is B1[.] * B2[.] (Hadamard product fused
 //   into the operand load; same layout and leading dimension).
 //   C2 != nullptr: the result is also written to C2 (same ldc).
-//   done != nullptr: the launch is a no-op once *done is set.
+//   done != nullptr: the problem is skipped once *done is set.
+//   gate != nullptr: the problem is skipped unless *gate == want (per-problem
+//   choice between the split-BF16 and the FP64 path).
+template <typename T>
+struct GemmArgs {
+  int M, N, K;
+  const T* A; int lda;
+  const T* B1; const T* B2; int ldb;
+  T* C; int ldc; T* C2;
+  T alpha, beta;
+  const int32_t* done;
+  const int32_t* gate = nullptr;
+  int32_t want = 0;
+};
 struct GemmF64 {
   int M, N, K;
   const double* A; int lda; bool a_t;
@@ -25,9 +43,6 @@ struct GemmF64 {
   double alpha, beta;
   const int32_t* done;
 };
-void gemm_f64(hipStream_t s, const GemmF64& g);
-
-// ---------------------------------------------------------------- GEMM (FP32)
 struct GemmF32 {
   int M, N, K;
   const float* A; int lda; bool a_t;
@@ -36,52 +51,103 @@ struct GemmF32 {
   float alpha, beta;
   const int32_t* done;
 };
+void gemm_f64(hipStream_t s, const GemmF64& g);
 void gemm_f32(hipStream_t s, const GemmF32& g);
-
-// ------------------------------------------------------ split-BF16 GEMM (mixed)
-// Operands are pre-split pairs hi = bf16(x), lo = bf16(x - hi) stored in
-// MFMA-ready k-packed layouts; see mixed.hip.
-struct GemmSplit;
-void gemm_split(hipStream_t s, const GemmSplit& g);
+// Tile edge the heuristic picks (128 when the 128-tiles cover the chip).
+int gemm_default_tile(int M, int N);
+inline int gemm_tile_count(int M, int N, int bm) { return ((M + bm - 1) / bm) * ((N + bm - 1) / bm); }
+// Grouped launch: tab[nprob] problems with identical (a_t, b_t, Hadamard)
+// flags, tile edge bm (64 or 128), offs[nprob + 1] prefix sums of
+// gemm_tile_count(M_p, N_p, bm).
+template <typename T>
+void gemm_group(hipStream_t s, const GemmArgs<T>* tab, const int* offs, int nprob, int total_tiles, bool a_t,
+                bool b_t, bool had, int bm);
 
 // -------------------------------------------------- Cholesky / triangular solve
-// V: Tp x Tp row-major (Tp = 64 * nblk), lower triangle factorised in place
-// (off-diagonal blocks); the diagonal blocks of L go to ldiag (nblk blocks
-// of 64 x 64, row-major), the diagonal of L to diagL (Tp).
+// One problem of the blocked factorisation and row solves.  V: Tp x Tp
+// row-major (Tp = 64 nblk); the diagonal blocks of L go to ldiag (nblk
+// 64 x 64 blocks), the diagonal of L to diagL; M: n x Tp right-hand sides.
 template <typename T>
-void chol_factor(hipStream_t s, T* V, int nblk, T* ldiag, T* diagL, DevState* st, int retry_pass);
-// Solve F V = M in place (M: n x Tp, ld Tp) given the factor above.
+struct StepProb {
+  T* V;
+  T* ldiag;
+  T* diagL;
+  T* M;
+  DevState* st;
+  int nblk;
+  int n;
+};
+enum StepMode { STEP_CHOL = 0, STEP_FWD = 1, STEP_BWD = 2, STEP_CHOL_FWD = 3 };
+// Workgroups of problem (nblk, n) at launch `step` of the given mode
+// (CHOL, FWD: step = j in -1 .. nblk-2; CHOL_FWD: t in -1 .. nblk-1;
+// BWD: s in 0 .. nblk-1 standing for j = nblk - s).
+int step_tiles(int mode, int nblk, int n, int step);
+// First step index of a mode and the number of launches for the largest
+// problem of a group.
+int step_first(int mode);
+int step_count(int mode, int max_nblk);
 template <typename T>
-void chol_solve_rows(hipStream_t s, const T* V, int nblk, const T* ldiag, T* M, int n, DevState* st);
-// Backward half of the solve only (F L = G, in place).
-template <typename T>
-void chol_solve_bwd(hipStream_t s, const T* V, int nblk, const T* ldiag, T* M, int n, DevState* st);
-// Factorisation fused with the forward half of the solve (G L^T = M, in
-// place), no damped retry: a failed pivot leaves st->chol_fail set.
-template <typename T>
-void chol_factor_fwd(hipStream_t s, T* V, int nblk, T* ldiag, T* diagL, T* M, int n, DevState* st);
+void step_group(hipStream_t s, int mode, const StepProb<T>* probs, const int* offs, int nprob, int total_tiles,
+                int step, int retry_pass);
 
 // ------------------------------------------------------------- element-wise
 template <typename T>
-void form_normal_matrix(hipStream_t s, T* V, int Tp, int R, const T* g0, const T* g1,
-                        const T* g2, DevState* st, int retry_pass);
+struct FormVArgs {
+  T* V; const T* g0; const T* g1; const T* g2; DevState* st; int Tp; int R;
+};
 template <typename T>
-void retry_prepare_launch(hipStream_t s, DevState* st, int allow_fallback, const T* g0, const T* g1,
-                          const T* g2, int R, int Tp);
+void form_v_group(hipStream_t s, const FormVArgs<T>* tab, int nprob, int max_Tp, int retry_pass);
 template <typename T>
-void normalise_columns(hipStream_t s, const T* Msol, int n, int R, int ld, T* F, T* lam,
-                       const T* Msave, double* inner_part, DevState* st);
+void retry_prepare_group(hipStream_t s, const FormVArgs<T>* tab, int nprob, int allow_fallback);
+
 template <typename T>
-void fit_update(hipStream_t s, const T* const g[4], const T* lam, int R, int ld,
-                const double* inner_part, double* scratch, double* fit_hist, int hist_cap,
-                double tol, double fit_floor, DevState* st);
+struct NormArgs {
+  const T* Msol; T* F; T* lam; const T* Msave; double* inner_part; DevState* st; int n; int R; int ld;
+};
+template <typename T>
+void normalise_group(hipStream_t s, const NormArgs<T>* tab, int nprob, int max_R);
+
+template <typename T>
+struct FitArgs {
+  const T* g[4]; const T* lam; const double* inner_part; double* row_part; double* fit_hist; DevState* st;
+  int R; int ld;
+};
+template <typename T>
+void fit_group(hipStream_t s, const FitArgs<T>* tab, int nprob, int max_R, int hist_cap, double tol,
+               double fit_floor, int guard, double cond_limit);
+// Non-fit sweep of a split-BF16 plan: sweep counter and precision guard.
+void sweep_tick_group(hipStream_t s, DevState* const* st_tab, int nprob, int guard, double cond_limit);
+// Precision guard bookkeeping (split-BF16 plans):
+//   cond_track: st->cond_max = max(st->cond_max, (max diagL / min diagL)^2)
+//   after each mode's factorisation; guard_begin: reset at sweep start.
+template <typename T>
+struct CondArgs {
+  const T* diagL; DevState* st; int R;
+};
+template <typename T>
+void cond_track_group(hipStream_t s, const CondArgs<T>* tab, int nprob);
+void guard_begin_group(hipStream_t s, DevState* const* st_tab, int nprob);
+// Sets path = 1 (FP64) and clears promote for the listed problems.
+void set_path_group(hipStream_t s, DevState* const* st_tab, int nprob, const int32_t* flags_dev);
+
+// Factor checkpoint: copies (dir = 0) F -> Fsave and st -> st_save, or back.
+struct CkptArgs {
+  void* a[4];
+  void* b[4];
+  size_t bytes[4];
+  DevState* st;
+  DevState* st_save;
+};
+void checkpoint_group(hipStream_t s, const CkptArgs* tab, int nprob, int dir);
+
 void hadamard_inplace_f64(hipStream_t s, double* A, const double* B, size_t count);
-void transposed_dot_f64(hipStream_t s, const double* P, const double* Q, int R, int ld,
-                        double* partials, double* out);
+void transposed_dot_f64(hipStream_t s, const double* P, const double* Q, int R, int ld, double* partials,
+                        double* out);
 void fill_bytes(hipStream_t s, void* p, size_t bytes);
 void state_reset(hipStream_t s, DevState* st, double* norm2_src);
 void cast_f64_to_f32(hipStream_t s, const double* a, float* b, size_t count);
-void cast_f32_to_f64(hipStream_t s, const float* a, double* b, size_t count);
 void copy_normalised_init(hipStream_t s, const double* src, int n, int R, int ld, double* dst);
+void lt_scale_rows(hipStream_t s, const double* X, const double* eps, int n, int r, double t, double sign,
+                   double* out);
 
 }  // namespace thccp

@@ -13,6 +13,7 @@
 
 namespace thccp {
 
+// Split-BF16 operand buffers of one problem.
 struct MixedBufs {
   int Rtp;             // R_thc rounded up to 32 (contraction length of Z and X products)
   int npad[4];         // n_m rounded up to 32
@@ -26,30 +27,44 @@ struct MixedBufs {
   __bf16 *FTh, *FTl;        // R_cp x npad_max (current factor, transposed, split)
 };
 
-// Workspace carving (base == nullptr: sizing only).  `off` is advanced.
-void mixed_carve(char* base, size_t* off, MixedBufs& mx, const int n[4], int Rt, int Rc,
-                 const double* const X[4]);
-// One-time split of X, X^T, Z, Z^T.
-void mixed_setup_inputs(hipStream_t s, MixedBufs& mx, const double* const X[4], const double* Z,
-                        const int n[4], int Rt);
-// W_m^T = (split F_m)^T-product with X_m, from the FP64 factor F (n_m x Tp).
-void mixed_refresh(hipStream_t s, MixedBufs& mx, int m, const double* F, const int n[4], int Rt, int Rc,
-                   int Tp, const int32_t* done);
-// Mode-n MTTKRP: (optionally) the core product, then the back-projection
-// written in FP64 to out (n_n x Tp) and out2 (if non-null).
-void mixed_mttkrp(hipStream_t s, MixedBufs& mx, int n, bool fresh_core, const int nd[4], int Rt, int Rc,
-                  int Tp, double* out, double* out2, const int32_t* done);
-
-// Raw launcher, exposed for the GEMM unit test entry point.
+// One operand: a pre-split (hi, lo) pair, or a pair of FP32 matrices whose
+// element-wise product is split on the fly.  K-contiguous, row stride ld.
 struct SplitOperand {
-  const __bf16* hi;  // pre-split pair, or
+  const __bf16* hi;
   const __bf16* lo;
-  const float* p;    // FP32 pair whose element-wise product is split on the fly
+  const float* p;
   const float* q;
   int ld;
 };
-void gemm_split_launch(hipStream_t s, int M, int N, int K, const SplitOperand& A, const SplitOperand& B,
-                       float* C32, double* C64, double* C64b, int ldc, const int32_t* done);
+// C[M x N] = A[M x K] B[N x K]^T (K a multiple of 32), output FP32 (C32)
+// and/or FP64 (C64, C64b), row stride ldc.
+struct SplitArgs {
+  int M, N, K;
+  SplitOperand A, B;
+  float* C32;
+  double* C64;
+  double* C64b;
+  int ldc;
+  const int32_t* done;
+  const int32_t* gate;  // skip unless *gate == want (per-problem precision path)
+  int32_t want;
+};
+int split_tile_count(int M, int N);
+// Grouped launch: all problems share (A pair?, B pair?).
+void gemm_split_group(hipStream_t s, const SplitArgs* tab, const int* offs, int nprob, int total_tiles,
+                      bool apair, bool bpair);
+
+// dst (cols x ldd) = split(src^T): dst[c][r] for c < cols, r < dcols
+// (r >= rows written as 0).
+struct SplitTArgs {
+  const double* src;
+  __bf16* hi;
+  __bf16* lo;
+  const int32_t* done;
+  const int32_t* gate;
+  int rows, cols, lds, ldd, dcols;
+};
+void split_transpose_group(hipStream_t s, const SplitTArgs* tab, int nprob, int max_cols, int max_dcols);
 void split_rows_f64(hipStream_t s, const double* src, int rows, int cols, int lds, __bf16* hi, __bf16* lo,
                     int ldd, int dcols);
 void split_transpose_f64(hipStream_t s, const double* src, int rows, int cols, int lds, __bf16* hi,

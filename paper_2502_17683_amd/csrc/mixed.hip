@@ -37,15 +37,6 @@ union Pack8 {
 };
 }  // namespace
 
-struct SplitArgs {
-  int M, N, K;
-  SplitOperand A, B;
-  float* C32;
-  double* C64;
-  double* C64b;
-  int ldc;
-  const int32_t* done;
-};
 
 template <bool PAIR>
 __device__ __forceinline__ void load_operand(const SplitOperand& op, int rows, int r0, int k0, int tid,
@@ -81,14 +72,18 @@ __device__ __forceinline__ void load_operand(const SplitOperand& op, int rows, i
 }
 
 template <bool APAIR, bool BPAIR>
-__global__ __launch_bounds__(256) void gemm_split_kernel(SplitArgs a) {
+__global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, const int* offs, int nprob) {
   __shared__ __attribute__((aligned(16))) __bf16 Ah[SBM * SLDK];
   __shared__ __attribute__((aligned(16))) __bf16 Al[SBM * SLDK];
   __shared__ __attribute__((aligned(16))) __bf16 Bh[SBN * SLDK];
   __shared__ __attribute__((aligned(16))) __bf16 Bl[SBN * SLDK];
+  int pid = 0;
+  while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
+  const SplitArgs a = tab[pid];
   if (a.done && *a.done) return;
+  if (a.gate && *a.gate != a.want) return;
   const int tiles_n = (a.N + SBN - 1) / SBN;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int bid = xcd_remap(blockIdx.x - offs[pid], offs[pid + 1] - offs[pid]);
   const int m0 = (bid / tiles_n) * SBM, n0 = (bid % tiles_n) * SBN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
@@ -168,16 +163,16 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(SplitArgs a) {
       }
 }
 
-void gemm_split_launch(hipStream_t s, int M, int N, int K, const SplitOperand& A, const SplitOperand& B,
-                       float* C32, double* C64, double* C64b, int ldc, const int32_t* done) {
-  if (M <= 0 || N <= 0 || K <= 0) return;
-  SplitArgs a{M, N, K, A, B, C32, C64, C64b, ldc, done};
-  const int tiles = ((M + SBM - 1) / SBM) * ((N + SBN - 1) / SBN);
-  const bool ap = A.p != nullptr, bp = B.p != nullptr;
-  if (!ap && !bp) hipLaunchKernelGGL((gemm_split_kernel<false, false>), dim3(tiles), dim3(256), 0, s, a);
-  else if (ap && !bp) hipLaunchKernelGGL((gemm_split_kernel<true, false>), dim3(tiles), dim3(256), 0, s, a);
-  else if (!ap && bp) hipLaunchKernelGGL((gemm_split_kernel<false, true>), dim3(tiles), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((gemm_split_kernel<true, true>), dim3(tiles), dim3(256), 0, s, a);
+int split_tile_count(int M, int N) { return ((M + SBM - 1) / SBM) * ((N + SBN - 1) / SBN); }
+
+void gemm_split_group(hipStream_t s, const SplitArgs* tab, const int* offs, int nprob, int total_tiles,
+                      bool apair, bool bpair) {
+  if (total_tiles <= 0) return;
+  dim3 grid(total_tiles), block(256);
+  if (!apair && !bpair) hipLaunchKernelGGL((gemm_split_kernel<false, false>), grid, block, 0, s, tab, offs, nprob);
+  else if (apair && !bpair) hipLaunchKernelGGL((gemm_split_kernel<true, false>), grid, block, 0, s, tab, offs, nprob);
+  else if (!apair && bpair) hipLaunchKernelGGL((gemm_split_kernel<false, true>), grid, block, 0, s, tab, offs, nprob);
+  else hipLaunchKernelGGL((gemm_split_kernel<true, true>), grid, block, 0, s, tab, offs, nprob);
 }
 
 // ------------------------------------------------------------- splitting
@@ -195,10 +190,9 @@ __global__ void split_rows_kernel(const double* src, int rows, int cols, int lds
 }
 
 // dst[c][r] = split(src[r][c]); r < dcols (r >= rows written as 0), c < cols.
-__global__ __launch_bounds__(256) void split_transpose_kernel(const double* src, int rows, int cols, int lds,
-                                                              __bf16* hi, __bf16* lo, int ldd, int dcols) {
+__device__ __forceinline__ void split_transpose_tile(const double* src, int rows, int cols, int lds, __bf16* hi,
+                                                     __bf16* lo, int ldd, int dcols, int tr, int tc) {
   __shared__ double t[64][65];
-  const int tr = blockIdx.y * 64, tc = blockIdx.x * 64;  // tile origin in src (rows, cols)
   const int tid = threadIdx.x;
   for (int e = tid; e < 64 * 64; e += 256) {
     const int r = e >> 6, c = e & 63;
@@ -217,6 +211,23 @@ __global__ __launch_bounds__(256) void split_transpose_kernel(const double* src,
     }
   }
 }
+__global__ __launch_bounds__(256) void split_transpose_kernel(const double* src, int rows, int cols, int lds,
+                                                              __bf16* hi, __bf16* lo, int ldd, int dcols) {
+  split_transpose_tile(src, rows, cols, lds, hi, lo, ldd, dcols, blockIdx.y * 64, blockIdx.x * 64);
+}
+// Grouped: blockIdx.z selects the problem; tiles beyond a problem's extent exit.
+__global__ __launch_bounds__(256) void split_transpose_group_kernel(const SplitTArgs* tab) {
+  const SplitTArgs a = tab[blockIdx.z];
+  if (a.done && *a.done) return;
+  if (a.gate && *a.gate != 0) return;
+  const int tr = blockIdx.y * 64, tc = blockIdx.x * 64;
+  if (tr >= a.dcols || tc >= a.cols) return;
+  split_transpose_tile(a.src, a.rows, a.cols, a.lds, a.hi, a.lo, a.ldd, a.dcols, tr, tc);
+}
+void split_transpose_group(hipStream_t s, const SplitTArgs* tab, int nprob, int max_cols, int max_dcols) {
+  dim3 grid((max_cols + 63) / 64, (max_dcols + 63) / 64, nprob);
+  hipLaunchKernelGGL(split_transpose_group_kernel, grid, dim3(256), 0, s, tab);
+}
 
 void split_rows_f64(hipStream_t s, const double* src, int rows, int cols, int lds, __bf16* hi, __bf16* lo,
                     int ldd, int dcols) {
@@ -233,83 +244,6 @@ void split_transpose_f64(hipStream_t s, const double* src, int rows, int cols, i
   dim3 grid((cols + 63) / 64, (dcols + 63) / 64);
   hipLaunchKernelGGL(split_transpose_kernel, grid, dim3(256), 0, s, src, rows, cols, lds, hi, lo, ldd,
                      dcols);
-}
-
-// ------------------------------------------------------------ plan hooks
-static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-void mixed_carve(char* base, size_t* off, MixedBufs& mx, const int n[4], int Rt, int Rc,
-                 const double* const X[4]) {
-  auto take = [&](size_t bytes) -> void* {
-    void* p = base ? (void*)(base + *off) : nullptr;
-    *off = al256(*off + bytes);
-    return p;
-  };
-  mx.Rtp = (Rt + 31) / 32 * 32;
-  mx.npad_max = 0;
-  for (int m = 0; m < 4; ++m) {
-    mx.npad[m] = (n[m] + 31) / 32 * 32;
-    if (mx.npad[m] > mx.npad_max) mx.npad_max = mx.npad[m];
-  }
-  for (int m = 0; m < 4; ++m) {
-    int alias = -1;
-    for (int q = 0; q < m; ++q)
-      if (X[q] == X[m]) alias = q;
-    if (alias >= 0) {
-      mx.Xh[m] = mx.Xh[alias]; mx.Xl[m] = mx.Xl[alias];
-      mx.XTh[m] = mx.XTh[alias]; mx.XTl[m] = mx.XTl[alias];
-      continue;
-    }
-    mx.Xh[m] = (__bf16*)take(2 * (size_t)n[m] * mx.Rtp);
-    mx.Xl[m] = (__bf16*)take(2 * (size_t)n[m] * mx.Rtp);
-    mx.XTh[m] = (__bf16*)take(2 * (size_t)Rt * mx.npad[m]);
-    mx.XTl[m] = (__bf16*)take(2 * (size_t)Rt * mx.npad[m]);
-  }
-  mx.Zh = (__bf16*)take(2 * (size_t)Rt * mx.Rtp);
-  mx.Zl = (__bf16*)take(2 * (size_t)Rt * mx.Rtp);
-  mx.ZTh = (__bf16*)take(2 * (size_t)Rt * mx.Rtp);
-  mx.ZTl = (__bf16*)take(2 * (size_t)Rt * mx.Rtp);
-  for (int m = 0; m < 4; ++m) mx.WT[m] = (float*)take(4 * (size_t)Rc * mx.Rtp);
-  mx.YT = (float*)take(4 * (size_t)Rc * mx.Rtp);
-  mx.FTh = (__bf16*)take(2 * (size_t)Rc * mx.npad_max);
-  mx.FTl = (__bf16*)take(2 * (size_t)Rc * mx.npad_max);
-}
-
-void mixed_setup_inputs(hipStream_t s, MixedBufs& mx, const double* const X[4], const double* Z,
-                        const int n[4], int Rt) {
-  for (int m = 0; m < 4; ++m) {
-    bool first = true;
-    for (int q = 0; q < m; ++q)
-      if (X[q] == X[m]) first = false;
-    if (!first) continue;
-    split_rows_f64(s, X[m], n[m], Rt, Rt, mx.Xh[m], mx.Xl[m], mx.Rtp, mx.Rtp);
-    split_transpose_f64(s, X[m], n[m], Rt, Rt, mx.XTh[m], mx.XTl[m], mx.npad[m], mx.npad[m]);
-  }
-  split_rows_f64(s, Z, Rt, Rt, Rt, mx.Zh, mx.Zl, mx.Rtp, mx.Rtp);
-  split_transpose_f64(s, Z, Rt, Rt, Rt, mx.ZTh, mx.ZTl, mx.Rtp, mx.Rtp);
-}
-
-void mixed_refresh(hipStream_t s, MixedBufs& mx, int m, const double* F, const int n[4], int Rt, int Rc,
-                   int Tp, const int32_t* done) {
-  split_transpose_f64(s, F, n[m], Rc, Tp, mx.FTh, mx.FTl, mx.npad_max, mx.npad[m]);
-  SplitOperand A{mx.FTh, mx.FTl, nullptr, nullptr, mx.npad_max};
-  SplitOperand B{mx.XTh[m], mx.XTl[m], nullptr, nullptr, mx.npad[m]};
-  gemm_split_launch(s, Rc, Rt, mx.npad[m], A, B, mx.WT[m], nullptr, nullptr, mx.Rtp, done);
-}
-
-void mixed_mttkrp(hipStream_t s, MixedBufs& mx, int n, bool fresh_core, const int nd[4], int Rt, int Rc,
-                  int Tp, double* out, double* out2, const int32_t* done) {
-  if (fresh_core) {
-    const int a = n < 2 ? 2 : 0, b = n < 2 ? 3 : 1;
-    SplitOperand A{nullptr, nullptr, mx.WT[a], mx.WT[b], mx.Rtp};
-    SplitOperand B = n < 2 ? SplitOperand{mx.Zh, mx.Zl, nullptr, nullptr, mx.Rtp}
-                           : SplitOperand{mx.ZTh, mx.ZTl, nullptr, nullptr, mx.Rtp};
-    gemm_split_launch(s, Rc, Rt, mx.Rtp, A, B, mx.YT, nullptr, nullptr, mx.Rtp, done);
-  }
-  static const int partner[4] = {1, 0, 3, 2};
-  SplitOperand A{mx.Xh[n], mx.Xl[n], nullptr, nullptr, mx.Rtp};
-  SplitOperand B{nullptr, nullptr, mx.WT[partner[n]], mx.YT, mx.Rtp};
-  gemm_split_launch(s, nd[n], Rc, mx.Rtp, A, B, nullptr, out, out2, Tp, done);
 }
 
 }  // namespace thccp

@@ -10,51 +10,52 @@
 namespace thccp {
 
 // V = g0 o g1 o g2 on the R x R block, identity on the padding, plus mu I
-// on the retry pass.
+// on the retry pass.  blockIdx.y selects the problem.
 template <typename T>
-__global__ __launch_bounds__(256) void form_V_kernel(T* V, int Tp, int R, const T* g0, const T* g1,
-                                                      const T* g2, DevState* st, int retry_pass) {
+__global__ __launch_bounds__(256) void form_V_kernel(const FormVArgs<T>* tab, int retry_pass) {
+  const FormVArgs<T> a = tab[blockIdx.y];
+  DevState* st = a.st;
   if (st->done) return;
   if (retry_pass && !st->retry_active) return;
   const T mu = retry_pass ? (T)st->mu : T(0);
+  const int Tp = a.Tp, R = a.R;
   const size_t total = (size_t)Tp * Tp;
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
     const int i = (int)(e / Tp), j = (int)(e % Tp);
     T v;
     if (i < R && j < R) {
-      v = g0[e] * g1[e] * g2[e];
+      v = a.g0[e] * a.g1[e] * a.g2[e];
       if (i == j) v += mu;
     } else {
       v = (i == j) ? T(1) : T(0);
     }
-    V[e] = v;
+    a.V[e] = v;
   }
 }
 
 template <typename T>
-void form_normal_matrix(hipStream_t s, T* V, int Tp, int R, const T* g0, const T* g1, const T* g2,
-                        DevState* st, int retry_pass) {
-  const size_t total = (size_t)Tp * Tp;
+void form_v_group(hipStream_t s, const FormVArgs<T>* tab, int nprob, int max_Tp, int retry_pass) {
+  const size_t total = (size_t)max_Tp * max_Tp;
   int grid = (int)((total + 255) / 256);
-  if (grid > 4096) grid = 4096;
-  hipLaunchKernelGGL((form_V_kernel<T>), dim3(grid), dim3(256), 0, s, V, Tp, R, g0, g1, g2, st,
-                     retry_pass);
+  if (grid > 2048) grid = 2048;
+  hipLaunchKernelGGL((form_V_kernel<T>), dim3(grid, nprob), dim3(256), 0, s, tab, retry_pass);
 }
 
 // After the first factorisation pass: arm the damped retry (mu = 1e-12
 // tr(V) / R, computed from the diagonals of the Grams) or flag failure.
 template <typename T>
-__global__ void retry_prepare_kernel(DevState* st, int allow_fallback, const T* g0, const T* g1,
-                                     const T* g2, int R, int Tp) {
+__global__ void retry_prepare_kernel(const FormVArgs<T>* tab, int allow_fallback) {
   __shared__ double part[256];
+  const FormVArgs<T> a = tab[blockIdx.x];
+  DevState* st = a.st;
   if (st->done) return;
   const int tid = threadIdx.x;
   const int failed = st->chol_fail;
   double acc = 0.0;
   if (failed)
-    for (int i = tid; i < R; i += 256) {
-      const size_t d = (size_t)i * Tp + i;
-      acc += (double)g0[d] * (double)g1[d] * (double)g2[d];
+    for (int i = tid; i < a.R; i += 256) {
+      const size_t d = (size_t)i * a.Tp + i;
+      acc += (double)a.g0[d] * (double)a.g1[d] * (double)a.g2[d];
     }
   part[tid] = acc;
   __syncthreads();
@@ -66,7 +67,7 @@ __global__ void retry_prepare_kernel(DevState* st, int allow_fallback, const T* 
     if (failed && allow_fallback) {
       st->retry_active = 1;
       st->fallbacks += 1;
-      st->mu = 1e-12 * part[0] / (double)R;
+      st->mu = 1e-12 * part[0] / (double)a.R;
     } else {
       st->retry_active = 0;
       if (failed) st->flags |= FLAG_NOT_SPD;
@@ -76,69 +77,66 @@ __global__ void retry_prepare_kernel(DevState* st, int allow_fallback, const T* 
 }
 
 template <typename T>
-void retry_prepare_launch(hipStream_t s, DevState* st, int allow_fallback, const T* g0, const T* g1,
-                          const T* g2, int R, int Tp) {
-  hipLaunchKernelGGL((retry_prepare_kernel<T>), dim3(1), dim3(256), 0, s, st, allow_fallback, g0,
-                     g1, g2, R, Tp);
+void retry_prepare_group(hipStream_t s, const FormVArgs<T>* tab, int nprob, int allow_fallback) {
+  hipLaunchKernelGGL((retry_prepare_kernel<T>), dim3(nprob), dim3(256), 0, s, tab, allow_fallback);
 }
 
 // Column norms lambda_k of the solved factor, F = Msol / lambda, and (for
 // the fit) the per-column partial sums of Msol o Msave.  One workgroup per
 // 64 columns; 4 row groups reduced in a fixed order.
 template <typename T>
-__global__ __launch_bounds__(256) void normalise_kernel(const T* Msol, int n, int R, int ld, T* F,
-                                                         T* lam, const T* Msave, double* inner_part,
-                                                         DevState* st) {
+__global__ __launch_bounds__(256) void normalise_kernel(const NormArgs<T>* tab) {
   __shared__ double ss[4][64];
   __shared__ double si[4][64];
-  if (st->done) return;
+  const NormArgs<T> a = tab[blockIdx.y];
+  if (a.st->done) return;
   const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
   const int col = blockIdx.x * 64 + c;
-  double a = 0.0, b = 0.0;
+  if (blockIdx.x * 64 >= a.R) return;
+  const int n = a.n, R = a.R, ld = a.ld;
+  double x = 0.0, y = 0.0;
   if (col < R)
     for (int s = g; s < n; s += 4) {
-      const double v = (double)Msol[(size_t)s * ld + col];
-      a += v * v;
-      if (Msave) b += v * (double)Msave[(size_t)s * ld + col];
+      const double v = (double)a.Msol[(size_t)s * ld + col];
+      x += v * v;
+      if (a.Msave) y += v * (double)a.Msave[(size_t)s * ld + col];
     }
-  ss[g][c] = a;
-  si[g][c] = b;
+  ss[g][c] = x;
+  si[g][c] = y;
   __syncthreads();
   const double nrm = sqrt((ss[0][c] + ss[1][c]) + (ss[2][c] + ss[3][c]));
   if (col < R) {
     const double scale = nrm > 0.0 ? 1.0 / nrm : 1.0;
     for (int s = g; s < n; s += 4) {
       const size_t off = (size_t)s * ld + col;
-      F[off] = (T)((double)Msol[off] * scale);
+      a.F[off] = (T)((double)a.Msol[off] * scale);
     }
     if (g == 0) {
-      lam[col] = (T)nrm;
-      if (inner_part) inner_part[col] = (si[0][c] + si[1][c]) + (si[2][c] + si[3][c]);
+      a.lam[col] = (T)nrm;
+      if (a.inner_part) a.inner_part[col] = (si[0][c] + si[1][c]) + (si[2][c] + si[3][c]);
     }
   }
 }
 
 template <typename T>
-void normalise_columns(hipStream_t s, const T* Msol, int n, int R, int ld, T* F, T* lam,
-                       const T* Msave, double* inner_part, DevState* st) {
-  hipLaunchKernelGGL((normalise_kernel<T>), dim3((R + 63) / 64), dim3(256), 0, s, Msol, n, R, ld, F,
-                     lam, Msave, inner_part, st);
+void normalise_group(hipStream_t s, const NormArgs<T>* tab, int nprob, int max_R) {
+  hipLaunchKernelGGL((normalise_kernel<T>), dim3((max_R + 63) / 64, nprob), dim3(256), 0, s, tab);
 }
 
 // ||G~||^2 = lambda^T (g0 o g1 o g2 o g3) lambda: per-row partials, then a
-// single-workgroup final pass that also forms the fit and applies the
-// stopping rule.
+// single-workgroup final pass per problem that also forms the fit and
+// applies the stopping rule.
 template <typename T>
-__global__ __launch_bounds__(256) void model_norm_rows_kernel(const T* g0, const T* g1, const T* g2,
-                                                              const T* g3, const T* lam, int R, int ld,
-                                                              double* row_part, DevState* st) {
+__global__ __launch_bounds__(256) void model_norm_rows_kernel(const FitArgs<T>* tab) {
   __shared__ double part[256];
-  if (st->done) return;
+  const FitArgs<T> a = tab[blockIdx.y];
+  if (a.st->done) return;
   const int i = blockIdx.x, tid = threadIdx.x;
+  if (i >= a.R) return;
   double acc = 0.0;
-  for (int j = tid; j < R; j += 256) {
-    const size_t e = (size_t)i * ld + j;
-    acc += (double)g0[e] * (double)g1[e] * (double)g2[e] * (double)g3[e] * (double)lam[j];
+  for (int j = tid; j < a.R; j += 256) {
+    const size_t e = (size_t)i * a.ld + j;
+    acc += (double)a.g[0][e] * (double)a.g[1][e] * (double)a.g[2][e] * (double)a.g[3][e] * (double)a.lam[j];
   }
   part[tid] = acc;
   __syncthreads();
@@ -146,23 +144,36 @@ __global__ __launch_bounds__(256) void model_norm_rows_kernel(const T* g0, const
     if (tid < w) part[tid] += part[tid + w];
     __syncthreads();
   }
-  if (tid == 0) row_part[i] = part[0] * (double)lam[i];
+  if (tid == 0) a.row_part[i] = part[0] * (double)a.lam[i];
 }
 
-__global__ __launch_bounds__(256) void fit_final_kernel(const double* row_part, const double* inner_part,
-                                                        int R, double* fit_hist, int hist_cap,
-                                                        double tol, double fit_floor, DevState* st) {
+// Precision guard of split-BF16 plans (guard != 0): a problem whose
+// normal matrices became too ill-conditioned for the split-BF16 MTTKRP
+// (cond estimate above cond_limit), that needed a damped retry, or whose
+// fit rose, is promoted to the FP64 path; `promote` tells the host to
+// replay the sweep.  The stopping rule is not applied in such a sweep.
+__device__ __forceinline__ bool guard_trips(const DevState* st, double fit, double prev, double cond_limit) {
+  if (st->path) return false;
+  return st->cond_max > cond_limit || st->fallbacks > st->fallbacks_start ||
+         (prev >= 0.0 && fit > prev * (1.0 + 1e-3)) || !(fit <= 1.0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fit_final_kernel(const FitArgs<T>* tab, int hist_cap, double tol,
+                                                        double fit_floor, int guard, double cond_limit) {
   __shared__ double pa[256];
   __shared__ double pb[256];
+  const FitArgs<T> a = tab[blockIdx.x];
+  DevState* st = a.st;
   if (st->done) return;
   const int tid = threadIdx.x;
-  double a = 0.0, b = 0.0;
-  for (int i = tid; i < R; i += 256) {
-    a += row_part[i];
-    b += inner_part[i];
+  double x = 0.0, y = 0.0;
+  for (int i = tid; i < a.R; i += 256) {
+    x += a.row_part[i];
+    y += a.inner_part[i];
   }
-  pa[tid] = a;
-  pb[tid] = b;
+  pa[tid] = x;
+  pb[tid] = y;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (tid < w) {
@@ -180,24 +191,134 @@ __global__ __launch_bounds__(256) void fit_final_kernel(const double* row_part, 
     st->model2 = model2;
     if (!isfinite(fit)) st->flags |= FLAG_NONFINITE;
     const int k = st->sweeps;
-    fit_hist[k % hist_cap] = fit;
+    a.fit_hist[k % hist_cap] = fit;
     st->sweeps = k + 1;
     const double prev = st->fit_prev;
-    if (fit <= fit_floor || (prev >= 0.0 && fabs(fit - prev) <= tol * prev) || !isfinite(fit) ||
-        (st->flags & FLAG_NOT_SPD))
+    if (guard && guard_trips(st, fit, prev, cond_limit)) {
+      st->path = 1;
+      st->promote = 1;
+    } else if (fit <= fit_floor || (prev >= 0.0 && fabs(fit - prev) <= tol * prev) || !isfinite(fit) ||
+               (st->flags & FLAG_NOT_SPD)) {
       st->done = 1;
+    }
     st->fit_prev = fit;
   }
 }
 
 template <typename T>
-void fit_update(hipStream_t s, const T* const g[4], const T* lam, int R, int ld,
-                const double* inner_part, double* scratch, double* fit_hist, int hist_cap, double tol,
-                double fit_floor, DevState* st) {
-  hipLaunchKernelGGL((model_norm_rows_kernel<T>), dim3(R), dim3(256), 0, s, g[0], g[1], g[2], g[3],
-                     lam, R, ld, scratch, st);
-  hipLaunchKernelGGL(fit_final_kernel, dim3(1), dim3(256), 0, s, scratch, inner_part, R, fit_hist,
-                     hist_cap, tol, fit_floor, st);
+void fit_group(hipStream_t s, const FitArgs<T>* tab, int nprob, int max_R, int hist_cap, double tol,
+               double fit_floor, int guard, double cond_limit) {
+  hipLaunchKernelGGL((model_norm_rows_kernel<T>), dim3(max_R, nprob), dim3(256), 0, s, tab);
+  hipLaunchKernelGGL((fit_final_kernel<T>), dim3(nprob), dim3(256), 0, s, tab, hist_cap, tol, fit_floor, guard,
+                     cond_limit);
+}
+
+__global__ void sweep_tick_kernel(DevState* const* st_tab, int guard, double cond_limit) {
+  DevState* st = st_tab[blockIdx.x];
+  if (threadIdx.x == 0 && !st->done) {
+    st->sweeps += 1;
+    if (guard && guard_trips(st, 0.0, -1.0, cond_limit)) {
+      st->path = 1;
+      st->promote = 1;
+    }
+  }
+}
+void sweep_tick_group(hipStream_t s, DevState* const* st_tab, int nprob, int guard, double cond_limit) {
+  hipLaunchKernelGGL(sweep_tick_kernel, dim3(nprob), dim3(64), 0, s, st_tab, guard, cond_limit);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cond_track_kernel(const CondArgs<T>* tab) {
+  __shared__ double lo[256];
+  __shared__ double hi[256];
+  const CondArgs<T> a = tab[blockIdx.x];
+  if (a.st->done) return;
+  const int tid = threadIdx.x;
+  double l = INFINITY, h = 0.0;
+  for (int i = tid; i < a.R; i += 256) {
+    const double v = fabs((double)a.diagL[i]);
+    l = fmin(l, v);
+    h = fmax(h, v);
+  }
+  lo[tid] = l;
+  hi[tid] = h;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      lo[tid] = fmin(lo[tid], lo[tid + w]);
+      hi[tid] = fmax(hi[tid], hi[tid + w]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double c = lo[0] > 0.0 ? (hi[0] / lo[0]) * (hi[0] / lo[0]) : INFINITY;
+    if (!(c <= a.st->cond_max)) a.st->cond_max = c;
+  }
+}
+template <typename T>
+void cond_track_group(hipStream_t s, const CondArgs<T>* tab, int nprob) {
+  hipLaunchKernelGGL((cond_track_kernel<T>), dim3(nprob), dim3(256), 0, s, tab);
+}
+template void cond_track_group<double>(hipStream_t, const CondArgs<double>*, int);
+template void cond_track_group<float>(hipStream_t, const CondArgs<float>*, int);
+
+__global__ void guard_begin_kernel(DevState* const* st_tab) {
+  DevState* st = st_tab[blockIdx.x];
+  if (threadIdx.x == 0) {
+    st->cond_max = 0.0;
+    st->fallbacks_start = st->fallbacks;
+    st->promote = 0;
+  }
+}
+void guard_begin_group(hipStream_t s, DevState* const* st_tab, int nprob) {
+  hipLaunchKernelGGL(guard_begin_kernel, dim3(nprob), dim3(64), 0, s, st_tab);
+}
+
+__global__ void set_path_kernel(DevState* const* st_tab, const int32_t* flags) {
+  DevState* st = st_tab[blockIdx.x];
+  if (threadIdx.x == 0 && flags[blockIdx.x]) {
+    st->path = 1;
+    st->promote = 0;
+  }
+}
+void set_path_group(hipStream_t s, DevState* const* st_tab, int nprob, const int32_t* flags_dev) {
+  hipLaunchKernelGGL(set_path_kernel, dim3(nprob), dim3(64), 0, s, st_tab, flags_dev);
+}
+
+__global__ void checkpoint_kernel(const CkptArgs* tab, int dir) {
+  const CkptArgs c = tab[blockIdx.y];
+  for (int m = 0; m < 4; ++m) {
+    const uint32_t* src = (const uint32_t*)(dir ? c.b[m] : c.a[m]);
+    uint32_t* dst = (uint32_t*)(dir ? c.a[m] : c.b[m]);
+    const size_t words = c.bytes[m] / 4;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < words; e += (size_t)gridDim.x * 256)
+      dst[e] = src[e];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (dir) *c.st = *c.st_save;
+    else *c.st_save = *c.st;
+  }
+}
+void checkpoint_group(hipStream_t s, const CkptArgs* tab, int nprob, int dir) {
+  hipLaunchKernelGGL(checkpoint_kernel, dim3(256, nprob), dim3(256), 0, s, tab, dir);
+}
+
+// Laplace-transform scaling of the THC rows: out[p, :] = exp(sign eps_p t) X[p, :].
+__global__ void lt_scale_kernel(const double* X, const double* eps, int n, int r, double t, double sign,
+                                double* out) {
+  const size_t total = (size_t)n * r;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    const int p = (int)(e / r);
+    out[e] = exp(sign * eps[p] * t) * X[e];
+  }
+}
+void lt_scale_rows(hipStream_t s, const double* X, const double* eps, int n, int r, double t, double sign,
+                   double* out) {
+  size_t total = (size_t)n * r;
+  int grid = (int)((total + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(lt_scale_kernel, dim3(grid), dim3(256), 0, s, X, eps, n, r, t, sign, out);
 }
 
 // ------------------------------------------------------------------ set-up
@@ -289,6 +410,10 @@ __global__ void state_reset_kernel(DevState* st, const double* norm2_src) {
     st->chol_fail = 0;
     st->fallbacks = 0;
     st->retry_active = 0;
+    st->path = 0;
+    st->promote = 0;
+    st->fallbacks_start = 0;
+    st->cond_max = 0.0;
     if (!(st->norm2 > 0.0) || !isfinite(st->norm2)) {
       st->flags |= FLAG_NONFINITE;
       st->done = 1;
@@ -343,21 +468,13 @@ void copy_normalised_init(hipStream_t s, const double* src, int n, int R, int ld
   hipLaunchKernelGGL(init_norm_kernel, dim3((R + 63) / 64), dim3(256), 0, s, src, n, R, ld, dst);
 }
 
-template void form_normal_matrix<double>(hipStream_t, double*, int, int, const double*, const double*,
-                                         const double*, DevState*, int);
-template void form_normal_matrix<float>(hipStream_t, float*, int, int, const float*, const float*,
-                                        const float*, DevState*, int);
-template void retry_prepare_launch<double>(hipStream_t, DevState*, int, const double*, const double*,
-                                           const double*, int, int);
-template void retry_prepare_launch<float>(hipStream_t, DevState*, int, const float*, const float*,
-                                          const float*, int, int);
-template void normalise_columns<double>(hipStream_t, const double*, int, int, int, double*, double*,
-                                        const double*, double*, DevState*);
-template void normalise_columns<float>(hipStream_t, const float*, int, int, int, float*, float*,
-                                       const float*, double*, DevState*);
-template void fit_update<double>(hipStream_t, const double* const*, const double*, int, int,
-                                 const double*, double*, double*, int, double, double, DevState*);
-template void fit_update<float>(hipStream_t, const float* const*, const float*, int, int,
-                                const double*, double*, double*, int, double, double, DevState*);
+template void form_v_group<double>(hipStream_t, const FormVArgs<double>*, int, int, int);
+template void form_v_group<float>(hipStream_t, const FormVArgs<float>*, int, int, int);
+template void retry_prepare_group<double>(hipStream_t, const FormVArgs<double>*, int, int);
+template void retry_prepare_group<float>(hipStream_t, const FormVArgs<float>*, int, int);
+template void normalise_group<double>(hipStream_t, const NormArgs<double>*, int, int);
+template void normalise_group<float>(hipStream_t, const NormArgs<float>*, int, int);
+template void fit_group<double>(hipStream_t, const FitArgs<double>*, int, int, int, double, double, int, double);
+template void fit_group<float>(hipStream_t, const FitArgs<float>*, int, int, int, double, double, int, double);
 
 }  // namespace thccp
