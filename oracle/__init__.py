@@ -13,7 +13,9 @@ Modules
            in the same step order as the GPU path, any size.
   lt       Laplace-transform row scaling of the THC factors (eq. mp1_t and
            the THC-LT amplitude that follows it).
-  mlp      Warm-start network: features, forward, manual backward, Adam.
+  warmstart  Warm-start features of the grid points, selection of the
+           initial CP columns, training targets from converged CPDs.
+  mlp      Warm-start network: forward, loss, manual backward, Adam.
 
 Pins: every function is checked by ``tests/test_oracle_*.py`` against
 brute-force loops, closed forms, planted decompositions, special cases and

@@ -94,3 +94,22 @@ def planted_diag_thc(n, r_thc, seed):
     X = rng.standard_normal((n, r_thc)) / np.sqrt(n)
     z = rng.uniform(0.5, 2.0, r_thc)
     return np.ascontiguousarray(X), np.ascontiguousarray(np.diag(z))
+
+
+def mlp_init_params(seed, shapes=((8, 256), (256,), (256, 256), (256,), (256, 2), (2,))):
+    """Initial warm-start network parameters as one float32 vector: each
+    weight matrix (fan_in x fan_out) ~ N(0, 1/fan_in), biases zero, blocks
+    in the given order."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in shapes:
+        if len(s) == 2:
+            out.append((rng.standard_normal(s) / np.sqrt(s[0])).ravel())
+        else:
+            out.append(np.zeros(s))
+    return np.concatenate(out).astype(np.float32)
+
+
+def minibatch_order(rows, seed):
+    """Seeded permutation of the training rows (int32)."""
+    return np.random.default_rng(seed).permutation(rows).astype(np.int32)
