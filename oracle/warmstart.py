@@ -27,7 +27,12 @@ Everything here is plain float64 NumPy written from those definitions:
   heuristic_scores    the raw feature 7: grid points with a large diagonal
                       contribution Z_PP S_PP^2 to ||G||^2 come first.
   select_init         top-R_cp grid points by score (ties: smaller P first),
-                      F_m[:, k] = exp(ell_{P_k}) X_m[:, P_k].
+                      F_m[:, k] = exp(ell_{P_k}) X_m[:, P_k], optionally
+                      blended with the caller's random guess R:
+                      + sigma ||X_m[:, P_k]|| R_m[:, k] / ||R_m[:, k]|| inside
+                      the bracket.  The grid columns are positive and
+                      overlap strongly, so a pure column start is nearly
+                      degenerate; the blend breaks that symmetry.
   match_labels        training targets from a converged CPD: greedy
                       one-to-one matching of its mode-0 columns to grid
                       columns by |cosine| (largest first; ties: smaller k,
@@ -38,7 +43,8 @@ Pins (tests/test_oracle_warmstart.py): closed-form participation ratios,
 invariance of the standardised features under X -> cX, Z -> cZ, grid-point
 permutation equivariance, zero mean / unit variance; the planted diagonal
 core, where the selected and scaled grid columns are an exact CPD (one ALS
-sweep reaches the fit floor); label recovery of a planted column choice
+sweep reaches the fit floor); the blend's norm identity for a random part
+orthogonal to the grid column; label recovery of a planted column choice
 with known scales; greedy matching against an exhaustive pick-the-maximum
 loop on small inputs.
 """
@@ -95,11 +101,24 @@ def selection_order(s):
     return np.lexsort((np.arange(len(s)), -s))
 
 
-def select_init(X, s, ell, r_cp):
-    """Initial CP factors from the top-r_cp grid points."""
+def select_init(X, s, ell, r_cp, noise=None, sigma=0.0):
+    """Initial CP factors from the top-r_cp grid points P_k:
+    F_m[:, k] = exp(ell_{P_k}) (X_m[:, P_k] + sigma ||X_m[:, P_k]|| R_m[:, k] / ||R_m[:, k]||)
+    with R = noise (the caller's random guess; sigma = 0 or noise None: the
+    plain grid columns)."""
     order = selection_order(s)[:r_cp]
     scale = np.exp(np.asarray(ell, dtype=np.float64)[order])
-    return [x[:, order] * scale[None, :] for x in X]
+    out = []
+    for m, x in enumerate(X):
+        cols = x[:, order]
+        if noise is not None and sigma != 0.0:
+            R = np.asarray(noise[m], dtype=np.float64)
+            rn = np.sqrt((R ** 2).sum(axis=0))
+            xn = np.sqrt((cols ** 2).sum(axis=0))
+            unit = np.where(rn > 0, R / np.where(rn > 0, rn, 1.0), 0.0)
+            cols = cols + sigma * xn[None, :] * unit
+        out.append(cols * scale[None, :])
+    return out
 
 
 def _abs_cosines(F0, X0):

@@ -121,3 +121,31 @@ def test_greedy_matching_against_exhaustive_loop():
         R, Pn = rng.integers(1, 6), rng.integers(1, 8)
         A = rng.integers(0, 4, (R, Pn)).astype(np.float64)  # many ties
         assert np.array_equal(ws.greedy_match(A), _iterative_max_matching(A)), A
+
+
+def test_blend_with_random_guess():
+    """X-part plus an orthogonal random part: the column norm is
+    exp(ell) ||x|| sqrt(1 + sigma^2) and the component along x is exp(ell) x."""
+    rng = np.random.default_rng(6)
+    n, R_t, R_c = 9, 7, 4
+    X = [rng.standard_normal((n, R_t)) for _ in range(4)]
+    s = rng.standard_normal(R_t)
+    ell = 0.2 * rng.standard_normal(R_t)
+    order = ws.selection_order(s)[:R_c]
+    noise = []
+    for m in range(4):
+        Rm = 3.0 * rng.standard_normal((n, R_c))
+        x = X[m][:, order]
+        Rm -= x * ((x * Rm).sum(0) / (x * x).sum(0))  # orthogonal to its grid column
+        noise.append(Rm)
+    sigma = 0.35
+    F = ws.select_init(X, s, ell, R_c, noise=noise, sigma=sigma)
+    F0 = ws.select_init(X, s, ell, R_c)
+    for m in range(4):
+        x = X[m][:, order]
+        e = np.exp(ell[order])
+        np.testing.assert_allclose(np.linalg.norm(F[m], axis=0),
+                                   e * np.linalg.norm(x, axis=0) * np.sqrt(1 + sigma ** 2), rtol=1e-13)
+        np.testing.assert_allclose((F[m] * x).sum(0) / (x * x).sum(0), e, rtol=1e-13)
+        np.testing.assert_allclose(F0[m], x * e, rtol=1e-15)
+    assert np.array_equal(ws.select_init(X, s, ell, R_c, noise=noise, sigma=0.0)[0], F0[0])
