@@ -201,6 +201,107 @@ cpd_status cpd_lt_scale_rows(const double* X, const double* eps, int32_t n, int3
                              double* out, void* stream);
 
 /* Releases the host plan and its private stream/graph (not the workspace). */
+/* ---- learned warm start ----
+ * An initial CP built from R_cp grid columns of the THC factors: with a
+ * diagonal core the THC form (eq. THC) is an exact CPD whose columns are
+ * X_m[:, P], so a scored selection of grid points, each column scaled, is
+ * the starting guess (the paper reports that the sweep count depends
+ * strongly on the initial guess, Results).  A network 8 -> 256 -> 256 -> 2
+ * (SiLU) maps eight standardised features of each grid point to a
+ * selection logit s and a log-scale ell.  Parameters: one FP32 vector of
+ * cpd_mlp_param_count() values, W1 (8 x 256, row-major), b1, W2 (256 x 256),
+ * b2, W3 (256 x 2), b3.  All pointers are DEVICE memory unless stated;
+ * every call is asynchronous on `stream` (a hipStream_t) unless stated,
+ * never allocates, and checks its arguments before any launch
+ * (CPD_ERR_INVALID_ARG, CPD_ERR_WORKSPACE for a short workspace). */
+
+/* Workspace bytes that cover cpd_ws_features, cpd_ws_labels and cpd_ws_init
+ * for a problem with n[0] = n0 (0 on bad sizes; r_cp <= r_thc required). */
+size_t cpd_ws_workspace_size(int32_t n0, int32_t r_thc, int32_t r_cp);
+
+/* Features of the r_thc grid points from X0 (n0 x r_thc) and Z (r_thc x
+ * r_thc), FP64 row-major, with S = X0^T X0:
+ *   0 log Z_PP, 1 log sum_Q |Z_PQ|, 2 log S_PP, 3 log sum_Q S_PQ^2,
+ *   4 log max_p |X0_pP|, 5 (sum_p X0_pP^2)^2 / (n0 sum_p X0_pP^4),
+ *   6 log sum_Q S_PQ^2 |Z_PQ|, 7 log Z_PP S_PP^2
+ * (log v = log max(v, 1e-300)), each standardised over P (population mean
+ * and deviation; a feature with deviation <= 1e-9 max(1, |mean|) is 0).
+ * feat: r_thc x 8 FP32 row-major.  heur (nullable): r_thc FP64, the raw
+ * feature 7, the heuristic ranking score. */
+cpd_status cpd_ws_features(int32_t n0, int32_t r_thc, const double* X0, const double* Z, float* feat,
+                           double* heur, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Initial factors from scores: grid points ranked by s (descending; ties:
+ * smaller P first); for the top r_cp points P_k
+ *   init[m][:, k] = exp(ell[P_k]) (X[m][:, P_k]
+ *                   + sigma ||X[m][:, P_k]|| noise[m][:, k] / ||noise[m][:, k]||)
+ * (ell NULL: scale 1; noise NULL or sigma = 0: the plain grid columns).
+ * noise[m]: n[m] x r_cp FP64, the caller's random guess; it may alias
+ * init[m].  The grid columns are positive and overlap strongly, so alone
+ * they make a nearly degenerate start; the blend breaks that.  s and ell
+ * are FP32 read with `stride` (2 for the network output) and must be
+ * finite.  init[m]: n[m] x r_cp FP64.  Workspace: cpd_ws_workspace_size. */
+cpd_status cpd_ws_select_init(const int32_t n[4], int32_t r_thc, int32_t r_cp, const double* const X[4],
+                              const float* s, const float* ell, int32_t stride, const double* const noise[4],
+                              double sigma, double* const init[4], void* workspace, size_t workspace_bytes,
+                              void* stream);
+
+/* Training targets from a converged CPD (F[m]: n[m] x r_cp with unit
+ * columns, lam: r_cp weights): mode-0 columns matched one-to-one to grid
+ * columns by |cosine| with X[0], largest first (ties: smaller k, then
+ * smaller P).  For a matched P: y = 1 and ell = mean over m of
+ * log |lam_k^(1/4) <F_m[:, k], X_m[:, P]> / ||X_m[:, P]||^2|, mask = 1;
+ * all other grid points 0.  y, ell, mask: r_thc FP32. */
+cpd_status cpd_ws_labels(const int32_t n[4], int32_t r_thc, int32_t r_cp, const double* const X[4],
+                         const double* const F[4], const double* lam, float* y, float* ell, float* mask,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* Complete warm start, SYNCHRONOUS: features, then the network (packed
+ * weights from cpd_mlp_pack, BF16 inference) and selection blended with
+ * noise (as cpd_ws_select_init); if `packed` is NULL or its scores are not
+ * finite, the heuristic score (feature 7, FP64) with scale 1; if that is
+ * not finite either, init is left as it was (the caller's random guess).
+ * *source (host, nullable): 0 network, 1 heuristic, 2 unchanged. */
+cpd_status cpd_ws_init(const int32_t n[4], int32_t r_thc, int32_t r_cp, const double* const X[4], const double* Z,
+                       const void* packed, const double* const noise[4], double sigma, double* const init[4],
+                       int32_t* source, void* workspace, size_t workspace_bytes, void* stream);
+
+int32_t cpd_mlp_param_count(void);
+/* Workspace of the training calls for `rows` rows (activations kept from
+ * cpd_mlp_forward for cpd_mlp_backward: pass the same workspace). */
+size_t cpd_mlp_workspace_size(int32_t rows);
+
+/* FP32 forward over rows x[idx[r]] (idx NULL: x[r]); x: 8 FP32 per row;
+ * out: rows x 2 (s, ell). */
+cpd_status cpd_mlp_forward(const float* params, const float* x, const int32_t* idx, int32_t rows, float* out,
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+/* Loss over the rows of the last forward, targets gathered like x:
+ *   L = (1/rows) sum BCE(s, y) + (1/max(1, sum mask)) sum mask (ell - ell_t)^2
+ * with BCE(s, y) = max(s, 0) - s y + log(1 + exp(-|s|)).  dout: rows x 2,
+ * dL/d(out).  loss_dev (nullable): one FP64. */
+cpd_status cpd_mlp_loss(const float* out, const float* y, const float* ell_t, const float* mask,
+                        const int32_t* idx, int32_t rows, float* dout, double* loss_dev, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
+/* Gradients of the loss with respect to every parameter (same layout as
+ * params), from dout and the activations of the last forward. */
+cpd_status cpd_mlp_backward(const float* params, const float* x, const int32_t* idx, const float* dout,
+                            int32_t rows, float* grads, void* workspace, size_t workspace_bytes, void* stream);
+
+/* One Adam step (Kingma and Ba, bias-corrected; step counts from 1) on all
+ * parameters; m and v: moment buffers of the same size, zero at step 1. */
+cpd_status cpd_mlp_adam(float* params, const float* grads, float* m, float* v, int32_t step, float lr,
+                        float beta1, float beta2, float eps, void* stream);
+
+/* Inference weights: cpd_mlp_packed_size() bytes, 256-byte aligned (W2 in
+ * BF16, the rest FP32). */
+size_t cpd_mlp_packed_size(void);
+cpd_status cpd_mlp_pack(const float* params, void* packed, void* stream);
+/* BF16 inference: the 256 x 256 layer on BF16 matrix cores with FP32
+ * accumulation, the other layers in FP32.  x: rows x 8, out: rows x 2. */
+cpd_status cpd_mlp_infer_bf16(const void* packed, const float* x, int32_t rows, float* out, void* stream);
+
 cpd_status cpd_destroy(cpd_plan p);
 
 const char* cpd_status_string(cpd_status s);

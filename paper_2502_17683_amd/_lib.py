@@ -93,6 +93,24 @@ EXPORTS = {
     "cpd_test_split_workspace": (ctypes.c_size_t, [i32, i32, i32]),
     "cpd_test_gemm_split": (i32, [i32, i32, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "cpd_test_mfma_probe": (i32, [i32, i32, vp, vp, vp, vp]),
+    "cpd_ws_workspace_size": (ctypes.c_size_t, [i32, i32, i32]),
+    "cpd_ws_features": (i32, [i32, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+    "cpd_ws_select_init": (i32, [ctypes.POINTER(i32), i32, i32, vp * 4, vp, vp, i32, ctypes.POINTER(vp * 4),
+                                 ctypes.c_double, vp * 4, vp, ctypes.c_size_t, vp]),
+    "cpd_ws_labels": (i32, [ctypes.POINTER(i32), i32, i32, vp * 4, vp * 4, vp, vp, vp, vp, vp,
+                            ctypes.c_size_t, vp]),
+    "cpd_ws_init": (i32, [ctypes.POINTER(i32), i32, i32, vp * 4, vp, vp, ctypes.POINTER(vp * 4), ctypes.c_double,
+                          vp * 4, ctypes.POINTER(i32), vp, ctypes.c_size_t, vp]),
+    "cpd_mlp_param_count": (i32, []),
+    "cpd_mlp_workspace_size": (ctypes.c_size_t, [i32]),
+    "cpd_mlp_packed_size": (ctypes.c_size_t, []),
+    "cpd_mlp_forward": (i32, [vp, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]),
+    "cpd_mlp_loss": (i32, [vp, vp, vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]),
+    "cpd_mlp_backward": (i32, [vp, vp, vp, vp, i32, vp, vp, ctypes.c_size_t, vp]),
+    "cpd_mlp_adam": (i32, [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, vp]),
+    "cpd_mlp_pack": (i32, [vp, vp, vp]),
+    "cpd_mlp_infer_bf16": (i32, [vp, vp, i32, vp, vp]),
 }
 
 
