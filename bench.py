@@ -81,12 +81,24 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", choices=("mixed", "lt", "warmstart"), default="mixed",
+                    help="mixed: the headline time-to-fit line (default); lt: the batched "
+                         "Laplace-transform CPDs; warmstart: train and evaluate the learned warm start")
+    ap.add_argument("--lt-sweeps", type=int, default=40)
+    ap.add_argument("--ws-train", type=int, default=512)
+    ap.add_argument("--ws-heldout", type=int, default=32)
+    ap.add_argument("--ws-heldout-large", type=int, default=4)
+    ap.add_argument("--ws-budget", type=int, default=200)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how it would shard).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "lt":
+        return bench_lt(args)
+    if args.workload == "warmstart":
+        return bench_warmstart(args)
 
     import torch
     from paper_2502_17683_amd import CPD
@@ -208,6 +220,197 @@ def main():
                                   "avg_launch_us": core_ms * 1e3},
         "sweep_ms_from_kernels": sweep_ms,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def sweep_flops(n, r_thc, r_cp):
+    """Useful flops of one sweep: MTTKRP, Gram SYRKs, Cholesky, triangular solves."""
+    return (mttkrp_flops(n, r_thc, r_cp) + r_cp * r_cp * sum(n) + 4.0 / 3.0 * r_cp ** 3
+            + 2.0 * r_cp * r_cp * sum(n))
+
+
+def bench_lt(args):
+    """48 CPDs (3 systems x 16 Laplace points) of uneven size as one grouped
+    sweep; throughput against the same CPDs run one after another, and the
+    time for all of them to converge (per-problem stopping rule)."""
+    import torch
+    from paper_2502_17683_amd import CPD, CPDBatch, lt_batch_problems
+    from synth import make_lt_system, init_factors, lt_points, LT_SYSTEMS
+
+    systems = [make_lt_system(o, v, i) for i, (o, v) in enumerate(LT_SYSTEMS)]
+    problems, meta = lt_batch_problems(systems, lt_points(),
+                                       init_fn=lambda dims, r, idx: init_factors(dims, r, 1000 + idx))
+    shapes = [([int(x.shape[0]) for x in p["X"]], int(p["Z"].shape[0]), p["r_cp"]) for p in problems]
+    useful = sum(sweep_flops(*sh) for sh in shapes)
+    mtt = sum(mttkrp_flops(*sh) for sh in shapes)
+    K = args.lt_sweeps
+    res = {}
+    from paper_2502_17683_amd import CpdError
+    for prec in ("mixed", "fp32", "fp64"):
+        b = CPDBatch(problems, precision=prec, tol=0.0, fit_floor=0.0, autotune=True)
+        try:
+            b.sweep(3)
+        except CpdError as e:
+            # all-FP32 (Cholesky included) cannot factor the normal matrices of
+            # the large-t problems, whose condition estimates reach ~1e12
+            res[prec] = {"error": str(e)}
+            b.close()
+            log(f"[bench-lt] batched {prec}: {e}")
+            continue
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.sweep(K, sync=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / K
+        res[prec] = {"ms_per_batched_sweep": ms, "sweeps_per_s": 1e3 / ms,
+                     "useful_tflops": useful / (ms * 1e-3) / 1e12}
+        if prec == "mixed":
+            res[prec]["autotune"] = b.autotune_log()
+            res[prec]["promoted_to_fp64"] = sum(b.stats(i)["fp64_path"] for i in range(len(problems)))
+        b.close()
+        log(f"[bench-lt] batched {prec}: {ms:.3f} ms/sweep")
+    # the same 48 CPDs one after another (one plan each, graph-replayed sweeps)
+    for prec in ("mixed", "fp64"):
+        plans = [CPD(p["X"], p["Z"], p["r_cp"], p["init"], precision=prec, tol=0.0, fit_floor=0.0)
+                 for p in problems]
+        for c in plans:
+            c.sweep(3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in plans:
+            c.sweep(K, sync=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / K
+        res[prec]["sequential_ms_per_sweep"] = ms
+        res[prec]["batched_speedup_vs_sequential"] = ms / res[prec]["ms_per_batched_sweep"]
+        for c in plans:
+            c.close()
+        log(f"[bench-lt] sequential {prec}: {ms:.3f} ms per sweep of all 48")
+    # time to converge every CPD (tol 1e-4), batched, mixed vs FP64
+    conv = {}
+    finals = {}
+    for prec in ("mixed", "fp64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = CPDBatch(problems, precision=prec, tol=1e-4, fit_floor=1e-7, fit_every=1)
+        fits = b.sweep(args.max_sweeps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _, done, sw = b.states()
+        finals[prec] = [f[-1] for f in fits]
+        conv[prec] = {"seconds": dt, "all_converged": bool(all(done)), "sweeps_max": int(max(sw)),
+                      "sweeps_total": int(sum(sw))}
+        b.close()
+        log(f"[bench-lt] converge {prec}: {dt:.3f}s max sweeps {max(sw)}")
+    rel = [abs(a - b) / b for a, b in zip(finals["mixed"], finals["fp64"]) if b > 0]
+    out = {
+        "metric": "batched LT CP-ALS sweep time (ms) and time to converge all CPDs (s), 1 MI355X",
+        "value": res["mixed"]["ms_per_batched_sweep"], "unit": "ms", "n_gpus": 1, "steps": K,
+        "higher_is_better": False, "data": "synthetic",
+        "dtype": "bf16-split(fp32 acc)+f64",
+        "config": {"workload": "48 LT CPDs: (o,v) in (20,100),(40,200),(80,400) x 16 Laplace points "
+                               "0.01-20, R_thc=4(o+v), R_cp=2(o+v)",
+                   "useful_gflop_per_batched_sweep": useful / 1e9, "mttkrp_gflop": mtt / 1e9},
+        "per_precision": res,
+        "converge_tol_1e-4": conv,
+        "final_fit_rel_diff_mixed_vs_fp64": {"max": max(rel), "median": float(np.median(rel))},
+        "speedup_converge_mixed_vs_fp64": conv["fp64"]["seconds"] / conv["mixed"]["seconds"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_warmstart(args):
+    """Train the warm-start network on converged CPDs (N=100, R_thc=500,
+    R_cp=400) and compare sweeps and wall time to the random start's best
+    fit on held-out seeds at N=100 and N=400."""
+    import torch
+    from paper_2502_17683_amd import CPD, CPDBatch, WarmStartMLP, training_set, ws_init
+    from synth import make_thc, init_factors, mlp_init_params, minibatch_order
+
+    dev = torch.device("cuda:0")
+    N, Rt, Rc = 100, 500, 400
+    t0 = time.perf_counter()
+    train = []
+    for k in range(args.ws_train):
+        X, Z = make_thc(N, Rt, 10000 + k)
+        train.append({"X": X, "Z": Z, "r_cp": Rc, "init": init_factors([N] * 4, Rc, 11000 + k)})
+    t_gen = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    data = training_set(train, sweeps=300, tol=1e-4, chunk=64)
+    torch.cuda.synchronize()
+    t_label = time.perf_counter() - t0
+    del train
+    net = WarmStartMLP(mlp_init_params(7))
+    order = minibatch_order(int(data[0].shape[0]), 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = net.train(data, order, batch_rows=8192, lr=2e-3, epochs=20)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    packed = net.pack()
+    log(f"[bench-ws] generated {args.ws_train} inputs in {t_gen:.1f}s, labelled in {t_label:.1f}s, "
+        f"trained {len(losses)} steps in {t_train:.2f}s, loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+
+    def evaluate(n, r_thc, r_cp, seeds, budget):
+        rows = []
+        for seed in seeds:
+            X, Z = make_thc(n, r_thc, seed)
+            rnd = init_factors([n] * 4, r_cp, seed + 1000)
+            Xd, Zd = torch.as_tensor(X, device=dev), torch.as_tensor(Z, device=dev)
+            rd = [torch.as_tensor(f, device=dev) for f in rnd]
+            ref = CPD(Xd, Zd, r_cp, rd, precision="fp64", tol=0.0, fit_floor=0.0)
+            target = min(ref.sweep(budget)) * (1 + 1e-4)
+            ref.close()
+            row = {"seed": seed}
+            for kind in ("random", "learned", "heuristic"):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                if kind == "random":
+                    init, src = rd, "random"
+                else:
+                    init, src = ws_init(Xd, Zd, r_cp, packed=packed if kind == "learned" else None, noise=rd)
+                c = CPD(Xd, Zd, r_cp, init, precision="fp64", tol=0.0, fit_floor=0.0)
+                sweeps, hit = 0, False
+                while sweeps < budget and not hit:
+                    f = c.sweep(1)
+                    sweeps += 1
+                    hit = f[-1] <= target
+                torch.cuda.synchronize()
+                row[kind] = {"sweeps": sweeps if hit else None, "seconds": time.perf_counter() - t,
+                             "source": src}
+                c.close()
+            rows.append(row)
+            log(f"[bench-ws] N={n} seed {seed}: " + ", ".join(
+                f"{k} {row[k]['sweeps']} sw {row[k]['seconds']:.3f}s" for k in ("random", "learned", "heuristic")))
+        return rows
+
+    def summary(rows, budget):
+        out = {}
+        for kind in ("random", "learned", "heuristic"):
+            sw = [r[kind]["sweeps"] if r[kind]["sweeps"] is not None else budget + 1 for r in rows]
+            tt = [r[kind]["seconds"] for r in rows]
+            out[kind] = {"median_sweeps": float(np.median(sw)), "reached": int(sum(s <= budget for s in sw)),
+                         "median_seconds": float(np.median(tt))}
+        out["speedup_median_seconds_learned_vs_random"] = (out["random"]["median_seconds"]
+                                                          / out["learned"]["median_seconds"])
+        return out
+
+    small = evaluate(N, Rt, Rc, range(20000, 20000 + args.ws_heldout), args.ws_budget)
+    large = evaluate(400, 2000, 1600, range(20000, 20000 + args.ws_heldout_large), args.ws_budget)
+    out = {
+        "metric": "warm-start sweeps and wall time to the random start's best fit x (1+1e-4), 1 MI355X",
+        "value": summary(small, args.ws_budget)["learned"]["median_seconds"], "unit": "s", "n_gpus": 1,
+        "higher_is_better": False, "data": "synthetic", "dtype": "f64 CP-ALS, f32 train / bf16 infer",
+        "config": {"workload": f"train {args.ws_train} converged CPDs N=100 R_thc=500 R_cp=400 "
+                               f"(seeds 10000+), held-out {args.ws_heldout} at N=100 and "
+                               f"{args.ws_heldout_large} at N=400 R_thc=2000 R_cp=1600 (seeds 20000+), "
+                               f"budget {args.ws_budget} sweeps, blend sigma 0.25"},
+        "train": {"rows": int(data[0].shape[0]), "steps": len(losses), "seconds": t_train,
+                  "label_seconds": t_label, "loss_first": float(losses[0]), "loss_last": float(losses[-1])},
+        "heldout_n100": summary(small, args.ws_budget),
+        "heldout_n400": summary(large, args.ws_budget),
     }
     print(json.dumps(out), flush=True)
 

@@ -91,6 +91,11 @@ typedef struct {
   int32_t autotune;       /* 1: time both GEMM tile shapes of every grouped
                              FP64/FP32 product at init and keep the faster
                              (cached per process by shape); 0: heuristic      */
+  int32_t solve_panel;    /* blocked Cholesky and triangular solves: 0 = one
+                             level (each 64-wide step updates the whole
+                             trailing matrix); k >= 1 = panels of k 64-wide
+                             blocks, the trailing matrix updated once per
+                             panel by a rank-64k GEMM                       */
   void* stream;           /* hipStream_t the work is ordered on (0 = null stream) */
   void* workspace;        /* DEVICE memory owned by the caller                    */
   size_t workspace_bytes;
@@ -315,11 +320,12 @@ cpd_status cpd_test_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, const vo
                          int32_t a_t, const void* B1, const void* B2, int32_t ldb, int32_t b_t, void* C,
                          int32_t ldc, void* stream);
 /* cpd_test_solve: F (n x R) = M V^{-1} for SPD V (R x R) by the blocked
- *   Cholesky and triangular solves of the sweep (no damped retry).  Sync;
- *   returns CPD_ERR_NOT_SPD (and *failed = 1) on a non-positive pivot. */
+ *   Cholesky and triangular solves of the sweep (no damped retry), with
+ *   panels of `panel` blocks (0: one level).  Sync; returns CPD_ERR_NOT_SPD
+ *   (and *failed = 1) on a non-positive pivot. */
 size_t cpd_test_solve_workspace(int32_t fp32, int32_t R, int32_t n);
 cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, const void* M, void* F,
-                          void* workspace, size_t ws_bytes, void* stream, int32_t* failed);
+                          void* workspace, size_t ws_bytes, void* stream, int32_t* failed, int32_t panel);
 /* cpd_test_gemm_split: C (M x N, FP64) = A B^T from FP64 A (M x K) and
  *   B (N x K) through the split-BF16 product (hi*hi + hi*lo + lo*hi, FP32
  *   accumulation).  With A2 != NULL the A operand is the FP32 product

@@ -35,6 +35,7 @@ class CpdDesc(ctypes.Structure):
         ("use_graph", i32),
         ("fit_every", i32),
         ("autotune", i32),
+        ("solve_panel", i32),
         ("stream", vp),
         ("workspace", vp),
         ("workspace_bytes", ctypes.c_size_t),
@@ -89,7 +90,7 @@ EXPORTS = {
     "cpd_status_string": (ctypes.c_char_p, [i32]),
     "cpd_test_gemm": (i32, [i32, i32, i32, i32, vp, i32, i32, vp, vp, i32, i32, vp, i32, vp]),
     "cpd_test_solve_workspace": (ctypes.c_size_t, [i32, i32, i32]),
-    "cpd_test_solve": (i32, [i32, i32, i32, vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(i32)]),
+    "cpd_test_solve": (i32, [i32, i32, i32, vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(i32), i32]),
     "cpd_test_split_workspace": (ctypes.c_size_t, [i32, i32, i32]),
     "cpd_test_gemm_split": (i32, [i32, i32, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "cpd_test_mfma_probe": (i32, [i32, i32, vp, vp, vp, vp]),

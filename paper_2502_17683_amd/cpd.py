@@ -34,7 +34,8 @@ class CPD:
     """
 
     def __init__(self, X, Z, r_cp, init, precision="fp64", tol=1e-4, fit_floor=1e-7,
-                 chol_fallback=True, use_graph=True, fit_every=1, autotune=False, device="cuda"):
+                 chol_fallback=True, use_graph=True, fit_every=1, autotune=False, solve_panel=0,
+                 device="cuda"):
         self.lib = _lib.load()
         self.device = torch.device(device)
         if not isinstance(X, (list, tuple)):
@@ -66,6 +67,7 @@ class CPD:
         d.use_graph = int(bool(use_graph))
         d.fit_every = int(fit_every)
         d.autotune = int(bool(autotune))
+        d.solve_panel = int(solve_panel)
         d.stream = _stream(self.device).value
         need = self.lib.cpd_workspace_size(ctypes.byref(d))
         if need == 0:
@@ -155,7 +157,7 @@ class CPDBatch:
     """
 
     def __init__(self, problems, precision="mixed", tol=1e-4, fit_floor=1e-7, chol_fallback=True,
-                 use_graph=True, fit_every=1, autotune=False, device="cuda"):
+                 use_graph=True, fit_every=1, autotune=False, solve_panel=0, device="cuda"):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.count = len(problems)
@@ -192,6 +194,7 @@ class CPDBatch:
             d.use_graph = int(bool(use_graph))
             d.fit_every = int(fit_every)
             d.autotune = int(bool(autotune))
+            d.solve_panel = int(solve_panel)
             d.stream = _stream(self.device).value
             self.shapes.append(([d.n[m] for m in range(4)], d.r_thc, d.r_cp))
         need = self.lib.cpd_batch_workspace_size(descs, self.count)
@@ -288,8 +291,9 @@ def test_gemm(A, B1, B2=None, a_t=False, b_t=False):
     return C
 
 
-def test_solve(V, M):
-    """F = M V^{-1} through the library's blocked Cholesky and solves."""
+def test_solve(V, M, panel=0):
+    """F = M V^{-1} through the library's blocked Cholesky and solves
+    (panels of `panel` 64-wide blocks; 0: one level)."""
     lib = _lib.load()
     fp32 = V.dtype == torch.float32
     R, n = V.shape[0], M.shape[0]
@@ -297,7 +301,7 @@ def test_solve(V, M):
     F = torch.empty_like(M)
     failed = ctypes.c_int32(0)
     code = lib.cpd_test_solve(int(fp32), R, n, _ptr(V), _ptr(M), _ptr(F), _ptr(ws), ws.numel(),
-                              _stream(V.device), ctypes.byref(failed))
+                              _stream(V.device), ctypes.byref(failed), int(panel))
     if code not in (_lib.CPD_OK, _lib.CPD_ERR_NOT_SPD):
         check(code, "cpd_test_solve")
     return F, bool(failed.value)

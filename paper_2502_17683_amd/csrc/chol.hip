@@ -2,14 +2,19 @@
 // row-wise solve F = M V^{-1} of the ALS normal equations.
 //
 // V is Tp x Tp row-major (Tp = 64 nblk; padding rows/columns hold the
-// identity).  Right-looking, 64-wide blocks, ONE launch per block step:
-// step j updates every trailing tile (i, k), k >= j+1, with panel j on the
-// matrix cores and, for the tiles of column j+1, immediately factors the
-// updated diagonal block -- every workgroup of that column does so
-// redundantly, so no workgroup ever waits on another -- and solves its own
-// panel tile.  The diagonal blocks of L are never written back to V (other
-// workgroups of the same launch still read the unfactored block); they go
-// to `ldiag` and feed the triangular solves.
+// identity).  Right-looking with two levels of blocking.  Block columns are
+// 64 wide and grouped into panels of pw blocks (pw >= nblk: one level).  Inside a panel, ONE
+// launch per block step: step j updates the panel's tiles (i, k), k >= j+1,
+// with block column j on the matrix cores and, for the tiles of column j+1,
+// immediately factors the updated diagonal block -- every workgroup of that
+// column does so redundantly, so no workgroup ever waits on another -- and
+// solves its own tile of the column.  After a panel, one GEMM applies its
+// rank-(64 PANEL) update to the trailing matrix (and, in the forward
+// solve, to the right-hand sides): the trailing matrix is read and written
+// once per panel instead of once per block column.  The diagonal blocks of
+// L are never written back to V (other workgroups of the same launch still
+// read the unfactored block); they go to `ldiag` and feed the triangular
+// solves.
 //
 // The sequential parts (diagonal factorisation, triangular solves of a
 // 64-wide strip) use the "strip" thread layout: thread t owns row t / 4 and
@@ -226,17 +231,56 @@ __device__ __forceinline__ void tri_tile(int bid, int k0, int nblk, int& i, int&
   i = k + bid;
 }
 
-// Tiles launched by each step.
-__host__ __device__ inline int chol_tiles(int nblk, int j) {
-  if (j > nblk - 2) return 0;
-  const int t = nblk - 1 - j;
-  return (j < 0) ? nblk : t * (t + 1) / 2;  // step -1: column 0 only
+// Block ranges of one launch.  Factorisation: step j (updates with block
+// column j when j >= lo, factors column j + 1) covers columns j+1 .. kmax.
+// Forward solve: same shape.  Backward solve: step js (updates with column
+// js when js <= hi, solves column js - 1) covers columns kmin .. js-1.
+// An empty range has kmax < j + 1 (kmin > js - 1).
+__host__ __device__ inline void chol_range(int nblk, int pw, int pc, int tc, int& j, int& lo, int& kmax) {
+  j = 0;
+  lo = 0;
+  kmax = -1;
+  if (pc < 0 || tc < 0) return;
+  lo = pw * pc;
+  const int hi = nblk - 1 < lo + pw - 1 ? nblk - 1 : lo + pw - 1;
+  j = lo - 1 + tc;
+  if (j >= hi) {
+    kmax = -1;
+    return;
+  }
+  kmax = j < lo ? j + 1 : hi;
 }
-__host__ __device__ inline int fwd_tiles(int nblk, int nrt, int j) {
-  if (j < -1 || j > nblk - 2) return 0;
-  return nrt * ((j < 0) ? 1 : nblk - 1 - j);
+__host__ __device__ inline void bwd_range(int nblk, int pw, int pf, int tf, int& js, int& hi, int& kmin) {
+  js = 0;
+  hi = -1;
+  kmin = 1;
+  if (pf < 0 || tf < 0) return;
+  const int lo = pw * pf;
+  hi = nblk - 1 < lo + pw - 1 ? nblk - 1 : lo + pw - 1;
+  js = hi + 1 - tf;
+  if (lo > hi || js < lo + 1) {
+    kmin = js;  // empty
+    return;
+  }
+  kmin = js > hi ? js - 1 : lo;
 }
-
+__host__ __device__ inline int chol_tiles(int nblk, int pw, int pc, int tc) {
+  int j, lo, kmax;
+  chol_range(nblk, pw, pc, tc, j, lo, kmax);
+  int t = 0;
+  for (int k = j + 1; k <= kmax; ++k) t += nblk - k;
+  return t;
+}
+__host__ __device__ inline int fwd_tiles(int nblk, int nrt, int pw, int pf, int tf) {
+  int js, lo, kmax;
+  chol_range(nblk, pw, pf, tf, js, lo, kmax);
+  return kmax >= js + 1 ? nrt * (kmax - js) : 0;
+}
+__host__ __device__ inline int bwd_tiles(int nblk, int nrt, int pw, int pf, int tf) {
+  int js, hi, kmin;
+  bwd_range(nblk, pw, pf, tf, js, hi, kmin);
+  return js - 1 >= kmin ? nrt * (js - kmin) : 0;
+}
 
 // One launch of the blocked factorisation / solve.
 //   STEP_CHOL:     Cholesky step j (tiles of the trailing lower triangle).
@@ -252,7 +296,7 @@ __host__ __device__ inline int fwd_tiles(int nblk, int nrt, int j) {
 // functions doubles the register use and spills.)
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, const int* offs, int nprob,
-                                                    int step, int retry_pass) {
+                                                    StepCfg cfg, int retry_pass) {
   typedef typename Acc4<T>::type acc_t;
   __shared__ T S0[TB * LDT];
   __shared__ T S1[TB * LDT];
@@ -269,7 +313,6 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
   DevState* const st = probs[pid].st;
   const int nblk = probs[pid].nblk;
   const int n = probs[pid].n;
-  const int j = MODE == STEP_BWD ? nblk - step : step;
   int bid = blockIdx.x - offs[pid];
   if (st->done) return;
   const int Tp = nblk * TB;
@@ -278,8 +321,11 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
 
   if constexpr (MODE == STEP_CHOL || MODE == STEP_CHOL_FWD) {
     if (MODE == STEP_CHOL_FWD ? st->chol_fail : (retry_pass ? !st->retry_active : st->chol_fail)) return;
-    const int nc = MODE == STEP_CHOL ? 1 << 30 : chol_tiles(nblk, j);
+    int j, jlo, kmax;
+    chol_range(nblk, cfg.pw, cfg.pc, cfg.tc, j, jlo, kmax);
+    const int nc = MODE == STEP_CHOL ? 1 << 30 : chol_tiles(nblk, cfg.pw, cfg.pc, cfg.tc);
     if (bid < nc) {
+      const bool upd = j >= jlo;  // update with block column j (inside the panel)
       int i, k;
       tri_tile(bid, j + 1, nblk, i, k);
       T* tile = V + (size_t)i * TB * Tp + (size_t)k * TB;
@@ -287,14 +333,14 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
       acc_t acc[4];
       T ra[16], rb[16];
       load_acc<T>(acc, tile, Tp, TB, lane, w);
-      if (j >= 0) {
+      if (upd) {
         fetch_block<T>(ra, V + (size_t)i * TB * Tp + (size_t)j * TB, Tp, TB, tid);
         fetch_block<T>(rb, V + (size_t)k * TB * Tp + (size_t)j * TB, Tp, TB, tid);
       }
       acc_t dd[4];
       const bool need_d = (k == j + 1) && (i != k);
       if (need_d) load_acc<T>(dd, V + (size_t)k * TB * Tp + (size_t)k * TB, Tp, TB, lane, w);
-      if (j >= 0) {
+      if (upd) {
         // tile -= L_ij L_kj^T
         put_block<T, true>(S0, ra, tid);
         put_block<T, true>(S1, rb, tid);
@@ -315,7 +361,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
       if (i == k) {
         acc_to_lds<T>(acc, S2, lane, w);
       } else {
-        if (j >= 0) {
+        if (upd) {
           acc_t p[4];
 #pragma unroll
           for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
@@ -357,14 +403,16 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
   }
   if constexpr (MODE != STEP_CHOL) {
     constexpr bool FWD = MODE != STEP_BWD;
-    const int js = MODE == STEP_CHOL_FWD ? j - 1 : j;  // solve step
+    int js, lim, kext;  // forward: lim = panel start; backward: lim = panel end
+    if (FWD) chol_range(nblk, cfg.pw, cfg.pf, cfg.tf, js, lim, kext);
+    else bwd_range(nblk, cfg.pw, cfg.pf, cfg.tf, js, lim, kext);
     const int nrt = (n + TB - 1) / TB;
     const int rt = bid % nrt;
     const int k = FWD ? js + 1 + bid / nrt : js - 1 - bid / nrt;
     const int r0 = rt * TB;
     const int nrows = min(TB, n - r0);
     T* tile = M + (size_t)r0 * Tp + (size_t)k * TB;
-    const bool has_update = FWD ? (js >= 0) : (js < nblk);
+    const bool has_update = FWD ? (js >= lim) : (js <= lim);
     const bool solve = FWD ? (k == js + 1) : (k == js - 1);
     // every global load of the step is issued up front
     acc_t acc[4];
@@ -406,51 +454,115 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
   }
 }
 
-int step_tiles(int mode, int nblk, int n, int step) {
+int step_tiles(int mode, int nblk, int n, StepCfg c) {
   const int nrt = (n + TB - 1) / TB;
   switch (mode) {
-    case STEP_CHOL: return chol_tiles(nblk, step);
-    case STEP_FWD: return fwd_tiles(nblk, nrt, step);
-    case STEP_CHOL_FWD: return chol_tiles(nblk, step) + fwd_tiles(nblk, nrt, step - 1);
-    default: {
-      const int j = nblk - step;
-      if (j < 1) return 0;
-      return nrt * (j == nblk ? 1 : j);
-    }
-  }
-}
-int step_first(int mode) { return mode == STEP_BWD ? 0 : -1; }
-int step_count(int mode, int max_nblk) {
-  switch (mode) {
-    case STEP_CHOL:
-    case STEP_FWD: return max_nblk;       // j = -1 .. nblk-2
-    case STEP_CHOL_FWD: return max_nblk + 1;  // t = -1 .. nblk-1
-    default: return max_nblk;              // s = 0 .. nblk-1
+    case STEP_CHOL: return chol_tiles(nblk, c.pw, c.pc, c.tc);
+    case STEP_FWD: return fwd_tiles(nblk, nrt, c.pw, c.pf, c.tf);
+    case STEP_CHOL_FWD: return chol_tiles(nblk, c.pw, c.pc, c.tc) + fwd_tiles(nblk, nrt, c.pw, c.pf, c.tf);
+    default: return bwd_tiles(nblk, nrt, c.pw, c.pf, c.tf);
   }
 }
 
 template <typename T>
 void step_group(hipStream_t s, int mode, const StepProb<T>* probs, const int* offs, int nprob, int total_tiles,
-                int step, int retry_pass) {
+                StepCfg cfg, int retry_pass) {
   if (total_tiles <= 0) return;
   dim3 grid(total_tiles), block(256);
   switch (mode) {
     case STEP_CHOL:
-      hipLaunchKernelGGL((step_kernel<T, STEP_CHOL>), grid, block, 0, s, probs, offs, nprob, step, retry_pass);
+      hipLaunchKernelGGL((step_kernel<T, STEP_CHOL>), grid, block, 0, s, probs, offs, nprob, cfg, retry_pass);
       break;
     case STEP_FWD:
-      hipLaunchKernelGGL((step_kernel<T, STEP_FWD>), grid, block, 0, s, probs, offs, nprob, step, retry_pass);
+      hipLaunchKernelGGL((step_kernel<T, STEP_FWD>), grid, block, 0, s, probs, offs, nprob, cfg, retry_pass);
       break;
     case STEP_BWD:
-      hipLaunchKernelGGL((step_kernel<T, STEP_BWD>), grid, block, 0, s, probs, offs, nprob, step, retry_pass);
+      hipLaunchKernelGGL((step_kernel<T, STEP_BWD>), grid, block, 0, s, probs, offs, nprob, cfg, retry_pass);
       break;
     default:
-      hipLaunchKernelGGL((step_kernel<T, STEP_CHOL_FWD>), grid, block, 0, s, probs, offs, nprob, step,
+      hipLaunchKernelGGL((step_kernel<T, STEP_CHOL_FWD>), grid, block, 0, s, probs, offs, nprob, cfg,
                          retry_pass);
   }
 }
 
-template void step_group<double>(hipStream_t, int, const StepProb<double>*, const int*, int, int, int, int);
-template void step_group<float>(hipStream_t, int, const StepProb<float>*, const int*, int, int, int, int);
+template <typename T>
+bool panel_gemm(int kind, const StepProb<T>& q, int pw, int p, GemmArgs<T>& g) {
+  const int Tp = TB * q.nblk;
+  const int lo = pw * p;
+  const int hi = q.nblk - 1 < lo + pw - 1 ? q.nblk - 1 : lo + pw - 1;
+  if (lo > hi) return false;
+  const int K = TB * (hi - lo + 1);
+  const int c0 = TB * (hi + 1);
+  const int32_t* done = &q.st->done;
+  T* const V = q.V;
+  T* const M = q.M;
+  switch (kind) {
+    case PG_SYRK:
+      if (c0 >= Tp) return false;
+      g = GemmArgs<T>{Tp - c0, Tp - c0, K, V + (size_t)c0 * Tp + TB * lo, Tp, V + (size_t)c0 * Tp + TB * lo,
+                      nullptr, Tp, V + (size_t)c0 * Tp + c0, Tp, nullptr, T(-1), T(1), done};
+      g.lower = 1;
+      return true;
+    case PG_FWD:
+      if (c0 >= Tp) return false;
+      g = GemmArgs<T>{q.n, Tp - c0, K, M + TB * lo, Tp, V + (size_t)c0 * Tp + TB * lo, nullptr, Tp, M + c0, Tp,
+                      nullptr, T(-1), T(1), done};
+      return true;
+    default:
+      if (lo == 0) return false;
+      g = GemmArgs<T>{q.n, TB * lo, K, M + TB * lo, Tp, V + (size_t)TB * lo * Tp, nullptr, Tp, M, Tp, nullptr,
+                      T(-1), T(1), done};
+      return true;
+  }
+}
+
+std::vector<SolveItem> solve_schedule(int sched, int max_nblk, int pw) {
+  std::vector<SolveItem> out;
+  if (pw < 1) pw = 1;
+  const int P = panel_count(max_nblk, pw);
+  auto step = [&](int mode, int pc, int tc, int pf, int tf) {
+    out.push_back(SolveItem{mode, StepCfg{pw, pc, tc, pf, tf}, {-1, -1}, {0, 0}});
+  };
+  auto gemm = [&](int k0, int p0, int k1, int p1) {
+    if (k0 < 0 && k1 < 0) return;
+    out.push_back(SolveItem{-1, StepCfg{pw, -1, 0, -1, 0}, {k0, k1}, {p0, p1}});
+  };
+  switch (sched) {
+    case SCHED_CHOL:
+      for (int p = 0; p < P; ++p) {
+        for (int t = 0; t < pw; ++t) step(STEP_CHOL, p, t, -1, 0);
+        if (p + 1 < P) gemm(PG_SYRK, p, -1, 0);
+      }
+      break;
+    case SCHED_CHOL_FWD:
+      if (P == 1) {
+        // one level: forward step t - 1 rides with factorisation step t
+        for (int t = 0; t <= max_nblk; ++t) step(STEP_CHOL_FWD, 0, t, 0, t - 1);
+        break;
+      }
+      for (int p = 0; p <= P; ++p) {
+        for (int t = 0; t < pw; ++t) step(STEP_CHOL_FWD, p < P ? p : -1, t, p - 1, t);
+        if (p < P) gemm(p + 1 < P ? PG_SYRK : -1, p, p >= 1 ? PG_FWD : -1, p - 1);
+      }
+      break;
+    case SCHED_FWD:
+      for (int p = 0; p < P; ++p) {
+        for (int t = 0; t < pw; ++t) step(STEP_FWD, -1, 0, p, t);
+        if (p + 1 < P) gemm(PG_FWD, p, -1, 0);
+      }
+      break;
+    default:
+      for (int p = P - 1; p >= 0; --p) {
+        for (int t = 0; t < pw; ++t) step(STEP_BWD, -1, 0, p, t);
+        if (p > 0) gemm(PG_BWD, p, -1, 0);
+      }
+  }
+  return out;
+}
+
+template void step_group<double>(hipStream_t, int, const StepProb<double>*, const int*, int, int, StepCfg, int);
+template void step_group<float>(hipStream_t, int, const StepProb<float>*, const int*, int, int, StepCfg, int);
+template bool panel_gemm<double>(int, const StepProb<double>&, int, int, GemmArgs<double>&);
+template bool panel_gemm<float>(int, const StepProb<float>&, int, int, GemmArgs<float>&);
 
 }  // namespace thccp

@@ -75,15 +75,25 @@ struct GroupOp {
   void* tab = nullptr;   // device: GemmArgs<T>[] / SplitArgs[]
   int* offs = nullptr;   // device: nprob + 1 prefix sums
   int total = 0;
+  int count = 0;         // table entries
   int bm = 64;
   bool a_t = false, b_t = false, had = false, apair = false, bpair = false;
 };
 
-// Step launches of the factorisation / solves of one mode.
+// One launch of a blocked solve: a step launch or a grouped panel GEMM.
+struct SolveLaunch {
+  int mode = -1;          // StepMode, or -1 for the GEMM
+  StepCfg cfg{1, -1, 0, -1, 0};
+  int* offs = nullptr;    // device, nprob + 1 prefix sums (step launches)
+  int total = 0;
+  GroupOp gemm;
+};
+// The factorisation and solves of one mode.
 struct StepOps {
   void* probs = nullptr;                // StepProb<T>[nprob]
-  std::vector<int*> offs[4];            // per step-mode: per launch, nprob + 1 ints (device)
-  std::vector<int> total[4];            // per step-mode: per launch, workgroups
+  std::vector<SolveLaunch> chol[2];     // factorisation; [1] the damped-retry pass
+  std::vector<SolveLaunch> cholfwd;     // factorisation fused with the forward solve
+  std::vector<SolveLaunch> fwd, bwd;
 };
 
 // Process-wide autotune cache: (kind, shapes) -> tile edge.
@@ -122,6 +132,7 @@ struct cpd_plan_s {
   int32_t* forced_dev = nullptr;                // nprob flags: problems promoted to the FP64 path
   std::vector<int32_t> forced;                  // host copy (sticky)
   double cond_limit = 1e5;
+  int panel_width = 0;                          // blocks per solve panel; 0: one level
   StepOps steps[4];
   void* formv[4] = {nullptr, nullptr, nullptr, nullptr};
   void* norm[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -302,6 +313,7 @@ GroupOp gemm_op(TableBuilder& tb, const std::vector<GemmArgs<T>>& v, bool at, bo
     t128 += gemm_tile_count(g.M, g.N, 128);
   }
   op.bm = t128 >= 256 ? 128 : 64;
+  op.count = (int)v.size();
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(tune_key(kind, dims));
@@ -319,6 +331,7 @@ GroupOp split_op(TableBuilder& tb, const std::vector<SplitArgs>& v, bool apair, 
   GroupOp op;
   op.apair = apair;
   op.bpair = bpair;
+  op.count = (int)v.size();
   std::vector<int> offs(1, 0);
   for (auto& g : v) offs.push_back(offs.back() + split_tile_count(g.M, g.N));
   op.total = offs.back();
@@ -328,6 +341,48 @@ GroupOp split_op(TableBuilder& tb, const std::vector<SplitArgs>& v, bool apair, 
 }
 
 const int partner_of[4] = {1, 0, 3, 2};
+
+// Device tables of one solve schedule.  gate_kind: 0 none, 1 skip problems
+// whose factorisation failed, 2 only problems in the damped-retry pass.
+template <typename T>
+std::vector<SolveLaunch> build_sched(TableBuilder& tb, int sched, int max_nblk, int pw,
+                                     const std::vector<StepProb<T>>& sp, int gate_kind, const std::string& kind) {
+  std::vector<SolveLaunch> out;
+  for (const SolveItem& it : solve_schedule(sched, max_nblk, pw)) {
+    SolveLaunch L;
+    L.mode = it.mode;
+    L.cfg = it.cfg;
+    if (it.mode >= 0) {
+      std::vector<int> offs(1, 0);
+      for (auto& q : sp) offs.push_back(offs.back() + step_tiles(it.mode, q.nblk, q.n, it.cfg));
+      L.total = offs.back();
+      L.offs = (int*)tb.put(offs);
+    } else {
+      std::vector<GemmArgs<T>> v;
+      bool bt = true;
+      for (int h = 0; h < 2; ++h) {
+        if (it.g_kind[h] < 0) continue;
+        bt = it.g_kind[h] != PG_BWD;
+        for (auto& q : sp) {
+          GemmArgs<T> g;
+          if (!panel_gemm<T>(it.g_kind[h], q, pw, it.g_panel[h], g)) continue;
+          if (gate_kind == 1) {
+            g.gate = &q.st->chol_fail;
+            g.want = 0;
+          } else if (gate_kind == 2) {
+            g.gate = &q.st->retry_active;
+            g.want = 1;
+          }
+          v.push_back(g);
+        }
+      }
+      L.gemm = gemm_op<T>(tb, v, false, false, kind + "panel");
+      L.gemm.b_t = bt;
+    }
+    out.push_back(L);
+  }
+  return out;
+}
 
 template <typename T>
 void build_typed(TableBuilder& tb, cpd_plan_s* p, Bufs<T> Prob::*bufs, bool gated) {
@@ -372,18 +427,12 @@ void build_typed(TableBuilder& tb, cpd_plan_s* p, Bufs<T> Prob::*bufs, bool gate
     p->proj[n] = gemm_op<T>(tb, proj, true, false, kind + "proj");
     StepOps& so = p->steps[n];
     so.probs = tb.put(sp);
-    for (int mode = 0; mode < 4; ++mode) {
-      so.offs[mode].clear();
-      so.total[mode].clear();
-      const int first = step_first(mode), cnt = step_count(mode, p->maxNblk);
-      for (int k = 0; k < cnt; ++k) {
-        std::vector<int> offs(1, 0);
-        for (int i = 0; i < np; ++i)
-          offs.push_back(offs.back() + step_tiles(mode, p->P[i].nblk, p->P[i].n[n], first + k));
-        so.total[mode].push_back(offs.back());
-        so.offs[mode].push_back((int*)tb.put(offs));
-      }
-    }
+    const int pw = p->panel_width > 0 ? p->panel_width : p->maxNblk;
+    so.chol[0] = build_sched<T>(tb, SCHED_CHOL, p->maxNblk, pw, sp, 1, kind);
+    so.chol[1] = build_sched<T>(tb, SCHED_CHOL, p->maxNblk, pw, sp, 2, kind);
+    so.cholfwd = build_sched<T>(tb, SCHED_CHOL_FWD, p->maxNblk, pw, sp, 1, kind);
+    so.fwd = build_sched<T>(tb, SCHED_FWD, p->maxNblk, pw, sp, 0, kind);
+    so.bwd = build_sched<T>(tb, SCHED_BWD, p->maxNblk, pw, sp, 0, kind);
     p->formv[n] = tb.put(fv);
     p->norm[n] = tb.put(nm);
     if (n == 3) {
@@ -527,6 +576,7 @@ int init_shape(cpd_plan_s* p, const cpd_desc* descs, int count) {
   p->allow_fallback = descs[0].chol_fallback;
   p->use_graph = descs[0].use_graph;
   p->autotune = descs[0].autotune;
+  p->panel_width = descs[0].solve_panel;
   p->tol = descs[0].tol;
   p->fit_floor = descs[0].fit_floor;
   p->launched = 0;
@@ -594,34 +644,37 @@ void split_inputs(Prob& q, hipStream_t s, std::map<const void*, int>& done_split
 // --------------------------------------------------------- grouped launches
 template <typename T>
 void run_gemm(cpd_plan_s* p, hipStream_t s, const GroupOp& op) {
-  gemm_group<T>(s, (const GemmArgs<T>*)op.tab, op.offs, p->count, op.total, op.a_t, op.b_t, op.had, op.bm);
+  (void)p;
+  gemm_group<T>(s, (const GemmArgs<T>*)op.tab, op.offs, op.count, op.total, op.a_t, op.b_t, op.had, op.bm);
 }
 void run_split(cpd_plan_s* p, hipStream_t s, const GroupOp& op) {
-  gemm_split_group(s, (const SplitArgs*)op.tab, op.offs, p->count, op.total, op.apair, op.bpair);
+  (void)p;
+  gemm_split_group(s, (const SplitArgs*)op.tab, op.offs, op.count, op.total, op.apair, op.bpair);
 }
 template <typename T>
-void run_steps(cpd_plan_s* p, hipStream_t s, int n, int mode, int retry_pass) {
-  StepOps& so = p->steps[n];
-  const int first = step_first(mode);
-  for (size_t k = 0; k < so.offs[mode].size(); ++k)
-    step_group<T>(s, mode, (const StepProb<T>*)so.probs, so.offs[mode][k], p->count, so.total[mode][k],
-                  first + (int)k, retry_pass);
+void run_sched(cpd_plan_s* p, hipStream_t s, int n, const std::vector<SolveLaunch>& sched, int retry_pass) {
+  const StepProb<T>* probs = (const StepProb<T>*)p->steps[n].probs;
+  for (const SolveLaunch& L : sched) {
+    if (L.mode < 0) run_gemm<T>(p, s, L.gemm);
+    else step_group<T>(s, L.mode, probs, L.offs, p->count, L.total, L.cfg, retry_pass);
+  }
 }
 
 template <typename T>
 void solve_mode(cpd_plan_s* p, int n, hipStream_t s, bool with_inner, bool fast) {
   const FormVArgs<T>* fv = (const FormVArgs<T>*)p->formv[n];
+  StepOps& so = p->steps[n];
   form_v_group<T>(s, fv, p->count, p->maxTp, 0);
   if (fast) {
-    run_steps<T>(p, s, n, STEP_CHOL_FWD, 0);
-    run_steps<T>(p, s, n, STEP_BWD, 0);
+    run_sched<T>(p, s, n, so.cholfwd, 0);
+    run_sched<T>(p, s, n, so.bwd, 0);
   } else {
-    run_steps<T>(p, s, n, STEP_CHOL, 0);
+    run_sched<T>(p, s, n, so.chol[0], 0);
     retry_prepare_group<T>(s, fv, p->count, p->allow_fallback);
     form_v_group<T>(s, fv, p->count, p->maxTp, 1);
-    run_steps<T>(p, s, n, STEP_CHOL, 1);
-    run_steps<T>(p, s, n, STEP_FWD, 0);
-    run_steps<T>(p, s, n, STEP_BWD, 0);
+    run_sched<T>(p, s, n, so.chol[1], 1);
+    run_sched<T>(p, s, n, so.fwd, 0);
+    run_sched<T>(p, s, n, so.bwd, 0);
   }
   normalise_group<T>(s, (const NormArgs<T>*)(with_inner ? p->norm_inner : p->norm[n]), p->count, p->maxR);
 }
@@ -849,9 +902,9 @@ void autotune_ops(cpd_plan_s* p, hipStream_t s) {
   }
   int* doffs = (int*)(p->ws + p->ws_bytes - 4096);
   auto tune = [&](GroupOp& op, const std::string& kind) {
-    if (op.total == 0 || !op.tab || (size_t)(p->count + 1) * sizeof(int) > 4096) return;
-    std::vector<GemmArgs<T>> host(p->count);
-    if (hipMemcpy(host.data(), op.tab, sizeof(GemmArgs<T>) * p->count, hipMemcpyDeviceToHost) != hipSuccess)
+    if (op.total == 0 || !op.tab || (size_t)(op.count + 1) * sizeof(int) > 4096) return;
+    std::vector<GemmArgs<T>> host(op.count);
+    if (hipMemcpy(host.data(), op.tab, sizeof(GemmArgs<T>) * op.count, hipMemcpyDeviceToHost) != hipSuccess)
       return;
     std::vector<int> dims;
     for (auto& g : host) {
@@ -878,7 +931,7 @@ void autotune_ops(cpd_plan_s* p, hipStream_t s) {
       for (int w = 0; w < 2; ++w) {  // second pass is the timed one
         (void)hipEventRecord(e0, s);
         for (int r = 0; r < 3; ++r)
-          gemm_group<T>(s, (const GemmArgs<T>*)op.tab, doffs, p->count, offs.back(), op.a_t, op.b_t, op.had, bm);
+          gemm_group<T>(s, (const GemmArgs<T>*)op.tab, doffs, op.count, offs.back(), op.a_t, op.b_t, op.had, bm);
         (void)hipEventRecord(e1, s);
         (void)hipEventSynchronize(e1);
         (void)hipEventElapsedTime(&ms, e0, e1);
@@ -1240,13 +1293,13 @@ cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out) {
         // forward solve, backward solve, normalisation
         if (f32) {
           if (which != 6) form_v_group<float>(s, (const FormVArgs<float>*)p->formv[0], p->count, p->maxTp, 0);
-          if (which != 6) run_steps<float>(p, s, 0, STEP_CHOL_FWD, 0);
-          if (which != 5) run_steps<float>(p, s, 0, STEP_BWD, 0);
+          if (which != 6) run_sched<float>(p, s, 0, p->steps[0].cholfwd, 0);
+          if (which != 5) run_sched<float>(p, s, 0, p->steps[0].bwd, 0);
           if (which == 4) normalise_group<float>(s, (const NormArgs<float>*)p->norm[0], p->count, p->maxR);
         } else {
           if (which != 6) form_v_group<double>(s, (const FormVArgs<double>*)p->formv[0], p->count, p->maxTp, 0);
-          if (which != 6) run_steps<double>(p, s, 0, STEP_CHOL_FWD, 0);
-          if (which != 5) run_steps<double>(p, s, 0, STEP_BWD, 0);
+          if (which != 6) run_sched<double>(p, s, 0, p->steps[0].cholfwd, 0);
+          if (which != 5) run_sched<double>(p, s, 0, p->steps[0].bwd, 0);
           if (which == 4) normalise_group<double>(s, (const NormArgs<double>*)p->norm[0], p->count, p->maxR);
         }
         return;

@@ -29,6 +29,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& p, int bid_in, int 
   const int tiles_n = (p.N + BN - 1) / BN;
   const int bid = xcd_remap(bid_in, nblocks);
   const int m0 = (bid / tiles_n) * BM, n0 = (bid % tiles_n) * BN;
+  if (p.lower && n0 > m0 + BM - 1) return;  // tile strictly above the diagonal
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
 
@@ -186,6 +187,7 @@ static void launch_group_tile(hipStream_t s, const GemmArgs<T>* tab, const int* 
   THCCP_GEMM_GCASE(true, false, false)
   THCCP_GEMM_GCASE(false, false, true)
   THCCP_GEMM_GCASE(true, false, true)
+  THCCP_GEMM_GCASE(false, true, false)
 #undef THCCP_GEMM_GCASE
 }
 
@@ -201,13 +203,13 @@ template void gemm_group<float>(hipStream_t, const GemmArgs<float>*, const int*,
 
 void gemm_f64(hipStream_t s, const GemmF64& g) {
   GemmArgs<double> a{g.M, g.N, g.K, g.A, g.lda, g.B1, g.B2, g.ldb, g.C, g.ldc, g.C2,
-                     g.alpha, g.beta, g.done, nullptr, 0};
+                     g.alpha, g.beta, g.done, nullptr, 0, 0};
   gemm_dispatch<double>(s, a, g.a_t, g.b_t, g.B2 != nullptr);
 }
 
 void gemm_f32(hipStream_t s, const GemmF32& g) {
   GemmArgs<float> a{g.M, g.N, g.K, g.A, g.lda, g.B1, g.B2, g.ldb, g.C, g.ldc, g.C2,
-                    g.alpha, g.beta, g.done, nullptr, 0};
+                    g.alpha, g.beta, g.done, nullptr, 0, 0};
   gemm_dispatch<float>(s, a, g.a_t, g.b_t, g.B2 != nullptr);
 }
 

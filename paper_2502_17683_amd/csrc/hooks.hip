@@ -55,13 +55,15 @@ template <typename T>
 size_t solve_ws(int R, int n) {
   const int nblk = (R + 63) / 64, Tp = nblk * 64;
   return al(sizeof(DevState)) + al(sizeof(T) * (size_t)Tp * Tp) + al(sizeof(T) * (size_t)nblk * 4096) +
-         al(sizeof(T) * Tp) + al(sizeof(T) * (size_t)n * Tp) + al(sizeof(StepProb<T>)) + al(sizeof(int) * 2);
+         al(sizeof(T) * Tp) + al(sizeof(T) * (size_t)n * Tp) + al(sizeof(StepProb<T>)) + al(sizeof(int) * 2) +
+         al(sizeof(GemmArgs<T>));
 }
 
-// One-problem run of the grouped factorisation (STEP_CHOL), forward and
-// backward solves -- the launches of a sweep with the damped retry left out.
+// One-problem run of the blocked factorisation, forward and backward solves
+// (the schedules of a sweep with the damped retry left out).
 template <typename T>
-cpd_status solve_impl(int R, int n, const T* V, const T* M, T* F, void* ws, hipStream_t s, int32_t* failed) {
+cpd_status solve_impl(int R, int n, const T* V, const T* M, T* F, void* ws, hipStream_t s, int32_t* failed,
+                      int pw) {
   const int nblk = (R + 63) / 64, Tp = nblk * 64;
   char* b = (char*)ws;
   DevState* st = (DevState*)b; b += al(sizeof(DevState));
@@ -70,22 +72,34 @@ cpd_status solve_impl(int R, int n, const T* V, const T* M, T* F, void* ws, hipS
   T* diagL = (T*)b; b += al(sizeof(T) * Tp);
   T* Mp = (T*)b; b += al(sizeof(T) * (size_t)n * Tp);
   StepProb<T>* prob = (StepProb<T>*)b; b += al(sizeof(StepProb<T>));
-  int* offs = (int*)b;
+  int* offs = (int*)b; b += al(sizeof(int) * 2);
+  GemmArgs<T>* gtab = (GemmArgs<T>*)b;
   hipLaunchKernelGGL(init_state, dim3(1), dim3(64), 0, s, st);
   hipLaunchKernelGGL((pad_square<T>), dim3(grid_of((size_t)Tp * Tp)), dim3(256), 0, s, V, R, Tp, Vp);
   hipLaunchKernelGGL((pad_rows<T>), dim3(grid_of((size_t)n * Tp)), dim3(256), 0, s, M, n, R, Tp, Mp);
   StepProb<T> hp{Vp, ldiag, diagL, Mp, st, nblk, n};
   if (hipMemcpyAsync(prob, &hp, sizeof(hp), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
-  const int modes[3] = {STEP_CHOL, STEP_FWD, STEP_BWD};
-  for (int mode : modes) {
-    const int first = step_first(mode), cnt = step_count(mode, nblk);
-    for (int k = 0; k < cnt; ++k) {
-      int ho[2] = {0, step_tiles(mode, nblk, n, first + k)};
-      // offsets are passed by value through a tiny per-launch upload (this
-      // hook is not performance-critical)
-      if (hipMemcpyAsync(offs, ho, sizeof(ho), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
-      if (hipStreamSynchronize(s) != hipSuccess) return CPD_ERR_HIP;
-      step_group<T>(s, mode, prob, offs, 1, ho[1], first + k, 0);
+  for (int sched : {SCHED_CHOL, SCHED_FWD, SCHED_BWD}) {
+    for (const SolveItem& it : solve_schedule(sched, nblk, pw)) {
+      // tables are passed through a tiny per-launch upload (this hook is not
+      // performance-critical)
+      if (it.mode >= 0) {
+        int ho[2] = {0, step_tiles(it.mode, nblk, n, it.cfg)};
+        if (hipMemcpyAsync(offs, ho, sizeof(ho), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return CPD_ERR_HIP;
+        step_group<T>(s, it.mode, prob, offs, 1, ho[1], it.cfg, 0);
+        continue;
+      }
+      for (int h = 0; h < 2; ++h) {
+        GemmArgs<T> g;
+        if (it.g_kind[h] < 0 || !panel_gemm<T>(it.g_kind[h], hp, pw, it.g_panel[h], g)) continue;
+        const int bm = gemm_default_tile(g.M, g.N);
+        int ho[2] = {0, gemm_tile_count(g.M, g.N, bm)};
+        if (hipMemcpyAsync(offs, ho, sizeof(ho), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
+        if (hipMemcpyAsync(gtab, &g, sizeof(g), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return CPD_ERR_HIP;
+        gemm_group<T>(s, gtab, offs, 1, ho[1], false, it.g_kind[h] != PG_BWD, false, bm);
+      }
     }
   }
   hipLaunchKernelGGL((unpad_rows<T>), dim3(grid_of((size_t)n * R)), dim3(256), 0, s, Mp, n, R, Tp, F);
@@ -123,12 +137,14 @@ size_t cpd_test_solve_workspace(int32_t fp32, int32_t R, int32_t n) {
 }
 
 cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, const void* M, void* F,
-                          void* workspace, size_t ws_bytes, void* stream, int32_t* failed) {
+                          void* workspace, size_t ws_bytes, void* stream, int32_t* failed, int32_t panel) {
+  if (panel < 0) return CPD_ERR_INVALID_ARG;
+  const int pw = panel > 0 ? panel : (R + 63) / 64;
   if (R <= 0 || n <= 0 || !V || !M || !F) return CPD_ERR_INVALID_ARG;
   if (!workspace || ws_bytes < cpd_test_solve_workspace(fp32, R, n)) return CPD_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  if (fp32) return solve_impl<float>(R, n, (const float*)V, (const float*)M, (float*)F, workspace, s, failed);
-  return solve_impl<double>(R, n, (const double*)V, (const double*)M, (double*)F, workspace, s, failed);
+  if (fp32) return solve_impl<float>(R, n, (const float*)V, (const float*)M, (float*)F, workspace, s, failed, pw);
+  return solve_impl<double>(R, n, (const double*)V, (const double*)M, (double*)F, workspace, s, failed, pw);
 }
 
 size_t cpd_test_split_workspace(int32_t M, int32_t N, int32_t K) {

@@ -10,6 +10,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "common.h"
 
 namespace thccp {
@@ -24,6 +26,8 @@ namespace thccp {
 //   done != nullptr: the problem is skipped once *done is set.
 //   gate != nullptr: the problem is skipped unless *gate == want (per-problem
 //   choice between the split-BF16 and the FP64 path).
+//   lower != 0: tiles strictly above the diagonal are skipped (C is only
+//   needed on and below it, as in a symmetric rank-k update).
 template <typename T>
 struct GemmArgs {
   int M, N, K;
@@ -34,6 +38,7 @@ struct GemmArgs {
   const int32_t* done;
   const int32_t* gate = nullptr;
   int32_t want = 0;
+  int32_t lower = 0;
 };
 struct GemmF64 {
   int M, N, K;
@@ -78,17 +83,61 @@ struct StepProb {
   int n;
 };
 enum StepMode { STEP_CHOL = 0, STEP_FWD = 1, STEP_BWD = 2, STEP_CHOL_FWD = 3 };
-// Workgroups of problem (nblk, n) at launch `step` of the given mode
-// (CHOL, FWD: step = j in -1 .. nblk-2; CHOL_FWD: t in -1 .. nblk-1;
-// BWD: s in 0 .. nblk-1 standing for j = nblk - s).
-int step_tiles(int mode, int nblk, int n, int step);
-// First step index of a mode and the number of launches for the largest
-// problem of a group.
-int step_first(int mode);
-int step_count(int mode, int max_nblk);
+
+// Two-level blocking: the 64-wide block columns are grouped into panels of
+// pw blocks.  Inside a panel the step kernel works one block column per
+// launch (panel-local updates only); after a panel, one grouped GEMM applies
+// its rank-(64 pw) update to everything right of it (factorisation, forward
+// solve) or left of it (backward solve).  pw >= nblk is the one-level form:
+// every step updates the whole trailing matrix.
+// One step launch: factorisation step tc of panel pc and solve step tf of
+// panel pf (a negative panel or step: none).  Factorisation step t of panel
+// p updates the panel's remaining block columns with block column
+// pw p - 1 + t (when inside the panel) and factors block column pw p + t;
+// forward step t likewise for the right-hand sides; backward step t solves
+// block column b1 - t of the panel (b1 its last block) after updating the
+// panel's columns left of it.
+struct StepCfg {
+  int pw;
+  int pc, tc;
+  int pf, tf;
+};
+inline int panel_count(int nblk, int pw) { return (nblk + pw - 1) / pw; }
+// Workgroups of problem (nblk, n) in a launch of `mode` with `cfg`.
+int step_tiles(int mode, int nblk, int n, StepCfg cfg);
 template <typename T>
 void step_group(hipStream_t s, int mode, const StepProb<T>* probs, const int* offs, int nprob, int total_tiles,
-                int step, int retry_pass);
+                StepCfg cfg, int retry_pass);
+// The panel update GEMM of panel p for one problem (false: none needed):
+//   PG_SYRK  V[c0:, c0:] -= L[c0:, panel] L[c0:, panel]^T (lower tiles),
+//   PG_FWD   M[:, c0:]   -= G[:, panel] L[c0:, panel]^T,
+//   PG_BWD   M[:, :b0]   -= X[:, panel] L[panel, :b0],
+// with c0 the first column after the panel and b0 its first column.  SYRK
+// and FWD take (a_t, b_t) = (false, true), BWD (false, false).
+enum PanelGemm { PG_SYRK = 0, PG_FWD = 1, PG_BWD = 2 };
+template <typename T>
+bool panel_gemm(int kind, const StepProb<T>& q, int pw, int p, GemmArgs<T>& g);
+
+// Launch order of a blocked solve with panel width pw for problems of up
+// to max_nblk blocks: step launches (mode >= 0) and panel GEMM launches
+// (mode < 0, up to two PanelGemm kinds in one grouped launch).
+//   SCHED_CHOL      factorisation: per panel, its steps, then its SYRK.
+//   SCHED_CHOL_FWD  factorisation fused with the forward solve.  With
+//                   panels, the latter runs one panel behind: the launches
+//                   of panel p also run the forward steps of panel p - 1, and
+//                   one GEMM launch holds the SYRK of panel p and the
+//                   forward update of panel p - 1.  One-level (pw >=
+//                   max_nblk): one block column behind.
+//   SCHED_FWD       forward solve alone;  SCHED_BWD  backward solve (panels
+//                   from the last one down).
+enum SolveSched { SCHED_CHOL = 0, SCHED_CHOL_FWD = 1, SCHED_FWD = 2, SCHED_BWD = 3 };
+struct SolveItem {
+  int mode;
+  StepCfg cfg;
+  int g_kind[2];
+  int g_panel[2];
+};
+std::vector<SolveItem> solve_schedule(int sched, int max_nblk, int pw);
 
 // ------------------------------------------------------------- element-wise
 template <typename T>

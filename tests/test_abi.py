@@ -41,10 +41,10 @@ def test_ctypes_layout_matches_c():
 #include <stddef.h>
 #include "thccp.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(cpd_desc), offsetof(cpd_desc, X),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(cpd_desc), offsetof(cpd_desc, X),
          offsetof(cpd_desc, tol), offsetof(cpd_desc, fit_every), offsetof(cpd_desc, autotune),
-         offsetof(cpd_desc, stream), offsetof(cpd_desc, workspace_bytes), sizeof(cpd_stats_t),
-         offsetof(cpd_stats_t, cond_est), offsetof(cpd_stats_t, fp64_path));
+         offsetof(cpd_desc, solve_panel), offsetof(cpd_desc, stream), offsetof(cpd_desc, workspace_bytes),
+         sizeof(cpd_stats_t), offsetof(cpd_stats_t, cond_est), offsetof(cpd_stats_t, fp64_path));
   return 0;
 }
 '''
@@ -56,8 +56,8 @@ int main(void) {
         got = [int(v) for v in subprocess.check_output([exe]).split()]
     D, S = _lib.CpdDesc, _lib.CpdStats
     want = [ctypes.sizeof(D), D.X.offset, D.tol.offset, D.fit_every.offset, D.autotune.offset,
-            D.stream.offset, D.workspace_bytes.offset, ctypes.sizeof(S), S.cond_est.offset,
-            S.fp64_path.offset]
+            D.solve_panel.offset, D.stream.offset, D.workspace_bytes.offset, ctypes.sizeof(S),
+            S.cond_est.offset, S.fp64_path.offset]
     assert got == want
 
 

@@ -50,17 +50,20 @@ def test_gemm(case, fp32):
     assert np.all(np.abs(C - ref) <= tol * scale + 1e-300)
 
 
-@pytest.mark.parametrize("R,n", [(60, 20), (64, 64), (150, 45), (300, 200), (1000, 130)])
+@pytest.mark.parametrize("R,n,panel", [(60, 20, 0), (64, 64, 0), (150, 45, 0), (300, 200, 0), (1000, 130, 0),
+                                        (150, 45, 1), (300, 200, 2), (1000, 130, 4), (1000, 70, 3)])
 @pytest.mark.parametrize("fp32", [False, True])
-def test_spd_solve(R, n, fp32):
+def test_spd_solve(R, n, panel, fp32):
+    """Blocked Cholesky and triangular solves, one level (panel 0) and with
+    panels of 1-4 blocks (rank-64 to rank-256 trailing updates)."""
     from paper_2502_17683_amd import test_solve
-    say(f"solve R={R} n={n} fp32={fp32}")
+    say(f"solve R={R} n={n} panel={panel} fp32={fp32}")
     rng = np.random.default_rng(R + n)
     A = rng.standard_normal((R, R + 5))
     V = A @ A.T / R + 0.5 * np.eye(R)
     M = rng.standard_normal((n, R))
     dt = torch.float32 if fp32 else torch.float64
-    F, failed = test_solve(to_dev(V, dt), to_dev(M, dt))
+    F, failed = test_solve(to_dev(V, dt), to_dev(M, dt), panel=panel)
     assert not failed
     F = F.cpu().numpy()
     ref = np.linalg.solve(V, M.T).T
