@@ -67,6 +67,18 @@ __device__ __forceinline__ double recip(double x) {
   return __builtin_fma(r, e, r);
 }
 __device__ __forceinline__ float recip(float x) { return 1.0f / x; }
+// 1/sqrt(x) to working precision: hardware estimate and two Newton steps
+// (y <- y (3/2 - x y^2 / 2)); sqrt(x) = x / sqrt(x).  Far shorter than the
+// correctly rounded square root on the factorisation's critical path.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double r = __builtin_fma(-h * y, y, 0.5);
+  y = __builtin_fma(y, r, y);
+  r = __builtin_fma(-h * y, y, 0.5);
+  return __builtin_fma(y, r, y);
+}
+__device__ __forceinline__ float rsqrt_nr(float x) { return 1.0f / sqrtf(x); }
 
 // ----------------------------------------------------------- strip solves
 // s holds columns q0 + 4u of one row of a 64-wide strip S.
@@ -97,6 +109,86 @@ __device__ __forceinline__ void strip_bwd(T s[16], const T* L, const T* invd, in
       if (u < uc || q0 < oc) s[u] -= x * L[c * LDT + q0 + 4 * u];
     }
   }
+}
+
+// ------------------------------------------------------ block-4 solves
+// Block-4 layout: thread t owns rows 4g .. 4g+3 (g = t >> 4) and columns
+// j + 16v (j = t & 15, v = 0..3) of a 64 x 64 tile, s[4 i + v] = S[4g+i][j+16v].
+// The 16 threads of a row group form one 16-lane DPP row, so the solved
+// value of column c is broadcast inside the group from lane c % 16
+// (row_newbcast) and every thread reads only 4 values of L per column --
+// a quarter of the LDS traffic of the strip layout.
+template <int N>
+__device__ __forceinline__ int rnb_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + N, 0xF, 0xF, false);
+}
+template <int N>
+__device__ __forceinline__ double rnb(double v) {
+  union { double d; int i[2]; } a, b;
+  a.d = v;
+  b.i[0] = rnb_int<N>(a.i[0]);
+  b.i[1] = rnb_int<N>(a.i[1]);
+  return b.d;
+}
+template <int N>
+__device__ __forceinline__ float rnb(float v) {
+  return __int_as_float(rnb_int<N>(__float_as_int(v)));
+}
+template <typename T>
+__device__ __forceinline__ void lds_to_b4(const T* S, T s[16], int g, int j) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s[4 * i + v] = S[(4 * g + i) * LDT + j + 16 * v];
+}
+template <typename T>
+__device__ __forceinline__ void store_b4(const T s[16], T* gp, size_t ld, int nrows, int g, int j) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = 4 * g + i;
+    if (r < nrows) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) gp[(size_t)r * ld + j + 16 * v] = s[4 * i + v];
+    }
+  }
+}
+// One column step of the block-4 solves (template recursion keeps every
+// register index a compile-time constant: a runtime index would put the
+// tile in indexed registers).
+//   FWD: S <- S L^{-T}  (solve X L^T = S, columns left to right)
+//   BWD: S <- S L^{-1}  (solve X L = S, columns right to left)
+// L in LDS row-major (stride LDT), invd[c] = 1 / L[c][c].
+template <typename T, bool FWD, int C>
+struct B4Solve {
+  __device__ __forceinline__ static void run(T s[16], const T* L, const T* invd, int j) {
+    if constexpr (C >= 0 && C < TB) {
+      constexpr int vc = C >> 4, jc = C & 15;
+      const T ic = invd[C];
+      T x[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[i] = rnb<jc>(s[4 * i + vc] * ic);
+      const bool own = j == jc;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s[4 * i + vc] = own ? x[i] : s[4 * i + vc];
+#pragma unroll
+      for (int v = FWD ? vc : 0; v <= (FWD ? 3 : vc); ++v) {
+        // FWD: L[k][C] for k = j + 16 v > C;  BWD: L[C][k] for k < C
+        T lk = FWD ? L[(j + 16 * v) * LDT + C] : L[C * LDT + j + 16 * v];
+        if (v == vc) lk = (FWD ? j > jc : j < jc) ? lk : T(0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[4 * i + v] -= x[i] * lk;
+      }
+      B4Solve<T, FWD, FWD ? C + 1 : C - 1>::run(s, L, invd, j);
+    }
+  }
+};
+template <typename T>
+__device__ __forceinline__ void b4_fwd(T s[16], const T* L, const T* invd, int j) {
+  B4Solve<T, true, 0>::run(s, L, invd, j);
+}
+template <typename T>
+__device__ __forceinline__ void b4_bwd(T s[16], const T* L, const T* invd, int j) {
+  B4Solve<T, false, TB - 1>::run(s, L, invd, j);
 }
 
 // Cholesky of the 64 x 64 block held in strip layout d (lower part used).
@@ -142,6 +234,104 @@ __device__ __forceinline__ bool strip_potrf(T d[16], T* L, T* invd, T* colbuf /*
     L[r * LDT + q] = v;
   }
   if (q0 == 0) invd[r] = T(1) / sqrt(pivs[r]);
+  __syncthreads();
+  return ok;
+}
+
+// Cholesky of the 64 x 64 block held in strip layout d (lower part used),
+// four columns per barrier.  Column block b (columns 4b .. 4b+3) is exactly
+// register d[b] of the four threads of a row (column offset q0).  Per
+// block: every thread publishes d[b] = A[r][4b+q0] (updated by all earlier
+// blocks) to cb[b & 1][q0][r]; one barrier (the two buffers alternate);
+// every thread then factors the 4 x 4 diagonal block D = Ld Ld^T from cb
+// (redundantly), forms y = a_r Ld^{-T} (row r of the block column of L,
+// a_r = A[r][4b..4b+3] gathered inside the quad) and w = y Ld^{-1} =
+// a_r D^{-1}, and updates its trailing columns k = q0 + 4u, u > b, by
+// d[u] -= w . A[k][4b..4b+3].  On return L is in LDS (row-major, stride
+// LDT, zero above the diagonal) and invd[c] = 1 / L[c][c].  Returns false
+// if a pivot was not positive (the factor is then finite garbage).
+template <typename T, int B>
+struct Potrf4 {
+  __device__ __forceinline__ static void run(T d[16], T* cb, T* invd, int r, int q0, bool& ok) {
+    if constexpr (B < 16) {
+      T* c = cb + (B & 1) * 4 * TB;
+      c[q0 * TB + r] = d[B];
+      __syncthreads();
+      constexpr int c0 = 4 * B;
+      // 4 x 4 diagonal block, lower part: D[p][q] = A[c0+p][c0+q] = c[q][c0+p]
+      T D[4][4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q <= p; ++q) D[p][q] = c[q * TB + c0 + p];
+      T Ld[4][4], il[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T piv = D[q][q];
+#pragma unroll
+        for (int m = 0; m < q; ++m) piv -= Ld[q][m] * Ld[q][m];
+        if (!(piv > T(0)) || !isfinite((double)piv)) {
+          ok = false;
+          piv = T(1);
+        }
+        il[q] = rsqrt_nr(piv);
+        Ld[q][q] = piv * il[q];
+#pragma unroll
+        for (int p = q + 1; p < 4; ++p) {
+          T v = D[p][q];
+#pragma unroll
+          for (int m = 0; m < q; ++m) v -= Ld[p][m] * Ld[q][m];
+          Ld[p][q] = v * il[q];
+        }
+      }
+      if (r == 0 && q0 == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) invd[c0 + q] = il[q];
+      }
+      // row r of the block column: a_r inside the quad, y = a_r Ld^{-T}
+      T a[4], y[4], wv[4];
+      a[0] = qb<0>(d[B]);
+      a[1] = qb<1>(d[B]);
+      a[2] = qb<2>(d[B]);
+      a[3] = qb<3>(d[B]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T v = a[q];
+#pragma unroll
+        for (int m = 0; m < q; ++m) v -= y[m] * Ld[q][m];
+        y[q] = v * il[q];
+      }
+#pragma unroll
+      for (int q = 3; q >= 0; --q) {
+        T v = y[q];
+#pragma unroll
+        for (int m = q + 1; m < 4; ++m) v -= wv[m] * Ld[m][q];
+        wv[q] = v * il[q];
+      }
+      // trailing columns of this thread
+#pragma unroll
+      for (int u = B + 1; u < 16; ++u) {
+        const int k = q0 + 4 * u;
+        d[u] -= wv[0] * c[k] + wv[1] * c[TB + k] + wv[2] * c[2 * TB + k] + wv[3] * c[3 * TB + k];
+        // keep the updates in order: otherwise every column's reads are
+        // hoisted at once and the tile spills
+        if constexpr (sizeof(T) == 8) __asm__ volatile("" : "+v"(d[u]));
+      }
+      // own entry of the block column: L[r][c0 + q0] = y[q0]
+      d[B] = q0 == 0 ? y[0] : q0 == 1 ? y[1] : q0 == 2 ? y[2] : y[3];
+      Potrf4<T, B + 1>::run(d, cb, invd, r, q0, ok);
+    }
+  }
+};
+template <typename T>
+__device__ __forceinline__ bool strip_potrf4(T d[16], T* L, T* invd, T* cb /* 2 x 4 x 64 */, int r, int q0) {
+  bool ok = true;
+  Potrf4<T, 0>::run(d, cb, invd, r, q0, ok);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int q = q0 + 4 * u;
+    L[r * LDT + q] = q <= r ? d[u] : T(0);
+  }
   __syncthreads();
   return ok;
 }
@@ -300,8 +490,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
   typedef typename Acc4<T>::type acc_t;
   __shared__ T S0[TB * LDT];
   __shared__ T S1[TB * LDT];
-  __shared__ T S2[TB * LDT];
-  __shared__ T colbuf[2 * TB];
+  __shared__ T colbuf[8 * TB];
   __shared__ T invd[TB];
   __shared__ T pivs[TB];
   int pid = 0;
@@ -317,7 +506,8 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
   if (st->done) return;
   const int Tp = nblk * TB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int sr = tid >> 2, q0 = tid & 3;
+  const int sr = tid >> 2, q0 = tid & 3;  // strip layout (diagonal factorisation)
+  const int bg = tid >> 4, bj = tid & 15;  // block-4 layout (triangular solves)
 
   if constexpr (MODE == STEP_CHOL || MODE == STEP_CHOL_FWD) {
     if (MODE == STEP_CHOL_FWD ? st->chol_fail : (retry_pass ? !st->retry_active : st->chol_fail)) return;
@@ -356,10 +546,13 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
           return;
         }
       }
-      // Column k = j + 1.  Updated diagonal block D = A_kk - L_kj L_kj^T.
+      // Column k = j + 1.  Updated diagonal block D = A_kk - L_kj L_kj^T,
+      // staged through S1 (two tile buffers per workgroup keep two
+      // workgroups resident per compute unit).
       T d[16];
       if (i == k) {
-        acc_to_lds<T>(acc, S2, lane, w);
+        __syncthreads();  // every wave is past its MMA reads of S0 / S1
+        acc_to_lds<T>(acc, S1, lane, w);
       } else {
         if (upd) {
           acc_t p[4];
@@ -369,15 +562,15 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
 #pragma unroll
           for (int tj = 0; tj < 4; ++tj) dd[tj] -= p[tj];
         }
-        acc_to_lds<T>(dd, S2, lane, w);
-        // own updated tile into S0 (free once every wave is past the MMAs)
         __syncthreads();
+        acc_to_lds<T>(dd, S1, lane, w);
         acc_to_lds<T>(acc, S0, lane, w);
       }
       __syncthreads();
-      lds_to_strip<T>(S2, d, sr, q0);
+      lds_to_strip<T>(S1, d, sr, q0);
+      __syncthreads();
       // S1 receives L_kk (every wave is past its last read of S1 here).
-      const bool ok = strip_potrf<T>(d, S1, invd, colbuf, pivs, sr, q0);
+      const bool ok = strip_potrf4<T>(d, S1, invd, colbuf, sr, q0);
       if (i == k) {
         if (!ok && tid == 0) {
           if (retry_pass) atomicOr(&st->flags, (int)FLAG_NOT_SPD);
@@ -394,9 +587,9 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
       }
       // Panel tile: L_ik = A'_ik L_kk^{-T}
       T s[16];
-      lds_to_strip<T>(S0, s, sr, q0);
-      strip_fwd<T>(s, S1, invd, q0);
-      store_strip<T>(s, tile, Tp, TB, sr, q0);
+      lds_to_b4<T>(S0, s, bg, bj);
+      b4_fwd<T>(s, S1, invd, bj);
+      store_b4<T>(s, tile, Tp, TB, bg, bj);
       return;
     }
     bid -= nc;
@@ -446,11 +639,11 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
     __syncthreads();
     if (tid < TB) invd[tid] = recip(S1[tid * LDT + tid]);
     T s[16];
-    lds_to_strip<T>(S0, s, sr, q0);
+    lds_to_b4<T>(S0, s, bg, bj);
     __syncthreads();
-    if (FWD) strip_fwd<T>(s, S1, invd, q0);
-    else strip_bwd<T>(s, S1, invd, q0);
-    store_strip<T>(s, tile, Tp, nrows, sr, q0);
+    if (FWD) b4_fwd<T>(s, S1, invd, bj);
+    else b4_bwd<T>(s, S1, invd, bj);
+    store_b4<T>(s, tile, Tp, nrows, bg, bj);
   }
 }
 
