@@ -43,6 +43,27 @@ def mttkrp_flops(n, r_thc, r_cp):
     return 4.0 * r_thc * r_cp * sum(n) + 4.0 * r_thc * r_thc * r_cp
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, or
+    None once the kernel's source has changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "step_kernel_chol_fwd_traffic_n800_r4000.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel=(\S+) traffic_bytes_per_launch=(\d+) source=(\S+) sha256=([0-9a-f]+)", text)
+    if not m or m.group(1) != kernel:
+        return None
+    src = os.path.join(ROOT, m.group(3))
+    try:
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return float(m.group(2)) if digest == m.group(4) else None
+
+
 def run_to_target(make, target, max_sweeps, chunk=1):
     """Wall time (s) from plan creation to the sweep that reaches target."""
     import torch
@@ -89,6 +110,8 @@ def main():
     ap.add_argument("--ws-heldout", type=int, default=32)
     ap.add_argument("--ws-heldout-large", type=int, default=4)
     ap.add_argument("--ws-budget", type=int, default=200)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this size first (for scaling HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -106,6 +129,14 @@ def main():
 
     N, Rt, Rc = args.n, args.r_thc, args.r_cp
     dev = torch.device("cuda:0")
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {nb} bytes read, {nb} bytes written")
+        del src, dst
     log(f"[bench] generating THC input N={N} R_thc={Rt} R_cp={Rc} seed={args.seed}")
     X, Z = make_thc(N, Rt, args.seed)
     init = init_factors([N] * 4, Rc, args.seed + 1000)
@@ -157,9 +188,10 @@ def main():
     core_ms = kt["mixed"]["core"]
     core_achieved = fl_core / (core_ms * 1e-3)
     # dominant kernel of the mixed sweep: the fused Cholesky + forward-solve
-    # step (nblk + 1 launches per mode update, FP64 matrix cores)
+    # step (nblk + 1 launches per mode update, FP64 matrix cores): Cholesky
+    # R^3 / 3 flops plus the forward triangular solve of n rows, n R^2
     nblk = (Rc + 63) // 64
-    fl_factor_fwd = 2.0 * Rc ** 3 / 3.0 + 1.0 * N * Rc * Rc
+    fl_factor_fwd = Rc ** 3 / 3.0 + 1.0 * N * Rc * Rc
     launches = nblk + 1
     per_launch_ms = kt["mixed"]["factor_fwd"] / launches
     fac_achieved = (fl_factor_fwd / launches) / (per_launch_ms * 1e-3)
@@ -211,7 +243,8 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "step_kernel<double, STEP_CHOL_FWD> (Cholesky step "
                                                   "fused with the forward triangular solve, FP64)",
                      "achieved": fac_achieved / 1e12, "peak": MFMA_PEAK["f64"] / 1e12,
-                     "unit": "TFLOP/s", "frac": fac_achieved / MFMA_PEAK["f64"], "traffic": None,
+                     "unit": "TFLOP/s", "frac": fac_achieved / MFMA_PEAK["f64"],
+                     "traffic": measured_traffic("step_kernel<double,3>"),
                      "avg_launch_us": per_launch_ms * 1e3, "launches_per_mode": launches},
         "roofline_core_product": {"bound": "mfma", "kernel": "gemm_split_kernel<true,false> (core product, "
                                                             "split BF16, useful flops)",
