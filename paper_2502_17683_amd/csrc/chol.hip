@@ -3,25 +3,27 @@
 //
 // V is Tp x Tp row-major (Tp = 64 nblk; padding rows/columns hold the
 // identity).  Right-looking with two levels of blocking.  Block columns are
-// 64 wide and grouped into panels of pw blocks (pw >= nblk: one level).  Inside a panel, ONE
-// launch per block step: step j updates the panel's tiles (i, k), k >= j+1,
+// 64 wide and grouped into panels of pw blocks (pw >= nblk: one level).
+// Inside a panel, ONE launch per block step: step j updates the panel's tiles (i, k), k >= j+1,
 // with block column j on the matrix cores and, for the tiles of column j+1,
 // immediately factors the updated diagonal block -- every workgroup of that
 // column does so redundantly, so no workgroup ever waits on another -- and
 // solves its own tile of the column.  After a panel, one GEMM applies its
-// rank-(64 PANEL) update to the trailing matrix (and, in the forward
+// rank-(64 pw) update to the trailing matrix (and, in the forward
 // solve, to the right-hand sides): the trailing matrix is read and written
 // once per panel instead of once per block column.  The diagonal blocks of
 // L are never written back to V (other workgroups of the same launch still
-// read the unfactored block); they go to `ldiag` and feed the triangular
-// solves.
+// read the unfactored block); the workgroup that owns one forms
+// X = L_kk^{-T} and writes it to `ldiag`, so every forward and backward
+// solve step with that block is a single MFMA product.
 //
-// The sequential parts (diagonal factorisation, triangular solves of a
-// 64-wide strip) use the "strip" thread layout: thread t owns row t / 4 and
-// the 16 columns (t % 4) + 4u of a 64 x 64 tile in registers; the value of
-// column c is broadcast inside each 4-lane quad with a DPP move, and L is
-// read from LDS.  A strip solve needs no barrier at all; the diagonal
-// factorisation needs one barrier per column.
+// The sequential parts keep a 64 x 64 tile in registers.  The diagonal
+// factorisation uses the "strip" layout (thread t owns row t / 4 and the
+// 16 columns (t % 4) + 4u, so the four threads of a row hold one 4-column
+// block) and publishes four columns per barrier.  The solve of a panel tile
+// with L_kk uses the "block-4" layout (4 rows x 4 columns per thread, the
+// solved value broadcast inside a 16-lane DPP row), which needs a quarter
+// of the strip layout's LDS reads.
 #include <math.h>
 
 #include "kernels.h"
@@ -344,6 +346,14 @@ __device__ __forceinline__ void acc_to_lds(const typename Acc4<T>::type acc[4], 
 #pragma unroll
     for (int r = 0; r < 4; ++r) S[acc_row<T>(lane, w, r) * LDT + acc_col(lane, tj)] = acc[tj][r];
 }
+// ... transposed: S[col][row] (the k-major A operand of tile_mma64).
+template <typename T>
+__device__ __forceinline__ void acc_to_lds_t(const typename Acc4<T>::type acc[4], T* S, int lane, int w) {
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S[acc_col(lane, tj) * LDT + acc_row<T>(lane, w, r)] = acc[tj][r];
+}
 template <typename T>
 __device__ __forceinline__ void lds_to_strip(const T* S, T s[16], int r, int q0) {
 #pragma unroll
@@ -576,13 +586,16 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
           if (retry_pass) atomicOr(&st->flags, (int)FLAG_NOT_SPD);
           else atomicExch(&st->chol_fail, 1);
         }
-        T* out = ldiag + (size_t)k * TB * TB;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int idx = tid + 256 * e;
-          out[idx] = S1[(idx >> 6) * LDT + (idx & 63)];
-        }
         if (tid < TB) diagL[k * TB + tid] = S1[tid * LDT + tid];
+        // X = L_kk^{-T} (the identity solved against L^T) replaces L_kk:
+        // every later triangular solve with this block is one MFMA product
+        T s[16];
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) s[4 * ii + v] = (4 * bg + ii == bj + 16 * v) ? T(1) : T(0);
+        b4_fwd<T>(s, S1, invd, bj);
+        store_b4<T>(s, ldiag + (size_t)k * TB * TB, TB, TB, bg, bj);
         return;
       }
       // Panel tile: L_ik = A'_ik L_kk^{-T}
@@ -633,17 +646,17 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
       store_acc<T>(acc, tile, Tp, nrows, lane, w);
       return;
     }
+    // Solve with the stored X = L_kk^{-T}: forward G = T X, backward T X^T.
     __syncthreads();
-    acc_to_lds<T>(acc, S0, lane, w);
-    put_block<T, false>(S1, rl, tid);
+    acc_to_lds_t<T>(acc, S0, lane, w);
+    if (FWD) put_block<T, false>(S1, rl, tid);
+    else put_block<T, true>(S1, rl, tid);
     __syncthreads();
-    if (tid < TB) invd[tid] = recip(S1[tid * LDT + tid]);
-    T s[16];
-    lds_to_b4<T>(S0, s, bg, bj);
-    __syncthreads();
-    if (FWD) b4_fwd<T>(s, S1, invd, bj);
-    else b4_bwd<T>(s, S1, invd, bj);
-    store_b4<T>(s, tile, Tp, nrows, bg, bj);
+    acc_t p[4];
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
+    tile_mma64<T>(p, S0, S1, lane, w);
+    store_acc<T>(p, tile, Tp, nrows, lane, w);
   }
 }
 
