@@ -281,7 +281,8 @@ def bench_lt(args):
     res = {}
     from paper_2502_17683_amd import CpdError
     for prec in ("mixed", "fp32", "fp64"):
-        b = CPDBatch(problems, precision=prec, tol=0.0, fit_floor=0.0, autotune=True)
+        b = CPDBatch(problems, precision=prec, tol=0.0, fit_floor=0.0, autotune=True,
+                     fit_every=args.fit_every)
         try:
             b.sweep(3)
         except CpdError as e:
@@ -305,8 +306,8 @@ def bench_lt(args):
         log(f"[bench-lt] batched {prec}: {ms:.3f} ms/sweep")
     # the same 48 CPDs one after another (one plan each, graph-replayed sweeps)
     for prec in ("mixed", "fp64"):
-        plans = [CPD(p["X"], p["Z"], p["r_cp"], p["init"], precision=prec, tol=0.0, fit_floor=0.0)
-                 for p in problems]
+        plans = [CPD(p["X"], p["Z"], p["r_cp"], p["init"], precision=prec, tol=0.0, fit_floor=0.0,
+                     fit_every=args.fit_every) for p in problems]
         for c in plans:
             c.sweep(3)
         torch.cuda.synchronize()
@@ -326,7 +327,7 @@ def bench_lt(args):
     for prec in ("mixed", "fp64"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        b = CPDBatch(problems, precision=prec, tol=1e-4, fit_floor=1e-7, fit_every=1)
+        b = CPDBatch(problems, precision=prec, tol=1e-4, fit_floor=1e-7, fit_every=args.fit_every)
         fits = b.sweep(args.max_sweeps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -343,7 +344,7 @@ def bench_lt(args):
         "higher_is_better": False, "data": "synthetic",
         "dtype": "bf16-split(fp32 acc)+f64",
         "config": {"workload": "48 LT CPDs: (o,v) in (20,100),(40,200),(80,400) x 16 Laplace points "
-                               "0.01-20, R_thc=4(o+v), R_cp=2(o+v)",
+                               "0.01-20, R_thc=4(o+v), R_cp=2(o+v)", "fit_every": args.fit_every,
                    "useful_gflop_per_batched_sweep": useful / 1e9, "mttkrp_gflop": mtt / 1e9},
         "per_precision": res,
         "converge_tol_1e-4": conv,

@@ -48,29 +48,9 @@ template <int K>
 __device__ __forceinline__ float qb(float v) {
   return __int_as_float(qb_int<K>(__float_as_int(v)));
 }
-// Value of lane (quad base + k) for every lane of the quad.
-template <typename T>
-__device__ __forceinline__ T quad_bcast(T v, int k) {
-  switch (k) {
-    case 0: return qb<0>(v);
-    case 1: return qb<1>(v);
-    case 2: return qb<2>(v);
-    default: return qb<3>(v);
-  }
-}
 
-// 1/x to working precision: hardware reciprocal estimate refined by two
-// Newton steps (keeps the long FP64 division sequence off the pivot chain).
-__device__ __forceinline__ double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
-__device__ __forceinline__ float recip(float x) { return 1.0f / x; }
 // 1/sqrt(x) to working precision: hardware estimate and two Newton steps
-// (y <- y (3/2 - x y^2 / 2)); sqrt(x) = x / sqrt(x).  Far shorter than the
+// (y <- y (3/2 - x y^2 / 2)); sqrt(x) = x (1/sqrt(x)).  Far shorter than the
 // correctly rounded square root on the factorisation's critical path.
 __device__ __forceinline__ double rsqrt_nr(double x) {
   double y = __builtin_amdgcn_rsq(x);
@@ -81,37 +61,6 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return __builtin_fma(y, r, y);
 }
 __device__ __forceinline__ float rsqrt_nr(float x) { return 1.0f / sqrtf(x); }
-
-// ----------------------------------------------------------- strip solves
-// s holds columns q0 + 4u of one row of a 64-wide strip S.
-// Forward:  S <- S L^{-T}   (solve X L^T = S, column by column, left to right)
-template <typename T>
-__device__ __forceinline__ void strip_fwd(T s[16], const T* L, const T* invd, int q0) {
-#pragma unroll
-  for (int c = 0; c < TB; ++c) {
-    const int uc = c >> 2, oc = c & 3;
-    const T x = quad_bcast<T>(s[uc] * invd[c], oc);
-    if (q0 == oc) s[uc] = x;
-#pragma unroll
-    for (int u = uc; u < 16; ++u) {
-      if (u > uc || q0 > oc) s[u] -= x * L[(q0 + 4 * u) * LDT + c];
-    }
-  }
-}
-// Backward: S <- S L^{-1}   (solve X L = S, column by column, right to left)
-template <typename T>
-__device__ __forceinline__ void strip_bwd(T s[16], const T* L, const T* invd, int q0) {
-#pragma unroll
-  for (int c = TB - 1; c >= 0; --c) {
-    const int uc = c >> 2, oc = c & 3;
-    const T x = quad_bcast<T>(s[uc] * invd[c], oc);
-    if (q0 == oc) s[uc] = x;
-#pragma unroll
-    for (int u = 0; u <= uc; ++u) {
-      if (u < uc || q0 < oc) s[u] -= x * L[c * LDT + q0 + 4 * u];
-    }
-  }
-}
 
 // ------------------------------------------------------ block-4 solves
 // Block-4 layout: thread t owns rows 4g .. 4g+3 (g = t >> 4) and columns
@@ -191,53 +140,6 @@ __device__ __forceinline__ void b4_fwd(T s[16], const T* L, const T* invd, int j
 template <typename T>
 __device__ __forceinline__ void b4_bwd(T s[16], const T* L, const T* invd, int j) {
   B4Solve<T, false, TB - 1>::run(s, L, invd, j);
-}
-
-// Cholesky of the 64 x 64 block held in strip layout d (lower part used).
-// Right-looking with deferred scaling: column c (unscaled) and its pivot
-// are published through LDS, one barrier per column.  On return L is in
-// LDS (row-major, stride LDT, upper part zero) and invd[c] = 1 / L[c][c].
-// Returns false if a pivot was not positive (the factor is then finite
-// garbage).
-template <typename T>
-__device__ __forceinline__ bool strip_potrf(T d[16], T* L, T* invd, T* colbuf /* 2 x 64 */, T* pivs, int r, int q0) {
-  bool ok = true;
-  if (q0 == 0) colbuf[r] = d[0];
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < TB; ++c) {
-    const int uc = c >> 2, oc = c & 3;
-    const T* col = colbuf + (c & 1) * TB;
-    T piv = col[c];
-    if (!(piv > T(0)) || !isfinite((double)piv)) {
-      ok = false;
-      piv = T(1);
-    }
-    const T f = col[r] * recip(piv);
-#pragma unroll
-    for (int u = uc; u < 16; ++u) {
-      if (u > uc || q0 > oc) d[u] -= f * col[q0 + 4 * u];
-    }
-    if (r == 0 && q0 == 0) pivs[c] = piv;
-    if (c + 1 < TB) {
-      const int un = (c + 1) >> 2, on = (c + 1) & 3;
-      if (q0 == on) colbuf[((c + 1) & 1) * TB + r] = d[un];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int q = q0 + 4 * u;
-    const T sq = sqrt(pivs[q]);
-    T v;
-    if (q < r) v = d[u] / sq;
-    else if (q == r) v = sq;
-    else v = T(0);
-    L[r * LDT + q] = v;
-  }
-  if (q0 == 0) invd[r] = T(1) / sqrt(pivs[r]);
-  __syncthreads();
-  return ok;
 }
 
 // Cholesky of the 64 x 64 block held in strip layout d (lower part used),
@@ -381,22 +283,6 @@ __device__ __forceinline__ void store_acc(const typename Acc4<T>::type acc[4], T
       if (row < nrows) g[(size_t)row * ld + acc_col(lane, tj)] = acc[tj][r];
     }
 }
-template <typename T>
-__device__ __forceinline__ void store_strip(const T s[16], T* g, size_t ld, int nrows, int r, int q0) {
-  if (r < nrows) {
-#pragma unroll
-    for (int u = 0; u < 16; ++u) g[(size_t)r * ld + q0 + 4 * u] = s[u];
-  }
-}
-template <typename T>
-__device__ __forceinline__ void load_block_lds(T* S, const T* g, size_t ld, int tid) {
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int idx = tid + 256 * e;
-    S[(idx >> 6) * LDT + (idx & 63)] = g[(size_t)(idx >> 6) * ld + (idx & 63)];
-  }
-}
-
 // Register prefetch of a 64 x 64 row-major block (16 values per thread,
 // element idx = tid + 256 e at (idx / 64, idx % 64)); rows >= nrows read 0.
 template <typename T>
@@ -502,7 +388,6 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
   __shared__ T S1[TB * LDT];
   __shared__ T colbuf[8 * TB];
   __shared__ T invd[TB];
-  __shared__ T pivs[TB];
   int pid = 0;
   while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
   T* const V = probs[pid].V;
