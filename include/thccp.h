@@ -164,7 +164,7 @@ cpd_status cpd_mttkrp(cpd_plan p, int32_t mode, double* M_dev);
  * stream, `reps` back-to-back repetitions after one warm-up) of each kernel
  * family of the sweep at the plan's shapes, for mode 0 (ms_out: 7 doubles):
  *   [0] projection X^T F,  [1] core product Z (W o W),
- *   [2] back-projection X (W o Y),  [3] Gram F^T F,
+ *   [2] back-projection X (W o Y),  [3] Gram F^T F (lower triangle),
  *   [4] whole normal-equation solve (V, factorisation fused with the
  *       forward triangular solve, backward solve, normalisation),
  *   [5] V + factorisation/forward solve (nblk + 1 launches of the fused

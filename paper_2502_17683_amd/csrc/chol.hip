@@ -93,7 +93,8 @@ __device__ __forceinline__ void lds_to_b4(const T* S, T s[16], int g, int j) {
     for (int v = 0; v < 4; ++v) s[4 * i + v] = S[(4 * g + i) * LDT + j + 16 * v];
 }
 template <typename T>
-__device__ __forceinline__ void store_b4(const T s[16], T* gp, size_t ld, int nrows, int g, int j) {
+__device__ __forceinline__ void store_b4(const T s[16], T* gp_, size_t ld, int nrows, int g, int j) {
+  const gptr<T> gp = as_global(gp_);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int r = 4 * g + i;
@@ -146,28 +147,30 @@ __device__ __forceinline__ void b4_bwd(T s[16], const T* L, const T* invd, int j
 // four columns per barrier.  Column block b (columns 4b .. 4b+3) is exactly
 // register d[b] of the four threads of a row (column offset q0).  Per
 // block: every thread publishes d[b] = A[r][4b+q0] (updated by all earlier
-// blocks) to cb[b & 1][q0][r]; one barrier (the two buffers alternate);
-// every thread then factors the 4 x 4 diagonal block D = Ld Ld^T from cb
-// (redundantly), forms y = a_r Ld^{-T} (row r of the block column of L,
-// a_r = A[r][4b..4b+3] gathered inside the quad) and w = y Ld^{-1} =
-// a_r D^{-1}, and updates its trailing columns k = q0 + 4u, u > b, by
-// d[u] -= w . A[k][4b..4b+3].  On return L is in LDS (row-major, stride
-// LDT, zero above the diagonal) and invd[c] = 1 / L[c][c].  Returns false
-// if a pivot was not positive (the factor is then finite garbage).
+// blocks) to cb[b & 1][r][q0] (row-major, so a row's four values are one
+// 32-byte read); one barrier (the two buffers alternate); every thread then
+// factors the 4 x 4 diagonal block D = Ld Ld^T from cb (redundantly), forms
+// y = a_r Ld^{-T} (row r of the block column of L, a_r = A[r][4b..4b+3]
+// gathered inside the quad) and w = y Ld^{-1} = a_r D^{-1}, and updates its
+// trailing columns k = q0 + 4u, u > b, by d[u] -= w . A[k][4b..4b+3], the
+// reads of A[k][.] running two columns ahead of the updates.  On return L
+// is in LDS (row-major, stride LDT, zero above the diagonal) and invd[c] =
+// 1 / L[c][c].  Returns false if a pivot was not positive (the factor is
+// then finite garbage).
 template <typename T, int B>
 struct Potrf4 {
   __device__ __forceinline__ static void run(T d[16], T* cb, T* invd, int r, int q0, bool& ok) {
     if constexpr (B < 16) {
       T* c = cb + (B & 1) * 4 * TB;
-      c[q0 * TB + r] = d[B];
+      c[r * 4 + q0] = d[B];
       __syncthreads();
       constexpr int c0 = 4 * B;
-      // 4 x 4 diagonal block, lower part: D[p][q] = A[c0+p][c0+q] = c[q][c0+p]
+      // 4 x 4 diagonal block, lower part: D[p][q] = A[c0+p][c0+q] = c[c0+p][q]
       T D[4][4];
 #pragma unroll
       for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int q = 0; q <= p; ++q) D[p][q] = c[q * TB + c0 + p];
+        for (int q = 0; q <= p; ++q) D[p][q] = c[(c0 + p) * 4 + q];
       T Ld[4][4], il[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -212,14 +215,33 @@ struct Potrf4 {
         for (int m = q + 1; m < 4; ++m) v -= wv[m] * Ld[m][q];
         wv[q] = v * il[q];
       }
-      // trailing columns of this thread
+      // trailing columns of this thread, A[k][c0..c0+3] = c[k][0..3] read
+      // two columns ahead
+      T ca[4], cn[4];
+      if constexpr (B + 1 < 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ca[q] = c[(q0 + 4 * (B + 1)) * 4 + q];
+      }
+      if constexpr (B + 2 < 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cn[q] = c[(q0 + 4 * (B + 2)) * 4 + q];
+      }
 #pragma unroll
       for (int u = B + 1; u < 16; ++u) {
-        const int k = q0 + 4 * u;
-        d[u] -= wv[0] * c[k] + wv[1] * c[TB + k] + wv[2] * c[2 * TB + k] + wv[3] * c[3 * TB + k];
+        T cf[4];
+        if (u + 2 < 16) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) cf[q] = c[(q0 + 4 * (u + 2)) * 4 + q];
+        }
+        d[u] -= wv[0] * ca[0] + wv[1] * ca[1] + wv[2] * ca[2] + wv[3] * ca[3];
         // keep the updates in order: otherwise every column's reads are
         // hoisted at once and the tile spills
         if constexpr (sizeof(T) == 8) __asm__ volatile("" : "+v"(d[u]));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ca[q] = cn[q];
+          cn[q] = cf[q];
+        }
       }
       // own entry of the block column: L[r][c0 + q0] = y[q0]
       d[B] = q0 == 0 ? y[0] : q0 == 1 ? y[1] : q0 == 2 ? y[2] : y[3];
@@ -228,7 +250,7 @@ struct Potrf4 {
   }
 };
 template <typename T>
-__device__ __forceinline__ bool strip_potrf4(T d[16], T* L, T* invd, T* cb /* 2 x 4 x 64 */, int r, int q0) {
+__device__ __forceinline__ bool strip_potrf4(T d[16], T* L, T* invd, T* cb /* 2 x 64 x 4 */, int r, int q0) {
   bool ok = true;
   Potrf4<T, 0>::run(d, cb, invd, r, q0, ok);
 #pragma unroll
@@ -262,8 +284,9 @@ __device__ __forceinline__ void lds_to_strip(const T* S, T s[16], int r, int q0)
   for (int u = 0; u < 16; ++u) s[u] = S[r * LDT + q0 + 4 * u];
 }
 template <typename T>
-__device__ __forceinline__ void load_acc(typename Acc4<T>::type acc[4], const T* g, size_t ld, int nrows,
+__device__ __forceinline__ void load_acc(typename Acc4<T>::type acc[4], const T* g_, size_t ld, int nrows,
                                          int lane, int w) {
+  const gptr<const T> g = as_global(g_);
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
@@ -273,8 +296,9 @@ __device__ __forceinline__ void load_acc(typename Acc4<T>::type acc[4], const T*
     }
 }
 template <typename T>
-__device__ __forceinline__ void store_acc(const typename Acc4<T>::type acc[4], T* g, size_t ld, int nrows,
+__device__ __forceinline__ void store_acc(const typename Acc4<T>::type acc[4], T* g_, size_t ld, int nrows,
                                           int lane, int w) {
+  const gptr<T> g = as_global(g_);
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
@@ -286,7 +310,8 @@ __device__ __forceinline__ void store_acc(const typename Acc4<T>::type acc[4], T
 // Register prefetch of a 64 x 64 row-major block (16 values per thread,
 // element idx = tid + 256 e at (idx / 64, idx % 64)); rows >= nrows read 0.
 template <typename T>
-__device__ __forceinline__ void fetch_block(T v[16], const T* g, size_t ld, int nrows, int tid) {
+__device__ __forceinline__ void fetch_block(T v[16], const T* g_, size_t ld, int nrows, int tid) {
+  const gptr<const T> g = as_global(g_);
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int idx = tid + 256 * e;
@@ -386,7 +411,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
   typedef typename Acc4<T>::type acc_t;
   __shared__ T S0[TB * LDT];
   __shared__ T S1[TB * LDT];
-  __shared__ T colbuf[8 * TB];
+  __shared__ __attribute__((aligned(16))) T colbuf[8 * TB];
   __shared__ T invd[TB];
   int pid = 0;
   while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
@@ -471,7 +496,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
           if (retry_pass) atomicOr(&st->flags, (int)FLAG_NOT_SPD);
           else atomicExch(&st->chol_fail, 1);
         }
-        if (tid < TB) diagL[k * TB + tid] = S1[tid * LDT + tid];
+        if (tid < TB) as_global(diagL)[k * TB + tid] = S1[tid * LDT + tid];
         // X = L_kk^{-T} (the identity solved against L^T) replaces L_kk:
         // every later triangular solve with this block is one MFMA product
         T s[16];

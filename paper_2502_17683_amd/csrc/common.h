@@ -9,6 +9,17 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 #define WAVE 64
 
+// Pointers read from argument tables in memory are generic (flat) to the
+// compiler, and flat loads and stores count against the LDS wait counter
+// too, so a prefetch into registers would be waited on at the next LDS
+// access.  Kernels convert such pointers once to the global address space.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+  return (gptr<T>)p;
+}
+
 // Device-side status flags written by kernels and read back by the host
 // at synchronisation points.
 enum {

@@ -310,7 +310,7 @@ GroupOp gemm_op(TableBuilder& tb, const std::vector<GemmArgs<T>>& v, bool at, bo
     dims.push_back(g.M);
     dims.push_back(g.N);
     dims.push_back(g.K);
-    t128 += gemm_tile_count(g.M, g.N, 128);
+    t128 += gemm_tile_count(g.M, g.N, 128, g.lower);
   }
   op.bm = t128 >= 256 ? 128 : 64;
   op.count = (int)v.size();
@@ -320,7 +320,7 @@ GroupOp gemm_op(TableBuilder& tb, const std::vector<GemmArgs<T>>& v, bool at, bo
     if (it != g_tune.end()) op.bm = it->second;
   }
   std::vector<int> offs(1, 0);
-  for (auto& g : v) offs.push_back(offs.back() + gemm_tile_count(g.M, g.N, op.bm));
+  for (auto& g : v) offs.push_back(offs.back() + gemm_tile_count(g.M, g.N, op.bm, g.lower));
   op.total = offs.back();
   op.tab = tb.put(v);
   op.offs = (int*)tb.put(offs);
@@ -403,6 +403,7 @@ void build_typed(TableBuilder& tb, cpd_plan_s* p, Bufs<T> Prob::*bufs, bool gate
       back.push_back({q.n[n], Rc, Rt, b.X[n], Rt, b.W[partner_of[n]], b.Y, Tp, b.Msol, Tp,
                       n == 3 ? b.Msave : nullptr, T(1), T(0), done});
       gram.push_back({Rc, Rc, q.n[n], b.F[n], Tp, b.F[n], nullptr, Tp, b.G[n], Tp, nullptr, T(1), T(0), done});
+      gram.back().lower = 1;  // consumers read the lower triangle only
       proj.push_back({Rt, Rc, q.n[n], b.X[n], Rt, b.F[n], nullptr, Tp, b.W[n], Tp, nullptr, T(1), T(0), done});
       if (gated) {
         // split-BF16 plans: these FP64 products serve only problems promoted
@@ -696,8 +697,8 @@ void enqueue_sweep_typed(cpd_plan_s* p, hipStream_t s, bool fast) {
 // else in FP64.  On fit sweeps the mode-3 MTTKRP is ALSO formed in FP64
 // (from the FP64 factors) for <G, G~>: the residual is first-order
 // sensitive to that inner product, which split BF16 cannot deliver.
-void mixed_refresh_mode(cpd_plan_s* p, hipStream_t s, int n) {
-  run_gemm<double>(p, s, p->gram[n]);
+void mixed_refresh_mode(cpd_plan_s* p, hipStream_t s, int n, bool with_gram = true) {
+  if (with_gram) run_gemm<double>(p, s, p->gram[n]);
   run_gemm<double>(p, s, p->proj[n]);  // FP64-path problems only (gated)
   int maxc = 0, maxd = 0;
   for (auto& q : p->P) {
@@ -925,7 +926,7 @@ void autotune_ops(cpd_plan_s* p, hipStream_t s) {
     int best_bm = op.bm;
     for (int bm : {64, 128}) {
       std::vector<int> offs(1, 0);
-      for (auto& g : host) offs.push_back(offs.back() + gemm_tile_count(g.M, g.N, bm));
+      for (auto& g : host) offs.push_back(offs.back() + gemm_tile_count(g.M, g.N, bm, g.lower));
       if (hipMemcpy(doffs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice) != hipSuccess) return;
       float ms = 0.f;
       for (int w = 0; w < 2; ++w) {  // second pass is the timed one
@@ -1305,7 +1306,7 @@ cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out) {
         return;
       }
       if (p->prec == CPD_MIXED_BF16) {
-        if (which == 0) mixed_refresh_mode(p, s, 0);
+        if (which == 0) mixed_refresh_mode(p, s, 0, false);  // the Gram is timed on its own
         else if (which == 1) run_split(p, s, p->score[0]);
         else if (which == 2) run_split(p, s, p->sback[0]);
         else run_gemm<double>(p, s, p->gram[0]);

@@ -28,23 +28,66 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& p, int bid_in, int 
   if (p.gate && *p.gate != p.want) return;
   const int tiles_n = (p.N + BN - 1) / BN;
   const int bid = xcd_remap(bid_in, nblocks);
-  const int m0 = (bid / tiles_n) * BM, n0 = (bid % tiles_n) * BN;
-  if (p.lower && n0 > m0 + BM - 1) return;  // tile strictly above the diagonal
+  int m0, n0;
+  if (BM == BN && p.lower && p.M == p.N) {
+    // only the lower tiles are launched, in row order (row r holds r + 1);
+    // the XCD remap above then spreads them evenly
+    int r = (int)((sqrtf(8.f * (float)bid + 1.f) - 1.f) * 0.5f);
+    while ((r + 1) * (r + 2) / 2 <= bid) ++r;
+    while (r * (r + 1) / 2 > bid) --r;
+    m0 = r * BM;
+    n0 = (bid - r * (r + 1) / 2) * BN;
+  } else {
+    m0 = (bid / tiles_n) * BM;
+    n0 = (bid % tiles_n) * BN;
+    if (p.lower && n0 > m0 + BM - 1) return;  // tile strictly above the diagonal
+  }
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
+  const gptr<const T> gA = as_global(p.A), gB1 = as_global(p.B1), gB2 = as_global(p.B2);
+  const gptr<T> gC = as_global(p.C), gC2 = as_global(p.C2);
 
-  T ra[AE], rb[BE];
+  // Operand loads are unconditional: interior tiles (the whole k-tile in
+  // range) load without checks; edge tiles read offset 0 for an
+  // out-of-range element and zero it at the LDS store from the validity
+  // bits.  The Hadamard product is also formed at the LDS store, so nothing
+  // waits on the prefetch until the current k-tile's products are issued.
+  T ra[AE], rb[BE], rb2[HAD ? BE : 1];
+  uint32_t va = 0, vb = 0;
+  const bool interior = m0 + BM <= p.M && n0 + BN <= p.N;
   auto load = [&](int k0) {
+    if (interior && k0 + BK <= p.K) {
+      va = vb = ~0u;
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        const int idx = tid + e * 256;
+        int i, k;
+        if (AT) { i = idx % BM; k = idx / BM; } else { k = idx % BK; i = idx / BK; }
+        ra[e] = AT ? gA[(size_t)(k0 + k) * p.lda + m0 + i] : gA[(size_t)(m0 + i) * p.lda + k0 + k];
+      }
+#pragma unroll
+      for (int e = 0; e < BE; ++e) {
+        const int idx = tid + e * 256;
+        int j, k;
+        if (BT) { k = idx % BK; j = idx / BK; } else { j = idx % BN; k = idx / BN; }
+        const size_t off = BT ? (size_t)(n0 + j) * p.ldb + k0 + k : (size_t)(k0 + k) * p.ldb + n0 + j;
+        rb[e] = gB1[off];
+        if constexpr (HAD) rb2[e] = gB2[off];
+      }
+      return;
+    }
+    va = 0;
+    vb = 0;
 #pragma unroll
     for (int e = 0; e < AE; ++e) {
       const int idx = tid + e * 256;
       int i, k;
       if (AT) { i = idx % BM; k = idx / BM; } else { k = idx % BK; i = idx / BK; }
       const int gi = m0 + i, gk = k0 + k;
-      T v = T(0);
-      if (gi < p.M && gk < p.K)
-        v = AT ? p.A[(size_t)gk * p.lda + gi] : p.A[(size_t)gi * p.lda + gk];
-      ra[e] = v;
+      const bool ok = gi < p.M && gk < p.K;
+      const size_t off = ok ? (AT ? (size_t)gk * p.lda + gi : (size_t)gi * p.lda + gk) : 0;
+      ra[e] = gA[off];
+      va |= (uint32_t)ok << e;
     }
 #pragma unroll
     for (int e = 0; e < BE; ++e) {
@@ -52,13 +95,11 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& p, int bid_in, int 
       int j, k;
       if (BT) { k = idx % BK; j = idx / BK; } else { j = idx % BN; k = idx / BN; }
       const int gj = n0 + j, gk = k0 + k;
-      T v = T(0);
-      if (gj < p.N && gk < p.K) {
-        const size_t off = BT ? (size_t)gj * p.ldb + gk : (size_t)gk * p.ldb + gj;
-        v = p.B1[off];
-        if (HAD) v *= p.B2[off];
-      }
-      rb[e] = v;
+      const bool ok = gj < p.N && gk < p.K;
+      const size_t off = ok ? (BT ? (size_t)gj * p.ldb + gk : (size_t)gk * p.ldb + gj) : 0;
+      rb[e] = gB1[off];
+      if constexpr (HAD) rb2[e] = gB2[off];
+      vb |= (uint32_t)ok << e;
     }
   };
   auto store = [&]() {
@@ -67,14 +108,22 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& p, int bid_in, int 
       const int idx = tid + e * 256;
       int i, k;
       if (AT) { i = idx % BM; k = idx / BM; } else { k = idx % BK; i = idx / BK; }
-      As[k][i] = ra[e];
+      As[k][i] = (va >> e) & 1 ? ra[e] : T(0);
     }
 #pragma unroll
     for (int e = 0; e < BE; ++e) {
       const int idx = tid + e * 256;
       int j, k;
       if (BT) { k = idx % BK; j = idx / BK; } else { j = idx % BN; k = idx / BN; }
-      Bs[k][j] = rb[e];
+      T v = rb[e];
+      if constexpr (HAD) {
+        // keeps the product (and the wait for both loads) here, after the
+        // current k-tile's matrix-core products
+        T w = rb2[e];
+        asm volatile("" : "+v"(v), "+v"(w));
+        v *= w;
+      }
+      Bs[k][j] = (vb >> e) & 1 ? v : T(0);
     }
   };
 
@@ -121,9 +170,9 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& p, int bid_in, int 
         if (row < p.M && col < p.N) {
           const size_t off = (size_t)row * p.ldc + col;
           T v = p.alpha * acc[a][b][r];
-          if (p.beta != T(0)) v += p.beta * p.C[off];
-          p.C[off] = v;
-          if (p.C2) p.C2[off] = v;
+          if (p.beta != T(0)) v += p.beta * gC[off];
+          gC[off] = v;
+          if (p.C2) gC2[off] = v;
         }
       }
 }
@@ -144,7 +193,7 @@ __global__ __launch_bounds__(256) void gemm_group_kernel(const GemmArgs<T>* tab,
 
 template <typename T, int BM, int BN>
 static void launch_tile(hipStream_t s, const GemmArgs<T>& a, bool at, bool bt, bool had) {
-  const int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+  const int tiles = BM == BN ? gemm_tile_count(a.M, a.N, BM, a.lower) : ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
   dim3 grid(tiles), block(256);
 #define THCCP_GEMM_CASE(AT_, BT_, HAD_)                                           \
   if (at == AT_ && bt == BT_ && had == HAD_) {                                    \

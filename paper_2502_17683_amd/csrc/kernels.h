@@ -27,7 +27,8 @@ namespace thccp {
 //   gate != nullptr: the problem is skipped unless *gate == want (per-problem
 //   choice between the split-BF16 and the FP64 path).
 //   lower != 0: tiles strictly above the diagonal are skipped (C is only
-//   needed on and below it, as in a symmetric rank-k update).
+//   needed on and below it, as in a symmetric rank-k update); for square
+//   C only the lower tiles are launched (see gemm_tile_count).
 template <typename T>
 struct GemmArgs {
   int M, N, K;
@@ -60,7 +61,12 @@ void gemm_f64(hipStream_t s, const GemmF64& g);
 void gemm_f32(hipStream_t s, const GemmF32& g);
 // Tile edge the heuristic picks (128 when the 128-tiles cover the chip).
 int gemm_default_tile(int M, int N);
-inline int gemm_tile_count(int M, int N, int bm) { return ((M + bm - 1) / bm) * ((N + bm - 1) / bm); }
+// Tiles of one GEMM; a lower-triangle GEMM (lower != 0, square) launches
+// only the T (T + 1) / 2 tiles on and below the diagonal.
+inline int gemm_tile_count(int M, int N, int bm, int lower = 0) {
+  const int tm = (M + bm - 1) / bm, tn = (N + bm - 1) / bm;
+  return lower && M == N ? tm * (tm + 1) / 2 : tm * tn;
+}
 // Grouped launch: tab[nprob] problems with identical (a_t, b_t, Hadamard)
 // flags, tile edge bm (64 or 128), offs[nprob + 1] prefix sums of
 // gemm_tile_count(M_p, N_p, bm).

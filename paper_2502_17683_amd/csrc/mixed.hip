@@ -38,38 +38,78 @@ union Pack8 {
 }  // namespace
 
 
+typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+
+// Register stage of one operand for one k-tile: two 8-element K-chunks per
+// thread.  Loads are unconditional (a row past the end reads row r0 and is
+// zeroed at the LDS store); a pair operand keeps the raw FP32 factors and
+// forms the product and its split at the LDS store.  Every value is pinned
+// there, so no wait on the prefetch moves ahead of the current k-tile's
+// matrix-core products.
 template <bool PAIR>
-__device__ __forceinline__ void load_operand(const SplitOperand& op, int rows, int r0, int k0, int tid,
-                                             uint4 h[2], uint4 l[2]) {
+struct Stage;
+
+template <>
+struct Stage<false> {
+  u4_t h[2], l[2];
+  uint32_t ok;
+  __device__ __forceinline__ void load(const SplitOperand& op, int rows, int r0, int k0, int tid) {
+    const gptr<const __bf16> hi = as_global(op.hi), lo = as_global(op.lo);
+    ok = 0;
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int row = (tid + 256 * c) >> 2;
-    const int kc = (tid & 3) * 8;
-    const int gr = r0 + row;
-    if (gr >= rows) {
-      h[c] = make_uint4(0, 0, 0, 0);
-      l[c] = make_uint4(0, 0, 0, 0);
-      continue;
-    }
-    const size_t off = (size_t)gr * op.ld + k0 + kc;
-    if (PAIR) {
-      const float4 p0 = *(const float4*)(op.p + off);
-      const float4 p1 = *(const float4*)(op.p + off + 4);
-      const float4 q0 = *(const float4*)(op.q + off);
-      const float4 q1 = *(const float4*)(op.q + off + 4);
-      const float x[8] = {p0.x * q0.x, p0.y * q0.y, p0.z * q0.z, p0.w * q0.w,
-                          p1.x * q1.x, p1.y * q1.y, p1.z * q1.z, p1.w * q1.w};
-      Pack8 ph, pl;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) split_f(x[j], ph.b[j], pl.b[j]);
-      h[c] = ph.u;
-      l[c] = pl.u;
-    } else {
-      h[c] = *(const uint4*)(op.hi + off);
-      l[c] = *(const uint4*)(op.lo + off);
+    for (int c = 0; c < 2; ++c) {
+      const int gr = r0 + ((tid + 256 * c) >> 2);
+      const bool v = gr < rows;
+      const size_t off = (size_t)(v ? gr : r0) * op.ld + k0 + (tid & 3) * 8;
+      h[c] = *(const gptr<const u4_t>)(hi + off);
+      l[c] = *(const gptr<const u4_t>)(lo + off);
+      ok |= (uint32_t)v << c;
     }
   }
-}
+  __device__ __forceinline__ void get(int c, u4_t& H, u4_t& L) {
+    u4_t x = h[c], y = l[c];
+    asm volatile("" : "+v"(x), "+v"(y));
+    const u4_t z = {0u, 0u, 0u, 0u};
+    H = (ok >> c) & 1 ? x : z;
+    L = (ok >> c) & 1 ? y : z;
+  }
+};
+
+template <>
+struct Stage<true> {
+  f4_t p[2][2], q[2][2];
+  uint32_t ok;
+  __device__ __forceinline__ void load(const SplitOperand& op, int rows, int r0, int k0, int tid) {
+    const gptr<const float> P = as_global(op.p), Q = as_global(op.q);
+    ok = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int gr = r0 + ((tid + 256 * c) >> 2);
+      const bool v = gr < rows;
+      const size_t off = (size_t)(v ? gr : r0) * op.ld + k0 + (tid & 3) * 8;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        p[c][u] = *(const gptr<const f4_t>)(P + off + 4 * u);
+        q[c][u] = *(const gptr<const f4_t>)(Q + off + 4 * u);
+      }
+      ok |= (uint32_t)v << c;
+    }
+  }
+  __device__ __forceinline__ void get(int c, u4_t& H, u4_t& L) {
+    f4_t a0 = p[c][0], a1 = p[c][1], b0 = q[c][0], b1 = q[c][1];
+    asm volatile("" : "+v"(a0), "+v"(a1), "+v"(b0), "+v"(b1));
+    const f4_t x0 = a0 * b0, x1 = a1 * b1;
+    Pack8 ph, pl;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      split_f(x0[j], ph.b[j], pl.b[j]);
+      split_f(x1[j], ph.b[4 + j], pl.b[4 + j]);
+    }
+    const bool v = (ok >> c) & 1;
+    H = v ? u4_t{ph.u.x, ph.u.y, ph.u.z, ph.u.w} : u4_t{0u, 0u, 0u, 0u};
+    L = v ? u4_t{pl.u.x, pl.u.y, pl.u.z, pl.u.w} : u4_t{0u, 0u, 0u, 0u};
+  }
+};
 
 template <bool APAIR, bool BPAIR>
 __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, const int* offs, int nprob) {
@@ -88,7 +128,8 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
 
-  uint4 rah[2], ral[2], rbh[2], rbl[2];
+  Stage<APAIR> sa;
+  Stage<BPAIR> sb;
   f4_t acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -100,23 +141,26 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
     for (int c = 0; c < 2; ++c) {
       const int row = (tid + 256 * c) >> 2;
       const int kc = (tid & 3) * 8;
-      *(uint4*)&Ah[row * SLDK + kc] = rah[c];
-      *(uint4*)&Al[row * SLDK + kc] = ral[c];
-      *(uint4*)&Bh[row * SLDK + kc] = rbh[c];
-      *(uint4*)&Bl[row * SLDK + kc] = rbl[c];
+      u4_t h, l;
+      sa.get(c, h, l);
+      *(u4_t*)&Ah[row * SLDK + kc] = h;
+      *(u4_t*)&Al[row * SLDK + kc] = l;
+      sb.get(c, h, l);
+      *(u4_t*)&Bh[row * SLDK + kc] = h;
+      *(u4_t*)&Bl[row * SLDK + kc] = l;
     }
   };
 
   const int nk = a.K / SBK;
-  load_operand<APAIR>(a.A, a.M, m0, 0, tid, rah, ral);
-  load_operand<BPAIR>(a.B, a.N, n0, 0, tid, rbh, rbl);
+  sa.load(a.A, a.M, m0, 0, tid);
+  sb.load(a.B, a.N, n0, 0, tid);
   store();
   __syncthreads();
   const int koff = 8 * (lane >> 4);
   for (int kt = 0; kt < nk; ++kt) {
     if (kt + 1 < nk) {
-      load_operand<APAIR>(a.A, a.M, m0, (kt + 1) * SBK, tid, rah, ral);
-      load_operand<BPAIR>(a.B, a.N, n0, (kt + 1) * SBK, tid, rbh, rbl);
+      sa.load(a.A, a.M, m0, (kt + 1) * SBK, tid);
+      sb.load(a.B, a.N, n0, (kt + 1) * SBK, tid);
     }
     bf16x8_t ah[4], al[4], bh[4], bl[4];
 #pragma unroll
@@ -156,9 +200,9 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
         const int col = n0 + wn * 64 + j * 16 + (lane & 15);
         if (row < a.M && col < a.N) {
           const size_t off = (size_t)row * a.ldc + col;
-          if (a.C32) a.C32[off] = acc[i][j][r];
-          if (a.C64) a.C64[off] = (double)acc[i][j][r];
-          if (a.C64b) a.C64b[off] = (double)acc[i][j][r];
+          if (a.C32) as_global(a.C32)[off] = acc[i][j][r];
+          if (a.C64) as_global(a.C64)[off] = (double)acc[i][j][r];
+          if (a.C64b) as_global(a.C64b)[off] = (double)acc[i][j][r];
         }
       }
 }

@@ -10,7 +10,10 @@
 namespace thccp {
 
 // V = g0 o g1 o g2 on the R x R block, identity on the padding, plus mu I
-// on the retry pass.  blockIdx.y selects the problem.
+// on the retry pass.  blockIdx.y selects the problem.  V is symmetric and
+// the factorisation reads only its lower 64 x 64 blocks (diagonal blocks
+// whole), so only those are formed; the Grams are computed on the lower
+// tiles only, which cover them.
 template <typename T>
 __global__ __launch_bounds__(256) void form_V_kernel(const FormVArgs<T>* tab, int retry_pass) {
   const FormVArgs<T> a = tab[blockIdx.y];
@@ -22,14 +25,15 @@ __global__ __launch_bounds__(256) void form_V_kernel(const FormVArgs<T>* tab, in
   const size_t total = (size_t)Tp * Tp;
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
     const int i = (int)(e / Tp), j = (int)(e % Tp);
+    if ((j >> 6) > (i >> 6)) continue;
     T v;
     if (i < R && j < R) {
-      v = a.g0[e] * a.g1[e] * a.g2[e];
+      v = as_global(a.g0)[e] * as_global(a.g1)[e] * as_global(a.g2)[e];
       if (i == j) v += mu;
     } else {
       v = (i == j) ? T(1) : T(0);
     }
-    a.V[e] = v;
+    as_global(a.V)[e] = v;
   }
 }
 
@@ -83,49 +87,61 @@ void retry_prepare_group(hipStream_t s, const FormVArgs<T>* tab, int nprob, int 
 
 // Column norms lambda_k of the solved factor, F = Msol / lambda, and (for
 // the fit) the per-column partial sums of Msol o Msave.  One workgroup per
-// 64 columns; 4 row groups reduced in a fixed order.
+// 16 columns (~R/16 workgroups, enough to keep HBM busy); 16 row groups
+// reduced in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(256) void normalise_kernel(const NormArgs<T>* tab) {
-  __shared__ double ss[4][64];
-  __shared__ double si[4][64];
+  __shared__ double ss[16][16];
+  __shared__ double si[16][16];
   const NormArgs<T> a = tab[blockIdx.y];
   if (a.st->done) return;
-  const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
-  const int col = blockIdx.x * 64 + c;
-  if (blockIdx.x * 64 >= a.R) return;
+  const int tid = threadIdx.x, c = tid & 15, g = tid >> 4;
+  const int col = blockIdx.x * 16 + c;
+  if (blockIdx.x * 16 >= a.R) return;
   const int n = a.n, R = a.R, ld = a.ld;
+  const gptr<const T> Msol = as_global(a.Msol), Msave = as_global(a.Msave);
   double x = 0.0, y = 0.0;
-  if (col < R)
-    for (int s = g; s < n; s += 4) {
-      const double v = (double)a.Msol[(size_t)s * ld + col];
+  if (col < R) {
+#pragma unroll 4
+    for (int s = g; s < n; s += 16) {
+      const double v = (double)Msol[(size_t)s * ld + col];
       x += v * v;
-      if (a.Msave) y += v * (double)a.Msave[(size_t)s * ld + col];
+      if (a.Msave) y += v * (double)Msave[(size_t)s * ld + col];
     }
+  }
   ss[g][c] = x;
   si[g][c] = y;
   __syncthreads();
-  const double nrm = sqrt((ss[0][c] + ss[1][c]) + (ss[2][c] + ss[3][c]));
+  double n2 = 0.0, ip = 0.0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    n2 += ss[r][c];
+    ip += si[r][c];
+  }
+  const double nrm = sqrt(n2);
   if (col < R) {
     const double scale = nrm > 0.0 ? 1.0 / nrm : 1.0;
-    for (int s = g; s < n; s += 4) {
+#pragma unroll 4
+    for (int s = g; s < n; s += 16) {
       const size_t off = (size_t)s * ld + col;
-      a.F[off] = (T)((double)a.Msol[off] * scale);
+      as_global(a.F)[off] = (T)((double)Msol[off] * scale);
     }
     if (g == 0) {
       a.lam[col] = (T)nrm;
-      if (a.inner_part) a.inner_part[col] = (si[0][c] + si[1][c]) + (si[2][c] + si[3][c]);
+      if (a.inner_part) a.inner_part[col] = ip;
     }
   }
 }
 
 template <typename T>
 void normalise_group(hipStream_t s, const NormArgs<T>* tab, int nprob, int max_R) {
-  hipLaunchKernelGGL((normalise_kernel<T>), dim3((max_R + 63) / 64, nprob), dim3(256), 0, s, tab);
+  hipLaunchKernelGGL((normalise_kernel<T>), dim3((max_R + 15) / 16, nprob), dim3(256), 0, s, tab);
 }
 
 // ||G~||^2 = lambda^T (g0 o g1 o g2 o g3) lambda: per-row partials, then a
 // single-workgroup final pass per problem that also forms the fit and
-// applies the stopping rule.
+// applies the stopping rule.  The Grams are symmetric and only their lower
+// triangles are computed: row i sums j < i twice and the diagonal once.
 template <typename T>
 __global__ __launch_bounds__(256) void model_norm_rows_kernel(const FitArgs<T>* tab) {
   __shared__ double part[256];
@@ -134,9 +150,11 @@ __global__ __launch_bounds__(256) void model_norm_rows_kernel(const FitArgs<T>* 
   const int i = blockIdx.x, tid = threadIdx.x;
   if (i >= a.R) return;
   double acc = 0.0;
-  for (int j = tid; j < a.R; j += 256) {
+  for (int j = tid; j <= i; j += 256) {
     const size_t e = (size_t)i * a.ld + j;
-    acc += (double)a.g[0][e] * (double)a.g[1][e] * (double)a.g[2][e] * (double)a.g[3][e] * (double)a.lam[j];
+    const double w = j < i ? 2.0 : 1.0;
+    acc += w * (double)as_global(a.g[0])[e] * (double)as_global(a.g[1])[e] * (double)as_global(a.g[2])[e] *
+           (double)as_global(a.g[3])[e] * (double)as_global(a.lam)[j];
   }
   part[tid] = acc;
   __syncthreads();
@@ -285,14 +303,21 @@ void set_path_group(hipStream_t s, DevState* const* st_tab, int nprob, const int
   hipLaunchKernelGGL(set_path_kernel, dim3(nprob), dim3(64), 0, s, st_tab, flags_dev);
 }
 
-__global__ void checkpoint_kernel(const CkptArgs* tab, int dir) {
+// Factor checkpoint (dir 0: save, 1: restore).  The factor buffers are
+// 256-byte aligned plan allocations, copied in 16-byte words (a 4-byte
+// tail loop covers any remainder).
+__global__ __launch_bounds__(256) void checkpoint_kernel(const CkptArgs* tab, int dir) {
   const CkptArgs c = tab[blockIdx.y];
+  const size_t t0 = (size_t)blockIdx.x * 256 + threadIdx.x, stride = (size_t)gridDim.x * 256;
   for (int m = 0; m < 4; ++m) {
-    const uint32_t* src = (const uint32_t*)(dir ? c.b[m] : c.a[m]);
-    uint32_t* dst = (uint32_t*)(dir ? c.a[m] : c.b[m]);
-    const size_t words = c.bytes[m] / 4;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < words; e += (size_t)gridDim.x * 256)
-      dst[e] = src[e];
+    typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+    const gptr<const u4_t> s16 = as_global((const u4_t*)(dir ? c.b[m] : c.a[m]));
+    const gptr<u4_t> d16 = as_global((u4_t*)(dir ? c.a[m] : c.b[m]));
+    const gptr<const uint32_t> s4 = as_global((const uint32_t*)(dir ? c.b[m] : c.a[m]));
+    const gptr<uint32_t> d4 = as_global((uint32_t*)(dir ? c.a[m] : c.b[m]));
+    const size_t n16 = c.bytes[m] / 16;
+    for (size_t e = t0; e < n16; e += stride) d16[e] = s16[e];
+    for (size_t e = n16 * 4 + t0; e < c.bytes[m] / 4; e += stride) d4[e] = s4[e];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (dir) *c.st = *c.st_save;
@@ -300,7 +325,7 @@ __global__ void checkpoint_kernel(const CkptArgs* tab, int dir) {
   }
 }
 void checkpoint_group(hipStream_t s, const CkptArgs* tab, int nprob, int dir) {
-  hipLaunchKernelGGL(checkpoint_kernel, dim3(256, nprob), dim3(256), 0, s, tab, dir);
+  hipLaunchKernelGGL(checkpoint_kernel, dim3(nprob > 4 ? 128 : 1024, nprob), dim3(256), 0, s, tab, dir);
 }
 
 // Laplace-transform scaling of the THC rows: out[p, :] = exp(sign eps_p t) X[p, :].
