@@ -375,21 +375,35 @@ __host__ __device__ inline void bwd_range(int nblk, int pw, int pf, int tf, int&
   }
   kmin = js > hi ? js - 1 : lo;
 }
+// One level (pw >= nblk): the columns beyond j + 2 take their updates in
+// pairs, at odd j (rank 128, columns j - 1 and j), and are left out of the
+// launches of even j; columns j + 1 and j + 2 are always brought up to date,
+// so a column is current when it becomes the next column to factor.  This
+// halves the trailing-matrix traffic of the early, bandwidth-bound steps.
+__host__ __device__ inline bool chol_paired(int nblk, int pw, int j) { return pw >= nblk && j >= 0; }
 __host__ __device__ inline int chol_tiles(int nblk, int pw, int pc, int tc) {
   int j, lo, kmax;
   chol_range(nblk, pw, pc, tc, j, lo, kmax);
+  if (chol_paired(nblk, pw, j) && !(j & 1) && kmax > j + 2) kmax = j + 2;
   int t = 0;
   for (int k = j + 1; k <= kmax; ++k) t += nblk - k;
   return t;
 }
+// The one-level triangular solves pair their far updates the same way:
+// forward step js updates blocks beyond js + 2 only at odd js (with G_{js-1}
+// and G_js); backward step js (s = hi - js steps from the end) updates
+// blocks below js - 2 only at odd s (with F_{js+1} and F_js).
+__host__ __device__ inline bool bwd_paired(int nblk, int pw, int js, int hi) { return pw >= nblk && js <= hi; }
 __host__ __device__ inline int fwd_tiles(int nblk, int nrt, int pw, int pf, int tf) {
   int js, lo, kmax;
   chol_range(nblk, pw, pf, tf, js, lo, kmax);
+  if (chol_paired(nblk, pw, js) && !(js & 1) && kmax > js + 2) kmax = js + 2;
   return kmax >= js + 1 ? nrt * (kmax - js) : 0;
 }
 __host__ __device__ inline int bwd_tiles(int nblk, int nrt, int pw, int pf, int tf) {
   int js, hi, kmin;
   bwd_range(nblk, pw, pf, tf, js, hi, kmin);
+  if (bwd_paired(nblk, pw, js, hi) && !((hi - js) & 1) && kmin < js - 2) kmin = js - 2;
   return js - 1 >= kmin ? nrt * (js - kmin) : 0;
 }
 
@@ -423,6 +437,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
   const int nblk = probs[pid].nblk;
   const int n = probs[pid].n;
   int bid = blockIdx.x - offs[pid];
+  const int nbid = offs[pid + 1] - offs[pid];
   if (st->done) return;
   const int Tp = nblk * TB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -437,28 +452,44 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
     if (bid < nc) {
       const bool upd = j >= jlo;  // update with block column j (inside the panel)
       int i, k;
+      // (no XCD remap here: the next column's tiles, the critical path,
+      // must spread over all XCDs)
       tri_tile(bid, j + 1, nblk, i, k);
       T* tile = V + (size_t)i * TB * Tp + (size_t)k * TB;
+      // a tile beyond column j + 1 at odd j also takes column j - 1
+      const bool two = upd && chol_paired(nblk, cfg.pw, j) && (j & 1) && k >= j + 2;
+      const int j0 = two ? j - 1 : j;
       // every global load of the step is issued up front
       acc_t acc[4];
       T ra[16], rb[16];
       load_acc<T>(acc, tile, Tp, TB, lane, w);
       if (upd) {
-        fetch_block<T>(ra, V + (size_t)i * TB * Tp + (size_t)j * TB, Tp, TB, tid);
-        fetch_block<T>(rb, V + (size_t)k * TB * Tp + (size_t)j * TB, Tp, TB, tid);
+        fetch_block<T>(ra, V + (size_t)i * TB * Tp + (size_t)j0 * TB, Tp, TB, tid);
+        fetch_block<T>(rb, V + (size_t)k * TB * Tp + (size_t)j0 * TB, Tp, TB, tid);
       }
       acc_t dd[4];
       const bool need_d = (k == j + 1) && (i != k);
       if (need_d) load_acc<T>(dd, V + (size_t)k * TB * Tp + (size_t)k * TB, Tp, TB, lane, w);
       if (upd) {
-        // tile -= L_ij L_kj^T
+        // tile -= L_ij0 L_kj0^T (and, for a paired update, then L_ij L_kj^T)
         put_block<T, true>(S0, ra, tid);
         put_block<T, true>(S1, rb, tid);
         __syncthreads();
+        if (two) {  // the second pair is fetched under the first product
+          fetch_block<T>(ra, V + (size_t)i * TB * Tp + (size_t)j * TB, Tp, TB, tid);
+          fetch_block<T>(rb, V + (size_t)k * TB * Tp + (size_t)j * TB, Tp, TB, tid);
+        }
         acc_t p[4];
 #pragma unroll
         for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
         tile_mma64<T>(p, S0, S1, lane, w);
+        if (two) {
+          __syncthreads();  // every wave is past its reads of S0 / S1
+          put_block<T, true>(S0, ra, tid);
+          put_block<T, true>(S1, rb, tid);
+          __syncthreads();
+          tile_mma64<T>(p, S0, S1, lane, w);
+        }
 #pragma unroll
         for (int tj = 0; tj < 4; ++tj) acc[tj] -= p[tj];
         if (k != j + 1) {
@@ -523,6 +554,9 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
     if (FWD) chol_range(nblk, cfg.pw, cfg.pf, cfg.tf, js, lim, kext);
     else bwd_range(nblk, cfg.pw, cfg.pf, cfg.tf, js, lim, kext);
     const int nrt = (n + TB - 1) / TB;
+    // the row blocks of one column share L_jk and the column's blocks of
+    // one row share F_j: XCD-contiguous ranges keep both in one L2
+    bid = xcd_remap(bid, MODE == STEP_CHOL_FWD ? nbid - chol_tiles(nblk, cfg.pw, cfg.pc, cfg.tc) : nbid);
     const int rt = bid % nrt;
     const int k = FWD ? js + 1 + bid / nrt : js - 1 - bid / nrt;
     const int r0 = rt * TB;
@@ -530,25 +564,41 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
     T* tile = M + (size_t)r0 * Tp + (size_t)k * TB;
     const bool has_update = FWD ? (js >= lim) : (js <= lim);
     const bool solve = FWD ? (k == js + 1) : (k == js - 1);
+    // a far block of a paired step also takes column js - 1 (forward) or
+    // js + 1 (backward), first
+    const bool two = has_update && (FWD ? chol_paired(nblk, cfg.pw, js) && (js & 1) && k >= js + 2
+                                        : bwd_paired(nblk, cfg.pw, js, lim) && ((lim - js) & 1) && k <= js - 2);
+    const int j0 = two ? (FWD ? js - 1 : js + 1) : js;
     // every global load of the step is issued up front
     acc_t acc[4];
     T ra[16], rb[16], rl[16];
-    load_acc<T>(acc, tile, Tp, nrows, lane, w);
-    if (has_update) {
-      fetch_block<T>(ra, M + (size_t)r0 * Tp + (size_t)js * TB, Tp, nrows, tid);
-      if (FWD) fetch_block<T>(rb, V + (size_t)k * TB * Tp + (size_t)js * TB, Tp, TB, tid);  // L_kj
-      else fetch_block<T>(rb, V + (size_t)js * TB * Tp + (size_t)k * TB, Tp, TB, tid);     // L_jk
-    }
-    if (solve) fetch_block<T>(rl, ldiag + (size_t)k * TB * TB, TB, TB, tid);
-    if (has_update) {
+    auto fetch_pair = [&](int jj) {
+      fetch_block<T>(ra, M + (size_t)r0 * Tp + (size_t)jj * TB, Tp, nrows, tid);
+      if (FWD) fetch_block<T>(rb, V + (size_t)k * TB * Tp + (size_t)jj * TB, Tp, TB, tid);  // L_kj
+      else fetch_block<T>(rb, V + (size_t)jj * TB * Tp + (size_t)k * TB, Tp, TB, tid);     // L_jk
+    };
+    auto put_pair = [&]() {
       put_block<T, true>(S0, ra, tid);
       if (FWD) put_block<T, true>(S1, rb, tid);   // B = L_kj^T
       else put_block<T, false>(S1, rb, tid);      // B = L_jk
+    };
+    load_acc<T>(acc, tile, Tp, nrows, lane, w);
+    if (has_update) fetch_pair(j0);
+    if (solve) fetch_block<T>(rl, ldiag + (size_t)k * TB * TB, TB, TB, tid);
+    if (has_update) {
+      put_pair();
       __syncthreads();
+      if (two) fetch_pair(js);  // under the first product
       acc_t p[4];
 #pragma unroll
       for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
       tile_mma64<T>(p, S0, S1, lane, w);
+      if (two) {
+        __syncthreads();  // every wave is past its reads of S0 / S1
+        put_pair();
+        __syncthreads();
+        tile_mma64<T>(p, S0, S1, lane, w);
+      }
 #pragma unroll
       for (int tj = 0; tj < 4; ++tj) acc[tj] -= p[tj];
     }
