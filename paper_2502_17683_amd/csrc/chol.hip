@@ -109,13 +109,34 @@ __device__ __forceinline__ void store_b4(const T s[16], T* gp_, size_t ld, int n
 // tile in indexed registers).
 //   FWD: S <- S L^{-T}  (solve X L^T = S, columns left to right)
 //   BWD: S <- S L^{-1}  (solve X L = S, columns right to left)
-// L in LDS row-major (stride LDT), invd[c] = 1 / L[c][c].
+// L in LDS row-major (stride LDT), invd[c] = 1 / L[c][c].  The LDS values a
+// column needs (1 / L[c][c] and four entries of L) do not depend on the
+// solve: each step reads those of the next column, so the reads stay off
+// the dependent chain of the columns.
+template <typename T, bool FWD, int C>
+__device__ __forceinline__ void b4_col_values(const T* L, const T* invd, int j, T& ic, T lk[4]) {
+  constexpr int vc = C >> 4, jc = C & 15;
+  ic = invd[C];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    // FWD: L[k][C] for k = j + 16 v > C;  BWD: L[C][k] for k < C
+    if (FWD ? v >= vc : v <= vc) {
+      T x = FWD ? L[(j + 16 * v) * LDT + C] : L[C * LDT + j + 16 * v];
+      if (v == vc) x = (FWD ? j > jc : j < jc) ? x : T(0);
+      lk[v] = x;
+    } else {
+      lk[v] = T(0);
+    }
+  }
+}
 template <typename T, bool FWD, int C>
 struct B4Solve {
-  __device__ __forceinline__ static void run(T s[16], const T* L, const T* invd, int j) {
+  __device__ __forceinline__ static void run(T s[16], const T* L, const T* invd, int j, T ic, const T lk[4]) {
     if constexpr (C >= 0 && C < TB) {
       constexpr int vc = C >> 4, jc = C & 15;
-      const T ic = invd[C];
+      constexpr int CN = FWD ? C + 1 : C - 1;
+      T icn = T(0), lkn[4] = {T(0), T(0), T(0), T(0)};
+      if constexpr (CN >= 0 && CN < TB) b4_col_values<T, FWD, CN>(L, invd, j, icn, lkn);
       T x[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) x[i] = rnb<jc>(s[4 * i + vc] * ic);
@@ -123,24 +144,24 @@ struct B4Solve {
 #pragma unroll
       for (int i = 0; i < 4; ++i) s[4 * i + vc] = own ? x[i] : s[4 * i + vc];
 #pragma unroll
-      for (int v = FWD ? vc : 0; v <= (FWD ? 3 : vc); ++v) {
-        // FWD: L[k][C] for k = j + 16 v > C;  BWD: L[C][k] for k < C
-        T lk = FWD ? L[(j + 16 * v) * LDT + C] : L[C * LDT + j + 16 * v];
-        if (v == vc) lk = (FWD ? j > jc : j < jc) ? lk : T(0);
+      for (int v = FWD ? vc : 0; v <= (FWD ? 3 : vc); ++v)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) s[4 * i + v] -= x[i] * lk;
-      }
-      B4Solve<T, FWD, FWD ? C + 1 : C - 1>::run(s, L, invd, j);
+        for (int i = 0; i < 4; ++i) s[4 * i + v] -= x[i] * lk[v];
+      B4Solve<T, FWD, CN>::run(s, L, invd, j, icn, lkn);
     }
   }
 };
 template <typename T>
 __device__ __forceinline__ void b4_fwd(T s[16], const T* L, const T* invd, int j) {
-  B4Solve<T, true, 0>::run(s, L, invd, j);
+  T ic, lk[4];
+  b4_col_values<T, true, 0>(L, invd, j, ic, lk);
+  B4Solve<T, true, 0>::run(s, L, invd, j, ic, lk);
 }
 template <typename T>
 __device__ __forceinline__ void b4_bwd(T s[16], const T* L, const T* invd, int j) {
-  B4Solve<T, false, TB - 1>::run(s, L, invd, j);
+  T ic, lk[4];
+  b4_col_values<T, false, TB - 1>(L, invd, j, ic, lk);
+  B4Solve<T, false, TB - 1>::run(s, L, invd, j, ic, lk);
 }
 
 // Cholesky of the 64 x 64 block held in strip layout d (lower part used),

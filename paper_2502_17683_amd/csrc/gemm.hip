@@ -210,10 +210,10 @@ static void launch_tile(hipStream_t s, const GemmArgs<T>& a, bool at, bool bt, b
 }
 
 int gemm_default_tile(int M, int N) {
-  // 128x128 tiles when there are enough of them to cover the 256 compute
-  // units, 64x64 otherwise.
+  // 64 x 64 tiles (three workgroups per compute unit) unless there are
+  // thousands of 128 x 128 tiles
   const long t128 = (long)((M + 127) / 128) * ((N + 127) / 128);
-  return t128 >= 256 ? 128 : 64;
+  return t128 >= 4096 ? 128 : 64;
 }
 
 template <typename T>

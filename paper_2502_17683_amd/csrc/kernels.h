@@ -59,7 +59,7 @@ struct GemmF32 {
 };
 void gemm_f64(hipStream_t s, const GemmF64& g);
 void gemm_f32(hipStream_t s, const GemmF32& g);
-// Tile edge the heuristic picks (128 when the 128-tiles cover the chip).
+// Tile edge the heuristic picks (64; 128 only for thousands of 128-tiles).
 int gemm_default_tile(int M, int N);
 // Tiles of one GEMM; a lower-triangle GEMM (lower != 0, square) launches
 // only the T (T + 1) / 2 tiles on and below the diagonal.
