@@ -476,6 +476,9 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
       // (no XCD remap here: the next column's tiles, the critical path,
       // must spread over all XCDs)
       tri_tile(bid, j + 1, nblk, i, k);
+      // the next column's workgroups are the critical path: their waves
+      // issue first on a compute unit shared with trailing updates
+      if (k == j + 1) __builtin_amdgcn_s_setprio(3);
       T* tile = V + (size_t)i * TB * Tp + (size_t)k * TB;
       // a tile beyond column j + 1 at odd j also takes column j - 1
       const bool two = upd && chol_paired(nblk, cfg.pw, j) && (j & 1) && k >= j + 2;
@@ -585,6 +588,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
     T* tile = M + (size_t)r0 * Tp + (size_t)k * TB;
     const bool has_update = FWD ? (js >= lim) : (js <= lim);
     const bool solve = FWD ? (k == js + 1) : (k == js - 1);
+    if (solve) __builtin_amdgcn_s_setprio(3);  // the solve chain, as above
     // a far block of a paired step also takes column js - 1 (forward) or
     // js + 1 (backward), first
     const bool two = has_update && (FWD ? chol_paired(nblk, cfg.pw, js) && (js & 1) && k >= js + 2

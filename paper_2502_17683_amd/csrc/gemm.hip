@@ -18,7 +18,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& p, int bid_in, int 
   constexpr int BK = 16;
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int TI = WTM / 16, TJ = WTN / 16;
-  constexpr int PAD = 4;
+  constexpr int PAD = 1;  // odd row stride: the k-contiguous A stores hit distinct banks
   constexpr int AE = BM * BK / 256, BE = BN * BK / 256;
   typedef typename Acc4<T>::type acc_t;
   __shared__ T As[BK][BM + PAD];

@@ -22,9 +22,11 @@ __device__ __forceinline__ f4_t mfma4(float a, float b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// 64x64 tiles held in LDS in "k-major" form: X[kk * LDT + idx].
+// 64x64 tiles held in LDS in "k-major" form: X[kk * LDT + idx].  The odd
+// row stride puts the 16 / 32 lanes of a column-wise (transposed) store in
+// distinct banks; row-wise fragment reads are consecutive either way.
 constexpr int TB = 64;
-constexpr int LDT = TB + 4;
+constexpr int LDT = TB + 1;
 
 // acc (wave w owns rows 16w..16w+15 and all 64 columns, 4 MFMA tiles)
 //   += A(64 x 64) * B(64 x 64), A given as Ak[kk][row], B as Bk[kk][col].
