@@ -329,11 +329,14 @@ cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, con
 /* cpd_test_gemm_split: C (M x N, FP64) = A B^T from FP64 A (M x K) and
  *   B (N x K) through the split-BF16 product (hi*hi + hi*lo + lo*hi, FP32
  *   accumulation).  With A2 != NULL the A operand is the FP32 product
- *   A o A2, split on the fly.  Uploads a one-entry argument table and
+ *   A o A2, split on the fly.  bm: row tile of the launch, 64 or 128 (0:
+ *   the heuristic the sweep uses); other values return
+ *   CPD_ERR_INVALID_ARG.  Uploads a one-entry argument table and
  *   synchronises before the launch. */
 size_t cpd_test_split_workspace(int32_t M, int32_t N, int32_t K);
 cpd_status cpd_test_gemm_split(int32_t M, int32_t N, int32_t K, const double* A, const double* A2,
-                               const double* B, double* C, void* workspace, size_t ws_bytes, void* stream);
+                               const double* B, double* C, void* workspace, size_t ws_bytes, void* stream,
+                               int32_t bm);
 /* cpd_test_mfma_probe: lane-layout probe of the 16x16x4 FP64 (fp32 = 0) or
  *   FP32 matrix instruction.  Probe p (of nprobe) feeds a[64p + lane] and
  *   b[64p + lane] to one wave with a zero accumulator and writes the four

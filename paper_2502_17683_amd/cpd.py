@@ -307,14 +307,15 @@ def test_solve(V, M, panel=0):
     return F, bool(failed.value)
 
 
-def test_gemm_split(A, B, A2=None):
-    """C = A B^T (or (A o A2) B^T) through the split-BF16 GEMM."""
+def test_gemm_split(A, B, A2=None, bm=0):
+    """C = A B^T (or (A o A2) B^T) through the split-BF16 GEMM (row tile bm:
+    64, 128, or 0 for the sweep's heuristic)."""
     lib = _lib.load()
     M, K = A.shape
     N = B.shape[0]
     ws = torch.empty(lib.cpd_test_split_workspace(M, N, K), dtype=torch.uint8, device=A.device)
     C = torch.empty(M, N, dtype=torch.float64, device=A.device)
     check(lib.cpd_test_gemm_split(M, N, K, _ptr(A), _ptr(A2), _ptr(B), _ptr(C), _ptr(ws), ws.numel(),
-                                  _stream(A.device)), "cpd_test_gemm_split")
+                                  _stream(A.device), int(bm)), "cpd_test_gemm_split")
     torch.cuda.current_stream(A.device).synchronize()
     return C

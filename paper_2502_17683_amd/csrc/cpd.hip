@@ -335,8 +335,18 @@ GroupOp split_op(TableBuilder& tb, const std::vector<SplitArgs>& v, bool apair, 
   op.apair = apair;
   op.bpair = bpair;
   op.count = (int)v.size();
+  // 64-row tiles when 128-row ones would pad a quarter more rows (short M,
+  // as in the Laplace batch) or leave most compute units idle; otherwise
+  // 128 (fewer re-reads of the B operand)
+  long t128 = 0, rows64 = 0, rows128 = 0;
+  for (auto& g : v) {
+    t128 += split_tile_count(g.M, g.N, 128);
+    rows64 += (long)(g.M + 63) / 64 * 64;
+    rows128 += (long)(g.M + 127) / 128 * 128;
+  }
+  op.bm = (4 * rows128 >= 5 * rows64 || t128 < 128) ? 64 : 128;
   std::vector<int> offs(1, 0);
-  for (auto& g : v) offs.push_back(offs.back() + split_tile_count(g.M, g.N));
+  for (auto& g : v) offs.push_back(offs.back() + split_tile_count(g.M, g.N, op.bm));
   op.total = offs.back();
   op.tab = tb.put(v);
   op.offs = (int*)tb.put(offs);
@@ -653,7 +663,7 @@ void run_gemm(cpd_plan_s* p, hipStream_t s, const GroupOp& op) {
 }
 void run_split(cpd_plan_s* p, hipStream_t s, const GroupOp& op) {
   (void)p;
-  gemm_split_group(s, (const SplitArgs*)op.tab, op.offs, op.count, op.total, op.apair, op.bpair);
+  gemm_split_group(s, (const SplitArgs*)op.tab, op.offs, op.count, op.total, op.apair, op.bpair, op.bm);
 }
 template <typename T>
 void run_sched(cpd_plan_s* p, hipStream_t s, int n, const std::vector<SolveLaunch>& sched, int retry_pass) {

@@ -158,8 +158,11 @@ size_t cpd_test_split_workspace(int32_t M, int32_t N, int32_t K) {
 // non-null the A operand is the FP32 element-wise product A o A2 (split on
 // the fly), as in the fused core product.
 cpd_status cpd_test_gemm_split(int32_t M, int32_t N, int32_t K, const double* A, const double* A2,
-                               const double* B, double* C, void* workspace, size_t ws_bytes, void* stream) {
+                               const double* B, double* C, void* workspace, size_t ws_bytes, void* stream,
+                               int32_t bm) {
   if (M <= 0 || N <= 0 || K <= 0 || !A || !B || !C) return CPD_ERR_INVALID_ARG;
+  if (bm == 0) bm = split_default_bm(M, N);
+  if (bm != 64 && bm != 128) return CPD_ERR_INVALID_ARG;
   if (!workspace || ws_bytes < cpd_test_split_workspace(M, N, K)) return CPD_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   const int Kp = (K + 31) / 32 * 32;
@@ -186,11 +189,11 @@ cpd_status cpd_test_gemm_split(int32_t M, int32_t N, int32_t K, const double* A,
     opA = SplitOperand{Ah, Al, nullptr, nullptr, Kp};
   }
   const SplitArgs ha{M, N, Kp, opA, opB, nullptr, C, nullptr, N, nullptr, nullptr, 0};
-  const int ho[2] = {0, split_tile_count(M, N)};
+  const int ho[2] = {0, split_tile_count(M, N, bm)};
   if (hipMemcpyAsync(tab, &ha, sizeof(ha), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
   if (hipMemcpyAsync(offs, ho, sizeof(ho), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return CPD_ERR_HIP;  // host copies of ha/ho go out of scope
-  gemm_split_group(s, tab, offs, 1, ho[1], opA.p != nullptr, false);
+  gemm_split_group(s, tab, offs, 1, ho[1], opA.p != nullptr, false, bm);
   return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
 }
 

@@ -49,10 +49,13 @@ struct SplitArgs {
   const int32_t* gate;  // skip unless *gate == want (per-problem precision path)
   int32_t want;
 };
-int split_tile_count(int M, int N);
-// Grouped launch: all problems share (A pair?, B pair?).
+// Tiles of one product with row tile bm (128, or 64 for short M or when
+// the 128-row tiles would leave most compute units idle: split_default_bm).
+int split_tile_count(int M, int N, int bm);
+int split_default_bm(int M, int N);
+// Grouped launch: all problems share (A pair?, B pair?) and the row tile bm.
 void gemm_split_group(hipStream_t s, const SplitArgs* tab, const int* offs, int nprob, int total_tiles,
-                      bool apair, bool bpair);
+                      bool apair, bool bpair, int bm);
 
 // dst (cols x ldd) = split(src^T): dst[c][r] for c < cols, r < dcols
 // (r >= rows written as 0).

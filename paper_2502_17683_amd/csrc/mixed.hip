@@ -46,18 +46,18 @@ typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
 // forms the product and its split at the LDS store.  Every value is pinned
 // there, so no wait on the prefetch moves ahead of the current k-tile's
 // matrix-core products.
-template <bool PAIR>
+template <bool PAIR, int C>
 struct Stage;
 
-template <>
-struct Stage<false> {
-  u4_t h[2], l[2];
+template <int C>
+struct Stage<false, C> {
+  u4_t h[C], l[C];
   uint32_t ok;
   __device__ __forceinline__ void load(const SplitOperand& op, int rows, int r0, int k0, int tid) {
     const gptr<const __bf16> hi = as_global(op.hi), lo = as_global(op.lo);
     ok = 0;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < C; ++c) {
       const int gr = r0 + ((tid + 256 * c) >> 2);
       const bool v = gr < rows;
       const size_t off = (size_t)(v ? gr : r0) * op.ld + k0 + (tid & 3) * 8;
@@ -75,15 +75,15 @@ struct Stage<false> {
   }
 };
 
-template <>
-struct Stage<true> {
-  f4_t p[2][2], q[2][2];
+template <int C>
+struct Stage<true, C> {
+  f4_t p[C][2], q[C][2];
   uint32_t ok;
   __device__ __forceinline__ void load(const SplitOperand& op, int rows, int r0, int k0, int tid) {
     const gptr<const float> P = as_global(op.p), Q = as_global(op.q);
     ok = 0;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < C; ++c) {
       const int gr = r0 + ((tid + 256 * c) >> 2);
       const bool v = gr < rows;
       const size_t off = (size_t)(v ? gr : r0) * op.ld + k0 + (tid & 3) * 8;
@@ -111,10 +111,13 @@ struct Stage<true> {
   }
 };
 
-template <bool APAIR, bool BPAIR>
+// Block tile BM x 128 (BM = 128, or 64 for short M so that the launch
+// still covers the compute units); 2 x 2 waves, each (BM / 2) x 64.
+template <bool APAIR, bool BPAIR, int BM>
 __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, const int* offs, int nprob) {
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[SBM * SLDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Al[SBM * SLDK];
+  constexpr int CA = BM / 64, TI = BM / 32;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[BM * SLDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[BM * SLDK];
   __shared__ __attribute__((aligned(16))) __bf16 Bh[SBN * SLDK];
   __shared__ __attribute__((aligned(16))) __bf16 Bl[SBN * SLDK];
   int pid = 0;
@@ -124,15 +127,15 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
   if (a.gate && *a.gate != a.want) return;
   const int tiles_n = (a.N + SBN - 1) / SBN;
   const int bid = xcd_remap(blockIdx.x - offs[pid], offs[pid + 1] - offs[pid]);
-  const int m0 = (bid / tiles_n) * SBM, n0 = (bid % tiles_n) * SBN;
+  const int m0 = (bid / tiles_n) * BM, n0 = (bid % tiles_n) * SBN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
 
-  Stage<APAIR> sa;
-  Stage<BPAIR> sb;
-  f4_t acc[4][4];
+  Stage<APAIR, CA> sa;
+  Stage<BPAIR, 2> sb;
+  f4_t acc[TI][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
@@ -142,9 +145,11 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
       const int row = (tid + 256 * c) >> 2;
       const int kc = (tid & 3) * 8;
       u4_t h, l;
-      sa.get(c, h, l);
-      *(u4_t*)&Ah[row * SLDK + kc] = h;
-      *(u4_t*)&Al[row * SLDK + kc] = l;
+      if (c < CA) {
+        sa.get(c, h, l);
+        *(u4_t*)&Ah[row * SLDK + kc] = h;
+        *(u4_t*)&Al[row * SLDK + kc] = l;
+      }
       sb.get(c, h, l);
       *(u4_t*)&Bh[row * SLDK + kc] = h;
       *(u4_t*)&Bl[row * SLDK + kc] = l;
@@ -162,10 +167,10 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
       sa.load(a.A, a.M, m0, (kt + 1) * SBK, tid);
       sb.load(a.B, a.N, n0, (kt + 1) * SBK, tid);
     }
-    bf16x8_t ah[4], al[4], bh[4], bl[4];
+    bf16x8_t ah[TI], al[TI], bh[4], bl[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = wm * 64 + i * 16 + (lane & 15);
+    for (int i = 0; i < TI; ++i) {
+      const int row = wm * (BM / 2) + i * 16 + (lane & 15);
       ah[i] = *(const bf16x8_t*)&Ah[row * SLDK + koff];
       al[i] = *(const bf16x8_t*)&Al[row * SLDK + koff];
     }
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
       bl[j] = *(const bf16x8_t*)&Bl[col * SLDK + koff];
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
@@ -191,12 +196,12 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
   }
 
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const int row = m0 + wm * (BM / 2) + i * 16 + 4 * (lane >> 4) + r;
         const int col = n0 + wn * 64 + j * 16 + (lane & 15);
         if (row < a.M && col < a.N) {
           const size_t off = (size_t)row * a.ldc + col;
@@ -207,16 +212,27 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
       }
 }
 
-int split_tile_count(int M, int N) { return ((M + SBM - 1) / SBM) * ((N + SBN - 1) / SBN); }
+int split_tile_count(int M, int N, int bm) { return ((M + bm - 1) / bm) * ((N + SBN - 1) / SBN); }
+int split_default_bm(int M, int N) {
+  const long r64 = (M + 63) / 64 * 64, r128 = (M + 127) / 128 * 128;
+  return (4 * r128 >= 5 * r64 || split_tile_count(M, N, 128) < 128) ? 64 : 128;
+}
 
 void gemm_split_group(hipStream_t s, const SplitArgs* tab, const int* offs, int nprob, int total_tiles,
-                      bool apair, bool bpair) {
+                      bool apair, bool bpair, int bm) {
   if (total_tiles <= 0) return;
   dim3 grid(total_tiles), block(256);
-  if (!apair && !bpair) hipLaunchKernelGGL((gemm_split_kernel<false, false>), grid, block, 0, s, tab, offs, nprob);
-  else if (apair && !bpair) hipLaunchKernelGGL((gemm_split_kernel<true, false>), grid, block, 0, s, tab, offs, nprob);
-  else if (!apair && bpair) hipLaunchKernelGGL((gemm_split_kernel<false, true>), grid, block, 0, s, tab, offs, nprob);
-  else hipLaunchKernelGGL((gemm_split_kernel<true, true>), grid, block, 0, s, tab, offs, nprob);
+#define THCCP_SPLIT_CASE(AP, BP)                                                                      \
+  if (apair == AP && bpair == BP) {                                                                  \
+    if (bm == 64) hipLaunchKernelGGL((gemm_split_kernel<AP, BP, 64>), grid, block, 0, s, tab, offs, nprob); \
+    else hipLaunchKernelGGL((gemm_split_kernel<AP, BP, 128>), grid, block, 0, s, tab, offs, nprob);        \
+    return;                                                                                          \
+  }
+  THCCP_SPLIT_CASE(false, false)
+  THCCP_SPLIT_CASE(true, false)
+  THCCP_SPLIT_CASE(false, true)
+  THCCP_SPLIT_CASE(true, true)
+#undef THCCP_SPLIT_CASE
 }
 
 // ------------------------------------------------------------- splitting

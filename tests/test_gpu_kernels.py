@@ -85,17 +85,18 @@ def test_spd_solve_detects_indefinite():
 
 @pytest.mark.parametrize("M,N,K", [(37, 29, 50), (256, 130, 300), (800, 1000, 1024)])
 @pytest.mark.parametrize("pair", [False, True])
-def test_gemm_split_error_bound(M, N, K, pair):
+@pytest.mark.parametrize("bm", [64, 128])
+def test_gemm_split_error_bound(M, N, K, pair, bm):
     """Split-BF16 product: every element within the bound of one correction
     pass (dropped lo*lo term and the two bf16 roundings, ~3 * 2^-16 of
     sum |a||b|) plus FP32 accumulation (K * 2^-24 of sum |a||b|)."""
     from paper_2502_17683_amd import test_gemm_split
-    say(f"split M={M} N={N} K={K} pair={pair}")
+    say(f"split M={M} N={N} K={K} pair={pair} bm={bm}")
     rng = np.random.default_rng(M + N + K)
     A = rng.standard_normal((M, K))
     A2 = rng.standard_normal((M, K)) if pair else None
     B = rng.standard_normal((N, K))
-    C = test_gemm_split(to_dev(A), to_dev(B), to_dev(A2) if pair else None).cpu().numpy()
+    C = test_gemm_split(to_dev(A), to_dev(B), to_dev(A2) if pair else None, bm=bm).cpu().numpy()
     Aop = (A.astype(np.float32) * A2.astype(np.float32)).astype(np.float64) if pair else A
     ref = Aop @ B.T
     scale = np.abs(Aop) @ np.abs(B).T
