@@ -302,11 +302,9 @@ GroupOp gemm_op(TableBuilder& tb, const std::vector<GemmArgs<T>>& v, bool at, bo
   GroupOp op;
   op.a_t = at;
   op.had = had;
-  // tile edge: autotune cache, else heuristic.  The 64 x 64 tiles keep
-  // three workgroups per compute unit (the 128 x 128 tiles hold ~400 VGPRs,
-  // one per unit) and measure faster at the shapes here (R = 4000, n = 800:
-  // Gram 0.31 vs 0.51 ms, core product 3.35 vs 3.65 ms); 128 only when
-  // there are thousands of 128-tiles.
+  // tile edge: autotune cache, else heuristic.  Register-staged tiles: 64
+  // (three workgroups per compute unit; the staged 128 x 128 form holds
+  // ~400 registers, one per unit), 128 only with thousands of tiles.
   std::vector<int> dims;
   long t128 = 0;
   for (auto& g : v) {
@@ -315,13 +313,24 @@ GroupOp gemm_op(TableBuilder& tb, const std::vector<GemmArgs<T>>& v, bool at, bo
     dims.push_back(g.K);
     t128 += gemm_tile_count(g.M, g.N, 128, g.lower);
   }
-  op.bm = t128 >= 4096 ? 128 : 64;
+  // FP64: 128 is the direct-load path (1.3-1.4x the 64-tiles at R = 4000),
+  // taken when every entry qualifies and the 128-tiles cover the compute
+  // units (the back-projection's 224 tiles at n = 800 stay on 64)
+  bool dma = sizeof(T) == 8, lower = false;
+  for (auto& g : v) {
+    dma = dma && gemm_dma_ok(g, had);
+    lower = lower || g.lower;
+  }
+  // (a lower-triangle product keeps the 64-tiles: its diagonal 128-tiles
+  // would compute twice the needed elements; Gram 0.30 vs 0.33 ms)
+  op.bm = dma && !lower ? (t128 >= 256 ? 128 : 64) : (t128 >= 4096 ? 128 : 64);
   op.count = (int)v.size();
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(tune_key(kind, dims));
     if (it != g_tune.end()) op.bm = it->second;
   }
+  if (sizeof(T) == 8 && !dma) op.bm = 64;
   std::vector<int> offs(1, 0);
   for (auto& g : v) offs.push_back(offs.back() + gemm_tile_count(g.M, g.N, op.bm, g.lower));
   op.total = offs.back();
@@ -937,7 +946,10 @@ void autotune_ops(cpd_plan_s* p, hipStream_t s) {
     }
     float best = 1e30f;
     int best_bm = op.bm;
+    bool dma = sizeof(T) == 8;
+    for (auto& g : host) dma = dma && gemm_dma_ok(g, op.had);
     for (int bm : {64, 128}) {
+      if (bm == 128 && sizeof(T) == 8 && !dma) continue;
       std::vector<int> offs(1, 0);
       for (auto& g : host) offs.push_back(offs.back() + gemm_tile_count(g.M, g.N, bm, g.lower));
       if (hipMemcpy(doffs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice) != hipSuccess) return;

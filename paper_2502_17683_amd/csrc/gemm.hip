@@ -191,6 +191,195 @@ __global__ __launch_bounds__(256) void gemm_group_kernel(const GemmArgs<T>* tab,
   gemm_body<T, BM, BN, AT, BT, HAD>(p, blockIdx.x - offs[pid], offs[pid + 1] - offs[pid]);
 }
 
+// ---------------------------------------------------------------------
+// FP64 with 128 x 128 block tiles and direct global -> LDS loads
+// (global_load_lds_dwordx4): no register staging, so the accumulators (64
+// per lane, in AGPRs) and the fragments fit two workgroups per compute unit
+// (~200 registers, 52-72 KB LDS with two stages), where the register-staged
+// 128 x 128 form holds ~400 registers and one workgroup.  One barrier per
+// k-step: the next k-tile is in flight while the current one is multiplied.
+// LDS layouts (a wave instruction writes 64 consecutive 16-byte chunks):
+//   - operand contiguous along its row index r (k-major, element (k, r) at
+//     base[k ld + r]): row k of the tile, 128 doubles, at stage + k * 144
+//     (the padding puts rows k and k + 1 in different banks);
+//   - operand contiguous along k (element (r, k) at base[r ld + k]): k-pair
+//     major, [k / 2][r][k % 2], so a fragment read of 16 consecutive r is
+//     conflict-free.
+// Rows or columns past the matrix edge read a clamped in-range address;
+// they only feed result elements that are not stored.  Requirements (checked
+// on the host, gemm_dma_ok): beta = 0, K a multiple of the k-step (8 with a
+// Hadamard operand pair, 16 otherwise), even leading dimensions, 16-byte
+// aligned operands.
+namespace {
+constexpr int DM = 128, DROW = 144;
+typedef __attribute__((address_space(3))) void* lds_vptr;
+typedef const __attribute__((address_space(1))) void* glb_cvptr;
+}  // namespace
+
+template <bool KMAJOR, int BKD>
+__device__ __forceinline__ void dma_operand(const double* base, int ld, int r0, int rows, int k0, double* stage,
+                                            int w, int lane) {
+#pragma unroll
+  for (int i = 0; i < BKD / 4; ++i) {
+    const int idx = w * (BKD / 4) + i;
+    const double* g;
+    double* dst;
+    if (KMAJOR) {
+      const int r = min(r0 + 2 * lane, (rows - 1) & ~1);
+      g = base + (size_t)(k0 + idx) * ld + r;
+      dst = stage + idx * DROW;
+    } else {
+      const int kp = idx >> 1, half = idx & 1;
+      const int r = min(r0 + half * 64 + lane, rows - 1);
+      g = base + (size_t)r * ld + k0 + 2 * kp;
+      dst = stage + kp * (2 * DM) + half * 64 * 2;
+    }
+    __builtin_amdgcn_global_load_lds((glb_cvptr)g, (lds_vptr)dst, 16, 0, 0);
+  }
+}
+template <bool KMAJOR>
+__device__ __forceinline__ double dma_frag(const double* st, int r, int k) {
+  return KMAJOR ? st[k * DROW + r] : st[(k >> 1) * (2 * DM) + r * 2 + (k & 1)];
+}
+
+template <bool AT, bool BT, bool HAD>
+__device__ __forceinline__ void gemm_dma_body(const GemmArgs<double>& p, int bid_in, int nblocks) {
+  constexpr int BKD = HAD ? 8 : 16;
+  constexpr int OPK = BKD * DROW, OPM = (BKD / 2) * DM * 2;
+  constexpr int SA = AT ? OPK : OPM, SB = BT ? OPM : OPK;
+  constexpr int STAGE = SA + SB * (HAD ? 2 : 1);
+  __shared__ __attribute__((aligned(16))) double lds[2 * STAGE];
+
+  if (p.done && *p.done) return;
+  if (p.gate && *p.gate != p.want) return;
+  const int tiles_n = (p.N + DM - 1) / DM;
+  const int bid = xcd_remap(bid_in, nblocks);
+  int m0, n0;
+  if (p.lower && p.M == p.N) {
+    int r = (int)((sqrtf(8.f * (float)bid + 1.f) - 1.f) * 0.5f);
+    while ((r + 1) * (r + 2) / 2 <= bid) ++r;
+    while (r * (r + 1) / 2 > bid) --r;
+    m0 = r * DM;
+    n0 = (bid - r * (r + 1) / 2) * DM;
+  } else {
+    m0 = (bid / tiles_n) * DM;
+    n0 = (bid % tiles_n) * DM;
+    if (p.lower && n0 > m0 + DM - 1) return;
+  }
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  // C = (alpha A) B; beta must be 0 (gemm_dma_ok): any read of C here kept
+  // the accumulators out of the AGPRs and cost the second workgroup per unit
+  const gptr<double> gC = as_global(p.C), gC2 = as_global(p.C2);
+  const double alpha = p.alpha;
+  d4_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = d4_t{0, 0, 0, 0};
+  auto issue = [&](int kt, int s) {
+    double* st = lds + s * STAGE;
+    dma_operand<AT, BKD>(p.A, p.lda, m0, p.M, kt * BKD, st, w, lane);
+    dma_operand<!BT, BKD>(p.B1, p.ldb, n0, p.N, kt * BKD, st + SA, w, lane);
+    if constexpr (HAD) dma_operand<!BT, BKD>(p.B2, p.ldb, n0, p.N, kt * BKD, st + SA + SB, w, lane);
+  };
+  const int nk = p.K / BKD;
+  issue(0, 0);
+  for (int kt = 0; kt < nk; ++kt) {
+    // this wave's loads of k-tile kt have landed; the barrier makes every
+    // wave's visible and ends all reads of the other stage
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (kt + 1 < nk) issue(kt + 1, (kt + 1) & 1);
+    const double* st = lds + (kt & 1) * STAGE;
+#pragma unroll
+    for (int kk = 0; kk < BKD; kk += 4) {
+      const int k = kk + (lane >> 4);
+      double af[4], bf[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) af[a] = alpha * dma_frag<AT>(st, wm * 64 + a * 16 + (lane & 15), k);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int c = wn * 64 + b * 16 + (lane & 15);
+        bf[b] = dma_frag<!BT>(st + SA, c, k);
+        if constexpr (HAD) bf[b] *= dma_frag<!BT>(st + SA + SB, c, k);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = mfma4(af[a], bf[b], acc[a][b]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 64 + a * 16 + dsub_row<double>(lane, r);
+        const int col = n0 + wn * 64 + b * 16 + (lane & 15);
+        if (row < p.M && col < p.N) {
+          const size_t off = (size_t)row * p.ldc + col;
+          gC[off] = acc[a][b][r];
+          if (p.C2) gC2[off] = acc[a][b][r];
+        }
+      }
+}
+
+template <bool AT, bool BT, bool HAD>
+__global__ __launch_bounds__(256) void gemm_dma_kernel(GemmArgs<double> p) {
+  gemm_dma_body<AT, BT, HAD>(p, blockIdx.x, gridDim.x);
+}
+template <bool AT, bool BT, bool HAD>
+__global__ __launch_bounds__(256) void gemm_dma_group_kernel(const GemmArgs<double>* tab, const int* offs,
+                                                              int nprob) {
+  int pid = 0;
+  while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
+  const GemmArgs<double> p = tab[pid];
+  gemm_dma_body<AT, BT, HAD>(p, blockIdx.x - offs[pid], offs[pid + 1] - offs[pid]);
+}
+
+template <typename T>
+bool gemm_dma_ok(const GemmArgs<T>& g, bool had) {
+  if (sizeof(T) != 8 || g.K <= 0 || g.M <= 0 || g.N <= 0) return false;
+  auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+  return g.beta == T(0) && g.K % (had ? 8 : 16) == 0 && g.lda % 2 == 0 && g.ldb % 2 == 0 && al16(g.A) &&
+         al16(g.B1) && (!had || al16(g.B2));
+}
+template bool gemm_dma_ok<double>(const GemmArgs<double>&, bool);
+template bool gemm_dma_ok<float>(const GemmArgs<float>&, bool);
+
+static void launch_dma(hipStream_t s, const GemmArgs<double>& a, bool at, bool bt, bool had) {
+  dim3 grid(gemm_tile_count(a.M, a.N, DM, a.lower)), block(256);
+#define THCCP_DMA_CASE(AT_, BT_, HAD_)                                                   \
+  if (at == AT_ && bt == BT_ && had == HAD_) {                                           \
+    hipLaunchKernelGGL((gemm_dma_kernel<AT_, BT_, HAD_>), grid, block, 0, s, a);         \
+    return;                                                                              \
+  }
+  THCCP_DMA_CASE(false, false, false)
+  THCCP_DMA_CASE(true, false, false)
+  THCCP_DMA_CASE(false, false, true)
+  THCCP_DMA_CASE(true, false, true)
+  THCCP_DMA_CASE(false, true, false)
+  THCCP_DMA_CASE(true, true, false)
+#undef THCCP_DMA_CASE
+}
+static void launch_dma_group(hipStream_t s, const GemmArgs<double>* tab, const int* offs, int nprob, int tiles,
+                             bool at, bool bt, bool had) {
+  dim3 grid(tiles), block(256);
+#define THCCP_DMA_GCASE(AT_, BT_, HAD_)                                                               \
+  if (at == AT_ && bt == BT_ && had == HAD_) {                                                        \
+    hipLaunchKernelGGL((gemm_dma_group_kernel<AT_, BT_, HAD_>), grid, block, 0, s, tab, offs, nprob); \
+    return;                                                                                           \
+  }
+  THCCP_DMA_GCASE(false, false, false)
+  THCCP_DMA_GCASE(true, false, false)
+  THCCP_DMA_GCASE(false, false, true)
+  THCCP_DMA_GCASE(true, false, true)
+  THCCP_DMA_GCASE(false, true, false)
+#undef THCCP_DMA_GCASE
+}
+
 template <typename T, int BM, int BN>
 static void launch_tile(hipStream_t s, const GemmArgs<T>& a, bool at, bool bt, bool had) {
   const int tiles = BM == BN ? gemm_tile_count(a.M, a.N, BM, a.lower) : ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
@@ -219,6 +408,13 @@ int gemm_default_tile(int M, int N) {
 template <typename T>
 static void gemm_dispatch(hipStream_t s, const GemmArgs<T>& a, bool at, bool bt, bool had) {
   if (a.M <= 0 || a.N <= 0) return;
+  if constexpr (sizeof(T) == 8) {
+    // the direct-load 128-tile path wherever its requirements hold
+    if (!(had && bt) && gemm_dma_ok(a, had)) {
+      launch_dma(s, a, at, bt, had);
+      return;
+    }
+  }
   if (gemm_default_tile(a.M, a.N) == 128) launch_tile<T, 128, 128>(s, a, at, bt, had);
   else launch_tile<T, 64, 64>(s, a, at, bt, had);
 }
@@ -244,6 +440,14 @@ template <typename T>
 void gemm_group(hipStream_t s, const GemmArgs<T>* tab, const int* offs, int nprob, int total_tiles, bool a_t,
                 bool b_t, bool had, int bm) {
   if (total_tiles <= 0) return;
+  if constexpr (sizeof(T) == 8) {
+    // FP64: bm = 128 is the direct-load path (the caller checked gemm_dma_ok
+    // for every entry)
+    if (bm == 128) {
+      launch_dma_group(s, (const GemmArgs<double>*)tab, offs, nprob, total_tiles, a_t, b_t, had);
+      return;
+    }
+  }
   if (bm == 128) launch_group_tile<T, 128>(s, tab, offs, nprob, total_tiles, a_t, b_t, had);
   else launch_group_tile<T, 64>(s, tab, offs, nprob, total_tiles, a_t, b_t, had);
 }

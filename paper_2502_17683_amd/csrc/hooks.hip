@@ -93,7 +93,8 @@ cpd_status solve_impl(int R, int n, const T* V, const T* M, T* F, void* ws, hipS
       for (int h = 0; h < 2; ++h) {
         GemmArgs<T> g;
         if (it.g_kind[h] < 0 || !panel_gemm<T>(it.g_kind[h], hp, pw, it.g_panel[h], g)) continue;
-        const int bm = gemm_default_tile(g.M, g.N);
+        int bm = gemm_default_tile(g.M, g.N);
+        if (bm == 128 && !gemm_dma_ok(g, false)) bm = 64;
         int ho[2] = {0, gemm_tile_count(g.M, g.N, bm, g.lower)};
         if (hipMemcpyAsync(offs, ho, sizeof(ho), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
         if (hipMemcpyAsync(gtab, &g, sizeof(g), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;

@@ -67,8 +67,14 @@ inline int gemm_tile_count(int M, int N, int bm, int lower = 0) {
   const int tm = (M + bm - 1) / bm, tn = (N + bm - 1) / bm;
   return lower && M == N ? tm * (tm + 1) / 2 : tm * tn;
 }
+// Whether the FP64 direct-load 128-tile path can take this product: beta =
+// 0, K a multiple of its k-step (8 with a Hadamard pair, 16 otherwise), even
+// leading dimensions, 16-byte aligned operands (always false for FP32).
+template <typename T>
+bool gemm_dma_ok(const GemmArgs<T>& g, bool had);
 // Grouped launch: tab[nprob] problems with identical (a_t, b_t, Hadamard)
-// flags, tile edge bm (64 or 128), offs[nprob + 1] prefix sums of
+// flags, tile edge bm (64 or 128; for FP64, 128 is the direct-load path and
+// every entry must pass gemm_dma_ok), offs[nprob + 1] prefix sums of
 // gemm_tile_count(M_p, N_p, bm).
 template <typename T>
 void gemm_group(hipStream_t s, const GemmArgs<T>* tab, const int* offs, int nprob, int total_tiles, bool a_t,

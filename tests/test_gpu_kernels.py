@@ -25,6 +25,17 @@ GEMM_CASES = [
     (70, 70, 19, True, True, False),
     (2100, 2080, 40, False, False, True),   # 128x128 tiles, ragged edges
     (2100, 2080, 40, True, False, False),
+    # FP64 shapes that meet the direct-load path's requirements (K a multiple
+    # of 16, or of 8 with the Hadamard pair; even leading dimensions): every
+    # operand layout, ragged edges in M and N, one or several k-steps
+    (130, 78, 48, False, False, False),
+    (130, 78, 48, True, False, True),
+    (300, 202, 64, False, False, True),
+    (64, 200, 32, False, True, False),
+    (70, 70, 16, True, True, False),
+    (258, 130, 8, False, False, True),
+    (2100, 2080, 64, False, False, True),
+    (2100, 2080, 48, True, False, False),
 ]
 
 
