@@ -421,6 +421,17 @@ __host__ __device__ inline int fwd_tiles(int nblk, int nrt, int pw, int pf, int 
   if (chol_paired(nblk, pw, js) && !(js & 1) && kmax > js + 2) kmax = js + 2;
   return kmax >= js + 1 ? nrt * (kmax - js) : 0;
 }
+// Two-column backward step t >= 1 (one level): js = nblk + 1 - 2t; F_js
+// and F_{js+1} are final and pending for every block left of js.  The
+// workgroups of block column js - 2 apply them to blocks js - 1 and js - 2,
+// solve both columns and store both (each block has one writer in the
+// launch); the blocks left of js - 2 take the two pending columns (rank
+// 128).  At js = 1 only column 0 is left.
+__host__ __device__ inline int bwd2_js(int nblk, int t) { return nblk + 1 - 2 * t; }
+__host__ __device__ inline int bwd2_tiles(int nblk, int nrt, int t) {
+  const int js = bwd2_js(nblk, t);
+  return js >= 2 ? nrt * (js - 1) : js == 1 ? nrt : 0;
+}
 __host__ __device__ inline int bwd_tiles(int nblk, int nrt, int pw, int pf, int tf) {
   int js, hi, kmin;
   bwd_range(nblk, pw, pf, tf, js, hi, kmin);
@@ -572,7 +583,102 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
     }
     bid -= nc;
   }
-  if constexpr (MODE != STEP_CHOL) {
+  if constexpr (MODE == STEP_BWD2) {
+    const int js = bwd2_js(nblk, cfg.tf);
+    const int nrt = (n + TB - 1) / TB;
+    bid = xcd_remap(bid, nbid);
+    const int rt = bid % nrt;
+    // js >= 2: k = js - 2 (both solves), then the blocks left of it;
+    // js = 1: k = 0 (the last solve)
+    const int k = js >= 2 ? js - 2 - bid / nrt : 0;
+    const int r0 = rt * TB;
+    const int nrows = min(TB, n - r0);
+    if (k >= js - 2) __builtin_amdgcn_s_setprio(3);  // the solve chain
+    const bool p1 = js + 1 < nblk;  // F_{js+1} exists (pending with F_js)
+    typedef typename Acc4<T>::type acc_t;
+    T ra[16], rb[16];
+    // The accumulators hold the negated right-hand side, so every product
+    // adds into them directly (a separate product tile would cost the
+    // second workgroup per compute unit).
+    auto neg = [](acc_t* a) {
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) a[tj] = -a[tj];
+    };
+    // a1 (and a2, the second tile for the js - 2 solve) += F_jj L_{jj, kc}
+    // for the pending columns jj; S0 = F^T, S1 = L
+    auto pending = [&](acc_t* a1, int k1, acc_t* a2, int k2) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int jj = h == 0 ? js + 1 : js;
+        if (h == 0 && !p1) continue;
+        fetch_block<T>(ra, M + (size_t)r0 * Tp + (size_t)jj * TB, Tp, nrows, tid);
+        fetch_block<T>(rb, V + (size_t)jj * TB * Tp + (size_t)k1 * TB, Tp, TB, tid);
+        __syncthreads();  // earlier reads of S0 / S1 are done
+        put_block<T, true>(S0, ra, tid);
+        put_block<T, false>(S1, rb, tid);
+        __syncthreads();
+        // the second tile's L block, under the first product
+        if (a2) fetch_block<T>(ra, V + (size_t)jj * TB * Tp + (size_t)k2 * TB, Tp, TB, tid);
+        tile_mma64<T>(a1, S0, S1, lane, w);
+        if (a2) {
+          __syncthreads();
+          put_block<T, false>(S1, ra, tid);
+          __syncthreads();
+          tile_mma64<T>(a2, S0, S1, lane, w);
+        }
+      }
+    };
+    // out = a X_kc^T (the stored X = L_kc^{-T}); a is consumed
+    auto solve = [&](acc_t* a, int kc, acc_t* out) {
+      fetch_block<T>(ra, ldiag + (size_t)kc * TB * TB, TB, TB, tid);
+      __syncthreads();
+      acc_to_lds_t<T>(a, S0, lane, w);
+      put_block<T, true>(S1, ra, tid);
+      __syncthreads();
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) out[tj] = acc_t{0, 0, 0, 0};
+      tile_mma64<T>(out, S0, S1, lane, w);
+    };
+    acc_t acc[4], acc2[4];
+    T* tile = M + (size_t)r0 * Tp + (size_t)k * TB;
+    if (k <= js - 3 || js == 1) {
+      load_acc<T>(acc, tile, Tp, nrows, lane, w);
+      neg(acc);
+      pending(acc, k, nullptr, 0);
+      if (js == 1) {
+        solve(acc, k, acc2);
+        neg(acc2);
+        store_acc<T>(acc2, tile, Tp, nrows, lane, w);
+      } else {
+        neg(acc);
+        store_acc<T>(acc, tile, Tp, nrows, lane, w);
+      }
+      return;
+    }
+    // k = js - 2: F_{js-1} (stored here), then Y_k -= F_{js-1} L_{js-1,k}
+    // and the solve of column k
+    T* tile1 = M + (size_t)r0 * Tp + (size_t)(js - 1) * TB;
+    load_acc<T>(acc, tile1, Tp, nrows, lane, w);
+    load_acc<T>(acc2, tile, Tp, nrows, lane, w);
+    neg(acc);
+    neg(acc2);
+    pending(acc, js - 1, acc2, k);
+    acc_t f1[4];
+    solve(acc, js - 1, f1);
+    neg(f1);  // F_{js-1}
+    store_acc<T>(f1, tile1, Tp, nrows, lane, w);
+    fetch_block<T>(rb, V + (size_t)(js - 1) * TB * Tp + (size_t)k * TB, Tp, TB, tid);
+    __syncthreads();
+    acc_to_lds_t<T>(f1, S0, lane, w);  // A = F_{js-1}^T
+    put_block<T, false>(S1, rb, tid);
+    __syncthreads();
+    tile_mma64<T>(acc2, S0, S1, lane, w);
+    solve(acc2, k, f1);
+    neg(f1);
+    store_acc<T>(f1, tile, Tp, nrows, lane, w);
+    return;
+  }
+  if constexpr (MODE != STEP_CHOL && MODE != STEP_BWD2) {
     constexpr bool FWD = MODE != STEP_BWD;
     int js, lim, kext;  // forward: lim = panel start; backward: lim = panel end
     if (FWD) chol_range(nblk, cfg.pw, cfg.pf, cfg.tf, js, lim, kext);
@@ -651,6 +757,7 @@ int step_tiles(int mode, int nblk, int n, StepCfg c) {
     case STEP_CHOL: return chol_tiles(nblk, c.pw, c.pc, c.tc);
     case STEP_FWD: return fwd_tiles(nblk, nrt, c.pw, c.pf, c.tf);
     case STEP_CHOL_FWD: return chol_tiles(nblk, c.pw, c.pc, c.tc) + fwd_tiles(nblk, nrt, c.pw, c.pf, c.tf);
+    case STEP_BWD2: return bwd2_tiles(nblk, nrt, c.tf);
     default: return bwd_tiles(nblk, nrt, c.pw, c.pf, c.tf);
   }
 }
@@ -669,6 +776,9 @@ void step_group(hipStream_t s, int mode, const StepProb<T>* probs, const int* of
       break;
     case STEP_BWD:
       hipLaunchKernelGGL((step_kernel<T, STEP_BWD>), grid, block, 0, s, probs, offs, nprob, cfg, retry_pass);
+      break;
+    case STEP_BWD2:
+      hipLaunchKernelGGL((step_kernel<T, STEP_BWD2>), grid, block, 0, s, probs, offs, nprob, cfg, retry_pass);
       break;
     default:
       hipLaunchKernelGGL((step_kernel<T, STEP_CHOL_FWD>), grid, block, 0, s, probs, offs, nprob, cfg,
@@ -743,6 +853,12 @@ std::vector<SolveItem> solve_schedule(int sched, int max_nblk, int pw) {
       }
       break;
     default:
+      if (P == 1) {
+        // one level: the last block column, then two columns per launch
+        step(STEP_BWD, -1, 0, 0, 0);
+        for (int t = 1; t <= max_nblk / 2; ++t) step(STEP_BWD2, -1, 0, 0, t);
+        break;
+      }
       for (int p = P - 1; p >= 0; --p) {
         for (int t = 0; t < pw; ++t) step(STEP_BWD, -1, 0, p, t);
         if (p > 0) gemm(PG_BWD, p, -1, 0);

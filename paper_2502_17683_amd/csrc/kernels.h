@@ -94,7 +94,7 @@ struct StepProb {
   int nblk;
   int n;
 };
-enum StepMode { STEP_CHOL = 0, STEP_FWD = 1, STEP_BWD = 2, STEP_CHOL_FWD = 3 };
+enum StepMode { STEP_CHOL = 0, STEP_FWD = 1, STEP_BWD = 2, STEP_CHOL_FWD = 3, STEP_BWD2 = 4 };
 
 // Two-level blocking: the 64-wide block columns are grouped into panels of
 // pw blocks.  Inside a panel the step kernel works one block column per
@@ -141,7 +141,9 @@ bool panel_gemm(int kind, const StepProb<T>& q, int pw, int p, GemmArgs<T>& g);
 //                   forward update of panel p - 1.  One-level (pw >=
 //                   max_nblk): one block column behind.
 //   SCHED_FWD       forward solve alone;  SCHED_BWD  backward solve (panels
-//                   from the last one down).
+//                   from the last one down; one level: after the launch
+//                   that solves the last block column, STEP_BWD2 launches
+//                   that solve two block columns each).
 enum SolveSched { SCHED_CHOL = 0, SCHED_CHOL_FWD = 1, SCHED_FWD = 2, SCHED_BWD = 3 };
 struct SolveItem {
   int mode;
