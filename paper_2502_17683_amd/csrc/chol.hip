@@ -4,11 +4,14 @@
 // V is Tp x Tp row-major (Tp = 64 nblk; padding rows/columns hold the
 // identity).  Right-looking with two levels of blocking.  Block columns are
 // 64 wide and grouped into panels of pw blocks (pw >= nblk: one level).
-// Inside a panel, ONE launch per block step: step j updates the panel's tiles (i, k), k >= j+1,
-// with block column j on the matrix cores and, for the tiles of column j+1,
-// immediately factors the updated diagonal block -- every workgroup of that
-// column does so redundantly, so no workgroup ever waits on another -- and
-// solves its own tile of the column.  After a panel, one GEMM applies its
+// Inside a panel, ONE launch per block step: step j updates the panel's
+// tiles (i, k), k >= j+1, with block column j on the matrix cores and, for
+// the tiles of column j+1, immediately factors the updated diagonal block --
+// every workgroup of that column does so redundantly, so no workgroup ever
+// waits on another -- and solves its own tile of the column.  In the
+// one-level form the blocks beyond column j+2 take their updates in pairs
+// (rank 128, every other step), and the backward solve works two block
+// columns per launch (STEP_BWD2).  After a panel, one GEMM applies its
 // rank-(64 pw) update to the trailing matrix (and, in the forward
 // solve, to the right-hand sides): the trailing matrix is read and written
 // once per panel instead of once per block column.  The diagonal blocks of

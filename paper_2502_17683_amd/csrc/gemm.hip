@@ -5,9 +5,13 @@
 // MTTKRP (projection X^T F, core product Z (W o W), back-projection
 // X (W o Y)), the Gram matrices F^T F and the set-up products.
 //
-// Tiling: 256 threads = 2 x 2 waves; block tile BM x BN, k-step 16 staged
-// through LDS in k-major form (conflict-free fragment reads), next k-tile
-// prefetched into registers while the current one is multiplied.
+// Two forms, 256 threads = 2 x 2 waves each:
+//   - register-staged (any shape, FP64 and FP32): block tile BM x BN (64 or
+//     128), k-step 16 staged through LDS in k-major form, the next k-tile
+//     prefetched into registers while the current one is multiplied;
+//   - direct-load (FP64, qualifying shapes, gemm_dma_ok): 128 x 128 tiles
+//     loaded from global memory straight into a two-stage LDS pipeline,
+//     which keeps two workgroups per compute unit (below).
 #include "kernels.h"
 #include "mfma.h"
 
