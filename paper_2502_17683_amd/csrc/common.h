@@ -46,6 +46,19 @@ struct DevState {
   double cond_max;       // largest (max L_ii / min L_ii)^2 seen in the sweep
 };
 
+// Tile (tm, tn) of linear index bid in groups of G tile rows: a group runs
+// column by column over its G rows, so consecutive indices -- the tiles an
+// XCD runs at the same time after xcd_remap -- form a roughly square block
+// that shares its A and B panels in the XCD's L2.
+__device__ __forceinline__ void grouped_tile(int bid, int tiles_m, int tiles_n, int G, int& tm, int& tn) {
+  const int per_group = G * tiles_n;
+  const int first = (bid / per_group) * G;
+  const int gm = tiles_m - first < G ? tiles_m - first : G;
+  const int in = bid - (bid / per_group) * per_group;
+  tm = first + in % gm;
+  tn = in / gm;
+}
+
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
   // contiguous range of tiles so neighbouring tiles share its L2.

@@ -42,8 +42,10 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& p, int bid_in, int 
     m0 = r * BM;
     n0 = (bid - r * (r + 1) / 2) * BN;
   } else {
-    m0 = (bid / tiles_n) * BM;
-    n0 = (bid % tiles_n) * BN;
+    int tm, tn;
+    grouped_tile(bid, (p.M + BM - 1) / BM, tiles_n, 8, tm, tn);
+    m0 = tm * BM;
+    n0 = tn * BN;
     if (p.lower && n0 > m0 + BM - 1) return;  // tile strictly above the diagonal
   }
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -266,8 +268,10 @@ __device__ __forceinline__ void gemm_dma_body(const GemmArgs<double>& p, int bid
     m0 = r * DM;
     n0 = (bid - r * (r + 1) / 2) * DM;
   } else {
-    m0 = (bid / tiles_n) * DM;
-    n0 = (bid % tiles_n) * DM;
+    int tm, tn;
+    grouped_tile(bid, (p.M + DM - 1) / DM, tiles_n, 8, tm, tn);
+    m0 = tm * DM;
+    n0 = tn * DM;
     if (p.lower && n0 > m0 + DM - 1) return;
   }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;

@@ -125,9 +125,11 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
   const SplitArgs a = tab[pid];
   if (a.done && *a.done) return;
   if (a.gate && *a.gate != a.want) return;
-  const int tiles_n = (a.N + SBN - 1) / SBN;
+  const int tiles_n = (a.N + SBN - 1) / SBN, tiles_m = (a.M + BM - 1) / BM;
   const int bid = xcd_remap(blockIdx.x - offs[pid], offs[pid + 1] - offs[pid]);
-  const int m0 = (bid / tiles_n) * BM, n0 = (bid % tiles_n) * SBN;
+  int tm, tn;
+  grouped_tile(bid, tiles_m, tiles_n, 8, tm, tn);
+  const int m0 = tm * BM, n0 = tn * SBN;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
 
