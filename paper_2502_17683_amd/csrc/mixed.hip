@@ -116,10 +116,10 @@ struct Stage<true, C> {
 template <bool APAIR, bool BPAIR, int BM>
 __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, const int* offs, int nprob) {
   constexpr int CA = BM / 64, TI = BM / 32;
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[BM * SLDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Al[BM * SLDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bh[SBN * SLDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bl[SBN * SLDK];
+  // two LDS stages: the next k-tile is stored into the other stage right
+  // after the current products are issued, one barrier per k-tile
+  constexpr int SA = BM * SLDK, SB = SBN * SLDK;
+  __shared__ __attribute__((aligned(16))) __bf16 lds[2 * (2 * SA + 2 * SB)];
   int pid = 0;
   while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
   const SplitArgs a = tab[pid];
@@ -141,7 +141,11 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-  auto store = [&]() {
+  auto store = [&](int s) {
+    __bf16* Ah = lds + s * (2 * SA + 2 * SB);
+    __bf16* Al = Ah + SA;
+    __bf16* Bh = Al + SA;
+    __bf16* Bl = Bh + SB;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int row = (tid + 256 * c) >> 2;
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
   const int nk = a.K / SBK;
   sa.load(a.A, a.M, m0, 0, tid);
   sb.load(a.B, a.N, n0, 0, tid);
-  store();
+  store(0);
   __syncthreads();
   const int koff = 8 * (lane >> 4);
   for (int kt = 0; kt < nk; ++kt) {
@@ -169,6 +173,10 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
       sa.load(a.A, a.M, m0, (kt + 1) * SBK, tid);
       sb.load(a.B, a.N, n0, (kt + 1) * SBK, tid);
     }
+    const __bf16* Ah = lds + (kt & 1) * (2 * SA + 2 * SB);
+    const __bf16* Al = Ah + SA;
+    const __bf16* Bh = Al + SA;
+    const __bf16* Bl = Bh + SB;
     bf16x8_t ah[TI], al[TI], bh[4], bl[4];
 #pragma unroll
     for (int i = 0; i < TI; ++i) {
@@ -190,11 +198,10 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(const SplitArgs* tab, c
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
       }
+    // the other stage was last read in iteration kt - 1, which every wave
+    // finished before the barrier that ended it
+    if (kt + 1 < nk) store((kt + 1) & 1);
     __syncthreads();
-    if (kt + 1 < nk) {
-      store();
-      __syncthreads();
-    }
   }
 
 #pragma unroll
