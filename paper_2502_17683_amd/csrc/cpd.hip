@@ -316,14 +316,9 @@ GroupOp gemm_op(TableBuilder& tb, const std::vector<GemmArgs<T>>& v, bool at, bo
   // FP64: 128 is the direct-load path (1.3-1.4x the 64-tiles at R = 4000),
   // taken when every entry qualifies and the 128-tiles cover the compute
   // units (the back-projection's 224 tiles at n = 800 stay on 64)
-  bool dma = sizeof(T) == 8, lower = false;
-  for (auto& g : v) {
-    dma = dma && gemm_dma_ok(g, had);
-    lower = lower || g.lower;
-  }
-  // (a lower-triangle product keeps the 64-tiles: its diagonal 128-tiles
-  // would compute twice the needed elements; Gram 0.30 vs 0.33 ms)
-  op.bm = dma && !lower ? (t128 >= 256 ? 128 : 64) : (t128 >= 4096 ? 128 : 64);
+  bool dma = sizeof(T) == 8;
+  for (auto& g : v) dma = dma && gemm_dma_ok(g, had);
+  op.bm = dma ? (t128 >= 256 ? 128 : 64) : (t128 >= 4096 ? 128 : 64);
   op.count = (int)v.size();
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);

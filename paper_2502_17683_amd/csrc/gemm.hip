@@ -213,9 +213,11 @@ __global__ __launch_bounds__(256) void gemm_group_kernel(const GemmArgs<T>* tab,
 //     conflict-free.
 // Rows or columns past the matrix edge read a clamped in-range address;
 // they only feed result elements that are not stored.  Requirements (checked
-// on the host, gemm_dma_ok): beta = 0, K a multiple of the k-step (8 with a
-// Hadamard operand pair, 16 otherwise), even leading dimensions, 16-byte
-// aligned operands.
+// on the host, gemm_dma_ok): beta = 0, a full (not lower-triangle) result,
+// K a multiple of the k-step (8 with a Hadamard operand pair, 16
+// otherwise), even leading dimensions, 16-byte aligned operands.  (The
+// lower-triangle Gram is faster on the 64-tiles: the 128-tiles on the
+// diagonal would compute twice the needed elements.)
 namespace {
 constexpr int DM = 128, DROW = 144;
 typedef __attribute__((address_space(3))) void* lds_vptr;
@@ -260,20 +262,9 @@ __device__ __forceinline__ void gemm_dma_body(const GemmArgs<double>& p, int bid
   if (p.gate && *p.gate != p.want) return;
   const int tiles_n = (p.N + DM - 1) / DM;
   const int bid = xcd_remap(bid_in, nblocks);
-  int m0, n0;
-  if (p.lower && p.M == p.N) {
-    int r = (int)((sqrtf(8.f * (float)bid + 1.f) - 1.f) * 0.5f);
-    while ((r + 1) * (r + 2) / 2 <= bid) ++r;
-    while (r * (r + 1) / 2 > bid) --r;
-    m0 = r * DM;
-    n0 = (bid - r * (r + 1) / 2) * DM;
-  } else {
-    int tm, tn;
-    grouped_tile(bid, (p.M + DM - 1) / DM, tiles_n, 8, tm, tn);
-    m0 = tm * DM;
-    n0 = tn * DM;
-    if (p.lower && n0 > m0 + DM - 1) return;
-  }
+  int tm, tn;
+  grouped_tile(bid, (p.M + DM - 1) / DM, tiles_n, 8, tm, tn);
+  const int m0 = tm * DM, n0 = tn * DM;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
   // C = (alpha A) B; beta must be 0 (gemm_dma_ok): any read of C here kept
@@ -351,14 +342,14 @@ template <typename T>
 bool gemm_dma_ok(const GemmArgs<T>& g, bool had) {
   if (sizeof(T) != 8 || g.K <= 0 || g.M <= 0 || g.N <= 0) return false;
   auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
-  return g.beta == T(0) && g.K % (had ? 8 : 16) == 0 && g.lda % 2 == 0 && g.ldb % 2 == 0 && al16(g.A) &&
-         al16(g.B1) && (!had || al16(g.B2));
+  return g.beta == T(0) && !g.lower && g.K % (had ? 8 : 16) == 0 && g.lda % 2 == 0 && g.ldb % 2 == 0 &&
+         al16(g.A) && al16(g.B1) && (!had || al16(g.B2));
 }
 template bool gemm_dma_ok<double>(const GemmArgs<double>&, bool);
 template bool gemm_dma_ok<float>(const GemmArgs<float>&, bool);
 
 static void launch_dma(hipStream_t s, const GemmArgs<double>& a, bool at, bool bt, bool had) {
-  dim3 grid(gemm_tile_count(a.M, a.N, DM, a.lower)), block(256);
+  dim3 grid(gemm_tile_count(a.M, a.N, DM)), block(256);
 #define THCCP_DMA_CASE(AT_, BT_, HAD_)                                                   \
   if (at == AT_ && bt == BT_ && had == HAD_) {                                           \
     hipLaunchKernelGGL((gemm_dma_kernel<AT_, BT_, HAD_>), grid, block, 0, s, a);         \

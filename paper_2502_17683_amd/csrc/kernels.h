@@ -68,8 +68,9 @@ inline int gemm_tile_count(int M, int N, int bm, int lower = 0) {
   return lower && M == N ? tm * (tm + 1) / 2 : tm * tn;
 }
 // Whether the FP64 direct-load 128-tile path can take this product: beta =
-// 0, K a multiple of its k-step (8 with a Hadamard pair, 16 otherwise), even
-// leading dimensions, 16-byte aligned operands (always false for FP32).
+// 0, not lower-triangle, K a multiple of its k-step (8 with a Hadamard pair,
+// 16 otherwise), even leading dimensions, 16-byte aligned operands (always
+// false for FP32).
 template <typename T>
 bool gemm_dma_ok(const GemmArgs<T>& g, bool had);
 // Grouped launch: tab[nprob] problems with identical (a_t, b_t, Hadamard)
