@@ -64,6 +64,17 @@ def lt_points(count=16, t_min=0.01, t_max=20.0):
     return np.logspace(np.log10(t_min), np.log10(t_max), count)
 
 
+def lt_quadrature(count=16, t_min=0.01, t_max=20.0):
+    """Laplace points (as lt_points) with trapezoid weights in ln t:
+    w_k = h t_k, h the step of ln t, so that sum_k w_k exp(-D t_k)
+    approximates the integral of exp(-D t) over the covered range.  A
+    synthetic stand-in for the paper's Legendre-based quadrature (12 points
+    in Computational Details)."""
+    t = lt_points(count, t_min, t_max)
+    h = (np.log(t_max) - np.log(t_min)) / (count - 1) if count > 1 else 1.0
+    return t, h * t
+
+
 def make_lt_system(n_occ, n_virt, seed, rank_factor=4):
     """One molecular system of the batched workload.
 
