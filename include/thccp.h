@@ -205,6 +205,44 @@ int32_t cpd_autotune_log(cpd_plan p, char* buf, int32_t len);
 cpd_status cpd_lt_scale_rows(const double* X, const double* eps, int32_t n, int32_t r, double t, double sign,
                              double* out, void* stream);
 
+/* ---- robust CPD+THC LT-MP2 exchange energy (Section 2.2) ----
+ * One system, n_points Laplace points (t_k, w_k).  Tensors are in the
+ * (i, a, j, b) mode order: the THC (ia|jb) = sum_PQ X_occ[i,P] X_virt[a,P]
+ * Z[P,Q] X_occ[j,Q] X_virt[b,Q] (eq. THC) and its CPD
+ * sum_r lam[r] F0[i,r] F1[a,r] F2[j,r] F3[b,r] (eq. cp4).  With the
+ * exchange pairing K(T, S) = sum_{iajb} T[i,a,j,b] S[i,b,j,a] and the
+ * Laplace factor exp(-(e_a + e_b - e_i - e_j) t_k) (eq. lt_D, eq. mp1_t):
+ *   k_single[k] = K(THC scaled at t_k, CPD)         (eq. cpd_single_k)
+ *   k_double[k] = K(CPD scaled at t_k, CPD)         (the double-CPD term)
+ *   e_k[0]      = - sum_k w_k (2 k_single[k] - k_double[k])   (eq. rob_K)
+ * The amplitude carries the whole factor w_k exp(-D t_k); the double-CPD
+ * term pairs each occupied index with its own particle's factor (the
+ * definition of g^{ba}_{ij}), so an exact CPD reproduces the exact
+ * exchange energy and the robust energy's error is second order in the
+ * CPD error.
+ *   X_occ n_occ x r_thc, X_virt n_virt x r_thc, Z r_thc x r_thc (any Z; no
+ *   symmetry is assumed), eps_occ n_occ, eps_virt n_virt, F0/F2
+ *   n_occ x r_cp, F1/F3 n_virt x r_cp, lam r_cp (NULL: all ones): DEVICE,
+ *   row-major, borrowed for the call.  t_host, w_host: HOST arrays of
+ *   n_points finite values, read before the call returns.
+ *   k_single, k_double (n_points each) and e_k (1): DEVICE outputs.
+ *   1 <= n_points <= CPD_LT_MAX_POINTS; n_points * r_cp must fit int32.
+ *   workspace: DEVICE, at least cpd_lt_exchange_workspace(...) bytes,
+ *   256-byte aligned; holds the scaled factor stacks and the products of
+ *   every point (about 8 (2 n_occ + 2 n_virt + 5 r_thc + 3 r_cp)
+ *   n_points r_cp bytes).
+ * Errors: CPD_ERR_INVALID_ARG (sizes, NULL pointers, non-finite t or w),
+ * CPD_ERR_WORKSPACE, CPD_ERR_HIP (launch failure).  Async on stream; the
+ * result is bitwise reproducible (fixed-order reductions). */
+#define CPD_LT_MAX_POINTS 64
+size_t cpd_lt_exchange_workspace(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t r_cp, int32_t n_points);
+cpd_status cpd_lt_exchange(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t r_cp, int32_t n_points,
+                           const double* X_occ, const double* X_virt, const double* Z, const double* eps_occ,
+                           const double* eps_virt, const double* t_host, const double* w_host, const double* F0,
+                           const double* F1, const double* F2, const double* F3, const double* lam,
+                           double* k_single, double* k_double, double* e_k, void* workspace,
+                           size_t workspace_bytes, void* stream);
+
 /* Releases the host plan and its private stream/graph (not the workspace). */
 /* ---- learned warm start ----
  * An initial CP built from R_cp grid columns of the THC factors: with a

@@ -1,0 +1,292 @@
+// Robust CPD+THC LT-MP2 exchange energy (Section 2.2: the single-CPD term
+// eq. cpd_single_k, the double-CPD term after it, and their robust
+// combination eq. rob_K) for one system over all its Laplace points.
+//
+// Tensors are in the (i, a, j, b) mode order: the THC (ia|jb) from X_occ,
+// X_virt and Z, and its CPD (F0 on i, F1 on a, F2 on j, F3 on b, weights
+// lam).  The exchange pairing is K(T, S) = sum T[i,a,j,b] S[i,b,j,a].
+//
+// The Laplace scaling exp(-D t) factors into row scalings, and for the
+// exchange pairing it may sit on either tensor (the paper's symmetry
+// remark).  Here it goes onto the CPD factors, one column block per point:
+//   Fs_m[p, k R + r] = exp(+-eps_p t_k) F_m[p, r].
+// All points then share a few wide products that read X, Z and F once:
+//   W0 = X_occ^T F0s   W1 = X_virt^T F3s   W2 = X_occ^T F2s   W3 = X_virt^T F1s
+//   Y  = Z (W2 o W3)                                  (R_thc x n_t R_cp each)
+//   k_single[k] = sum_{P, r} lam_r W0 W1 Y [P, k R + r]
+// The LT-scaled CPD gives the double-CPD overlaps from the same stacks:
+//   C0 = F0^T F0s   C2 = F2^T F2s   C13 = F1^T F3s    (R_cp x n_t R_cp)
+//   k_double[k] = sum_{r, r'} lam_r lam_r' C0 C2 C13 [r, k R + r'] C13[r', k R + r]
+// and E_K = - sum_k w_k (2 k_single[k] - k_double[k]).
+//
+// Products run on the FP64 matrix cores (gemm_f64); the stacks and the two
+// dot products are HBM-bound element-wise kernels.  Every reduction has a
+// fixed order (per-block partials, then one serial pass per point), so
+// repeated calls are bitwise identical.
+#include <math.h>
+#include <stdint.h>
+
+#include "../../include/thccp.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace thccp {
+
+namespace {
+
+struct LtQuad {
+  int n;
+  double t[CPD_LT_MAX_POINTS];
+  double w[CPD_LT_MAX_POINTS];
+};
+
+struct StackArgs {
+  const double* F[4];
+  const double* eps[4];
+  double* out[4];
+  int rows[4];
+};
+
+constexpr int kDotRows = 16;  // rows of W per single-term block
+constexpr int kTile = 64;     // double-term tile edge
+
+// Fs_m[p, k R + r] = exp(sign_m eps_p t_k) F_m[p, r]; blockIdx.y = m
+// (sign +1 for the occupied modes 0 and 2, -1 for the virtual modes 1, 3).
+__global__ __launch_bounds__(256) void lt_stack_kernel(StackArgs a, LtQuad q, int R) {
+  const int m = blockIdx.y;
+  const double sign = (m & 1) ? -1.0 : 1.0;
+  const int n = a.rows[m];
+  const size_t L = (size_t)q.n * R;
+  const size_t total = (size_t)n * L;
+  auto F = as_global(a.F[m]);
+  auto eps = as_global(a.eps[m]);
+  auto out = as_global(a.out[m]);
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    const size_t p = e / L;
+    const size_t c = e - p * L;
+    const int k = (int)(c / R);
+    const int r = (int)(c - (size_t)k * R);
+    out[e] = exp(sign * eps[p] * q.t[k]) * F[p * R + r];
+  }
+}
+
+// partials[k * chunks + c] = sum over rows [c kDotRows, ...) and columns r
+// of lam_r W0 W1 Y at column k R + r.  grid (chunks, n_t).
+__global__ __launch_bounds__(256) void single_dot_kernel(const double* W0, const double* W1, const double* Y,
+                                                         const double* lam, int Rt, int R, size_t L,
+                                                         double* partials) {
+  __shared__ double part[256];
+  const int c = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
+  const int p0 = c * kDotRows;
+  const int p1 = p0 + kDotRows < Rt ? p0 + kDotRows : Rt;
+  auto w0 = as_global(W0);
+  auto w1 = as_global(W1);
+  auto y = as_global(Y);
+  double acc = 0.0;
+  for (int r = tid; r < R; r += 256) {
+    const double l = lam ? as_global(lam)[r] : 1.0;
+    double s = 0.0;
+    for (int p = p0; p < p1; ++p) {
+      const size_t e = (size_t)p * L + (size_t)k * R + r;
+      s += w0[e] * w1[e] * y[e];
+    }
+    acc += l * s;
+  }
+  part[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) part[tid] += part[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) as_global(partials)[(size_t)k * gridDim.x + c] = part[0];
+}
+
+// partials[k * nt^2 + (bi nt + bj)]: the (bi, bj) 64 x 64 tile of point k,
+// rows r in tile bi, columns r' in tile bj:
+//   sum lam_r lam_r' C0[r, kR + r'] C2[r, kR + r'] C13[r, kR + r'] C13[r', kR + r].
+// The transposed C13 tile is staged through LDS (odd row stride, so the
+// column-wise reads do not conflict).  grid (nt^2, n_t).
+__global__ __launch_bounds__(256) void double_dot_kernel(const double* C0, const double* C2, const double* C13,
+                                                         const double* lam, int R, size_t L, double* partials) {
+  __shared__ double tt[kTile][kTile + 1];
+  __shared__ double part[256];
+  const int nt = (R + kTile - 1) / kTile;
+  const int bi = blockIdx.x / nt, bj = blockIdx.x % nt, k = blockIdx.y, tid = threadIdx.x;
+  const size_t col0 = (size_t)k * R;
+  auto c0 = as_global(C0);
+  auto c2 = as_global(C2);
+  auto c13 = as_global(C13);
+  // tt[r'_l][r_l] = C13[bj 64 + r'_l, kR + bi 64 + r_l]
+  for (int e = tid; e < kTile * kTile; e += 256) {
+    const int rl = e & (kTile - 1), rpl = e >> 6;
+    const int r = bi * kTile + rl, rp = bj * kTile + rpl;
+    tt[rpl][rl] = (r < R && rp < R) ? c13[(size_t)rp * L + col0 + r] : 0.0;
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (int e = tid; e < kTile * kTile; e += 256) {
+    const int rpl = e & (kTile - 1), rl = e >> 6;
+    const int r = bi * kTile + rl, rp = bj * kTile + rpl;
+    if (r < R && rp < R) {
+      const size_t g = (size_t)r * L + col0 + rp;
+      const double lr = lam ? as_global(lam)[r] * as_global(lam)[rp] : 1.0;
+      acc += lr * c0[g] * c2[g] * c13[g] * tt[rpl][rl];
+    }
+  }
+  part[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) part[tid] += part[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) as_global(partials)[(size_t)k * gridDim.x + blockIdx.x] = part[0];
+}
+
+// One workgroup: thread k sums point k's partials in order, then thread 0
+// forms E_K = - sum_k w_k (2 k_single[k] - k_double[k]) in point order.
+__global__ __launch_bounds__(64) void exchange_finish_kernel(const double* p1, int n1, const double* p2, int n2,
+                                                             LtQuad q, double* k1, double* k2, double* ek) {
+  __shared__ double s1[CPD_LT_MAX_POINTS], s2[CPD_LT_MAX_POINTS];
+  const int k = threadIdx.x;
+  if (k < q.n) {
+    double a = 0.0, b = 0.0;
+    for (int c = 0; c < n1; ++c) a += as_global(p1)[(size_t)k * n1 + c];
+    for (int c = 0; c < n2; ++c) b += as_global(p2)[(size_t)k * n2 + c];
+    s1[k] = a;
+    s2[k] = b;
+    as_global(k1)[k] = a;
+    as_global(k2)[k] = b;
+  }
+  __syncthreads();
+  if (k == 0) {
+    double e = 0.0;
+    for (int j = 0; j < q.n; ++j) e += q.w[j] * (2.0 * s1[j] - s2[j]);
+    as_global(ek)[0] = -e;
+  }
+}
+
+struct ExchangeLayout {
+  size_t fs[4], w[4], y, c[3], p1, p2, total;
+  int chunks, tiles;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+ExchangeLayout exchange_layout(int o, int v, int Rt, int R, int n) {
+  ExchangeLayout l{};
+  const size_t L = (size_t)n * R, d = sizeof(double);
+  size_t off = 0;
+  const int rows[4] = {o, v, o, v};
+  for (int m = 0; m < 4; ++m) {
+    l.fs[m] = off;
+    off += align256((size_t)rows[m] * L * d);
+  }
+  for (int m = 0; m < 4; ++m) {
+    l.w[m] = off;
+    off += align256((size_t)Rt * L * d);
+  }
+  l.y = off;
+  off += align256((size_t)Rt * L * d);
+  for (int m = 0; m < 3; ++m) {
+    l.c[m] = off;
+    off += align256((size_t)R * L * d);
+  }
+  l.chunks = (Rt + kDotRows - 1) / kDotRows;
+  const int nt = (R + kTile - 1) / kTile;
+  l.tiles = nt * nt;
+  l.p1 = off;
+  off += align256((size_t)n * l.chunks * d);
+  l.p2 = off;
+  off += align256((size_t)n * l.tiles * d);
+  l.total = off;
+  return l;
+}
+
+bool exchange_sizes_ok(int o, int v, int Rt, int R, int n) {
+  if (o <= 0 || v <= 0 || Rt <= 0 || R <= 0 || n <= 0 || n > CPD_LT_MAX_POINTS) return false;
+  // the products index columns with int
+  return (int64_t)n * R <= INT32_MAX && (int64_t)Rt * Rt <= ((int64_t)1 << 40);
+}
+
+}  // namespace
+
+}  // namespace thccp
+
+using namespace thccp;
+
+extern "C" {
+
+size_t cpd_lt_exchange_workspace(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t r_cp, int32_t n_points) {
+  if (!exchange_sizes_ok(n_occ, n_virt, r_thc, r_cp, n_points)) return 0;
+  return exchange_layout(n_occ, n_virt, r_thc, r_cp, n_points).total;
+}
+
+cpd_status cpd_lt_exchange(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t r_cp, int32_t n_points,
+                           const double* X_occ, const double* X_virt, const double* Z, const double* eps_occ,
+                           const double* eps_virt, const double* t_host, const double* w_host, const double* F0,
+                           const double* F1, const double* F2, const double* F3, const double* lam,
+                           double* k_single, double* k_double, double* e_k, void* workspace,
+                           size_t workspace_bytes, void* stream) {
+  if (!exchange_sizes_ok(n_occ, n_virt, r_thc, r_cp, n_points)) return CPD_ERR_INVALID_ARG;
+  if (!X_occ || !X_virt || !Z || !eps_occ || !eps_virt || !t_host || !w_host || !F0 || !F1 || !F2 || !F3 ||
+      !k_single || !k_double || !e_k)
+    return CPD_ERR_INVALID_ARG;
+  LtQuad q{};
+  q.n = n_points;
+  for (int k = 0; k < n_points; ++k) {
+    if (!isfinite(t_host[k]) || !isfinite(w_host[k])) return CPD_ERR_INVALID_ARG;
+    q.t[k] = t_host[k];
+    q.w[k] = w_host[k];
+  }
+  const ExchangeLayout l = exchange_layout(n_occ, n_virt, r_thc, r_cp, n_points);
+  if (!workspace || workspace_bytes < l.total) return CPD_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  auto buf = [&](size_t off) { return (double*)(ws + off); };
+  const int o = n_occ, v = n_virt, Rt = r_thc, R = r_cp;
+  const int L = n_points * R;
+
+  StackArgs sa{};
+  const double* Fm[4] = {F0, F1, F2, F3};
+  const double* em[4] = {eps_occ, eps_virt, eps_occ, eps_virt};
+  const int rows[4] = {o, v, o, v};
+  for (int m = 0; m < 4; ++m) {
+    sa.F[m] = Fm[m];
+    sa.eps[m] = em[m];
+    sa.out[m] = buf(l.fs[m]);
+    sa.rows[m] = rows[m];
+  }
+  {
+    const size_t most = (size_t)(o > v ? o : v) * L;
+    int grid = (int)((most + 255) / 256);
+    if (grid > 2048) grid = 2048;
+    hipLaunchKernelGGL(lt_stack_kernel, dim3(grid, 4), dim3(256), 0, s, sa, q, R);
+  }
+  // projections (A = X^T, stored n x R_thc) and the double-term overlaps
+  // (A = F^T, stored n x R_cp), all against the scaled stacks
+  auto proj = [&](const double* A, int lda, int M, int K, const double* B, double* C) {
+    GemmF64 g{M, L, K, A, lda, true, B, nullptr, L, false, C, L, nullptr, 1.0, 0.0, nullptr};
+    gemm_f64(s, g);
+  };
+  proj(X_occ, Rt, Rt, o, buf(l.fs[0]), buf(l.w[0]));   // W0 = X_occ^T F0s
+  proj(X_virt, Rt, Rt, v, buf(l.fs[3]), buf(l.w[1]));  // W1 = X_virt^T F3s
+  proj(X_occ, Rt, Rt, o, buf(l.fs[2]), buf(l.w[2]));   // W2 = X_occ^T F2s
+  proj(X_virt, Rt, Rt, v, buf(l.fs[1]), buf(l.w[3]));  // W3 = X_virt^T F1s
+  {
+    // Y = Z (W2 o W3)
+    GemmF64 g{Rt, L, Rt, Z, Rt, false, buf(l.w[2]), buf(l.w[3]), L, false, buf(l.y), L, nullptr, 1.0, 0.0, nullptr};
+    gemm_f64(s, g);
+  }
+  proj(F0, R, R, o, buf(l.fs[0]), buf(l.c[0]));  // C0 = F0^T F0s
+  proj(F2, R, R, o, buf(l.fs[2]), buf(l.c[1]));  // C2 = F2^T F2s
+  proj(F1, R, R, v, buf(l.fs[3]), buf(l.c[2]));  // C13 = F1^T F3s
+  hipLaunchKernelGGL(single_dot_kernel, dim3(l.chunks, n_points), dim3(256), 0, s, buf(l.w[0]), buf(l.w[1]),
+                     buf(l.y), lam, Rt, R, (size_t)L, buf(l.p1));
+  hipLaunchKernelGGL(double_dot_kernel, dim3(l.tiles, n_points), dim3(256), 0, s, buf(l.c[0]), buf(l.c[1]),
+                     buf(l.c[2]), lam, R, (size_t)L, buf(l.p2));
+  hipLaunchKernelGGL(exchange_finish_kernel, dim3(1), dim3(64), 0, s, buf(l.p1), l.chunks, buf(l.p2), l.tiles, q,
+                     k_single, k_double, e_k);
+  return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
+}
+
+}  // extern "C"

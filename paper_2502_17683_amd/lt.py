@@ -1,4 +1,5 @@
-"""Batched Laplace-transform workload: one order-4 CPD per (system, t_k).
+"""Laplace-transform LT-MP2 workloads: one order-4 CPD per (system, t_k),
+and the robust CPD+THC exchange energy.
 
 Section 2.2: with the Laplace transform of the energy denominator
 (eq. lt_D), the LT-MP2 energy is a sum of independent terms over the
@@ -8,9 +9,14 @@ the factor rows change (eq. mp1_t and the THC-LT amplitude after it).  The
 scaling runs on the GPU (cpd_lt_scale_rows); Z is shared by all points of a
 system.
 """
+import ctypes
+
+import numpy as np
 import torch
 
-from .cpd import lt_scale_rows
+from . import _lib
+from ._lib import check
+from .cpd import lt_scale_rows, _ptr, _stream
 
 
 def lt_batch_problems(systems, t_points, rank_factors=(4, 2), init_fn=None, device="cuda"):
@@ -41,3 +47,40 @@ def lt_batch_problems(systems, t_points, rank_factors=(4, 2), init_fn=None, devi
             meta.append((si, float(t)))
             idx += 1
     return problems, meta
+
+
+def lt_exchange_workspace_bytes(n_occ, n_virt, r_thc, r_cp, n_points):
+    return int(_lib.load().cpd_lt_exchange_workspace(n_occ, n_virt, r_thc, r_cp, n_points))
+
+
+def lt_exchange(X_occ, X_virt, Z, eps_occ, eps_virt, t_points, weights, F, lam=None, workspace=None):
+    """Robust CPD+THC LT-MP2 exchange energy of one system (Section 2.2,
+    eq. cpd_single_k, the double-CPD term, eq. rob_K) on the GPU.
+
+    X_occ, X_virt, Z, eps_*, F[0..3] (modes i, a, j, b) and lam: float64
+    device tensors; t_points, weights: host sequences.  Returns device
+    tensors (k_single[n_t], k_double[n_t], e_k[1]).  workspace: optional
+    uint8 device tensor of at least lt_exchange_workspace_bytes(...) bytes.
+    """
+    lib = _lib.load()
+    o, v = int(X_occ.shape[0]), int(X_virt.shape[0])
+    r_thc, r_cp = int(Z.shape[0]), int(F[0].shape[1])
+    t_h = np.ascontiguousarray(np.asarray(t_points, dtype=np.float64))
+    w_h = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+    n = int(t_h.shape[0])
+    if w_h.shape[0] != n:
+        raise ValueError("t_points and weights differ in length")
+    dev = X_occ.device
+    args = [x.contiguous() for x in (X_occ, X_virt, Z, eps_occ, eps_virt, *F)]
+    lam_c = lam.contiguous() if lam is not None else None
+    k1 = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    k2 = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    ek = torch.empty(1, dtype=torch.float64, device=dev)
+    need = lib.cpd_lt_exchange_workspace(o, v, r_thc, r_cp, n)
+    if workspace is None:
+        workspace = torch.empty(max(int(need), 1), dtype=torch.uint8, device=dev)
+    check(lib.cpd_lt_exchange(o, v, r_thc, r_cp, n, *[_ptr(a) for a in args[:5]],
+                              ctypes.c_void_p(t_h.ctypes.data), ctypes.c_void_p(w_h.ctypes.data),
+                              *[_ptr(a) for a in args[5:]], _ptr(lam_c), _ptr(k1), _ptr(k2), _ptr(ek),
+                              _ptr(workspace), workspace.numel(), _stream(dev)), "cpd_lt_exchange")
+    return k1[:n], k2[:n], ek

@@ -88,3 +88,32 @@ def test_workspace_size_validates_arguments():
     assert lib.cpd_init(ctypes.byref(d), ctypes.byref(plan)) == _lib.CPD_ERR_WORKSPACE
     assert lib.cpd_init(None, ctypes.byref(plan)) == _lib.CPD_ERR_INVALID_ARG
     assert lib.cpd_status_string(_lib.CPD_ERR_NOT_SPD).decode().startswith("normal matrix")
+
+
+def test_lt_exchange_rejects_bad_arguments_before_any_launch():
+    # validation happens on the host before any HIP call, so it runs without a GPU
+    from paper_2502_17683_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libthccp.so not built")
+    lib = _lib.load()
+    t = (ctypes.c_double * 65)(*([0.5] * 65))
+    w = (ctypes.c_double * 65)(*([1.0] * 65))
+    fake = ctypes.c_void_p(256)  # never dereferenced: every case fails validation first
+
+    def call(n_points, o=4, v=8, r_thc=16, r_cp=8, ws=None, ws_bytes=0, tt=t):
+        return lib.cpd_lt_exchange(o, v, r_thc, r_cp, n_points, fake, fake, fake, fake, fake,
+                                   ctypes.cast(tt, ctypes.c_void_p), ctypes.cast(w, ctypes.c_void_p),
+                                   fake, fake, fake, fake, None, fake, fake, fake, ws, ws_bytes, None)
+
+    assert call(0) == _lib.CPD_ERR_INVALID_ARG
+    assert call(65) == _lib.CPD_ERR_INVALID_ARG
+    assert call(4, o=0) == _lib.CPD_ERR_INVALID_ARG
+    assert call(4, r_cp=-1) == _lib.CPD_ERR_INVALID_ARG
+    need = lib.cpd_lt_exchange_workspace(4, 8, 16, 8, 4)
+    assert need >= 8 * (2 * 4 + 2 * 8 + 5 * 16 + 3 * 8) * 4 * 8
+    assert call(4) == _lib.CPD_ERR_WORKSPACE
+    assert call(4, ws=fake, ws_bytes=need - 1) == _lib.CPD_ERR_WORKSPACE
+    bad_t = (ctypes.c_double * 4)(0.5, float("nan"), 0.5, 0.5)
+    assert call(4, ws=fake, ws_bytes=need, tt=bad_t) == _lib.CPD_ERR_INVALID_ARG
+    assert lib.cpd_lt_exchange_workspace(4, 8, 16, 8, 0) == 0
+    assert lib.cpd_lt_exchange_workspace(4, 8, 16, 8, 65) == 0
