@@ -43,12 +43,12 @@ def mttkrp_flops(n, r_thc, r_cp):
     return 4.0 * r_thc * r_cp * sum(n) + 4.0 * r_thc * r_thc * r_cp
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed PMC summary, or
+def measured_traffic(kernel, profile="step_kernel_chol_fwd_traffic_n800_r4000.md"):
+    """HBM bytes per launch of `kernel` from a committed PMC summary, or
     None once the kernel's source has changed since the counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "step_kernel_chol_fwd_traffic_n800_r4000.md")
+    path = os.path.join(ROOT, "profiles", profile)
     try:
         text = open(path).read()
     except OSError:
@@ -102,9 +102,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("mixed", "lt", "warmstart"), default="mixed",
+    ap.add_argument("--workload", choices=("mixed", "lt", "warmstart", "exchange"), default="mixed",
                     help="mixed: the headline time-to-fit line (default); lt: the batched "
-                         "Laplace-transform CPDs; warmstart: train and evaluate the learned warm start")
+                         "Laplace-transform CPDs; warmstart: train and evaluate the learned warm start; "
+                         "exchange: the robust CPD+THC LT-MP2 exchange energy of the batched systems")
     ap.add_argument("--lt-sweeps", type=int, default=40)
     ap.add_argument("--ws-train", type=int, default=512)
     ap.add_argument("--ws-heldout", type=int, default=32)
@@ -118,10 +119,21 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how it would shard).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration_mib > 0:
+        import torch
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {nb} bytes read, {nb} bytes written")
+        del src, dst
     if args.workload == "lt":
         return bench_lt(args)
     if args.workload == "warmstart":
         return bench_warmstart(args)
+    if args.workload == "exchange":
+        return bench_exchange(args)
 
     import torch
     from paper_2502_17683_amd import CPD
@@ -129,14 +141,6 @@ def main():
 
     N, Rt, Rc = args.n, args.r_thc, args.r_cp
     dev = torch.device("cuda:0")
-    if args.copy_calibration_mib > 0:
-        nb = args.copy_calibration_mib << 20
-        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] copy calibration: {nb} bytes read, {nb} bytes written")
-        del src, dst
     log(f"[bench] generating THC input N={N} R_thc={Rt} R_cp={Rc} seed={args.seed}")
     X, Z = make_thc(N, Rt, args.seed)
     init = init_factors([N] * 4, Rc, args.seed + 1000)
@@ -350,6 +354,123 @@ def bench_lt(args):
         "converge_tol_1e-4": conv,
         "final_fit_rel_diff_mixed_vs_fp64": {"max": max(rel), "median": float(np.median(rel))},
         "speedup_converge_mixed_vs_fp64": conv["fp64"]["seconds"] / conv["mixed"]["seconds"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def exchange_flops(o, v, r_thc, r_cp, n_points):
+    """Useful flops of one exchange call: the four projections, the Z
+    product and the three double-term overlaps, over all points."""
+    L = n_points * r_cp
+    return 2.0 * r_thc * L * (2 * o + 2 * v) + 2.0 * r_thc * r_thc * L + 2.0 * r_cp * L * (2 * o + v)
+
+
+def bench_exchange(args):
+    """Robust CPD+THC LT-MP2 exchange energy (k_single, k_double and E_K at
+    16 Laplace points) of the three systems of the batched workload.  value:
+    summed milliseconds per call of the three systems, inputs resident in
+    HBM.  Roofline: the Z product Y = Z (W2 o W3) of the largest system
+    (the Hadamard product formed beforehand, as in the library call),
+    timed with hipEvents around the same library product on the stream it
+    runs on.  CPU baseline: the oracle on the largest system."""
+    import ctypes
+    import multiprocessing
+    import torch
+    from paper_2502_17683_amd import lt_exchange, lt_exchange_workspace_bytes, _lib
+    from synth import make_lt_system, init_factors, lt_quadrature, LT_SYSTEMS
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ts, w = lt_quadrature()
+    npt = len(ts)
+    per_system, total_ms, total_flops = [], 0.0, 0.0
+    largest = None
+    for si, (o, v) in enumerate(LT_SYSTEMS):
+        Xo, Xv, Z, eo, ev = make_lt_system(o, v, si)
+        r_thc, r_cp = Z.shape[0], 2 * (o + v)
+        F = init_factors([o, v, o, v], r_cp, 1000 + 16 * si)
+        d = [torch.as_tensor(a, device=dev) for a in (Xo, Xv, Z, eo, ev)]
+        Fd = [torch.as_tensor(f, device=dev) for f in F]
+        lam = torch.ones(r_cp, dtype=torch.float64, device=dev)
+        ws = torch.empty(lt_exchange_workspace_bytes(o, v, r_thc, r_cp, npt), dtype=torch.uint8, device=dev)
+        for _ in range(args.warmup + 1):
+            lt_exchange(*d, ts, w, Fd, lam, workspace=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            k1, k2, ek = lt_exchange(*d, ts, w, Fd, lam, workspace=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        fl = exchange_flops(o, v, r_thc, r_cp, npt)
+        total_ms += ms
+        total_flops += fl
+        per_system.append({"o": o, "v": v, "r_thc": r_thc, "r_cp": r_cp, "ms": ms,
+                           "useful_tflops": fl / (ms * 1e-3) / 1e12, "e_k": float(ek.cpu()[0]),
+                           "workspace_mib": ws.numel() / 2 ** 20})
+        log(f"[bench-exchange] ({o},{v}) R_thc={r_thc} R_cp={r_cp}: {ms:.3f} ms/call "
+            f"{fl / (ms * 1e-3) / 1e12:.1f} TF/s")
+        largest = (Xo, Xv, Z, eo, ev, F, d, o, v, r_thc, r_cp)
+        del ws
+
+    # the Z product of the largest system (Y = Z S2, S2 = W2 o W3 formed
+    # beforehand) through the same library product
+    Xo, Xv, Z, eo, ev, F, d, o, v, r_thc, r_cp = largest
+    L = npt * r_cp
+    lib = _lib.load()
+    g = torch.Generator(device="cpu").manual_seed(5)
+    B1 = torch.randn(r_thc, L, dtype=torch.float64, generator=g).to(dev)
+    C = torch.empty(r_thc, L, dtype=torch.float64, device=dev)
+    vp = ctypes.c_void_p
+    sp = vp(stream.cuda_stream)
+
+    def zprod():
+        _lib.check(lib.cpd_test_gemm(0, r_thc, L, r_thc, vp(d[2].data_ptr()), r_thc, 0, vp(B1.data_ptr()),
+                                     None, L, 0, vp(C.data_ptr()), L, sp), "cpd_test_gemm")
+    zprod()
+    torch.cuda.synchronize()
+    reps = 10
+    e0.record(stream)
+    for _ in range(reps):
+        zprod()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    z_ms = e0.elapsed_time(e1) / reps
+    z_flops = 2.0 * r_thc * r_thc * L
+    z_achieved = z_flops / (z_ms * 1e-3) / 1e12
+    del B1, C
+
+    cpu = None
+    if not args.no_cpu:
+        sys.path.insert(0, ROOT)
+        from oracle import exchange as ox
+        cores = int(os.environ.get("OMP_NUM_THREADS", multiprocessing.cpu_count()))
+        t0 = time.perf_counter()
+        ox.exchange_terms(Xo, Xv, Z, F, np.ones(r_cp), eo, ev, ts)
+        dt = time.perf_counter() - t0
+        cpu = {"value": dt * 1e3, "unit": "ms", "cores": cores, "kind": "oracle",
+               "sample": f"one full call of the largest system ({o},{v}), 16 points"}
+        log(f"[bench-exchange] CPU oracle ({o},{v}): {dt * 1e3:.1f} ms on {cores} threads")
+
+    out = {
+        "metric": "robust CPD+THC LT-MP2 exchange energy, time per call summed over the three systems (ms), "
+                  "1 MI355X",
+        "value": total_ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": False, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "exchange energy of the systems (o,v) in (20,100),(40,200),(80,400); "
+                               "R_thc=4(o+v), R_cp=2(o+v), 16 Laplace points 0.01-20 with log-trapezoid "
+                               "weights; CPD = seeded factors (the cost does not depend on their values)"},
+        "useful_tflops": total_flops / (total_ms * 1e-3) / 1e12,
+        "per_system": per_system,
+        "roofline": {"bound": "mfma", "kernel": "gemm_dma_kernel<false,false,false>: FP64 Z product Y = Z (W2 o W3), largest system",
+                     "achieved": z_achieved, "peak": MFMA_PEAK["f64"] / 1e12, "unit": "TFLOP/s",
+                     "frac": z_achieved * 1e12 / MFMA_PEAK["f64"],
+                     "traffic": measured_traffic("gemm_dma_kernel<false,false,false>",
+                                                 "exchange_zproduct_traffic_lt80x400.md"),
+                     "avg_launch_us": z_ms * 1e3,
+                     "shape": [r_thc, L, r_thc]},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
