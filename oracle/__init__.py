@@ -16,6 +16,9 @@ Modules
   warmstart  Warm-start features of the grid points, selection of the
            initial CP columns, training targets from converged CPDs.
   mlp      Warm-start network: forward, loss, manual backward, Adam.
+  exchange Robust CPD+THC LT-MP2 exchange energy (single- and double-CPD
+           terms, eq. rob_K).
+  mp2      THC LT-MP2 Coulomb and exchange terms and the LT-MP2 energy.
 
 Pins: every function is checked by ``tests/test_oracle_*.py`` against
 brute-force loops, closed forms, planted decompositions, special cases and
