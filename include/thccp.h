@@ -243,6 +243,39 @@ cpd_status cpd_lt_exchange(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t
                            double* k_single, double* k_double, double* e_k, void* workspace,
                            size_t workspace_bytes, void* stream);
 
+/* ---- THC LT-MP2 Coulomb and exchange terms and energy (Section 2.2) ----
+ * Same tensors, mode order and Laplace factor as cpd_lt_exchange, with the
+ * THC tensor on both sides:
+ *   J[k] = sum_{iajb} exp(-D t_k) G[i,a,j,b] G[i,a,j,b]      (eq. thc_Ej)
+ *   K[k] = sum_{iajb} exp(-D t_k) G[i,a,j,b] G[i,b,j,a]      (eq. thc_Ek)
+ *   energies[0] = E_J = 2 sum_k w_k J[k]
+ *   energies[1] = E_K = - sum_k w_k K[k]   (0 when thc_exchange = 0)
+ *   energies[2] = E_J + E_K                                 (eq. LT-Emp2)
+ * J costs O(n_points r_thc^3) through the grid overlaps and two (one with
+ * z_symmetric = 1) wide products with Z.  K (thc_exchange = 1) forms the
+ * (o v) x (o v) matrix (ia|jb) from the THC factors: O(o^2 v^2 r_thc) flops
+ * and 16 (o v)^2 bytes of workspace, the cost the robust CPD+THC exchange
+ * (cpd_lt_exchange) avoids.  The CPD+THC energy is E_J + cpd_lt_exchange's
+ * e_k.
+ *   X_occ, X_virt, Z, eps_occ, eps_virt: DEVICE, as for cpd_lt_exchange.
+ *   z_symmetric = 1 asserts Z = Z^T (true of a THC core of the symmetric
+ *   (ia|jb)); the Coulomb term then needs one product instead of two.  A
+ *   non-symmetric Z with z_symmetric = 1 gives a wrong J.
+ *   t_host, w_host: HOST, n_points finite values.
+ *   J, K (n_points each; K may be NULL when thc_exchange = 0), energies (3):
+ *   DEVICE outputs.  1 <= n_points <= CPD_LT_MAX_POINTS; with thc_exchange,
+ *   o v <= 46340 and o^2 v must fit int32.
+ *   workspace: DEVICE, at least cpd_lt_mp2_workspace(...) bytes.
+ * Errors: CPD_ERR_INVALID_ARG, CPD_ERR_WORKSPACE, CPD_ERR_HIP.  Async on
+ * stream; fixed-order reductions (bitwise reproducible). */
+size_t cpd_lt_mp2_workspace(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t n_points, int32_t thc_exchange,
+                            int32_t z_symmetric);
+cpd_status cpd_lt_mp2(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t n_points, const double* X_occ,
+                      const double* X_virt, const double* Z, const double* eps_occ, const double* eps_virt,
+                      const double* t_host, const double* w_host, int32_t thc_exchange, int32_t z_symmetric,
+                      double* J, double* K, double* energies, void* workspace, size_t workspace_bytes,
+                      void* stream);
+
 /* Releases the host plan and its private stream/graph (not the workspace). */
 /* ---- learned warm start ----
  * An initial CP built from R_cp grid columns of the THC factors: with a

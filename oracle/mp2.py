@@ -37,9 +37,11 @@ def coulomb_term(X_occ, X_virt, Z, eps_occ, eps_virt, t):
     return float(np.sum(B * M))                  # sum_{Q,T} B[Q,T] M[Q,T]
 
 
-def exchange_term(X_occ, X_virt, Z, eps_occ, eps_virt, t):
-    """K(t) from the dense tensor (plain definition)."""
-    G = dense.dense_tensor([X_occ, X_virt, X_occ, X_virt], Z)
+def exchange_term(X_occ, X_virt, Z, eps_occ, eps_virt, t, G=None):
+    """K(t) from the dense tensor (plain definition); G: the dense tensor,
+    if already formed."""
+    if G is None:
+        G = dense.dense_tensor([X_occ, X_virt, X_occ, X_virt], Z)
     D = (eps_virt[None, :, None, None] + eps_virt[None, None, None, :]
          - eps_occ[:, None, None, None] - eps_occ[None, None, :, None])
     return float(np.sum(np.exp(-D * t) * G * G.transpose(0, 3, 2, 1)))
@@ -48,8 +50,10 @@ def exchange_term(X_occ, X_virt, Z, eps_occ, eps_virt, t):
 def lt_mp2(X_occ, X_virt, Z, eps_occ, eps_virt, t_points, weights, exchange=True):
     """Per-point J and K (K only if exchange) and (E_J, E_K, E)."""
     J = np.array([coulomb_term(X_occ, X_virt, Z, eps_occ, eps_virt, t) for t in t_points])
-    K = (np.array([exchange_term(X_occ, X_virt, Z, eps_occ, eps_virt, t) for t in t_points])
-         if exchange else None)
+    K = None
+    if exchange:
+        G = dense.dense_tensor([X_occ, X_virt, X_occ, X_virt], Z)
+        K = np.array([exchange_term(X_occ, X_virt, Z, eps_occ, eps_virt, t, G) for t in t_points])
     w = np.asarray(weights, dtype=np.float64)
     e_j = 2.0 * float(np.sum(w * J))
     e_k = -float(np.sum(w * K)) if exchange else None

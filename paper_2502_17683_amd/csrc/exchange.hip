@@ -20,6 +20,9 @@
 //   k_double[k] = sum_{r, r'} lam_r lam_r' C0 C2 C13 [r, k R + r'] C13[r', k R + r]
 // and E_K = - sum_k w_k (2 k_single[k] - k_double[k]).
 //
+// The same file holds the THC LT-MP2 Coulomb and exchange terms and the
+// LT-MP2 energy (below).
+//
 // Products run on the FP64 matrix cores (gemm_f64); the stacks and the two
 // dot products are HBM-bound element-wise kernels.  Every reduction has a
 // fixed order (per-block partials, then a fixed tree per point), so
@@ -219,6 +222,228 @@ bool exchange_sizes_ok(int o, int v, int Rt, int R, int n) {
   return (int64_t)n * R <= INT32_MAX && (int64_t)Rt * Rt <= ((int64_t)1 << 40);
 }
 
+
+// ----------------------------------------------------------------------
+// THC LT-MP2 Coulomb and exchange terms (eq. thc_Ej, eq. thc_Ek, eq.
+// LT-Emp2).
+//
+// Coulomb: with the occupied and virtual factors scaled per point (stacks
+// Xs_o, Xs_v, one R_thc block per point), M_k = (X_o^T Xs_o)_k o
+// (X_v^T Xs_v)_k is symmetric, and
+//   J[k] = sum_{P,S} M_k[P,S] (Z M_k Z^T)[P,S] = sum_{P,T} A_k[P,T] B_k[T,P]
+// with A = Z M and B = Z^T M (B = A for a symmetric Z): one or two wide
+// products over all points, then a transposed dot per point.
+//
+// Exchange: the (ia|jb) matrix G = Bp Z Bp^T with Bp[(i,a), P] =
+// X_o[i,P] X_v[a,P] ((o v) x (o v), o^2 v^2 R_thc flops: the THC exchange
+// costs a power of N more than the Coulomb term), the swapped product
+// Pm[(i,a),(j,b)] = G[(i,a),(j,b)] G[(i,b),(j,a)], the virtual Laplace
+// factors H^T = U^T Pm_flat^T with U[b,k] = exp(-eps_b t_k) and Pm_flat the
+// (o v o) x v view of Pm, and
+//   K[k] = sum_{i,a,j} exp((eps_i + eps_j - eps_a) t_k) H^T[k, (i,a,j)].
+
+// partials[k * nt^2 + (bi nt + bj)] = sum over the (bi, bj) tile of point
+// k of A[r, kR + c] B[c, kR + r] (B tile transposed through LDS).
+__global__ __launch_bounds__(256) void tdot_blocks_kernel(const double* A, const double* B, int R, size_t L,
+                                                          double* partials) {
+  __shared__ double tt[kTile][kTile + 1];
+  __shared__ double part[256];
+  const int nt = (R + kTile - 1) / kTile;
+  const int bi = blockIdx.x / nt, bj = blockIdx.x % nt, k = blockIdx.y, tid = threadIdx.x;
+  const size_t col0 = (size_t)k * R;
+  auto a = as_global(A);
+  auto b = as_global(B);
+  // tt[c_l][r_l] = B[bj 64 + c_l, kR + bi 64 + r_l]
+  for (int e = tid; e < kTile * kTile; e += 256) {
+    const int rl = e & (kTile - 1), cl = e >> 6;
+    const int r = bi * kTile + rl, c = bj * kTile + cl;
+    tt[cl][rl] = (r < R && c < R) ? b[(size_t)c * L + col0 + r] : 0.0;
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (int e = tid; e < kTile * kTile; e += 256) {
+    const int cl = e & (kTile - 1), rl = e >> 6;
+    const int r = bi * kTile + rl, c = bj * kTile + cl;
+    if (r < R && c < R) acc += a[(size_t)r * L + col0 + c] * tt[cl][rl];
+  }
+  part[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) part[tid] += part[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) as_global(partials)[(size_t)k * gridDim.x + blockIdx.x] = part[0];
+}
+
+// Bp[(i v + a), P] = X_o[i, P] X_v[a, P]
+__global__ __launch_bounds__(256) void pair_rows_kernel(const double* Xo, const double* Xv, int o, int v, int Rt,
+                                                        double* Bp) {
+  const size_t total = (size_t)o * v * Rt;
+  auto xo = as_global(Xo);
+  auto xv = as_global(Xv);
+  auto out = as_global(Bp);
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    const size_t row = e / Rt;
+    const int P = (int)(e - row * Rt);
+    const int i = (int)(row / v), a = (int)(row - (size_t)i * v);
+    out[e] = xo[(size_t)i * Rt + P] * xv[(size_t)a * Rt + P];
+  }
+}
+
+// Pm[(i,a),(j,b)] = G[(i,a),(j,b)] G[(i,b),(j,a)]: block (i, j) of G is
+// v x v; the swapped factor is the transposed block, read through LDS.
+// grid o^2 nv^2 (flat), nv = ceil(v / 64); block = (i, j, tile row, tile col).
+__global__ __launch_bounds__(256) void swap_product_kernel(const double* G, int o, int v, double* Pm) {
+  __shared__ double tt[kTile][kTile + 1];
+  const int nv = (v + kTile - 1) / kTile;
+  const int tile = blockIdx.x % (nv * nv), pair = blockIdx.x / (nv * nv);
+  const int ta = tile / nv, tb = tile % nv;
+  const int i = pair / o, j = pair % o;
+  const size_t ld = (size_t)o * v;
+  const size_t base = (size_t)i * v * ld + (size_t)j * v;  // block (i, j)
+  auto g = as_global(G);
+  auto out = as_global(Pm);
+  const int tid = threadIdx.x;
+  // tt[b_l][a_l] = G[(i, tb 64 + b_l), (j, ta 64 + a_l)]
+  for (int e = tid; e < kTile * kTile; e += 256) {
+    const int al = e & (kTile - 1), bl = e >> 6;
+    const int a = ta * kTile + al, b = tb * kTile + bl;
+    tt[bl][al] = (a < v && b < v) ? g[base + (size_t)b * ld + a] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < kTile * kTile; e += 256) {
+    const int bl = e & (kTile - 1), al = e >> 6;
+    const int a = ta * kTile + al, b = tb * kTile + bl;
+    if (a < v && b < v) {
+      const size_t idx = base + (size_t)a * ld + b;
+      out[idx] = g[idx] * tt[bl][al];
+    }
+  }
+}
+
+// U^T[k, b] = exp(-eps_b t_k)  (n x v)
+__global__ __launch_bounds__(256) void virt_factor_kernel(const double* eps_v, int v, LtQuad q, double* Ut) {
+  const int total = q.n * v;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+    const int k = e / v, b = e - k * v;
+    as_global(Ut)[e] = exp(-as_global(eps_v)[b] * q.t[k]);
+  }
+}
+
+// partials[k * chunks + c] = sum over rows r = (i, a, j) of chunk c of
+// exp((eps_i + eps_j - eps_a) t_k) Ht[k, r].  grid (chunks, n).
+constexpr int kRowsPerBlock = 4096;
+__global__ __launch_bounds__(256) void occ_weight_dot_kernel(const double* Ht, const double* eps_o,
+                                                             const double* eps_v, int o, int v, LtQuad q,
+                                                             double* partials) {
+  __shared__ double part[256];
+  const int c = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
+  const size_t rows = (size_t)o * v * o;
+  const size_t r0 = (size_t)c * kRowsPerBlock;
+  const size_t r1 = r0 + kRowsPerBlock < rows ? r0 + kRowsPerBlock : rows;
+  const double tk = q.t[k];
+  auto h = as_global(Ht);
+  auto eo = as_global(eps_o);
+  auto ev = as_global(eps_v);
+  double acc = 0.0;
+  for (size_t r = r0 + tid; r < r1; r += 256) {
+    const int j = (int)(r % o);
+    const size_t ia = r / o;
+    const int a = (int)(ia % v), i = (int)(ia / v);
+    acc += exp((eo[i] + eo[j] - ev[a]) * tk) * h[(size_t)k * rows + r];
+  }
+  part[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) part[tid] += part[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) as_global(partials)[(size_t)k * gridDim.x + c] = part[0];
+}
+
+// One workgroup of 16 waves: per-point sums of both partial sets in a fixed
+// tree (as exchange_finish_kernel), then e[0] = E_J = 2 sum_k w_k J[k],
+// e[1] = E_K = - sum_k w_k K[k] (0 without the exchange term), e[2] = E_J + E_K.
+__global__ __launch_bounds__(64 * kFinishWaves) void mp2_finish_kernel(const double* pj, int nj, const double* pk,
+                                                                       int nk, LtQuad q, double* J, double* K,
+                                                                       double* e) {
+  __shared__ double sj[CPD_LT_MAX_POINTS], sk[CPD_LT_MAX_POINTS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = wave; k < q.n; k += kFinishWaves) {
+    double a = 0.0, b = 0.0;
+    for (int c = lane; c < nj; c += 64) a += as_global(pj)[(size_t)k * nj + c];
+    for (int c = lane; c < nk; c += 64) b += as_global(pk)[(size_t)k * nk + c];
+    for (int w = 32; w > 0; w >>= 1) {
+      a += __shfl_down(a, w);
+      b += __shfl_down(b, w);
+    }
+    if (lane == 0) {
+      sj[k] = a;
+      sk[k] = b;
+      as_global(J)[k] = a;
+      if (K) as_global(K)[k] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ej = 0.0, ek = 0.0;
+    for (int k = 0; k < q.n; ++k) {
+      ej += q.w[k] * sj[k];
+      ek += q.w[k] * sk[k];
+    }
+    as_global(e)[0] = 2.0 * ej;
+    as_global(e)[1] = -ek;
+    as_global(e)[2] = 2.0 * ej - ek;
+  }
+}
+
+struct Mp2Layout {
+  size_t xs[2], om, vm, a, b, pj;  // Coulomb
+  size_t bp, c1, g, pm, ut, ht, pk;  // exchange
+  size_t total;
+  int jtiles, kchunks;
+};
+
+Mp2Layout mp2_layout(int o, int v, int Rt, int n, bool with_k, bool z_sym) {
+  Mp2Layout l{};
+  const size_t L = (size_t)n * Rt, d = sizeof(double);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align256(bytes);
+    return at;
+  };
+  l.xs[0] = take((size_t)o * L * d);
+  l.xs[1] = take((size_t)v * L * d);
+  l.om = take((size_t)Rt * L * d);
+  l.vm = take((size_t)Rt * L * d);
+  l.a = take((size_t)Rt * L * d);
+  l.b = z_sym ? l.a : take((size_t)Rt * L * d);
+  const int nt = (Rt + kTile - 1) / kTile;
+  l.jtiles = nt * nt;
+  l.pj = take((size_t)n * l.jtiles * d);
+  if (with_k) {
+    const size_t ov = (size_t)o * v, rows = ov * o;
+    l.bp = take(ov * Rt * d);
+    l.c1 = take(ov * Rt * d);
+    l.g = take(ov * ov * d);
+    l.pm = take(ov * ov * d);
+    l.ut = take((size_t)n * v * d);
+    l.ht = take((size_t)n * rows * d);
+    l.kchunks = (int)((rows + kRowsPerBlock - 1) / kRowsPerBlock);
+    l.pk = take((size_t)n * l.kchunks * d);
+  }
+  l.total = off;
+  return l;
+}
+
+bool mp2_sizes_ok(int o, int v, int Rt, int n, bool with_k) {
+  if (o <= 0 || v <= 0 || Rt <= 0 || n <= 0 || n > CPD_LT_MAX_POINTS) return false;
+  if ((int64_t)n * Rt > INT32_MAX) return false;
+  // the exchange products index (o v) and (o v o) rows with int
+  if (with_k && ((int64_t)o * v * o > INT32_MAX || (int64_t)o * v > 46340)) return false;
+  return true;
+}
 }  // namespace
 
 }  // namespace thccp
@@ -300,6 +525,97 @@ cpd_status cpd_lt_exchange(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t
                      buf(l.c[2]), lam, R, (size_t)L, buf(l.p2));
   hipLaunchKernelGGL(exchange_finish_kernel, dim3(1), dim3(64 * kFinishWaves), 0, s, buf(l.p1), l.chunks, buf(l.p2), l.tiles, q,
                      k_single, k_double, e_k);
+  return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
+}
+
+
+size_t cpd_lt_mp2_workspace(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t n_points, int32_t thc_exchange,
+                            int32_t z_symmetric) {
+  if (!mp2_sizes_ok(n_occ, n_virt, r_thc, n_points, thc_exchange != 0)) return 0;
+  return mp2_layout(n_occ, n_virt, r_thc, n_points, thc_exchange != 0, z_symmetric != 0).total;
+}
+
+cpd_status cpd_lt_mp2(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t n_points, const double* X_occ,
+                      const double* X_virt, const double* Z, const double* eps_occ, const double* eps_virt,
+                      const double* t_host, const double* w_host, int32_t thc_exchange, int32_t z_symmetric,
+                      double* J, double* K, double* energies, void* workspace, size_t workspace_bytes,
+                      void* stream) {
+  const bool with_k = thc_exchange != 0, z_sym = z_symmetric != 0;
+  if (!mp2_sizes_ok(n_occ, n_virt, r_thc, n_points, with_k)) return CPD_ERR_INVALID_ARG;
+  if (!X_occ || !X_virt || !Z || !eps_occ || !eps_virt || !t_host || !w_host || !J || !energies ||
+      (with_k && !K))
+    return CPD_ERR_INVALID_ARG;
+  LtQuad q{};
+  q.n = n_points;
+  for (int k = 0; k < n_points; ++k) {
+    if (!isfinite(t_host[k]) || !isfinite(w_host[k])) return CPD_ERR_INVALID_ARG;
+    q.t[k] = t_host[k];
+    q.w[k] = w_host[k];
+  }
+  const Mp2Layout l = mp2_layout(n_occ, n_virt, r_thc, n_points, with_k, z_sym);
+  if (!workspace || workspace_bytes < l.total) return CPD_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  auto buf = [&](size_t off) { return (double*)(ws + off); };
+  const int o = n_occ, v = n_virt, Rt = r_thc;
+  const int L = n_points * Rt;
+
+  // Coulomb term
+  StackArgs sa{};
+  sa.F[0] = X_occ;
+  sa.eps[0] = eps_occ;
+  sa.out[0] = buf(l.xs[0]);
+  sa.rows[0] = o;
+  sa.F[1] = X_virt;
+  sa.eps[1] = eps_virt;
+  sa.out[1] = buf(l.xs[1]);
+  sa.rows[1] = v;
+  {
+    const size_t most = (size_t)(o > v ? o : v) * L;
+    int grid = (int)((most + 255) / 256);
+    if (grid > 2048) grid = 2048;
+    hipLaunchKernelGGL(lt_stack_kernel, dim3(grid, 2), dim3(256), 0, s, sa, q, Rt);
+  }
+  auto gemm = [&](int M, int N, int Kd, const double* A, int lda, bool at, const double* B, int ldb, bool bt,
+                  double* C, int ldc) {
+    GemmF64 g{M, N, Kd, A, lda, at, B, nullptr, ldb, bt, C, ldc, nullptr, 1.0, 0.0, nullptr};
+    gemm_f64(s, g);
+  };
+  gemm(Rt, L, o, X_occ, Rt, true, buf(l.xs[0]), L, false, buf(l.om), L);   // O = X_o^T Xs_o
+  gemm(Rt, L, v, X_virt, Rt, true, buf(l.xs[1]), L, false, buf(l.vm), L);  // V = X_v^T Xs_v
+  hadamard_inplace_f64(s, buf(l.om), buf(l.vm), (size_t)Rt * L);             // M = O o V
+  gemm(Rt, L, Rt, Z, Rt, false, buf(l.om), L, false, buf(l.a), L);          // A = Z M
+  if (!z_sym) gemm(Rt, L, Rt, Z, Rt, true, buf(l.om), L, false, buf(l.b), L);  // B = Z^T M
+  hipLaunchKernelGGL(tdot_blocks_kernel, dim3(l.jtiles, n_points), dim3(256), 0, s, buf(l.a), buf(l.b), Rt,
+                     (size_t)L, buf(l.pj));
+
+  // THC exchange term
+  if (with_k) {
+    const int ov = o * v;
+    {
+      const size_t total = (size_t)ov * Rt;
+      int grid = (int)((total + 255) / 256);
+      if (grid > 8192) grid = 8192;
+      hipLaunchKernelGGL(pair_rows_kernel, dim3(grid), dim3(256), 0, s, X_occ, X_virt, o, v, Rt, buf(l.bp));
+    }
+    gemm(ov, Rt, Rt, buf(l.bp), Rt, false, Z, Rt, false, buf(l.c1), Rt);    // C1 = Bp Z
+    gemm(ov, ov, Rt, buf(l.c1), Rt, false, buf(l.bp), Rt, true, buf(l.g), ov);  // G = C1 Bp^T
+    {
+      const int nv = (v + kTile - 1) / kTile;
+      hipLaunchKernelGGL(swap_product_kernel, dim3(nv * nv * o * o), dim3(256), 0, s, buf(l.g), o, v, buf(l.pm));
+    }
+    {
+      int grid = (n_points * v + 255) / 256;
+      hipLaunchKernelGGL(virt_factor_kernel, dim3(grid), dim3(256), 0, s, eps_virt, v, q, buf(l.ut));
+    }
+    const int rows = ov * o;
+    gemm(n_points, rows, v, buf(l.ut), v, false, buf(l.pm), v, true, buf(l.ht), rows);  // H^T = U^T Pm^T
+    hipLaunchKernelGGL(occ_weight_dot_kernel, dim3(l.kchunks, n_points), dim3(256), 0, s, buf(l.ht), eps_occ,
+                       eps_virt, o, v, q, buf(l.pk));
+  }
+  hipLaunchKernelGGL(mp2_finish_kernel, dim3(1), dim3(64 * kFinishWaves), 0, s, buf(l.pj), l.jtiles,
+                     with_k ? buf(l.pk) : buf(l.pj), with_k ? l.kchunks : 0, q, J, with_k ? K : nullptr,
+                     energies);
   return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
 }
 

@@ -84,3 +84,35 @@ def lt_exchange(X_occ, X_virt, Z, eps_occ, eps_virt, t_points, weights, F, lam=N
                               *[_ptr(a) for a in args[5:]], _ptr(lam_c), _ptr(k1), _ptr(k2), _ptr(ek),
                               _ptr(workspace), workspace.numel(), _stream(dev)), "cpd_lt_exchange")
     return k1[:n], k2[:n], ek
+
+
+def lt_mp2_workspace_bytes(n_occ, n_virt, r_thc, n_points, thc_exchange=True, z_symmetric=False):
+    return int(_lib.load().cpd_lt_mp2_workspace(n_occ, n_virt, r_thc, n_points, int(thc_exchange),
+                                                int(z_symmetric)))
+
+
+def lt_mp2(X_occ, X_virt, Z, eps_occ, eps_virt, t_points, weights, thc_exchange=True, z_symmetric=False,
+           workspace=None):
+    """THC LT-MP2 Coulomb (and, with thc_exchange, exchange) terms and the
+    energies (E_J, E_K, E_J + E_K) on the GPU (eq. thc_Ej, thc_Ek, LT-Emp2).
+    Returns device tensors (J[n_t], K[n_t] or None, energies[3])."""
+    lib = _lib.load()
+    o, v, r_thc = int(X_occ.shape[0]), int(X_virt.shape[0]), int(Z.shape[0])
+    t_h = np.ascontiguousarray(np.asarray(t_points, dtype=np.float64))
+    w_h = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+    n = int(t_h.shape[0])
+    if w_h.shape[0] != n:
+        raise ValueError("t_points and weights differ in length")
+    dev = X_occ.device
+    args = [x.contiguous() for x in (X_occ, X_virt, Z, eps_occ, eps_virt)]
+    J = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    K = torch.empty(max(n, 1), dtype=torch.float64, device=dev) if thc_exchange else None
+    e = torch.empty(3, dtype=torch.float64, device=dev)
+    need = lib.cpd_lt_mp2_workspace(o, v, r_thc, n, int(thc_exchange), int(z_symmetric))
+    if workspace is None:
+        workspace = torch.empty(max(int(need), 1), dtype=torch.uint8, device=dev)
+    check(lib.cpd_lt_mp2(o, v, r_thc, n, *[_ptr(a) for a in args],
+                         ctypes.c_void_p(t_h.ctypes.data), ctypes.c_void_p(w_h.ctypes.data),
+                         int(thc_exchange), int(z_symmetric), _ptr(J), _ptr(K), _ptr(e),
+                         _ptr(workspace), workspace.numel(), _stream(dev)), "cpd_lt_mp2")
+    return J[:n], (K[:n] if K is not None else None), e

@@ -1,0 +1,113 @@
+"""THC LT-MP2 Coulomb and exchange terms and energies on the GPU against
+the oracle.
+
+Tolerance: as for the exchange energy, |gpu - oracle| <= 1e-12 x A with A
+the same sum over absolute values (computed by the oracle from |X|, |Z|):
+every term is a sum of products with accumulation chains of a few thousand
+at most.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import need_gpu, say, to_dev, torch
+from oracle import mp2
+from synth import LT_SYSTEMS, lt_quadrature, make_lt_system
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _run(Xo, Xv, Z, eo, ev, ts, w, thc_exchange=True, z_symmetric=False):
+    from paper_2502_17683_amd import lt_mp2
+    J, K, e = lt_mp2(to_dev(Xo), to_dev(Xv), to_dev(Z), to_dev(eo), to_dev(ev), ts, w,
+                     thc_exchange=thc_exchange, z_symmetric=z_symmetric)
+    torch.cuda.synchronize()
+    return J.cpu().numpy(), (K.cpu().numpy() if K is not None else None), e.cpu().numpy()
+
+
+def _check(Xo, Xv, Z, eo, ev, ts, w, label, thc_exchange=True, z_symmetric=False):
+    say(f"[mp2] {label}: o={Xo.shape[0]} v={Xv.shape[0]} r_thc={Z.shape[0]} points={len(ts)} "
+        f"exchange={thc_exchange} z_symmetric={z_symmetric}")
+    gJ, gK, ge = _run(Xo, Xv, Z, eo, ev, ts, w, thc_exchange, z_symmetric)
+    rJ, rK, (ej, ek, e) = mp2.lt_mp2(Xo, Xv, Z, eo, ev, ts, w, exchange=thc_exchange)
+    if (Xo >= 0).all() and (Xv >= 0).all() and (Z >= 0).all():
+        # every term is non-negative (the synthetic factors and core are
+        # positive): the sums are their own absolute bounds
+        aJ, aK = rJ, rK
+    else:
+        aJ, aK, _ = mp2.lt_mp2(np.abs(Xo), np.abs(Xv), np.abs(Z), eo, ev, ts, w, exchange=thc_exchange)
+    errJ = np.abs(gJ - rJ) / aJ
+    msg = f"[mp2] {label}: max err/bound J {errJ.max():.2e}"
+    assert np.all(errJ <= TOL)
+    bj = 2.0 * float(np.sum(np.abs(w) * aJ))
+    assert abs(ge[0] - ej) <= TOL * bj
+    if thc_exchange:
+        errK = np.abs(gK - rK) / aK
+        msg += f" K {errK.max():.2e}"
+        assert np.all(errK <= TOL)
+        bk = float(np.sum(np.abs(w) * aK))
+        assert abs(ge[1] - ek) <= TOL * bk
+        assert abs(ge[2] - e) <= TOL * (bj + bk)
+    else:
+        assert ge[1] == 0.0 and ge[2] == ge[0]
+    say(msg)
+    return gJ, gK, ge
+
+
+@pytest.mark.parametrize("z_symmetric", [False, True])
+def test_mp2_ragged(z_symmetric):
+    # R_thc 80 (two and a ragged 64-tile), o v = 84, v = 14
+    ts, w = lt_quadrature(3, 0.05, 4.0)
+    _check(*make_lt_system(6, 14, 3, rank_factor=4), ts, w, "ragged", z_symmetric=z_symmetric)
+
+
+def test_mp2_nonsymmetric_core():
+    rng = np.random.default_rng(12)
+    Xo, Xv, _, eo, ev = make_lt_system(4, 9, 12, rank_factor=3)
+    Z = rng.standard_normal((39, 39))
+    _check(Xo, Xv, Z, eo, ev, [0.3, 1.7], [0.5, 0.9], "non-symmetric Z")
+
+
+def test_mp2_odd_sizes_one_point_coulomb_only():
+    _check(*make_lt_system(5, 11, 4, rank_factor=3), [0.6], [1.3], "odd, J only", thc_exchange=False)
+
+
+def test_mp2_multiple_of_sixteen():
+    ts, w = lt_quadrature(4)
+    _check(*make_lt_system(16, 64, 5, rank_factor=2), ts, w, "multiples of 16", z_symmetric=True)
+
+
+@pytest.mark.parametrize("system", [0, 1])
+def test_mp2_full_size(system):
+    o, v = LT_SYSTEMS[system]
+    ts, w = lt_quadrature()
+    _check(*make_lt_system(o, v, system), ts, w, f"full size {o},{v}", z_symmetric=True)
+
+
+def test_mp2_largest_system():
+    """(80, 400) at 16 points: the Coulomb term against the oracle; the
+    exchange term (an 8 GB (ia|jb) matrix in the oracle) by a property that
+    holds at any size: |K(t)| <= J(t) (Cauchy-Schwarz, the Laplace factor
+    being symmetric in a <-> b)."""
+    o, v = LT_SYSTEMS[2]
+    ts, w = lt_quadrature()
+    args = make_lt_system(o, v, 2)
+    _check(*args, ts, w, "full size 80,400 J", thc_exchange=False, z_symmetric=True)
+    gJ, gK, ge = _run(*args, ts, w, thc_exchange=True, z_symmetric=True)
+    say(f"[mp2] 80,400: E_J {ge[0]:.10e} E_K {ge[1]:.10e}; max |K|/J {np.max(np.abs(gK) / gJ):.3f}")
+    assert np.all(np.abs(gK) <= gJ * (1 + 1e-12))
+    assert abs(ge[2] - (ge[0] + ge[1])) <= 1e-14 * abs(ge[0])
+
+
+def test_mp2_is_deterministic():
+    ts, w = lt_quadrature(5)
+    args = make_lt_system(8, 24, 6, rank_factor=4)
+    a = _run(*args, ts, w)
+    b = _run(*args, ts, w)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
