@@ -107,6 +107,8 @@ def main():
                          "Laplace-transform CPDs; warmstart: train and evaluate the learned warm start; "
                          "exchange: the robust CPD+THC LT-MP2 exchange energy of the batched systems")
     ap.add_argument("--lt-sweeps", type=int, default=40)
+    ap.add_argument("--accuracy-sweeps", type=int, default=100,
+                    help="exchange workload: CP-ALS sweep cap for the accuracy comparison (0: skip)")
     ap.add_argument("--ws-train", type=int, default=512)
     ap.add_argument("--ws-heldout", type=int, default=32)
     ap.add_argument("--ws-heldout-large", type=int, default=4)
@@ -376,7 +378,8 @@ def bench_exchange(args):
     import ctypes
     import multiprocessing
     import torch
-    from paper_2502_17683_amd import lt_exchange, lt_exchange_workspace_bytes, _lib
+    from paper_2502_17683_amd import (lt_exchange, lt_exchange_workspace_bytes, lt_mp2, lt_mp2_workspace_bytes,
+                                      CPD, _lib)
     from synth import make_lt_system, init_factors, lt_quadrature, LT_SYSTEMS
 
     dev = torch.device("cuda:0")
@@ -406,13 +409,33 @@ def bench_exchange(args):
         fl = exchange_flops(o, v, r_thc, r_cp, npt)
         total_ms += ms
         total_flops += fl
+        del ws
+        # the THC LT-MP2 terms of the same system: Coulomb alone, then with
+        # the THC exchange (the dense (ia|jb) route the CPD avoids)
+        mp2_ms = {}
+        for with_k in (False, True):
+            wsm = torch.empty(lt_mp2_workspace_bytes(o, v, r_thc, npt, with_k, True), dtype=torch.uint8,
+                              device=dev)
+            for _ in range(args.warmup + 1):
+                lt_mp2(*d, ts, w, thc_exchange=with_k, z_symmetric=True, workspace=wsm)
+            torch.cuda.synchronize()
+            reps = max(1, args.steps // 2) if with_k else args.steps
+            e0.record(stream)
+            for _ in range(reps):
+                _, _, en = lt_mp2(*d, ts, w, thc_exchange=with_k, z_symmetric=True, workspace=wsm)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            mp2_ms[with_k] = e0.elapsed_time(e1) / reps
+            del wsm
+        thc_k_ms = mp2_ms[True] - mp2_ms[False]
         per_system.append({"o": o, "v": v, "r_thc": r_thc, "r_cp": r_cp, "ms": ms,
                            "useful_tflops": fl / (ms * 1e-3) / 1e12, "e_k": float(ek.cpu()[0]),
-                           "workspace_mib": ws.numel() / 2 ** 20})
-        log(f"[bench-exchange] ({o},{v}) R_thc={r_thc} R_cp={r_cp}: {ms:.3f} ms/call "
-            f"{fl / (ms * 1e-3) / 1e12:.1f} TF/s")
+                           "coulomb_ms": mp2_ms[False], "thc_exchange_ms": thc_k_ms,
+                           "robust_vs_thc_exchange_speedup": thc_k_ms / ms})
+        log(f"[bench-exchange] ({o},{v}) R_thc={r_thc} R_cp={r_cp}: robust exchange {ms:.3f} ms/call "
+            f"{fl / (ms * 1e-3) / 1e12:.1f} TF/s; THC Coulomb {mp2_ms[False]:.3f} ms; THC exchange "
+            f"{thc_k_ms:.3f} ms ({thc_k_ms / ms:.1f}x the robust one)")
         largest = (Xo, Xv, Z, eo, ev, F, d, o, v, r_thc, r_cp)
-        del ws
 
     # the Z product of the largest system (Y = Z S2, S2 = W2 o W3 formed
     # beforehand) through the same library product
@@ -441,6 +464,33 @@ def bench_exchange(args):
     z_achieved = z_flops / (z_ms * 1e-3) / 1e12
     del B1, C
 
+    # accuracy (the paper's comparison): a CPD of each bare tensor by FP64
+    # CP-ALS (stopping rule 1e-4 or --accuracy-sweeps), then the THC LT-MP2
+    # exchange energy against the robust and the single-CPD ones
+    accuracy = []
+    for si, (o, v) in enumerate(LT_SYSTEMS if args.accuracy_sweeps > 0 else ()):
+        Xo, Xv, Z, eo, ev = make_lt_system(o, v, si)
+        r_thc, r_cp = Z.shape[0], 2 * (o + v)
+        d = [torch.as_tensor(a, device=dev) for a in (Xo, Xv, Z, eo, ev)]
+        c = CPD([d[0], d[1], d[0], d[1]], d[2], r_cp, init_factors([o, v, o, v], r_cp, 1000 + 16 * si),
+                precision="fp64", tol=1e-4, fit_floor=1e-7)
+        fits = c.sweep(args.accuracy_sweeps)
+        Fd, lam = c.factors()
+        c.close()
+        k1, k2, ek = lt_exchange(*d, ts, w, Fd, lam)
+        _, _, en = lt_mp2(*d, ts, w, thc_exchange=True, z_symmetric=True)
+        e_j, e_thc = float(en[0]), float(en[1])
+        e_rob = float(ek[0])
+        e_single = -float(np.sum(w * k1.cpu().numpy()))
+        accuracy.append({"o": o, "v": v, "cpd_sweeps": len(fits), "cpd_fit": float(fits[-1]),
+                         "E_J": e_j, "E_K_thc": e_thc, "E_K_robust": e_rob, "E_K_single": e_single,
+                         "rel_err_robust": (e_rob - e_thc) / abs(e_thc),
+                         "rel_err_single": (e_single - e_thc) / abs(e_thc),
+                         "rel_err_total_robust": (e_rob - e_thc) / abs(e_j + e_thc)})
+        log(f"[bench-exchange] accuracy ({o},{v}): CPD fit {fits[-1]:.3e} after {len(fits)} sweeps; "
+            f"E_K THC {e_thc:.8e} robust err {(e_rob - e_thc) / abs(e_thc):.2e} single err "
+            f"{(e_single - e_thc) / abs(e_thc):.2e}")
+
     cpu = None
     if not args.no_cpu:
         sys.path.insert(0, ROOT)
@@ -463,6 +513,7 @@ def bench_exchange(args):
                                "weights; CPD = seeded factors (the cost does not depend on their values)"},
         "useful_tflops": total_flops / (total_ms * 1e-3) / 1e12,
         "per_system": per_system,
+        "accuracy_vs_thc_exchange": accuracy,
         "roofline": {"bound": "mfma", "kernel": "gemm_dma_kernel<false,false,false>: FP64 Z product Y = Z (W2 o W3), largest system",
                      "achieved": z_achieved, "peak": MFMA_PEAK["f64"] / 1e12, "unit": "TFLOP/s",
                      "frac": z_achieved * 1e12 / MFMA_PEAK["f64"],
