@@ -218,30 +218,40 @@ cpd_status cpd_lt_scale_rows(const double* X, const double* eps, int32_t n, int3
  * The amplitude carries the whole factor w_k exp(-D t_k); the double-CPD
  * term pairs each occupied index with its own particle's factor (the
  * definition of g^{ba}_{ij}), so an exact CPD reproduces the exact
- * exchange energy and the robust energy's error is second order in the
- * CPD error.
+ * exchange energy.  By default the CPD of the scaled tensor is the
+ * LT-scaled bare CPD (its rows scaled like the THC factors); then the
+ * robust energy's error is second order in the CPD error.  With E_host,
+ * separate CPDs of the scaled tensors (for instance the batched per-point
+ * CPDs of cpd_batch_*) take that place in k_double.
  *   X_occ n_occ x r_thc, X_virt n_virt x r_thc, Z r_thc x r_thc (any Z; no
  *   symmetry is assumed), eps_occ n_occ, eps_virt n_virt, F0/F2
  *   n_occ x r_cp, F1/F3 n_virt x r_cp, lam r_cp (NULL: all ones): DEVICE,
  *   row-major, borrowed for the call.  t_host, w_host: HOST arrays of
  *   n_points finite values, read before the call returns.
+ *   E_host: NULL, or a HOST array of 4 n_points DEVICE pointers, entry
+ *   4k + m the mode-m factor (n_occ or n_virt x r_cp, modes i, a, j, b) of
+ *   point k's CPD; lam_e_host: NULL (all ones) or a HOST array of n_points
+ *   DEVICE pointers to their weights (an entry may be NULL: ones).
  *   k_single, k_double (n_points each) and e_k (1): DEVICE outputs.
  *   1 <= n_points <= CPD_LT_MAX_POINTS; n_points * r_cp must fit int32.
- *   workspace: DEVICE, at least cpd_lt_exchange_workspace(...) bytes,
- *   256-byte aligned; holds the scaled factor stacks and the products of
- *   every point (about 8 (2 n_occ + 2 n_virt + 5 r_thc + 3 r_cp)
- *   n_points r_cp bytes).
+ *   workspace: DEVICE, at least cpd_lt_exchange_workspace(...,
+ *   per_point_cpds = E_host != NULL) bytes, 256-byte aligned; holds the
+ *   scaled factor stacks and the products of every point (about
+ *   8 (2 n_occ + 2 n_virt + 5 r_thc + 3 r_cp) n_points r_cp bytes, plus
+ *   8 (2 n_occ + 2 n_virt + r_cp + 1) n_points r_cp with per-point CPDs).
  * Errors: CPD_ERR_INVALID_ARG (sizes, NULL pointers, non-finite t or w),
  * CPD_ERR_WORKSPACE, CPD_ERR_HIP (launch failure).  Async on stream; the
  * result is bitwise reproducible (fixed-order reductions). */
 #define CPD_LT_MAX_POINTS 64
-size_t cpd_lt_exchange_workspace(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t r_cp, int32_t n_points);
+size_t cpd_lt_exchange_workspace(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t r_cp, int32_t n_points,
+                                 int32_t per_point_cpds);
 cpd_status cpd_lt_exchange(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t r_cp, int32_t n_points,
                            const double* X_occ, const double* X_virt, const double* Z, const double* eps_occ,
                            const double* eps_virt, const double* t_host, const double* w_host, const double* F0,
                            const double* F1, const double* F2, const double* F3, const double* lam,
-                           double* k_single, double* k_double, double* e_k, void* workspace,
-                           size_t workspace_bytes, void* stream);
+                           const double* const* E_host, const double* const* lam_e_host, double* k_single,
+                           double* k_double, double* e_k, void* workspace, size_t workspace_bytes,
+                           void* stream);
 
 /* ---- THC LT-MP2 Coulomb and exchange terms and energy (Section 2.2) ----
  * Same tensors, mode order and Laplace factor as cpd_lt_exchange, with the

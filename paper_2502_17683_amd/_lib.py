@@ -86,12 +86,12 @@ EXPORTS = {
     "cpd_batch_stats": (i32, [vp, i32, ctypes.POINTER(CpdStats)]),
     "cpd_autotune_log": (i32, [vp, ctypes.c_char_p, i32]),
     "cpd_lt_scale_rows": (i32, [vp, vp, i32, i32, ctypes.c_double, ctypes.c_double, vp, vp]),
-    "cpd_lt_exchange_workspace": (ctypes.c_size_t, [i32, i32, i32, i32, i32]),
+    "cpd_lt_exchange_workspace": (ctypes.c_size_t, [i32, i32, i32, i32, i32, i32]),
     "cpd_lt_mp2_workspace": (ctypes.c_size_t, [i32, i32, i32, i32, i32, i32]),
     "cpd_lt_mp2": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, ctypes.c_size_t,
                          vp]),
     "cpd_lt_exchange": (i32, [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
-                              vp, ctypes.c_size_t, vp]),
+                              vp, vp, vp, ctypes.c_size_t, vp]),
     "cpd_destroy": (i32, [vp]),
     "cpd_status_string": (ctypes.c_char_p, [i32]),
     "cpd_test_gemm": (i32, [i32, i32, i32, i32, vp, i32, i32, vp, vp, i32, i32, vp, i32, vp]),

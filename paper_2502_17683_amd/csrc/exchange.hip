@@ -19,6 +19,10 @@
 //   C0 = F0^T F0s   C2 = F2^T F2s   C13 = F1^T F3s    (R_cp x n_t R_cp)
 //   k_double[k] = sum_{r, r'} lam_r lam_r' C0 C2 C13 [r, k R + r'] C13[r', k R + r]
 // and E_K = - sum_k w_k (2 k_single[k] - k_double[k]).
+// Given separate CPDs E_k of the scaled tensors instead (per_point), their
+// factors are stacked and the double term takes four plain overlaps,
+//   Cm = Es_m^T F_{pm}  (L x R; pm = 0, 3, 2, 1),
+//   k_double[k] = sum_{r, r'} lam_e[kR + r] lam_r' C0 C1 C2 C3 [kR + r, r'].
 //
 // The same file holds the THC LT-MP2 Coulomb and exchange terms and the
 // LT-MP2 energy (below).
@@ -146,6 +150,67 @@ __global__ __launch_bounds__(256) void double_dot_kernel(const double* C0, const
   if (tid == 0) as_global(partials)[(size_t)k * gridDim.x + blockIdx.x] = part[0];
 }
 
+// Point k's separate CPD into the stacks: Es_m[:, kR : kR + R] = E_m and
+// lame[kR : kR + R] = lam_e (ones for NULL).  blockIdx.y = m (4: weights).
+struct GatherArgs {
+  const double* E[4];
+  const double* lam;
+  double* out[4];
+  double* lam_out;
+  int rows[4];
+};
+__global__ __launch_bounds__(256) void gather_point_kernel(GatherArgs g, int k, int R, size_t L) {
+  const int m = blockIdx.y;
+  if (m == 4) {
+    for (int r = blockIdx.x * 256 + threadIdx.x; r < R; r += gridDim.x * 256)
+      as_global(g.lam_out)[(size_t)k * R + r] = g.lam ? as_global(g.lam)[r] : 1.0;
+    return;
+  }
+  const size_t total = (size_t)g.rows[m] * R;
+  auto src = as_global(g.E[m]);
+  auto dst = as_global(g.out[m]);
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    const size_t p = e / R;
+    const int r = (int)(e - p * R);
+    dst[p * L + (size_t)k * R + r] = src[e];
+  }
+}
+
+// Separate per-point CPDs: partials[k * dchunks + c] = sum over rows
+// r in chunk c of point k and all r' of
+//   lame[kR + r] lam[r'] C0 C1 C2 C3 [kR + r, r']   (each L x R).
+// grid (dchunks, n_t).
+__global__ __launch_bounds__(256) void double_dot_sep_kernel(const double* C0, const double* C1, const double* C2,
+                                                             const double* C3, const double* lame,
+                                                             const double* lam, int R, double* partials) {
+  __shared__ double part[256];
+  const int c = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
+  const int r0 = c * kDotRows;
+  const int r1 = r0 + kDotRows < R ? r0 + kDotRows : R;
+  auto c0 = as_global(C0);
+  auto c1 = as_global(C1);
+  auto c2 = as_global(C2);
+  auto c3 = as_global(C3);
+  double acc = 0.0;
+  for (int rp = tid; rp < R; rp += 256) {
+    const double lf = lam ? as_global(lam)[rp] : 1.0;
+    double s = 0.0;
+    for (int r = r0; r < r1; ++r) {
+      const size_t row = (size_t)k * R + r;
+      const size_t e = row * R + rp;
+      s += as_global(lame)[row] * c0[e] * c1[e] * c2[e] * c3[e];
+    }
+    acc += lf * s;
+  }
+  part[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) part[tid] += part[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) as_global(partials)[(size_t)k * gridDim.x + c] = part[0];
+}
+
 // One workgroup of 16 waves: wave j reduces points j, j + 16, ...; each lane
 // sums a strided subset of the point's partials, then the wave's 64 sums
 // are combined in a fixed shuffle tree.  Thread 0 then forms
@@ -180,38 +245,38 @@ __global__ __launch_bounds__(64 * kFinishWaves) void exchange_finish_kernel(cons
 }
 
 struct ExchangeLayout {
-  size_t fs[4], w[4], y, c[3], p1, p2, total;
-  int chunks, tiles;
+  size_t fs[4], w[4], y, c[4], es[4], lame, p1, p2, total;
+  int chunks, tiles, dchunks;
 };
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-ExchangeLayout exchange_layout(int o, int v, int Rt, int R, int n) {
+// per_point: separate CPDs of the scaled tensors (the E stacks, their
+// weights and a fourth overlap) instead of the LT-scaled bare CPD.
+ExchangeLayout exchange_layout(int o, int v, int Rt, int R, int n, bool per_point) {
   ExchangeLayout l{};
   const size_t L = (size_t)n * R, d = sizeof(double);
   size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align256(bytes);
+    return at;
+  };
   const int rows[4] = {o, v, o, v};
-  for (int m = 0; m < 4; ++m) {
-    l.fs[m] = off;
-    off += align256((size_t)rows[m] * L * d);
-  }
-  for (int m = 0; m < 4; ++m) {
-    l.w[m] = off;
-    off += align256((size_t)Rt * L * d);
-  }
-  l.y = off;
-  off += align256((size_t)Rt * L * d);
-  for (int m = 0; m < 3; ++m) {
-    l.c[m] = off;
-    off += align256((size_t)R * L * d);
+  for (int m = 0; m < 4; ++m) l.fs[m] = take((size_t)rows[m] * L * d);
+  for (int m = 0; m < 4; ++m) l.w[m] = take((size_t)Rt * L * d);
+  l.y = take((size_t)Rt * L * d);
+  for (int m = 0; m < (per_point ? 4 : 3); ++m) l.c[m] = take((size_t)R * L * d);
+  if (per_point) {
+    for (int m = 0; m < 4; ++m) l.es[m] = take((size_t)rows[m] * L * d);
+    l.lame = take(L * d);
   }
   l.chunks = (Rt + kDotRows - 1) / kDotRows;
   const int nt = (R + kTile - 1) / kTile;
   l.tiles = nt * nt;
-  l.p1 = off;
-  off += align256((size_t)n * l.chunks * d);
-  l.p2 = off;
-  off += align256((size_t)n * l.tiles * d);
+  l.dchunks = (R + kDotRows - 1) / kDotRows;
+  l.p1 = take((size_t)n * l.chunks * d);
+  l.p2 = take((size_t)n * (per_point ? l.dchunks : l.tiles) * d);
   l.total = off;
   return l;
 }
@@ -452,21 +517,27 @@ using namespace thccp;
 
 extern "C" {
 
-size_t cpd_lt_exchange_workspace(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t r_cp, int32_t n_points) {
+size_t cpd_lt_exchange_workspace(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t r_cp, int32_t n_points,
+                                 int32_t per_point_cpds) {
   if (!exchange_sizes_ok(n_occ, n_virt, r_thc, r_cp, n_points)) return 0;
-  return exchange_layout(n_occ, n_virt, r_thc, r_cp, n_points).total;
+  return exchange_layout(n_occ, n_virt, r_thc, r_cp, n_points, per_point_cpds != 0).total;
 }
 
 cpd_status cpd_lt_exchange(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t r_cp, int32_t n_points,
                            const double* X_occ, const double* X_virt, const double* Z, const double* eps_occ,
                            const double* eps_virt, const double* t_host, const double* w_host, const double* F0,
                            const double* F1, const double* F2, const double* F3, const double* lam,
-                           double* k_single, double* k_double, double* e_k, void* workspace,
-                           size_t workspace_bytes, void* stream) {
+                           const double* const* E_host, const double* const* lam_e_host, double* k_single,
+                           double* k_double, double* e_k, void* workspace, size_t workspace_bytes,
+                           void* stream) {
   if (!exchange_sizes_ok(n_occ, n_virt, r_thc, r_cp, n_points)) return CPD_ERR_INVALID_ARG;
   if (!X_occ || !X_virt || !Z || !eps_occ || !eps_virt || !t_host || !w_host || !F0 || !F1 || !F2 || !F3 ||
       !k_single || !k_double || !e_k)
     return CPD_ERR_INVALID_ARG;
+  const bool per_point = E_host != nullptr;
+  if (per_point)
+    for (int e = 0; e < 4 * n_points; ++e)
+      if (!E_host[e]) return CPD_ERR_INVALID_ARG;
   LtQuad q{};
   q.n = n_points;
   for (int k = 0; k < n_points; ++k) {
@@ -474,7 +545,7 @@ cpd_status cpd_lt_exchange(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t
     q.t[k] = t_host[k];
     q.w[k] = w_host[k];
   }
-  const ExchangeLayout l = exchange_layout(n_occ, n_virt, r_thc, r_cp, n_points);
+  const ExchangeLayout l = exchange_layout(n_occ, n_virt, r_thc, r_cp, n_points, per_point);
   if (!workspace || workspace_bytes < l.total) return CPD_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   char* ws = (char*)workspace;
@@ -516,15 +587,43 @@ cpd_status cpd_lt_exchange(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t
     GemmF64 g{Rt, L, Rt, Z, Rt, false, buf(l.w[2]), nullptr, L, false, buf(l.y), L, nullptr, 1.0, 0.0, nullptr};
     gemm_f64(s, g);
   }
-  proj(F0, R, R, o, buf(l.fs[0]), buf(l.c[0]));  // C0 = F0^T F0s
-  proj(F2, R, R, o, buf(l.fs[2]), buf(l.c[1]));  // C2 = F2^T F2s
-  proj(F1, R, R, v, buf(l.fs[3]), buf(l.c[2]));  // C13 = F1^T F3s
   hipLaunchKernelGGL(single_dot_kernel, dim3(l.chunks, n_points), dim3(256), 0, s, buf(l.w[0]), buf(l.w[1]),
                      buf(l.y), lam, Rt, R, (size_t)L, buf(l.p1));
-  hipLaunchKernelGGL(double_dot_kernel, dim3(l.tiles, n_points), dim3(256), 0, s, buf(l.c[0]), buf(l.c[1]),
-                     buf(l.c[2]), lam, R, (size_t)L, buf(l.p2));
-  hipLaunchKernelGGL(exchange_finish_kernel, dim3(1), dim3(64 * kFinishWaves), 0, s, buf(l.p1), l.chunks, buf(l.p2), l.tiles, q,
-                     k_single, k_double, e_k);
+  if (!per_point) {
+    proj(F0, R, R, o, buf(l.fs[0]), buf(l.c[0]));  // C0 = F0^T F0s
+    proj(F2, R, R, o, buf(l.fs[2]), buf(l.c[1]));  // C2 = F2^T F2s
+    proj(F1, R, R, v, buf(l.fs[3]), buf(l.c[2]));  // C13 = F1^T F3s
+    hipLaunchKernelGGL(double_dot_kernel, dim3(l.tiles, n_points), dim3(256), 0, s, buf(l.c[0]), buf(l.c[1]),
+                       buf(l.c[2]), lam, R, (size_t)L, buf(l.p2));
+  } else {
+    // separate CPDs E_k of the scaled tensors: stack them, then the four
+    // overlaps (E0^T F0)(E1^T F3)(E2^T F2)(E3^T F1) of every point at once
+    for (int k = 0; k < n_points; ++k) {
+      GatherArgs g{};
+      for (int m = 0; m < 4; ++m) {
+        g.E[m] = E_host[4 * k + m];
+        g.out[m] = buf(l.es[m]);
+        g.rows[m] = rows[m];
+      }
+      g.lam = lam_e_host ? lam_e_host[k] : nullptr;
+      g.lam_out = buf(l.lame);
+      const int most = (o > v ? o : v) * R;
+      int grid = (most + 255) / 256;
+      if (grid > 1024) grid = 1024;
+      hipLaunchKernelGGL(gather_point_kernel, dim3(grid, 5), dim3(256), 0, s, g, k, R, (size_t)L);
+    }
+    const double* partner[4] = {F0, F3, F2, F1};
+    for (int m = 0; m < 4; ++m) {
+      // C_m = Es_m^T partner_m  (L x R)
+      GemmF64 g{L, R, rows[m], buf(l.es[m]), L, true, partner[m], nullptr, R, false, buf(l.c[m]), R, nullptr,
+                1.0, 0.0, nullptr};
+      gemm_f64(s, g);
+    }
+    hipLaunchKernelGGL(double_dot_sep_kernel, dim3(l.dchunks, n_points), dim3(256), 0, s, buf(l.c[0]),
+                       buf(l.c[1]), buf(l.c[2]), buf(l.c[3]), buf(l.lame), lam, R, buf(l.p2));
+  }
+  hipLaunchKernelGGL(exchange_finish_kernel, dim3(1), dim3(64 * kFinishWaves), 0, s, buf(l.p1), l.chunks,
+                     buf(l.p2), per_point ? l.dchunks : l.tiles, q, k_single, k_double, e_k);
   return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
 }
 

@@ -49,18 +49,22 @@ def lt_batch_problems(systems, t_points, rank_factors=(4, 2), init_fn=None, devi
     return problems, meta
 
 
-def lt_exchange_workspace_bytes(n_occ, n_virt, r_thc, r_cp, n_points):
-    return int(_lib.load().cpd_lt_exchange_workspace(n_occ, n_virt, r_thc, r_cp, n_points))
+def lt_exchange_workspace_bytes(n_occ, n_virt, r_thc, r_cp, n_points, per_point_cpds=False):
+    return int(_lib.load().cpd_lt_exchange_workspace(n_occ, n_virt, r_thc, r_cp, n_points, int(per_point_cpds)))
 
 
-def lt_exchange(X_occ, X_virt, Z, eps_occ, eps_virt, t_points, weights, F, lam=None, workspace=None):
+def lt_exchange(X_occ, X_virt, Z, eps_occ, eps_virt, t_points, weights, F, lam=None, E=None, lam_e=None,
+                workspace=None):
     """Robust CPD+THC LT-MP2 exchange energy of one system (Section 2.2,
     eq. cpd_single_k, the double-CPD term, eq. rob_K) on the GPU.
 
     X_occ, X_virt, Z, eps_*, F[0..3] (modes i, a, j, b) and lam: float64
-    device tensors; t_points, weights: host sequences.  Returns device
-    tensors (k_single[n_t], k_double[n_t], e_k[1]).  workspace: optional
-    uint8 device tensor of at least lt_exchange_workspace_bytes(...) bytes.
+    device tensors; t_points, weights: host sequences.  E: optional list
+    (one per point) of 4 device factor tensors, separate CPDs of the scaled
+    tensors (default: the LT-scaled F); lam_e: their weights (list of
+    device tensors or None).  Returns device tensors (k_single[n_t],
+    k_double[n_t], e_k[1]).  workspace: optional uint8 device tensor of at
+    least lt_exchange_workspace_bytes(...) bytes.
     """
     lib = _lib.load()
     o, v = int(X_occ.shape[0]), int(X_virt.shape[0])
@@ -76,13 +80,27 @@ def lt_exchange(X_occ, X_virt, Z, eps_occ, eps_virt, t_points, weights, F, lam=N
     k1 = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
     k2 = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
     ek = torch.empty(1, dtype=torch.float64, device=dev)
-    need = lib.cpd_lt_exchange_workspace(o, v, r_thc, r_cp, n)
+    E_arr = lam_arr = None
+    keep = []
+    if E is not None:
+        if len(E) != n or any(len(e) != 4 for e in E):
+            raise ValueError("E needs 4 factors per Laplace point")
+        keep = [f.contiguous() for e in E for f in e]
+        E_arr = (ctypes.c_void_p * (4 * n))(*[f.data_ptr() for f in keep])
+        if lam_e is not None:
+            lk = [None if x is None else x.contiguous() for x in lam_e]
+            keep += [x for x in lk if x is not None]
+            lam_arr = (ctypes.c_void_p * n)(*[0 if x is None else x.data_ptr() for x in lk])
+    need = lib.cpd_lt_exchange_workspace(o, v, r_thc, r_cp, n, int(E is not None))
     if workspace is None:
         workspace = torch.empty(max(int(need), 1), dtype=torch.uint8, device=dev)
     check(lib.cpd_lt_exchange(o, v, r_thc, r_cp, n, *[_ptr(a) for a in args[:5]],
                               ctypes.c_void_p(t_h.ctypes.data), ctypes.c_void_p(w_h.ctypes.data),
-                              *[_ptr(a) for a in args[5:]], _ptr(lam_c), _ptr(k1), _ptr(k2), _ptr(ek),
-                              _ptr(workspace), workspace.numel(), _stream(dev)), "cpd_lt_exchange")
+                              *[_ptr(a) for a in args[5:]], _ptr(lam_c),
+                              ctypes.cast(E_arr, ctypes.c_void_p) if E_arr is not None else None,
+                              ctypes.cast(lam_arr, ctypes.c_void_p) if lam_arr is not None else None,
+                              _ptr(k1), _ptr(k2), _ptr(ek), _ptr(workspace), workspace.numel(),
+                              _stream(dev)), "cpd_lt_exchange")
     return k1[:n], k2[:n], ek
 
 

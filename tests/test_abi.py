@@ -100,20 +100,27 @@ def test_lt_exchange_rejects_bad_arguments_before_any_launch():
     w = (ctypes.c_double * 65)(*([1.0] * 65))
     fake = ctypes.c_void_p(256)  # never dereferenced: every case fails validation first
 
-    def call(n_points, o=4, v=8, r_thc=16, r_cp=8, ws=None, ws_bytes=0, tt=t):
+    def call(n_points, o=4, v=8, r_thc=16, r_cp=8, ws=None, ws_bytes=0, tt=t, E=None):
         return lib.cpd_lt_exchange(o, v, r_thc, r_cp, n_points, fake, fake, fake, fake, fake,
                                    ctypes.cast(tt, ctypes.c_void_p), ctypes.cast(w, ctypes.c_void_p),
-                                   fake, fake, fake, fake, None, fake, fake, fake, ws, ws_bytes, None)
+                                   fake, fake, fake, fake, None, E, None, fake, fake, fake, ws, ws_bytes, None)
 
     assert call(0) == _lib.CPD_ERR_INVALID_ARG
     assert call(65) == _lib.CPD_ERR_INVALID_ARG
     assert call(4, o=0) == _lib.CPD_ERR_INVALID_ARG
     assert call(4, r_cp=-1) == _lib.CPD_ERR_INVALID_ARG
-    need = lib.cpd_lt_exchange_workspace(4, 8, 16, 8, 4)
+    need = lib.cpd_lt_exchange_workspace(4, 8, 16, 8, 4, 0)
     assert need >= 8 * (2 * 4 + 2 * 8 + 5 * 16 + 3 * 8) * 4 * 8
+    need_pp = lib.cpd_lt_exchange_workspace(4, 8, 16, 8, 4, 1)
+    assert need_pp >= need + 8 * (2 * 4 + 2 * 8 + 8 + 1) * 4 * 8
+    # per-point CPDs with a NULL factor pointer, then a workspace sized for the default
+    E_bad = (ctypes.c_void_p * 16)(*([256] * 15 + [0]))
+    assert call(4, ws=fake, ws_bytes=need_pp, E=ctypes.cast(E_bad, ctypes.c_void_p)) == _lib.CPD_ERR_INVALID_ARG
+    E_ok = (ctypes.c_void_p * 16)(*([256] * 16))
+    assert call(4, ws=fake, ws_bytes=need, E=ctypes.cast(E_ok, ctypes.c_void_p)) == _lib.CPD_ERR_WORKSPACE
     assert call(4) == _lib.CPD_ERR_WORKSPACE
     assert call(4, ws=fake, ws_bytes=need - 1) == _lib.CPD_ERR_WORKSPACE
     bad_t = (ctypes.c_double * 4)(0.5, float("nan"), 0.5, 0.5)
     assert call(4, ws=fake, ws_bytes=need, tt=bad_t) == _lib.CPD_ERR_INVALID_ARG
-    assert lib.cpd_lt_exchange_workspace(4, 8, 16, 8, 0) == 0
-    assert lib.cpd_lt_exchange_workspace(4, 8, 16, 8, 65) == 0
+    assert lib.cpd_lt_exchange_workspace(4, 8, 16, 8, 0, 0) == 0
+    assert lib.cpd_lt_exchange_workspace(4, 8, 16, 8, 65, 0) == 0

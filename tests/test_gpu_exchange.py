@@ -125,3 +125,74 @@ def test_exchange_with_converged_cpd_is_robust():
     single = -float(np.sum(w * g1))
     say(f"[exchange] exact {exact:.10e} robust err {ge - exact:.3e} single err {single - exact:.3e}")
     assert abs(ge - exact) < abs(single - exact)
+
+
+def _run_pp(Xo, Xv, Z, eo, ev, F, lam_h, ts, w, E, lam_e):
+    from paper_2502_17683_amd import lt_exchange
+    k1, k2, ek = lt_exchange(to_dev(Xo), to_dev(Xv), to_dev(Z), to_dev(eo), to_dev(ev), ts, w,
+                             [to_dev(f) for f in F], None if lam_h is None else to_dev(lam_h),
+                             E=[[to_dev(f) for f in e] for e in E],
+                             lam_e=None if lam_e is None else [None if x is None else to_dev(x) for x in lam_e])
+    torch.cuda.synchronize()
+    return k1.cpu().numpy(), k2.cpu().numpy(), float(ek.cpu().numpy()[0])
+
+
+def _check_pp(Xo, Xv, Z, eo, ev, F, lam_h, ts, w, E, lam_e, label):
+    say(f"[exchange] {label}: per-point CPDs, o={Xo.shape[0]} v={Xv.shape[0]} r_cp={F[0].shape[1]} points={len(ts)}")
+    g1, g2, ge = _run_pp(Xo, Xv, Z, eo, ev, F, lam_h, ts, w, E, lam_e)
+    lam_e_h = None if lam_e is None else [np.ones(F[0].shape[1]) if x is None else x for x in lam_e]
+    r1, r2 = exchange.exchange_terms(Xo, Xv, Z, F, lam_h, eo, ev, ts, E=E, lam_e=lam_e_h)
+    a1, a2 = exchange.exchange_terms(Xo, Xv, Z, F, lam_h, eo, ev, ts, E=E, lam_e=lam_e_h, absolute=True)
+    re = exchange.robust_exchange(r1, r2, w)
+    ae = float(np.sum(np.abs(w) * (2.0 * a1 + a2)))
+    e1, e2 = np.abs(g1 - r1) / a1, np.abs(g2 - r2) / a2
+    say(f"[exchange] {label}: max err/bound single {e1.max():.2e} double {e2.max():.2e} "
+        f"robust {abs(ge - re) / ae:.2e}")
+    assert np.all(e1 <= TOL) and np.all(e2 <= TOL)
+    assert abs(ge - re) <= TOL * ae
+    return g1, g2, ge
+
+
+def test_exchange_per_point_cpds_random():
+    # separate random CPDs per point, ragged sizes, one weight vector missing
+    Xo, Xv, Z, eo, ev, F, lam_h = _case(6, 14, 4, 40, 13)
+    ts, w = lt_quadrature(3, 0.05, 4.0)
+    rng = np.random.default_rng(99)
+    E = [[rng.standard_normal((n, 40)) for n in (6, 14, 6, 14)] for _ in ts]
+    lam_e = [rng.uniform(0.5, 2.0, 40), None, rng.uniform(0.5, 2.0, 40)]
+    _check_pp(Xo, Xv, Z, eo, ev, F, lam_h, ts, w, E, lam_e, "random per-point")
+
+
+def test_exchange_per_point_scaled_cpd_matches_default():
+    # the LT-scaled bare CPD passed explicitly gives the default path's result
+    Xo, Xv, Z, eo, ev, F, lam_h = _case(16, 32, 4, 96, 14)
+    ts, w = lt_quadrature(4)
+    E = [[np.exp(s * e * t)[:, None] * f for f, e, s in zip(F, (eo, ev, eo, ev), (1, -1, 1, -1))] for t in ts]
+    d1, d2, de = _run(Xo, Xv, Z, eo, ev, F, lam_h, ts, w)
+    p1, p2, pe = _run_pp(Xo, Xv, Z, eo, ev, F, lam_h, ts, w, E, [lam_h] * len(ts))
+    assert np.array_equal(d1, p1)
+    a1, a2 = exchange.exchange_terms(Xo, Xv, Z, F, lam_h, eo, ev, ts, absolute=True)
+    assert np.all(np.abs(p2 - d2) <= TOL * a2)
+    assert abs(pe - de) <= TOL * float(np.sum(np.abs(w) * (2.0 * a1 + a2)))
+
+
+def test_exchange_consumes_batched_cpds():
+    """The batched per-point CPDs of the library (one per Laplace point, of
+    the scaled tensors) and a CPD of the bare tensor (t = 0) feed the
+    exchange energy; parity with the oracle on the same factors."""
+    from paper_2502_17683_amd import CPDBatch, lt_batch_problems
+    o, v = 6, 18
+    system = make_lt_system(o, v, 15)
+    ts, w = lt_quadrature(4, 0.05, 8.0)
+    problems, _ = lt_batch_problems([system], [0.0] + list(ts),
+                                    init_fn=lambda dims, r, idx: init_factors(dims, r, 3000 + idx))
+    b = CPDBatch(problems, precision="fp64", tol=0.0, fit_floor=0.0)
+    b.sweep(20)
+    facs = [b.factors(i) for i in range(len(problems))]
+    b.close()
+    F = [f.cpu().numpy() for f in facs[0][0]]
+    lam_h = facs[0][1].cpu().numpy()
+    E = [[f.cpu().numpy() for f in fk] for fk, _ in facs[1:]]
+    lam_e = [lk.cpu().numpy() for _, lk in facs[1:]]
+    Xo, Xv, Z, eo, ev = system
+    _check_pp(Xo, Xv, Z, eo, ev, F, lam_h, ts, w, E, lam_e, "batched CPDs")
