@@ -222,6 +222,28 @@ def test_zero_column_fallback_matches_oracle():
     assert e.value.code == -3
 
 
+@pytest.mark.parametrize("where", ["X", "Z"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_nonfinite_input_is_reported(where, precision):
+    """A NaN in X or an Inf in Z makes ||G||^2 non-finite: the plan is
+    flagged at init, its sweeps do nothing, and the first synchronising
+    call reports CPD_ERR_NONFINITE."""
+    from paper_2502_17683_amd import CPD, CpdError
+    X, Z = make_thc(20, 80, 7)
+    init = init_factors([20] * 4, 60, 1007)
+    if where == "X":
+        X = X.copy()
+        X[3, 5] = np.nan
+    else:
+        Z = Z.copy()
+        Z[10, 10] = np.inf
+    c = CPD(X, Z, 60, init, precision=precision, tol=0.0, fit_floor=0.0)
+    with pytest.raises(CpdError) as e:
+        c.sweep(2)
+    assert e.value.code == -4
+    c.close()
+
+
 def test_workspace_too_small_is_rejected():
     from paper_2502_17683_amd import _lib
     lib = _lib.load()
