@@ -2,7 +2,7 @@
 
 Workload (default): the mixed-precision configuration -- THC input with
 N = 800 orbitals, R_thc = 4000, R_cp = 4000, from the seeded generator
-(synthetic stand-in for the paper's water clusters; see DESIGN.md).
+(synthetic stand-in for the paper's water clusters).
 
 Protocol
   1. Reference (untimed): plain FP64 CP-ALS for --ref-sweeps sweeps with the
@@ -118,8 +118,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how it would shard).", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path "
+              "(the design notes describe how it would shard).", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration_mib > 0:
         import torch

@@ -52,7 +52,7 @@ enum {
                                damped retry, if enabled)                      */
   CPD_ERR_NONFINITE = -4,   /* NaN/Inf reached the fit or ||G||^2 <= 0        */
   CPD_ERR_WORKSPACE = -5,   /* workspace missing or smaller than required     */
-  CPD_ERR_UNSUPPORTED = -6  /* option not available in this build             */
+  CPD_ERR_UNSUPPORTED = -6  /* option the library does not support           */
 };
 
 typedef enum {

@@ -11,7 +11,7 @@ def need_gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2502_17683_amd import _lib
-    _lib.load()  # a GPU box without the built library must fail loudly
+    _lib.load()  # a GPU machine without the built library must fail loudly
 
 
 def say(msg):
