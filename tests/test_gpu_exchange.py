@@ -196,3 +196,21 @@ def test_exchange_consumes_batched_cpds():
     lam_e = [lk.cpu().numpy() for _, lk in facs[1:]]
     Xo, Xv, Z, eo, ev = system
     _check_pp(Xo, Xv, Z, eo, ev, F, lam_h, ts, w, E, lam_e, "batched CPDs")
+
+
+@pytest.mark.parametrize("o,v,r_thc,r_cp", [(1, 1, 1, 1), (1, 3, 2, 1), (2, 1, 3, 2)])
+def test_exchange_degenerate_sizes(o, v, r_thc, r_cp):
+    # one orbital of a kind, rank one: every product is a single tile with a
+    # ragged edge, every reduction a single partial
+    rng = np.random.default_rng(100 + o + 3 * v + 7 * r_thc)
+    Xo, Xv = rng.uniform(0.1, 1.0, (o, r_thc)), rng.uniform(0.1, 1.0, (v, r_thc))
+    Z = rng.standard_normal((r_thc, r_thc))
+    eo, ev = np.sort(rng.uniform(-1.5, -0.3, o)), np.sort(rng.uniform(0.1, 3.0, v))
+    F = [rng.standard_normal((n, r_cp)) for n in (o, v, o, v)]
+    _check(Xo, Xv, Z, eo, ev, F, rng.uniform(0.5, 2.0, r_cp), [0.4], [1.0], f"degenerate {o},{v},{r_thc},{r_cp}")
+
+
+def test_exchange_zero_weights_give_zero_energy():
+    ts = [0.1, 1.0]
+    g1, g2, ge = _run(*_case(4, 8, 4, 24, 21), ts, [0.0, 0.0])
+    assert ge == 0.0 and np.all(np.isfinite(g1)) and np.all(np.isfinite(g2))

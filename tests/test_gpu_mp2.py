@@ -111,3 +111,12 @@ def test_mp2_is_deterministic():
     a = _run(*args, ts, w)
     b = _run(*args, ts, w)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("o,v,r_thc", [(1, 1, 1), (1, 3, 2), (2, 1, 3)])
+def test_mp2_degenerate_sizes(o, v, r_thc):
+    rng = np.random.default_rng(200 + o + 3 * v + 7 * r_thc)
+    Xo, Xv = rng.uniform(0.1, 1.0, (o, r_thc)), rng.uniform(0.1, 1.0, (v, r_thc))
+    Z = rng.standard_normal((r_thc, r_thc))
+    eo, ev = np.sort(rng.uniform(-1.5, -0.3, o)), np.sort(rng.uniform(0.1, 3.0, v))
+    _check(Xo, Xv, Z, eo, ev, [0.4], [1.0], f"degenerate {o},{v},{r_thc}")
