@@ -264,13 +264,15 @@ cpd_status cpd_lt_exchange(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t
  * J costs O(n_points r_thc^3) through the grid overlaps and two (one with
  * z_symmetric = 1) wide products with Z.  K (thc_exchange = 1) forms the
  * (o v) x (o v) matrix (ia|jb) from the THC factors: O(o^2 v^2 r_thc) flops
- * and 16 (o v)^2 bytes of workspace, the cost the robust CPD+THC exchange
+ * and up to 16 (o v)^2 bytes of workspace, the cost the robust CPD+THC exchange
  * (cpd_lt_exchange) avoids.  The CPD+THC energy is E_J + cpd_lt_exchange's
  * e_k.
  *   X_occ, X_virt, Z, eps_occ, eps_virt: DEVICE, as for cpd_lt_exchange.
  *   z_symmetric = 1 asserts Z = Z^T (true of a THC core of the symmetric
- *   (ia|jb)); the Coulomb term then needs one product instead of two.  A
- *   non-symmetric Z with z_symmetric = 1 gives a wrong J.
+ *   (ia|jb)); the Coulomb term then needs one product instead of two, and
+ *   the exchange term forms only the blocks i >= j of (ia|jb) (about half
+ *   the flops).  A non-symmetric Z with z_symmetric = 1 gives wrong
+ *   results.
  *   t_host, w_host: HOST, n_points finite values.
  *   J, K (n_points each; K may be NULL when thc_exchange = 0), energies (3):
  *   DEVICE outputs.  1 <= n_points <= CPD_LT_MAX_POINTS; with thc_exchange,

@@ -299,7 +299,8 @@ bool exchange_sizes_ok(int o, int v, int Rt, int R, int n) {
 // with A = Z M and B = Z^T M (B = A for a symmetric Z): one or two wide
 // products over all points, then a transposed dot per point.
 //
-// Exchange: the (ia|jb) matrix G = Bp Z Bp^T with Bp[(i,a), P] =
+// Exchange (for a symmetric Z only the blocks i >= j, see below): the
+// (ia|jb) matrix G = Bp Z Bp^T with Bp[(i,a), P] =
 // X_o[i,P] X_v[a,P] ((o v) x (o v), o^2 v^2 R_thc flops: the THC exchange
 // costs a power of N more than the Coulomb term), the swapped product
 // Pm[(i,a),(j,b)] = G[(i,a),(j,b)] G[(i,b),(j,a)], the virtual Laplace
@@ -386,6 +387,43 @@ __global__ __launch_bounds__(256) void swap_product_kernel(const double* G, int 
   }
 }
 
+// Symmetric Z: (ia|jb) = (jb|ia), and both factors of a swapped product
+// lie in the same block (i, j), whose contribution equals that of (j, i).
+// Only the blocks i >= j are formed, and pair p = i (i + 1) / 2 + j is
+// stored compactly: Pc[(p v + a), b] = G[(i,a),(j,b)] G[(i,b),(j,a)].
+__device__ __forceinline__ void pair_decode(int p, int& i, int& j) {
+  i = (int)((sqrtf(8.f * (float)p + 1.f) - 1.f) * 0.5f);
+  while ((i + 1) * (i + 2) / 2 <= p) ++i;
+  while (i * (i + 1) / 2 > p) --i;
+  j = p - i * (i + 1) / 2;
+}
+// grid npairs nv^2 (flat); block = (pair, tile row, tile col).
+__global__ __launch_bounds__(256) void swap_product_lower_kernel(const double* G, int o, int v, double* Pc) {
+  __shared__ double tt[kTile][kTile + 1];
+  const int nv = (v + kTile - 1) / kTile;
+  const int tile = blockIdx.x % (nv * nv), pair = blockIdx.x / (nv * nv);
+  const int ta = tile / nv, tb = tile % nv;
+  int i, j;
+  pair_decode(pair, i, j);
+  const size_t ld = (size_t)o * v;
+  const size_t base = (size_t)i * v * ld + (size_t)j * v;  // block (i, j)
+  const size_t obase = (size_t)pair * v * v;
+  auto g = as_global(G);
+  auto out = as_global(Pc);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kTile * kTile; e += 256) {
+    const int al = e & (kTile - 1), bl = e >> 6;
+    const int a = ta * kTile + al, b = tb * kTile + bl;
+    tt[bl][al] = (a < v && b < v) ? g[base + (size_t)b * ld + a] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < kTile * kTile; e += 256) {
+    const int bl = e & (kTile - 1), al = e >> 6;
+    const int a = ta * kTile + al, b = tb * kTile + bl;
+    if (a < v && b < v) out[obase + (size_t)a * v + b] = g[base + (size_t)a * ld + b] * tt[bl][al];
+  }
+}
+
 // U^T[k, b] = exp(-eps_b t_k)  (n x v)
 __global__ __launch_bounds__(256) void virt_factor_kernel(const double* eps_v, int v, LtQuad q, double* Ut) {
   const int total = q.n * v;
@@ -416,6 +454,38 @@ __global__ __launch_bounds__(256) void occ_weight_dot_kernel(const double* Ht, c
     const size_t ia = r / o;
     const int a = (int)(ia % v), i = (int)(ia / v);
     acc += exp((eo[i] + eo[j] - ev[a]) * tk) * h[(size_t)k * rows + r];
+  }
+  part[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) part[tid] += part[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) as_global(partials)[(size_t)k * gridDim.x + c] = part[0];
+}
+
+// Compact lower-block rows r = p v + a (pair p = (i, j), i >= j):
+// partials[k * chunks + c] = sum over the chunk of
+// m_ij exp((eps_i + eps_j - eps_a) t_k) Ht[k, r], m_ij = 1 (i = j) or 2.
+__global__ __launch_bounds__(256) void occ_weight_dot_lower_kernel(const double* Ht, const double* eps_o,
+                                                                   const double* eps_v, int o, int v, LtQuad q,
+                                                                   double* partials) {
+  __shared__ double part[256];
+  const int c = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
+  const size_t rows = (size_t)o * (o + 1) / 2 * v;
+  const size_t r0 = (size_t)c * kRowsPerBlock;
+  const size_t r1 = r0 + kRowsPerBlock < rows ? r0 + kRowsPerBlock : rows;
+  const double tk = q.t[k];
+  auto h = as_global(Ht);
+  auto eo = as_global(eps_o);
+  auto ev = as_global(eps_v);
+  double acc = 0.0;
+  for (size_t r = r0 + tid; r < r1; r += 256) {
+    const int p = (int)(r / v), a = (int)(r - (size_t)p * v);
+    int i, j;
+    pair_decode(p, i, j);
+    const double m = i == j ? 1.0 : 2.0;
+    acc += m * exp((eo[i] + eo[j] - ev[a]) * tk) * h[(size_t)k * rows + r];
   }
   part[tid] = acc;
   __syncthreads();
@@ -488,11 +558,12 @@ Mp2Layout mp2_layout(int o, int v, int Rt, int n, bool with_k, bool z_sym) {
   l.jtiles = nt * nt;
   l.pj = take((size_t)n * l.jtiles * d);
   if (with_k) {
-    const size_t ov = (size_t)o * v, rows = ov * o;
+    // symmetric Z: the lower block triangle, pairs stored compactly
+    const size_t ov = (size_t)o * v, rows = z_sym ? (size_t)o * (o + 1) / 2 * v : ov * o;
     l.bp = take(ov * Rt * d);
     l.c1 = take(ov * Rt * d);
     l.g = take(ov * ov * d);
-    l.pm = take(ov * ov * d);
+    l.pm = take(rows * v * d);
     l.ut = take((size_t)n * v * d);
     l.ht = take((size_t)n * rows * d);
     l.kchunks = (int)((rows + kRowsPerBlock - 1) / kRowsPerBlock);
@@ -697,20 +768,42 @@ cpd_status cpd_lt_mp2(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t n_po
       if (grid > 8192) grid = 8192;
       hipLaunchKernelGGL(pair_rows_kernel, dim3(grid), dim3(256), 0, s, X_occ, X_virt, o, v, Rt, buf(l.bp));
     }
-    gemm(ov, Rt, Rt, buf(l.bp), Rt, false, Z, Rt, false, buf(l.c1), Rt);    // C1 = Bp Z
-    gemm(ov, ov, Rt, buf(l.c1), Rt, false, buf(l.bp), Rt, true, buf(l.g), ov);  // G = C1 Bp^T
-    {
-      const int nv = (v + kTile - 1) / kTile;
+    gemm(ov, Rt, Rt, buf(l.bp), Rt, false, Z, Rt, false, buf(l.c1), Rt);  // C1 = Bp Z
+    const int nv = (v + kTile - 1) / kTile;
+    int rows;
+    if (z_sym) {
+      // the block rows in at most 8 panels, each up to its last diagonal
+      // block (blocks above the diagonal inside a panel are formed and not
+      // read): about (P + 1) / (2 P) of the full product in P launches.
+      // Below o v = 4096 one full product is faster than several small
+      // ones (0.23 vs 0.76 ms for the whole exchange term at o v = 2000).
+      const int P = ov < 4096 ? 1 : (o < 8 ? o : 8);
+      for (int pn = 0; pn < P; ++pn) {
+        const int i0 = pn * o / P, i1 = (pn + 1) * o / P;
+        if (i1 <= i0) continue;
+        gemm((i1 - i0) * v, i1 * v, Rt, buf(l.c1) + (size_t)i0 * v * Rt, Rt, false, buf(l.bp), Rt, true,
+             buf(l.g) + (size_t)i0 * v * ov, ov);
+      }
+      const int npairs = o * (o + 1) / 2;
+      hipLaunchKernelGGL(swap_product_lower_kernel, dim3(nv * nv * npairs), dim3(256), 0, s, buf(l.g), o, v,
+                         buf(l.pm));
+      rows = npairs * v;
+    } else {
+      gemm(ov, ov, Rt, buf(l.c1), Rt, false, buf(l.bp), Rt, true, buf(l.g), ov);  // G = C1 Bp^T
       hipLaunchKernelGGL(swap_product_kernel, dim3(nv * nv * o * o), dim3(256), 0, s, buf(l.g), o, v, buf(l.pm));
+      rows = ov * o;
     }
     {
       int grid = (n_points * v + 255) / 256;
       hipLaunchKernelGGL(virt_factor_kernel, dim3(grid), dim3(256), 0, s, eps_virt, v, q, buf(l.ut));
     }
-    const int rows = ov * o;
     gemm(n_points, rows, v, buf(l.ut), v, false, buf(l.pm), v, true, buf(l.ht), rows);  // H^T = U^T Pm^T
-    hipLaunchKernelGGL(occ_weight_dot_kernel, dim3(l.kchunks, n_points), dim3(256), 0, s, buf(l.ht), eps_occ,
-                       eps_virt, o, v, q, buf(l.pk));
+    if (z_sym)
+      hipLaunchKernelGGL(occ_weight_dot_lower_kernel, dim3(l.kchunks, n_points), dim3(256), 0, s, buf(l.ht),
+                         eps_occ, eps_virt, o, v, q, buf(l.pk));
+    else
+      hipLaunchKernelGGL(occ_weight_dot_kernel, dim3(l.kchunks, n_points), dim3(256), 0, s, buf(l.ht), eps_occ,
+                         eps_virt, o, v, q, buf(l.pk));
   }
   hipLaunchKernelGGL(mp2_finish_kernel, dim3(1), dim3(64 * kFinishWaves), 0, s, buf(l.pj), l.jtiles,
                      with_k ? buf(l.pk) : buf(l.pj), with_k ? l.kchunks : 0, q, J, with_k ? K : nullptr,

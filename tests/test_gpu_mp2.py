@@ -120,3 +120,10 @@ def test_mp2_degenerate_sizes(o, v, r_thc):
     Z = rng.standard_normal((r_thc, r_thc))
     eo, ev = np.sort(rng.uniform(-1.5, -0.3, o)), np.sort(rng.uniform(0.1, 3.0, v))
     _check(Xo, Xv, Z, eo, ev, [0.4], [1.0], f"degenerate {o},{v},{r_thc}")
+
+
+def test_mp2_symmetric_uneven_panels():
+    # o v = 4200 >= 4096: the symmetric exchange forms (ia|jb) in 8 row panels,
+    # 21 block rows split unevenly (2 or 3 per panel)
+    ts, w = lt_quadrature(4)
+    _check(*make_lt_system(21, 200, 9, rank_factor=2), ts, w, "uneven panels", z_symmetric=True)
