@@ -299,17 +299,24 @@ def bench_lt(args):
             log(f"[bench-lt] batched {prec}: {e}")
             continue
         torch.cuda.synchronize()
+        # asynchronous sweeps (one graph launch each, the damped retry inside
+        # the graph), then the default synchronised ones (the fused solve,
+        # a host check per sweep, replay on a failed pivot)
         t0 = time.perf_counter()
         b.sweep(K, sync=False)
         torch.cuda.synchronize()
+        ms_async = (time.perf_counter() - t0) * 1e3 / K
+        t0 = time.perf_counter()
+        b.sweep(K)
+        torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / K
-        res[prec] = {"ms_per_batched_sweep": ms, "sweeps_per_s": 1e3 / ms,
+        res[prec] = {"ms_per_batched_sweep": ms, "ms_per_batched_sweep_async": ms_async, "sweeps_per_s": 1e3 / ms,
                      "useful_tflops": useful / (ms * 1e-3) / 1e12}
         if prec == "mixed":
             res[prec]["autotune"] = b.autotune_log()
             res[prec]["promoted_to_fp64"] = sum(b.stats(i)["fp64_path"] for i in range(len(problems)))
         b.close()
-        log(f"[bench-lt] batched {prec}: {ms:.3f} ms/sweep")
+        log(f"[bench-lt] batched {prec}: {ms:.3f} ms/sweep (asynchronous sweeps {ms_async:.3f})")
     # the same 48 CPDs one after another (one plan each, graph-replayed sweeps)
     for prec in ("mixed", "fp64"):
         plans = [CPD(p["X"], p["Z"], p["r_cp"], p["init"], precision=prec, tol=0.0, fit_floor=0.0,
