@@ -95,6 +95,36 @@ class CPD:
         check(self.lib.cpd_sweep(self.plan, int(n), fits, ctypes.byref(ran)), "cpd_sweep")
         return list(fits[: ran.value])
 
+    def run_logged(self, max_sweeps, path):
+        """Run up to max_sweeps sweeps one at a time (each synchronised) and
+        append one JSON line per sweep to `path`: sweep, fit (null where it
+        was not evaluated), relative fit change, wall time of the sweep,
+        damped-retry count, condition estimate of the last normal matrix,
+        whether the problem runs on the FP64 products.  Stops at
+        convergence.  Returns the list of fits."""
+        import json
+        import time
+        fits, prev = [], None
+        with open(path, "a") as out:
+            for _ in range(int(max_sweeps)):
+                t0 = time.perf_counter()
+                got = self.sweep(1)
+                dt = (time.perf_counter() - t0) * 1e3
+                if not got:
+                    break
+                st = self.stats()
+                f = got[0] if got[0] >= 0 else None
+                rel = (abs(f - prev) / prev) if (f is not None and prev) else None
+                out.write(json.dumps({"sweep": int(st["sweeps"]), "fit": f, "dfit_rel": rel, "t_sweep_ms": dt,
+                                      "chol_fallbacks": int(st["fallbacks"]), "condV_est": float(st["cond_est"]),
+                                      "fp64_path": int(st["fp64_path"])}) + "\n")
+                fits.append(got[0])
+                if f is not None:
+                    prev = f
+                if st["converged"]:
+                    break
+        return fits
+
     def fit(self):
         f = ctypes.c_double()
         check(self.lib.cpd_fit(self.plan, ctypes.byref(f)), "cpd_fit")

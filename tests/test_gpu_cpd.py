@@ -293,3 +293,23 @@ def test_async_fallback_matches_replay():
     b.sweep(4, sync=False)
     assert b.fit() == fa[-1]
     assert a.stats()["fallbacks"] == b.stats()["fallbacks"] > 0
+
+
+def test_run_logged_writes_one_line_per_sweep(tmp_path):
+    """The per-sweep JSONL log follows the same trajectory as plain sweeps."""
+    import json
+    X, Z = make_thc(20, 80, 0)
+    init = init_factors([20] * 4, 60, 1000)
+    a = _plan(X, Z, init, 60, tol=0.0)
+    ref = a.sweep(6)
+    a.close()
+    b = _plan(X, Z, init, 60, tol=0.0)
+    path = tmp_path / "sweeps.jsonl"
+    fits = b.run_logged(6, str(path))
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert fits == ref and len(lines) == 6
+    assert [d["sweep"] for d in lines] == list(range(1, 7))
+    assert [d["fit"] for d in lines] == ref
+    assert lines[0]["dfit_rel"] is None and lines[1]["dfit_rel"] == abs(ref[1] - ref[0]) / ref[0]
+    assert all(d["t_sweep_ms"] > 0 and d["chol_fallbacks"] == 0 for d in lines)
+    b.close()
