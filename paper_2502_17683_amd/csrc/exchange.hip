@@ -678,9 +678,8 @@ cpd_status cpd_lt_exchange(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t
       }
       g.lam = lam_e_host ? lam_e_host[k] : nullptr;
       g.lam_out = buf(l.lame);
-      const int most = (o > v ? o : v) * R;
-      int grid = (most + 255) / 256;
-      if (grid > 1024) grid = 1024;
+      const size_t most = (size_t)(o > v ? o : v) * R;
+      int grid = (int)((most + 255) / 256 < 1024 ? (most + 255) / 256 : 1024);
       hipLaunchKernelGGL(gather_point_kernel, dim3(grid, 5), dim3(256), 0, s, g, k, R, (size_t)L);
     }
     const double* partner[4] = {F0, F3, F2, F1};
