@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--init", choices=("normal", "uniform"), default="normal",
+                    help="initial factors: N(0,1)/sqrt(n) (default) or the paper's U[-1,1]")
     ap.add_argument("--workload", choices=("mixed", "lt", "warmstart", "exchange"), default="mixed",
                     help="mixed: the headline time-to-fit line (default); lt: the batched "
                          "Laplace-transform CPDs; warmstart: train and evaluate the learned warm start; "
@@ -139,13 +141,13 @@ def main():
 
     import torch
     from paper_2502_17683_amd import CPD
-    from synth import make_thc, init_factors
+    from synth import make_thc, init_factors, init_factors_uniform
 
     N, Rt, Rc = args.n, args.r_thc, args.r_cp
     dev = torch.device("cuda:0")
     log(f"[bench] generating THC input N={N} R_thc={Rt} R_cp={Rc} seed={args.seed}")
     X, Z = make_thc(N, Rt, args.seed)
-    init = init_factors([N] * 4, Rc, args.seed + 1000)
+    init = (init_factors_uniform if args.init == "uniform" else init_factors)([N] * 4, Rc, args.seed + 1000)
     Xd = torch.as_tensor(X, device=dev)
     Zd = torch.as_tensor(Z, device=dev)
     Id = [torch.as_tensor(f, device=dev) for f in init]
@@ -238,7 +240,7 @@ def main():
         "config": {"workload": f"mixed-precision THC CP-ALS, N={N}, R_thc={Rt}, R_cp={Rc}, "
                                f"seed {args.seed}, target fit = FP64 best over "
                                f"{args.ref_sweeps} sweeps x (1+1e-4)",
-                   "n": N, "r_thc": Rt, "r_cp": Rc, "fit_every": args.fit_every},
+                   "n": N, "r_thc": Rt, "r_cp": Rc, "fit_every": args.fit_every, "init": args.init},
         "fp64_time_to_fit_s": t64,
         "speedup_vs_fp64": t64 / value if value > 0 else None,
         "sweeps_to_fit": {"mixed": sweeps_m, "fp64": s64},
