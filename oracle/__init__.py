@@ -19,6 +19,8 @@ Modules
   exchange Robust CPD+THC LT-MP2 exchange energy (single- and double-CPD
            terms, eq. rob_K).
   mp2      THC LT-MP2 Coulomb and exchange terms and the LT-MP2 energy.
+  tied     Particle-tied CP-ALS (eq. cp4's one factor per particle) by
+           symmetric ALS.
 
 Pins: every function is checked by ``tests/test_oracle_*.py`` against
 brute-force loops, closed forms, planted decompositions, special cases and
