@@ -99,6 +99,14 @@ typedef struct {
   void* stream;           /* hipStream_t the work is ordered on (0 = null stream) */
   void* workspace;        /* DEVICE memory owned by the caller                    */
   size_t workspace_bytes;
+  int32_t tied;           /* 1: particle-tied model (eq. cp4: one factor for both
+                             indices of a particle), F1 = F0 and F3 = F2, fitted by
+                             symmetric ALS: each sweep updates modes 0 and 2 by
+                             their normal equations with the tied copy held, then
+                             copies them to modes 1 and 3.  Needs n[1] = n[0] and
+                             n[3] = n[2]; init[1] and init[3] are not read.
+                             FP64 and FP32 only (split BF16: UNSUPPORTED).  Every
+                             problem of a batch must agree.  0: four factors  */
 } cpd_desc;
 
 typedef struct {

@@ -39,6 +39,7 @@ class CpdDesc(ctypes.Structure):
         ("stream", vp),
         ("workspace", vp),
         ("workspace_bytes", ctypes.c_size_t),
+        ("tied", i32),
     ]
 
 

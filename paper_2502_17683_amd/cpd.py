@@ -35,7 +35,9 @@ class CPD:
 
     def __init__(self, X, Z, r_cp, init, precision="fp64", tol=1e-4, fit_floor=1e-7,
                  chol_fallback=True, use_graph=True, fit_every=1, autotune=False, solve_panel=0,
-                 device="cuda"):
+                 device="cuda", tied=False):
+        """tied: the particle-tied model F1 = F0, F3 = F2 (symmetric ALS;
+        FP64/FP32 only; init[1] and init[3] are not used)."""
         self.lib = _lib.load()
         self.device = torch.device(device)
         if not isinstance(X, (list, tuple)):
@@ -68,6 +70,7 @@ class CPD:
         d.fit_every = int(fit_every)
         d.autotune = int(bool(autotune))
         d.solve_panel = int(solve_panel)
+        d.tied = int(bool(tied))
         d.stream = _stream(self.device).value
         need = self.lib.cpd_workspace_size(ctypes.byref(d))
         if need == 0:

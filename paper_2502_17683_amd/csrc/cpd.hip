@@ -133,6 +133,10 @@ struct cpd_plan_s {
   std::vector<int32_t> forced;                  // host copy (sticky)
   double cond_limit = 1e5;
   int panel_width = 0;                          // blocks per solve panel; 0: one level
+  int tied = 0;                                 // particle-tied model (F1 = F0, F3 = F2)
+  bool tie_alias = true;                        // every problem has X1 = X0 and X3 = X2
+  void* tie[2] = {nullptr, nullptr};            // CkptArgs: F, G (and W when aliased) n -> n + 1
+  void* tinner = nullptr;                       // NormArgs: tied <G, G~> partials
   StepOps steps[4];
   void* formv[4] = {nullptr, nullptr, nullptr, nullptr};
   void* norm[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -492,6 +496,35 @@ void build_typed(TableBuilder& tb, cpd_plan_s* p, Bufs<T> Prob::*bufs, bool gate
   p->fit = tb.put(ft);
   p->ckpt = tb.put(ck);
   p->cond = tb.put(cd);
+  if (p->tied) {
+    // the tied copies after the updates of modes 0 and 2, and the <G, G~>
+    // partials from the mode-3 MTTKRP of the tied factors
+    std::vector<NormArgs<T>> ti;
+    for (int h = 0; h < 2; ++h) {
+      const int n = 2 * h;
+      std::vector<CkptArgs> tc;
+      for (int i = 0; i < np; ++i) {
+        Prob& q = p->P[i];
+        Bufs<T>& b = q.*bufs;
+        CkptArgs c{};
+        c.a[0] = b.F[n];
+        c.b[0] = b.F[n + 1];
+        c.bytes[0] = sizeof(T) * (size_t)q.n[n] * q.Tp;
+        c.a[1] = b.G[n];
+        c.b[1] = b.G[n + 1];
+        c.bytes[1] = sizeof(T) * (size_t)q.Tp * q.Tp;
+        if (p->tie_alias) {
+          c.a[2] = b.W[n];
+          c.b[2] = b.W[n + 1];
+          c.bytes[2] = sizeof(T) * (size_t)q.Rt * q.Tp;
+        }
+        tc.push_back(c);
+        if (h == 1) ti.push_back({b.F[3], nullptr, b.lam, b.Msave, q.inner_part, q.st, q.n[3], q.Rc, q.Tp});
+      }
+      p->tie[h] = tb.put(tc);
+    }
+    p->tinner = tb.put(ti);
+  }
 }
 
 void build_mixed(TableBuilder& tb, cpd_plan_s* p) {
@@ -590,6 +623,16 @@ int init_shape(cpd_plan_s* p, const cpd_desc* descs, int count) {
     fill_prob(p->P[i], &descs[i]);
   }
   p->prec = descs[0].precision;
+  p->tied = descs[0].tied != 0;
+  p->tie_alias = true;
+  for (int i = 0; i < count; ++i) {
+    if ((descs[i].tied != 0) != (p->tied != 0)) return CPD_ERR_INVALID_ARG;
+    if (p->tied) {
+      if (descs[i].n[1] != descs[i].n[0] || descs[i].n[3] != descs[i].n[2]) return CPD_ERR_INVALID_ARG;
+      if (descs[i].X[1] != descs[i].X[0] || descs[i].X[3] != descs[i].X[2]) p->tie_alias = false;
+    }
+  }
+  if (p->tied && p->prec == CPD_MIXED_BF16) return CPD_ERR_UNSUPPORTED;
   p->fit_every = descs[0].fit_every > 0 ? descs[0].fit_every : 1;
   p->allow_fallback = descs[0].chol_fallback;
   p->use_graph = descs[0].use_graph;
@@ -697,8 +740,33 @@ void solve_mode(cpd_plan_s* p, int n, hipStream_t s, bool with_inner, bool fast)
   normalise_group<T>(s, (const NormArgs<T>*)(with_inner ? p->norm_inner : p->norm[n]), p->count, p->maxR);
 }
 
+// Particle-tied sweep (symmetric ALS): modes 0 and 2 are updated, each
+// followed by its copy to the tied mode (factor, Gram, and the projection
+// by copy when the two modes share X, else by product); <G, G~> comes from
+// the mode-3 MTTKRP of the tied factors, X3 (W2 o Y'), with Y' of mode 2.
+template <typename T>
+void enqueue_sweep_tied(cpd_plan_s* p, hipStream_t s, bool fast) {
+  if (fast) checkpoint_group(s, (const CkptArgs*)p->ckpt, p->count, 0);
+  for (int n = 0; n < 4; n += 2) {
+    run_gemm<T>(p, s, p->core[n]);
+    run_gemm<T>(p, s, p->back[n]);
+    solve_mode<T>(p, n, s, false, fast);
+    run_gemm<T>(p, s, p->gram[n]);
+    run_gemm<T>(p, s, p->proj[n]);
+    checkpoint_group(s, (const CkptArgs*)p->tie[n / 2], p->count, 0);
+    if (!p->tie_alias) run_gemm<T>(p, s, p->proj[n + 1]);
+  }
+  run_gemm<T>(p, s, p->back[3]);
+  tied_inner_group<T>(s, (const NormArgs<T>*)p->tinner, p->count, p->maxR);
+  fit_group<T>(s, (const FitArgs<T>*)p->fit, p->count, p->maxR, HIST_CAP, p->tol, p->fit_floor, 0, 0.0);
+}
+
 template <typename T>
 void enqueue_sweep_typed(cpd_plan_s* p, hipStream_t s, bool fast) {
+  if (p->tied) {
+    enqueue_sweep_tied<T>(p, s, fast);
+    return;
+  }
   if (fast) checkpoint_group(s, (const CkptArgs*)p->ckpt, p->count, 0);
   for (int n = 0; n < 4; ++n) {
     if (n == 0 || n == 2) run_gemm<T>(p, s, p->core[n]);
@@ -1041,12 +1109,14 @@ int plan_create(const cpd_desc* descs, int count, void* workspace, size_t ws_byt
       }
       cast_f64_to_f32(s, q.d.Z, (float*)q.b32.Z, (size_t)q.Rt * q.Rt);
       for (int m = 0; m < 4; ++m) {
-        copy_normalised_init(s, q.d.init[m], q.n[m], q.Rc, q.Tp, q.scratch64);
+        // (tied: modes 1 and 3 start as copies of modes 0 and 2)
+        copy_normalised_init(s, q.d.init[p->tied ? m & 2 : m], q.n[m], q.Rc, q.Tp, q.scratch64);
         cast_f64_to_f32(s, q.scratch64, q.b32.F[m], (size_t)q.n[m] * q.Tp);
       }
     } else {
       if (p->prec == CPD_MIXED_BF16) split_inputs(q, s, split_done);
-      for (int m = 0; m < 4; ++m) copy_normalised_init(s, q.d.init[m], q.n[m], q.Rc, q.Tp, q.b64.F[m]);
+      for (int m = 0; m < 4; ++m)
+        copy_normalised_init(s, q.d.init[p->tied ? m & 2 : m], q.n[m], q.Rc, q.Tp, q.b64.F[m]);
     }
     state_reset(s, q.st, q.norm2);
   }

@@ -170,6 +170,10 @@ struct NormArgs {
 };
 template <typename T>
 void normalise_group(hipStream_t s, const NormArgs<T>* tab, int nprob, int max_R);
+// Tied model: <G, G~> partials lam[k] sum_s F3[s,k] M3[s,k] (F3 passed as
+// Msol, M3 as Msave; F unused).
+template <typename T>
+void tied_inner_group(hipStream_t s, const NormArgs<T>* tab, int nprob, int max_R);
 
 template <typename T>
 struct FitArgs {
@@ -202,6 +206,9 @@ struct CkptArgs {
   DevState* st;
   DevState* st_save;
 };
+// Copies a[m] -> b[m] (dir 0) or back (dir 1), bytes[m] each, and the
+// device state with them; with st or st_save NULL only the regions (the
+// tied model's factor copies).
 void checkpoint_group(hipStream_t s, const CkptArgs* tab, int nprob, int dir);
 
 void hadamard_inplace_f64(hipStream_t s, double* A, const double* B, size_t count);

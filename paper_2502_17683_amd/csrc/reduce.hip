@@ -138,6 +138,39 @@ void normalise_group(hipStream_t s, const NormArgs<T>* tab, int nprob, int max_R
   hipLaunchKernelGGL((normalise_kernel<T>), dim3((max_R + 15) / 16, nprob), dim3(256), 0, s, tab);
 }
 
+// Tied model: inner_part[k] = lam[k] sum_s F3[s,k] M3[s,k] (the <G, G~>
+// partials from the mode-3 MTTKRP of the tied factors; F3 is read through
+// the Msol field, F is unused).
+template <typename T>
+__global__ __launch_bounds__(256) void tied_inner_kernel(const NormArgs<T>* tab) {
+  __shared__ double si[16][16];
+  const NormArgs<T> a = tab[blockIdx.y];
+  if (a.st->done) return;
+  const int tid = threadIdx.x, c = tid & 15, g = tid >> 4;
+  const int col = blockIdx.x * 16 + c;
+  if (blockIdx.x * 16 >= a.R) return;
+  const gptr<const T> F3 = as_global(a.Msol), M3 = as_global(a.Msave);
+  double y = 0.0;
+  if (col < a.R) {
+#pragma unroll 4
+    for (int s = g; s < a.n; s += 16) y += (double)F3[(size_t)s * a.ld + col] * (double)M3[(size_t)s * a.ld + col];
+  }
+  si[g][c] = y;
+  __syncthreads();
+  if (g == 0 && col < a.R) {
+    double ip = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ip += si[r][c];
+    a.inner_part[col] = (double)as_global(a.lam)[col] * ip;
+  }
+}
+template <typename T>
+void tied_inner_group(hipStream_t s, const NormArgs<T>* tab, int nprob, int max_R) {
+  hipLaunchKernelGGL((tied_inner_kernel<T>), dim3((max_R + 15) / 16, nprob), dim3(256), 0, s, tab);
+}
+template void tied_inner_group<double>(hipStream_t, const NormArgs<double>*, int, int);
+template void tied_inner_group<float>(hipStream_t, const NormArgs<float>*, int, int);
+
 // ||G~||^2 = lambda^T (g0 o g1 o g2 o g3) lambda: per-row partials, then a
 // single-workgroup final pass per problem that also forms the fit and
 // applies the stopping rule.  The Grams are symmetric and only their lower
@@ -319,7 +352,7 @@ __global__ __launch_bounds__(256) void checkpoint_kernel(const CkptArgs* tab, in
     for (size_t e = t0; e < n16; e += stride) d16[e] = s16[e];
     for (size_t e = n16 * 4 + t0; e < c.bytes[m] / 4; e += stride) d4[e] = s4[e];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && c.st && c.st_save) {  // (no state: a plain copy)
     if (dir) *c.st = *c.st_save;
     else *c.st_save = *c.st;
   }
