@@ -104,10 +104,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--init", choices=("normal", "uniform"), default="normal",
                     help="initial factors: N(0,1)/sqrt(n) (default) or the paper's U[-1,1]")
-    ap.add_argument("--workload", choices=("mixed", "lt", "warmstart", "exchange"), default="mixed",
+    ap.add_argument("--workload", choices=("mixed", "lt", "warmstart", "exchange", "tied"), default="mixed",
                     help="mixed: the headline time-to-fit line (default); lt: the batched "
                          "Laplace-transform CPDs; warmstart: train and evaluate the learned warm start; "
-                         "exchange: the robust CPD+THC LT-MP2 exchange energy of the batched systems")
+                         "exchange: the robust CPD+THC LT-MP2 exchange energy of the batched systems; "
+                         "tied: the particle-tied CPD (symmetric ALS) against the four-factor one, FP64")
     ap.add_argument("--lt-sweeps", type=int, default=40)
     ap.add_argument("--accuracy-sweeps", type=int, default=100,
                     help="exchange workload: CP-ALS sweep cap for the accuracy comparison (0: skip)")
@@ -138,6 +139,8 @@ def main():
         return bench_warmstart(args)
     if args.workload == "exchange":
         return bench_exchange(args)
+    if args.workload == "tied":
+        return bench_tied(args)
 
     import torch
     from paper_2502_17683_amd import CPD
@@ -552,6 +555,49 @@ def bench_exchange(args):
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_tied(args):
+    """Particle-tied CPD (F1 = F0, F3 = F2, symmetric ALS) against the
+    four-factor CPD at the headline shape, FP64 (the tied model has no split
+    BF16 path): time per sweep and the fit after --ref-sweeps sweeps, both
+    from the same initial factors (modes 0 and 2 of the usual draw)."""
+    import torch
+    from paper_2502_17683_amd import CPD
+    from synth import make_thc, init_factors, init_factors_uniform
+    N, Rt, Rc = args.n, args.r_thc, args.r_cp
+    dev = torch.device("cuda:0")
+    X, Z = make_thc(N, Rt, args.seed)
+    init = (init_factors_uniform if args.init == "uniform" else init_factors)([N] * 4, Rc, args.seed + 1000)
+    Xd, Zd = torch.as_tensor(X, device=dev), torch.as_tensor(Z, device=dev)
+    Id = [torch.as_tensor(f, device=dev) for f in init]
+    tied_init = [Id[0], Id[0], Id[2], Id[2]]
+    out = {}
+    for name, tie, ini in (("four_factor", False, tied_init), ("tied", True, tied_init)):
+        c = CPD(Xd, Zd, Rc, ini, precision="fp64", tol=0.0, fit_floor=0.0, tied=tie)
+        c.sweep(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.sweep(args.steps * 4, sync=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / (args.steps * 4)
+        c.close()
+        c = CPD(Xd, Zd, Rc, ini, precision="fp64", tol=0.0, fit_floor=0.0, tied=tie)
+        fits = c.sweep(args.ref_sweeps)
+        c.close()
+        out[name] = {"ms_per_sweep": ms, "fit_after": fits[-1], "sweeps": len(fits),
+                     "best_fit": min(fits), "fit_at_10": fits[min(9, len(fits) - 1)]}
+        log(f"[bench-tied] {name}: {ms:.2f} ms/sweep, fit after {len(fits)} sweeps {fits[-1]:.6f}")
+    line = {
+        "metric": "particle-tied vs four-factor CP-ALS, FP64, time per sweep (ms) and fit after a fixed sweep count",
+        "value": out["tied"]["ms_per_sweep"], "unit": "ms", "n_gpus": 1, "higher_is_better": False,
+        "data": "synthetic", "dtype": "f64",
+        "config": {"workload": f"THC CP-ALS N={N}, R_thc={Rt}, R_cp={Rc}, seed {args.seed}, init {args.init}, "
+                               f"{args.ref_sweeps} sweeps"},
+        "per_model": out,
+        "sweep_time_ratio_tied_vs_four_factor": out["tied"]["ms_per_sweep"] / out["four_factor"]["ms_per_sweep"],
+    }
+    print(json.dumps(line), flush=True)
 
 
 def bench_warmstart(args):
