@@ -21,6 +21,7 @@ Modules
   mp2      THC LT-MP2 Coulomb and exchange terms and the LT-MP2 energy.
   tied     Particle-tied CP-ALS (eq. cp4's one factor per particle) by
            symmetric ALS.
+  df       Density-fitting tensors (eq. df_loss) and their exact THC form.
 
 Pins: every function is checked by ``tests/test_oracle_*.py`` against
 brute-force loops, closed forms, planted decompositions, special cases and

@@ -9,7 +9,7 @@ none of the CP-ALS arithmetic.  Every random number a CP-ALS run consumes
 oracle and the GPU path as an input.
 """
 from .thc import (make_thc, init_factors, init_factors_uniform, make_lt_system,
-                  lt_points, lt_quadrature, LT_SYSTEMS, planted_diag_thc, mlp_init_params, minibatch_order)
+                  lt_points, lt_quadrature, LT_SYSTEMS, planted_diag_thc, make_df, mlp_init_params, minibatch_order)
 
 __all__ = ["make_thc", "init_factors", "init_factors_uniform", "make_lt_system",
-           "lt_points", "lt_quadrature", "LT_SYSTEMS", "planted_diag_thc", "mlp_init_params", "minibatch_order"]
+           "lt_points", "lt_quadrature", "LT_SYSTEMS", "make_df", "planted_diag_thc", "mlp_init_params", "minibatch_order"]

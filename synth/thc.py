@@ -94,6 +94,21 @@ def make_lt_system(n_occ, n_virt, seed, rank_factor=4):
             eps_occ, eps_virt)
 
 
+def make_df(n, n_aux, seed, rank_factor=4):
+    """Synthetic density-fitting factor B ((n n) x n_aux, row (p, q) = p n + q)
+    of a Coulomb-like tensor, g[p,q,r,s] ~= sum_X B[(p,q),X] B[(r,s),X]
+    (eq. df_loss).  Built from the THC stand-in of make_thc(n, rank_factor
+    n, seed): the core Z is truncated to its n_aux leading eigenpairs,
+    Z ~= C C^T with C = U sqrt(Lambda), and B[(p,q), X] = sum_P X[p,P] X[q,P]
+    C[P,X]."""
+    X, Z = make_thc(n, rank_factor * n, seed)
+    ev, U = np.linalg.eigh(Z)
+    top = np.argsort(ev)[::-1][:n_aux]
+    C = U[:, top] * np.sqrt(np.clip(ev[top], 0.0, None))[None, :]
+    pairs = (X[:, None, :] * X[None, :, :]).reshape(n * n, -1)
+    return np.ascontiguousarray(pairs @ C)
+
+
 def planted_diag_thc(n, r_thc, seed):
     """THC input with a diagonal core: Z = diag(z), z > 0.
 
