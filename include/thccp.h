@@ -296,6 +296,18 @@ cpd_status cpd_lt_mp2(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t n_po
                       double* J, double* K, double* energies, void* workspace, size_t workspace_bytes,
                       void* stream);
 
+/* ---- density-fitting tensors in THC form (eq. df_loss) ----
+ * A DF tensor G[p,q,r,s] = sum_X B[(p,q),X] B[(r,s),X] is exactly the THC
+ * tensor with the orbital pairs as grid, R_thc = n^2:
+ *   X0[p, (p',q')] = [p = p'],  X1[q, (p',q')] = [q = q'],  Z = B B^T.
+ * Passing X = {X0, X1, X0, X1} and Z with r_thc = n^2 to cpd_init runs the
+ * CP-ALS of the DF loss matrix-free, at O(n^4 R_cp) per sweep.
+ *   B: DEVICE (n n) x n_aux, row (p, q) = p n + q.  X0, X1: DEVICE outputs,
+ *   n x n^2 each; Z: DEVICE output, n^2 x n^2 (8 n^4 bytes).  1 <= n <= 1024.
+ * Errors: CPD_ERR_INVALID_ARG, CPD_ERR_HIP.  Async on stream. */
+cpd_status cpd_df_to_thc(int32_t n, int32_t n_aux, const double* B, double* X0, double* X1, double* Z,
+                         void* stream);
+
 /* Releases the host plan and its private stream/graph (not the workspace). */
 /* ---- learned warm start ----
  * An initial CP built from R_cp grid columns of the THC factors: with a

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libthccp.so")
-SOURCES = ["gemm.hip", "chol.hip", "reduce.hip", "mixed.hip", "cpd.hip", "hooks.hip", "warmstart.hip", "exchange.hip"]
+SOURCES = ["gemm.hip", "chol.hip", "reduce.hip", "mixed.hip", "cpd.hip", "hooks.hip", "warmstart.hip", "exchange.hip", "df.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

@@ -352,3 +352,19 @@ def test_gemm_split(A, B, A2=None, bm=0):
                                   _stream(A.device), int(bm)), "cpd_test_gemm_split")
     torch.cuda.current_stream(A.device).synchronize()
     return C
+
+
+def df_to_thc(B, n):
+    """The exact THC form (X0, X1, Z) of the DF tensor
+    G[p,q,r,s] = sum_X B[(p,q),X] B[(r,s),X] (eq. df_loss) on the GPU: pair
+    selection factors and Z = B B^T; CPD([X0, X1, X0, X1], Z, ...) then
+    runs the CP-ALS of the DF loss."""
+    lib = _lib.load()
+    B = B.contiguous()
+    nn = n * n
+    X0 = torch.empty(n, nn, dtype=torch.float64, device=B.device)
+    X1 = torch.empty(n, nn, dtype=torch.float64, device=B.device)
+    Z = torch.empty(nn, nn, dtype=torch.float64, device=B.device)
+    check(lib.cpd_df_to_thc(int(n), int(B.shape[1]), _ptr(B), _ptr(X0), _ptr(X1), _ptr(Z), _stream(B.device)),
+          "cpd_df_to_thc")
+    return X0, X1, Z
