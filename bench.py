@@ -104,11 +104,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--init", choices=("normal", "uniform"), default="normal",
                     help="initial factors: N(0,1)/sqrt(n) (default) or the paper's U[-1,1]")
-    ap.add_argument("--workload", choices=("mixed", "lt", "warmstart", "exchange", "tied"), default="mixed",
+    ap.add_argument("--workload", choices=("mixed", "lt", "warmstart", "exchange", "tied", "df"), default="mixed",
                     help="mixed: the headline time-to-fit line (default); lt: the batched "
                          "Laplace-transform CPDs; warmstart: train and evaluate the learned warm start; "
                          "exchange: the robust CPD+THC LT-MP2 exchange energy of the batched systems; "
-                         "tied: the particle-tied CPD (symmetric ALS) against the four-factor one, FP64")
+                         "tied: the particle-tied CPD (symmetric ALS) against the four-factor one, FP64; "
+                         "df: DF-based against THC-based CP-ALS, FP64, growing n")
     ap.add_argument("--lt-sweeps", type=int, default=40)
     ap.add_argument("--accuracy-sweeps", type=int, default=100,
                     help="exchange workload: CP-ALS sweep cap for the accuracy comparison (0: skip)")
@@ -141,6 +142,8 @@ def main():
         return bench_exchange(args)
     if args.workload == "tied":
         return bench_tied(args)
+    if args.workload == "df":
+        return bench_df(args)
 
     import torch
     from paper_2502_17683_amd import CPD
@@ -596,6 +599,64 @@ def bench_tied(args):
                                f"{args.ref_sweeps} sweeps"},
         "per_model": out,
         "sweep_time_ratio_tied_vs_four_factor": out["tied"]["ms_per_sweep"] / out["four_factor"]["ms_per_sweep"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_df(args):
+    """CP-ALS on the DF loss (eq. df_loss, run through the exact THC form with
+    R_thc = n^2) against CP-ALS on the THC loss (eq. lossF, R_thc = 4n), FP64,
+    n = 50, 100, 200, R_cp = 2n, n_aux = 3n.  The DF tensor is the THC
+    stand-in with its core truncated to n_aux eigenpairs, so the two losses
+    describe nearly the same tensor.  Per sweep: O(n^4 R_cp) against
+    O(n^3 R_cp)."""
+    import torch
+    from paper_2502_17683_amd import CPD, df_to_thc
+    from synth import make_thc, make_df, init_factors
+    dev = torch.device("cuda:0")
+    rows = []
+    for n in (50, 100, 200):
+        r_cp, naux = 2 * n, 3 * n
+        X, Z = make_thc(n, 4 * n, args.seed)
+        B = make_df(n, naux, args.seed)
+        init = [torch.as_tensor(f, device=dev) for f in init_factors([n] * 4, r_cp, args.seed + 1000)]
+        Bd = torch.as_tensor(B, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X0, X1, Zd, nrm = df_to_thc(Bd, n)
+        torch.cuda.synchronize()
+        conv_ms = (time.perf_counter() - t0) * 1e3
+        res = {"n": n, "r_cp": r_cp, "n_aux": naux, "df_to_thc_ms": conv_ms}
+        for name, Xs, Zs, nr in (("df", [X0, X1, X0, X1], Zd, nrm),
+                                 ("thc", torch.as_tensor(X, device=dev), torch.as_tensor(Z, device=dev), None)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c = CPD(Xs, Zs, r_cp, init, precision="fp64", tol=0.0, fit_floor=0.0, norm2=nr)
+            torch.cuda.synchronize()
+            init_ms = (time.perf_counter() - t0) * 1e3
+            c.sweep(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.sweep(10, sync=False)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / 10
+            fits = c.sweep(20)
+            c.close()
+            res[name] = {"r_thc": int(Zs.shape[0]), "ms_per_sweep": ms, "fit_after_32": fits[-1], "init_ms": init_ms}
+        res["df_vs_thc_sweep_time"] = res["df"]["ms_per_sweep"] / res["thc"]["ms_per_sweep"]
+        rows.append(res)
+        log(f"[bench-df] n={n}: DF (R_thc={n * n}) {res['df']['ms_per_sweep']:.2f} ms/sweep, THC (R_thc={4 * n}) "
+            f"{res['thc']['ms_per_sweep']:.2f} ms/sweep ({res['df_vs_thc_sweep_time']:.1f}x); fits "
+            f"{res['df']['fit_after_32']:.4f} / {res['thc']['fit_after_32']:.4f}")
+        del X0, X1, Zd, Bd, nrm
+        torch.cuda.empty_cache()
+    line = {
+        "metric": "CP-ALS sweep time (ms), DF loss vs THC loss, FP64, 1 MI355X",
+        "value": rows[-1]["df_vs_thc_sweep_time"], "unit": "ratio", "n_gpus": 1, "higher_is_better": False,
+        "data": "synthetic", "dtype": "f64",
+        "config": {"workload": "n = 50, 100, 200; R_cp = 2n; DF: n_aux = 3n, R_thc = n^2 (exact THC form); "
+                               "THC: R_thc = 4n"},
+        "per_n": rows,
     }
     print(json.dumps(line), flush=True)
 

@@ -107,6 +107,10 @@ typedef struct {
                              n[3] = n[2]; init[1] and init[3] are not read.
                              FP64 and FP32 only (split BF16: UNSUPPORTED).  Every
                              problem of a batch must agree.  0: four factors  */
+  const double* norm2;    /* optional DEVICE pointer to ||G||^2, read at init;
+                             NULL: computed from X and Z, which costs
+                             O(r_thc^3) and three r_thc^2 buffers (supply it
+                             for the DF form, where r_thc = n^2)              */
 } cpd_desc;
 
 typedef struct {
@@ -299,14 +303,16 @@ cpd_status cpd_lt_mp2(int32_t n_occ, int32_t n_virt, int32_t r_thc, int32_t n_po
 /* ---- density-fitting tensors in THC form (eq. df_loss) ----
  * A DF tensor G[p,q,r,s] = sum_X B[(p,q),X] B[(r,s),X] is exactly the THC
  * tensor with the orbital pairs as grid, R_thc = n^2:
- *   X0[p, (p',q')] = [p = p'],  X1[q, (p',q')] = [q = q'],  Z = B B^T.
- * Passing X = {X0, X1, X0, X1} and Z with r_thc = n^2 to cpd_init runs the
- * CP-ALS of the DF loss matrix-free, at O(n^4 R_cp) per sweep.
- *   B: DEVICE (n n) x n_aux, row (p, q) = p n + q.  X0, X1: DEVICE outputs,
- *   n x n^2 each; Z: DEVICE output, n^2 x n^2 (8 n^4 bytes).  1 <= n <= 1024.
+ *   X0[p, (p',q')] = [p = p'],  X1[q, (p',q')] = [q = q'],  Z = B B^T,
+ * and ||G||^2 = ||B^T B||_F^2.  Passing X = {X0, X1, X0, X1}, Z and norm2
+ * with r_thc = n^2 to cpd_init runs the CP-ALS of the DF loss matrix-free,
+ * at O(n^4 R_cp) per sweep.
+ *   B: DEVICE (n n) x n_aux, row (p, q) = p n + q; n_aux <= n^2.  X0, X1:
+ *   DEVICE outputs, n x n^2 each; Z: DEVICE output, n^2 x n^2 (8 n^4
+ *   bytes); norm2: DEVICE output, 1 value (may be NULL).  1 <= n <= 1024.
  * Errors: CPD_ERR_INVALID_ARG, CPD_ERR_HIP.  Async on stream. */
 cpd_status cpd_df_to_thc(int32_t n, int32_t n_aux, const double* B, double* X0, double* X1, double* Z,
-                         void* stream);
+                         double* norm2, void* stream);
 
 /* Releases the host plan and its private stream/graph (not the workspace). */
 /* ---- learned warm start ----

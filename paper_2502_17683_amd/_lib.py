@@ -40,6 +40,7 @@ class CpdDesc(ctypes.Structure):
         ("workspace", vp),
         ("workspace_bytes", ctypes.c_size_t),
         ("tied", i32),
+        ("norm2", vp),
     ]
 
 
@@ -88,7 +89,7 @@ EXPORTS = {
     "cpd_autotune_log": (i32, [vp, ctypes.c_char_p, i32]),
     "cpd_lt_scale_rows": (i32, [vp, vp, i32, i32, ctypes.c_double, ctypes.c_double, vp, vp]),
     "cpd_lt_exchange_workspace": (ctypes.c_size_t, [i32, i32, i32, i32, i32, i32]),
-    "cpd_df_to_thc": (i32, [i32, i32, vp, vp, vp, vp, vp]),
+    "cpd_df_to_thc": (i32, [i32, i32, vp, vp, vp, vp, vp, vp]),
     "cpd_lt_mp2_workspace": (ctypes.c_size_t, [i32, i32, i32, i32, i32, i32]),
     "cpd_lt_mp2": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, ctypes.c_size_t,
                          vp]),

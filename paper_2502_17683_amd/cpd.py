@@ -35,9 +35,11 @@ class CPD:
 
     def __init__(self, X, Z, r_cp, init, precision="fp64", tol=1e-4, fit_floor=1e-7,
                  chol_fallback=True, use_graph=True, fit_every=1, autotune=False, solve_panel=0,
-                 device="cuda", tied=False):
+                 device="cuda", tied=False, norm2=None):
         """tied: the particle-tied model F1 = F0, F3 = F2 (symmetric ALS;
-        FP64/FP32 only; init[1] and init[3] are not used)."""
+        FP64/FP32 only; init[1] and init[3] are not used).  norm2: optional
+        one-element device tensor holding ||G||^2 (skips its O(R_thc^3)
+        set-up; see df_to_thc)."""
         self.lib = _lib.load()
         self.device = torch.device(device)
         if not isinstance(X, (list, tuple)):
@@ -71,6 +73,8 @@ class CPD:
         d.autotune = int(bool(autotune))
         d.solve_panel = int(solve_panel)
         d.tied = int(bool(tied))
+        self.norm2 = None if norm2 is None else norm2.to(device=self.device, dtype=torch.float64).contiguous()
+        d.norm2 = self.norm2.data_ptr() if self.norm2 is not None else None
         d.stream = _stream(self.device).value
         need = self.lib.cpd_workspace_size(ctypes.byref(d))
         if need == 0:
@@ -355,16 +359,18 @@ def test_gemm_split(A, B, A2=None, bm=0):
 
 
 def df_to_thc(B, n):
-    """The exact THC form (X0, X1, Z) of the DF tensor
+    """The exact THC form (X0, X1, Z, norm2) of the DF tensor
     G[p,q,r,s] = sum_X B[(p,q),X] B[(r,s),X] (eq. df_loss) on the GPU: pair
-    selection factors and Z = B B^T; CPD([X0, X1, X0, X1], Z, ...) then
-    runs the CP-ALS of the DF loss."""
+    selection factors, Z = B B^T and ||G||^2 = ||B^T B||_F^2 (one-element
+    tensor); CPD([X0, X1, X0, X1], Z, ..., norm2=norm2) then runs the
+    CP-ALS of the DF loss."""
     lib = _lib.load()
     B = B.contiguous()
     nn = n * n
     X0 = torch.empty(n, nn, dtype=torch.float64, device=B.device)
     X1 = torch.empty(n, nn, dtype=torch.float64, device=B.device)
     Z = torch.empty(nn, nn, dtype=torch.float64, device=B.device)
-    check(lib.cpd_df_to_thc(int(n), int(B.shape[1]), _ptr(B), _ptr(X0), _ptr(X1), _ptr(Z), _stream(B.device)),
-          "cpd_df_to_thc")
-    return X0, X1, Z
+    norm2 = torch.empty(1, dtype=torch.float64, device=B.device)
+    check(lib.cpd_df_to_thc(int(n), int(B.shape[1]), _ptr(B), _ptr(X0), _ptr(X1), _ptr(Z), _ptr(norm2),
+                            _stream(B.device)), "cpd_df_to_thc")
+    return X0, X1, Z, norm2

@@ -262,8 +262,10 @@ void carve_prob(Layout& L, Prob& q, int prec, SplitShare& sh) {
   q.norm2 = (double*)L.take(sizeof(double) * 8);
   const size_t nt = (size_t)((Rt + 63) / 64);
   q.partials = (double*)L.take(sizeof(double) * nt * nt);
+  // the ||G||^2 set-up products (not needed when the caller supplies ||G||^2)
   size_t setup_elems = (size_t)Rt * Rt;
   if ((size_t)q.nmax * Tp > setup_elems) setup_elems = (size_t)q.nmax * Tp;
+  if (q.d.norm2) setup_elems = 0;
   for (int i = 0; i < 3; ++i) q.setup[i] = (double*)L.take(sizeof(double) * setup_elems);
   q.scratch64 = (double*)L.take(sizeof(double) * (size_t)q.nmax * Tp);
   if (prec == CPD_FP32) {
@@ -653,6 +655,10 @@ int init_shape(cpd_plan_s* p, const cpd_desc* descs, int count) {
 
 // ------------------------------------------------------------------ set-up
 int setup_norm2(Prob& q, hipStream_t s) {
+  if (q.d.norm2) {  // supplied by the caller (a DF input: ||B^T B||_F^2)
+    HIPCHK(hipMemcpyAsync(q.norm2, q.d.norm2, sizeof(double), hipMemcpyDeviceToDevice, s));
+    return CPD_OK;
+  }
   const int Rt = q.Rt;
   double *A = q.setup[0], *B = q.setup[1], *C = q.setup[2];
   const double* const* X = q.d.X;

@@ -4,6 +4,8 @@
 // tensor whose grid index runs over the orbital pairs P = (p', q'):
 //   X0[p, P] = [p = p'],  X1[q, P] = [q = q'],  X2 = X0,  X3 = X1,
 //   Z = B B^T  ((n n) x (n n)).
+// and ||G||^2 = ||B^T B||_F^2 (which spares the CP-ALS set-up its
+// O(R_thc^3) = O(n^6) products).
 // With these inputs the matrix-free CP-ALS of the library is the CP-ALS on
 // the DF loss; its products then cost O(n^4 R_cp) per sweep, the scaling
 // the paper gives for the DF variant, where a THC rank proportional to n
@@ -28,6 +30,23 @@ __global__ __launch_bounds__(256) void pair_selection_kernel(int n, double* X0, 
   }
 }
 
+// out = sum of the squares of S (count values), one workgroup, fixed order.
+__global__ __launch_bounds__(256) void sum_squares_kernel(const double* S, size_t count, double* out) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (size_t e = threadIdx.x; e < count; e += 256) {
+    const double v = as_global(S)[e];
+    acc += v * v;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) as_global(out)[0] = part[0];
+}
+
 }  // namespace
 }  // namespace thccp
 
@@ -36,10 +55,19 @@ using namespace thccp;
 extern "C" {
 
 cpd_status cpd_df_to_thc(int32_t n, int32_t n_aux, const double* B, double* X0, double* X1, double* Z,
-                         void* stream) {
+                         double* norm2, void* stream) {
   // the THC rank n^2 must stay within the CP-ALS limit (2^20)
-  if (n <= 0 || n > 1024 || n_aux <= 0 || !B || !X0 || !X1 || !Z) return CPD_ERR_INVALID_ARG;
+  if (n <= 0 || n > 1024 || n_aux <= 0 || (int64_t)n_aux > (int64_t)n * n || !B || !X0 || !X1 || !Z)
+    return CPD_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
+  if (norm2) {
+    // ||G||^2 = ||B^T B||_F^2; B^T B (n_aux^2 <= n^4 values) is staged in Z
+    // before Z itself is formed
+    GemmF64 g{n_aux, n_aux, n * n, B, n_aux, true, B, nullptr, n_aux, false, Z, n_aux, nullptr, 1.0, 0.0,
+              nullptr};
+    gemm_f64(s, g);
+    hipLaunchKernelGGL(sum_squares_kernel, dim3(1), dim3(256), 0, s, Z, (size_t)n_aux * n_aux, norm2);
+  }
   const size_t total = (size_t)n * n * n;
   int grid = (int)((total + 255) / 256);
   if (grid > 4096) grid = 4096;

@@ -18,28 +18,34 @@ def test_df_to_thc_matches_oracle():
     from paper_2502_17683_amd import df_to_thc
     n, naux = 9, 21
     B = make_df(n, naux, 5)
-    X0, X1, Z = (t.cpu().numpy() for t in df_to_thc(to_dev(B), n))
+    X0, X1, Z, nrm = (t.cpu().numpy() for t in df_to_thc(to_dev(B), n))
     torch.cuda.synchronize()
     R0, R1, RZ = df.df_to_thc(B, n)
     assert np.array_equal(X0, R0) and np.array_equal(X1, R1)
     bound = 1e-14 * np.sqrt(naux) * (np.abs(B) @ np.abs(B).T)
     assert np.all(np.abs(Z - RZ) <= bound + 1e-300)
+    # ||G||^2 of the dense DF tensor
+    ref = float(np.sum(df.df_tensor(B, n) ** 2))
+    assert nrm[0] == pytest.approx(ref, rel=1e-12)
 
 
-def _run(B, n, init, r_cp, sweeps, precision="fp64"):
+def _run(B, n, init, r_cp, sweeps, precision="fp64", supply_norm2=True):
     from paper_2502_17683_amd import CPD, df_to_thc
-    X0, X1, Z = df_to_thc(to_dev(B), n)
-    c = CPD([X0, X1, X0, X1], Z, r_cp, [to_dev(f) for f in init], precision=precision, tol=0.0, fit_floor=0.0)
+    X0, X1, Z, nrm = df_to_thc(to_dev(B), n)
+    c = CPD([X0, X1, X0, X1], Z, r_cp, [to_dev(f) for f in init], precision=precision, tol=0.0, fit_floor=0.0,
+            norm2=nrm if supply_norm2 else None)
     fits = np.array(c.sweep(sweeps))
     c.close()
     return fits
 
 
-def test_df_cp_als_matches_dense_oracle():
+@pytest.mark.parametrize("supply_norm2", [True, False])
+def test_df_cp_als_matches_dense_oracle(supply_norm2):
+    # with ||G||^2 supplied, or computed by the THC set-up
     n, naux, r_cp = 5, 8, 6
     B = make_df(n, naux, 4)
     init = init_factors([n] * 4, r_cp, 1004)
-    fits = _run(B, n, init, r_cp, 15)
+    fits = _run(B, n, init, r_cp, 15, supply_norm2=supply_norm2)
     ref = np.array(dense.dense_cp_als(df.df_tensor(B, n), init, 15, tol=0.0, fit_floor=0.0)["fits"])
     err = np.abs(fits - ref) / ref
     say(f"[df] dense: max fit rel err {err.max():.2e}")
