@@ -194,7 +194,7 @@ class CPDBatch:
     """
 
     def __init__(self, problems, precision="mixed", tol=1e-4, fit_floor=1e-7, chol_fallback=True,
-                 use_graph=True, fit_every=1, autotune=False, solve_panel=0, device="cuda"):
+                 use_graph=True, fit_every=1, autotune=False, solve_panel=0, device="cuda", tied=False):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.count = len(problems)
@@ -232,6 +232,7 @@ class CPDBatch:
             d.fit_every = int(fit_every)
             d.autotune = int(bool(autotune))
             d.solve_panel = int(solve_panel)
+            d.tied = int(bool(tied))
             d.stream = _stream(self.device).value
             self.shapes.append(([d.n[m] for m in range(4)], d.r_thc, d.r_cp))
         need = self.lib.cpd_batch_workspace_size(descs, self.count)

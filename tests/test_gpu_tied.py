@@ -104,3 +104,24 @@ def test_tied_rejects_mixed_and_mismatched_modes():
     X6, _ = make_thc(6, 80, 18)
     with pytest.raises(CpdError):
         _cpd([X, X6, X, X], Z, [init[0], init_factors([6], 60, 1)[0], init[2], init[3]], 60, precision="fp64")
+
+
+def test_tied_batch_equals_single_runs():
+    """Grouped tied problems of uneven size: each equals its single run, bit
+    for bit (the grouped launches and tied copies are per problem)."""
+    from paper_2502_17683_amd import CPD, CPDBatch
+    probs = []
+    for i, (n, rt, rc) in enumerate([(12, 48, 30), (20, 80, 60), (9, 40, 17)]):
+        X, Z = make_thc(n, rt, 30 + i)
+        probs.append({"X": X, "Z": Z, "r_cp": rc, "init": init_factors([n] * 4, rc, 1030 + i)})
+    b = CPDBatch(probs, precision="fp64", tol=0.0, fit_floor=0.0, tied=True)
+    fb = b.sweep(8)
+    for i, pr in enumerate(probs):
+        c = CPD(pr["X"], pr["Z"], pr["r_cp"], pr["init"], precision="fp64", tol=0.0, fit_floor=0.0, tied=True)
+        fs = c.sweep(8)
+        Fs, ls = c.factors()
+        c.close()
+        Fb, lb = b.factors(i)
+        assert fb[i] == fs
+        assert all(torch.equal(x, y) for x, y in zip(Fs, Fb)) and torch.equal(ls, lb)
+    b.close()
