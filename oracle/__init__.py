@@ -22,6 +22,8 @@ Modules
   tied     Particle-tied CP-ALS (eq. cp4's one factor per particle) by
            symmetric ALS.
   df       Density-fitting tensors (eq. df_loss) and their exact THC form.
+  order3   Order-3 THC-like tensors as the order-4 form with a singleton
+           mode; the three-way CP-ALS they are pinned against.
 
 Pins: every function is checked by ``tests/test_oracle_*.py`` against
 brute-force loops, closed forms, planted decompositions, special cases and
