@@ -214,3 +214,17 @@ def test_exchange_zero_weights_give_zero_energy():
     ts = [0.1, 1.0]
     g1, g2, ge = _run(*_case(4, 8, 4, 24, 21), ts, [0.0, 0.0])
     assert ge == 0.0 and np.all(np.isfinite(g1)) and np.all(np.isfinite(g2))
+
+
+def test_exchange_per_point_cpds_full_size():
+    # the largest system at 16 points, separate per-point CPDs
+    o, v = LT_SYSTEMS[2]
+    Xo, Xv, Z, eo, ev = make_lt_system(o, v, 2)
+    r_cp = 2 * (o + v)
+    F = init_factors([o, v, o, v], r_cp, 1032)
+    lam_h = np.random.default_rng(79).uniform(0.5, 2.0, r_cp)
+    ts, w = lt_quadrature()
+    rng = np.random.default_rng(80)
+    E = [init_factors([o, v, o, v], r_cp, 5000 + k) for k in range(len(ts))]
+    lam_e = [rng.uniform(0.5, 2.0, r_cp) for _ in ts]
+    _check_pp(Xo, Xv, Z, eo, ev, F, lam_h, ts, w, E, lam_e, "per-point full size 80,400")
