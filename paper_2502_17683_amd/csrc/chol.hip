@@ -474,6 +474,8 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
   int bid = blockIdx.x - offs[pid];
   const int nbid = offs[pid + 1] - offs[pid];
   if (st->done) return;
+  // the forward solve of the damped-retry pass serves only the retried problems
+  if (MODE == STEP_FWD && retry_pass && !st->retry_active) return;
   const int Tp = nblk * TB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int sr = tid >> 2, q0 = tid & 3;  // strip layout (diagonal factorisation)

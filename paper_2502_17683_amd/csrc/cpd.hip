@@ -44,6 +44,7 @@ struct Bufs {
   T* Y;
   T* Msol;
   T* Msave;
+  T* Mbak;      // right-hand side kept for a damped retry of a fused solve
   T* F[4];
   T* Fsave[4];  // factors at the start of the sweep (fast-path checkpoint)
   T* G[4];
@@ -91,9 +92,12 @@ struct SolveLaunch {
 // The factorisation and solves of one mode.
 struct StepOps {
   void* probs = nullptr;                // StepProb<T>[nprob]
-  std::vector<SolveLaunch> chol[2];     // factorisation; [1] the damped-retry pass
   std::vector<SolveLaunch> cholfwd;     // factorisation fused with the forward solve
-  std::vector<SolveLaunch> fwd, bwd;
+  std::vector<SolveLaunch> bwd;         // backward solve
+  std::vector<SolveLaunch> chol_retry;  // damped-retry factorisation (retried problems only)
+  std::vector<SolveLaunch> fwd_retry;   // forward solve of the retried problems only
+  void* mkeep = nullptr;                // CkptArgs: Msol -> Mbak
+  void* mrestore = nullptr;             // CkptArgs: Mbak -> Msol for retried problems
 };
 
 // Process-wide autotune cache: (kind, shapes) -> tile edge.
@@ -200,6 +204,7 @@ void carve_typed(Layout& L, Prob& q, Bufs<T>& b, bool own_inputs) {
   b.Y = (T*)L.take(sizeof(T) * (size_t)Rt * Tp);
   b.Msol = (T*)L.take(sizeof(T) * (size_t)q.nmax * Tp);
   b.Msave = (T*)L.take(sizeof(T) * (size_t)q.n[3] * Tp);
+  b.Mbak = (T*)L.take(sizeof(T) * (size_t)q.nmax * Tp);
   for (int m = 0; m < 4; ++m) b.F[m] = (T*)L.take(sizeof(T) * (size_t)q.n[m] * Tp);
   for (int m = 0; m < 4; ++m) b.Fsave[m] = (T*)L.take(sizeof(T) * (size_t)q.n[m] * Tp);
   for (int m = 0; m < 4; ++m) b.G[m] = (T*)L.take(sizeof(T) * (size_t)Tp * Tp);
@@ -452,11 +457,27 @@ void build_typed(TableBuilder& tb, cpd_plan_s* p, Bufs<T> Prob::*bufs, bool gate
     StepOps& so = p->steps[n];
     so.probs = tb.put(sp);
     const int pw = p->panel_width > 0 ? p->panel_width : p->maxNblk;
-    so.chol[0] = build_sched<T>(tb, SCHED_CHOL, p->maxNblk, pw, sp, 1, kind);
-    so.chol[1] = build_sched<T>(tb, SCHED_CHOL, p->maxNblk, pw, sp, 2, kind);
+    so.chol_retry = build_sched<T>(tb, SCHED_CHOL, p->maxNblk, pw, sp, 2, kind);
     so.cholfwd = build_sched<T>(tb, SCHED_CHOL_FWD, p->maxNblk, pw, sp, 1, kind);
-    so.fwd = build_sched<T>(tb, SCHED_FWD, p->maxNblk, pw, sp, 0, kind);
     so.bwd = build_sched<T>(tb, SCHED_BWD, p->maxNblk, pw, sp, 0, kind);
+    so.fwd_retry = build_sched<T>(tb, SCHED_FWD, p->maxNblk, pw, sp, 2, kind);
+    {
+      std::vector<CkptArgs> keep, restore;
+      for (int i = 0; i < np; ++i) {
+        Prob& q = p->P[i];
+        Bufs<T>& b = q.*bufs;
+        CkptArgs c{};
+        c.a[0] = b.Msol;
+        c.b[0] = b.Mbak;
+        c.bytes[0] = sizeof(T) * (size_t)q.n[n] * q.Tp;
+        keep.push_back(c);
+        c.gate = &q.st->retry_active;
+        c.want = 1;
+        restore.push_back(c);
+      }
+      so.mkeep = tb.put(keep);
+      so.mrestore = tb.put(restore);
+    }
     p->formv[n] = tb.put(fv);
     p->norm[n] = tb.put(nm);
     if (n == 3) {
@@ -485,7 +506,7 @@ void build_typed(TableBuilder& tb, cpd_plan_s* p, Bufs<T> Prob::*bufs, bool gate
     f.R = q.Rc;
     f.ld = q.Tp;
     ft.push_back(f);
-    CkptArgs c;
+    CkptArgs c{};
     for (int m = 0; m < 4; ++m) {
       c.a[m] = b.F[m];
       c.b[m] = b.Fsave[m];
@@ -736,11 +757,18 @@ void solve_mode(cpd_plan_s* p, int n, hipStream_t s, bool with_inner, bool fast)
     run_sched<T>(p, s, n, so.cholfwd, 0);
     run_sched<T>(p, s, n, so.bwd, 0);
   } else {
-    run_sched<T>(p, s, n, so.chol[0], 0);
+    // Asynchronous sweeps cannot be replayed from the host, so the damped
+    // retry stays in the graph: the fused factorisation and forward solve
+    // run on a copy-protected right-hand side; a problem whose pivot failed
+    // is refactored from V + mu I, gets its right-hand side back and its
+    // forward solve alone (launches that are no-ops without a failure).
+    checkpoint_group(s, (const CkptArgs*)so.mkeep, p->count, 0);
+    run_sched<T>(p, s, n, so.cholfwd, 0);
     retry_prepare_group<T>(s, fv, p->count, p->allow_fallback);
     form_v_group<T>(s, fv, p->count, p->maxTp, 1);
-    run_sched<T>(p, s, n, so.chol[1], 1);
-    run_sched<T>(p, s, n, so.fwd, 0);
+    run_sched<T>(p, s, n, so.chol_retry, 1);
+    checkpoint_group(s, (const CkptArgs*)so.mrestore, p->count, 1);
+    run_sched<T>(p, s, n, so.fwd_retry, 1);
     run_sched<T>(p, s, n, so.bwd, 0);
   }
   normalise_group<T>(s, (const NormArgs<T>*)(with_inner ? p->norm_inner : p->norm[n]), p->count, p->maxR);

@@ -205,10 +205,12 @@ struct CkptArgs {
   size_t bytes[4];
   DevState* st;
   DevState* st_save;
+  const int32_t* gate;  // non-NULL: copy only while *gate == want
+  int32_t want;
 };
 // Copies a[m] -> b[m] (dir 0) or back (dir 1), bytes[m] each, and the
 // device state with them; with st or st_save NULL only the regions (the
-// tied model's factor copies).
+// tied model's factor copies, the right-hand-side backups of the solve).
 void checkpoint_group(hipStream_t s, const CkptArgs* tab, int nprob, int dir);
 
 void hadamard_inplace_f64(hipStream_t s, double* A, const double* B, size_t count);

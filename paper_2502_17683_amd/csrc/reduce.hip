@@ -341,6 +341,7 @@ void set_path_group(hipStream_t s, DevState* const* st_tab, int nprob, const int
 // tail loop covers any remainder).
 __global__ __launch_bounds__(256) void checkpoint_kernel(const CkptArgs* tab, int dir) {
   const CkptArgs c = tab[blockIdx.y];
+  if (c.gate && *c.gate != c.want) return;
   const size_t t0 = (size_t)blockIdx.x * 256 + threadIdx.x, stride = (size_t)gridDim.x * 256;
   for (int m = 0; m < 4; ++m) {
     typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
