@@ -10,8 +10,8 @@
 // every workgroup of that column does so redundantly, so no workgroup ever
 // waits on another -- and solves its own tile of the column.  In the
 // one-level form the blocks beyond column j+2 take their updates in pairs
-// (rank 128, every other step), and the backward solve works two block
-// columns per launch (STEP_BWD2).  After a panel, one GEMM applies its
+// (rank 128, every other step), and the backward solve is one dataflow
+// launch (STEP_BWD_FLOW, below).  After a panel, one GEMM applies its
 // rank-(64 pw) update to the trailing matrix (and, in the forward
 // solve, to the right-hand sides): the trailing matrix is read and written
 // once per panel instead of once per block column.  The diagonal blocks of
@@ -424,17 +424,6 @@ __host__ __device__ inline int fwd_tiles(int nblk, int nrt, int pw, int pf, int 
   if (chol_paired(nblk, pw, js) && !(js & 1) && kmax > js + 2) kmax = js + 2;
   return kmax >= js + 1 ? nrt * (kmax - js) : 0;
 }
-// Two-column backward step t >= 1 (one level): js = nblk + 1 - 2t; F_js
-// and F_{js+1} are final and pending for every block left of js.  The
-// workgroups of block column js - 2 apply them to blocks js - 1 and js - 2,
-// solve both columns and store both (each block has one writer in the
-// launch); the blocks left of js - 2 take the two pending columns (rank
-// 128).  At js = 1 only column 0 is left.
-__host__ __device__ inline int bwd2_js(int nblk, int t) { return nblk + 1 - 2 * t; }
-__host__ __device__ inline int bwd2_tiles(int nblk, int nrt, int t) {
-  const int js = bwd2_js(nblk, t);
-  return js >= 2 ? nrt * (js - 1) : js == 1 ? nrt : 0;
-}
 __host__ __device__ inline int bwd_tiles(int nblk, int nrt, int pw, int pf, int tf) {
   int js, hi, kmin;
   bwd_range(nblk, pw, pf, tf, js, hi, kmin);
@@ -588,102 +577,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
     }
     bid -= nc;
   }
-  if constexpr (MODE == STEP_BWD2) {
-    const int js = bwd2_js(nblk, cfg.tf);
-    const int nrt = (n + TB - 1) / TB;
-    bid = xcd_remap(bid, nbid);
-    const int rt = bid % nrt;
-    // js >= 2: k = js - 2 (both solves), then the blocks left of it;
-    // js = 1: k = 0 (the last solve)
-    const int k = js >= 2 ? js - 2 - bid / nrt : 0;
-    const int r0 = rt * TB;
-    const int nrows = min(TB, n - r0);
-    if (k >= js - 2) __builtin_amdgcn_s_setprio(3);  // the solve chain
-    const bool p1 = js + 1 < nblk;  // F_{js+1} exists (pending with F_js)
-    typedef typename Acc4<T>::type acc_t;
-    T ra[16], rb[16];
-    // The accumulators hold the negated right-hand side, so every product
-    // adds into them directly (a separate product tile would cost the
-    // second workgroup per compute unit).
-    auto neg = [](acc_t* a) {
-#pragma unroll
-      for (int tj = 0; tj < 4; ++tj) a[tj] = -a[tj];
-    };
-    // a1 (and a2, the second tile for the js - 2 solve) += F_jj L_{jj, kc}
-    // for the pending columns jj; S0 = F^T, S1 = L
-    auto pending = [&](acc_t* a1, int k1, acc_t* a2, int k2) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int jj = h == 0 ? js + 1 : js;
-        if (h == 0 && !p1) continue;
-        fetch_block<T>(ra, M + (size_t)r0 * Tp + (size_t)jj * TB, Tp, nrows, tid);
-        fetch_block<T>(rb, V + (size_t)jj * TB * Tp + (size_t)k1 * TB, Tp, TB, tid);
-        __syncthreads();  // earlier reads of S0 / S1 are done
-        put_block<T, true>(S0, ra, tid);
-        put_block<T, false>(S1, rb, tid);
-        __syncthreads();
-        // the second tile's L block, under the first product
-        if (a2) fetch_block<T>(ra, V + (size_t)jj * TB * Tp + (size_t)k2 * TB, Tp, TB, tid);
-        tile_mma64<T>(a1, S0, S1, lane, w);
-        if (a2) {
-          __syncthreads();
-          put_block<T, false>(S1, ra, tid);
-          __syncthreads();
-          tile_mma64<T>(a2, S0, S1, lane, w);
-        }
-      }
-    };
-    // out = a X_kc^T (the stored X = L_kc^{-T}); a is consumed
-    auto solve = [&](acc_t* a, int kc, acc_t* out) {
-      fetch_block<T>(ra, ldiag + (size_t)kc * TB * TB, TB, TB, tid);
-      __syncthreads();
-      acc_to_lds_t<T>(a, S0, lane, w);
-      put_block<T, true>(S1, ra, tid);
-      __syncthreads();
-#pragma unroll
-      for (int tj = 0; tj < 4; ++tj) out[tj] = acc_t{0, 0, 0, 0};
-      tile_mma64<T>(out, S0, S1, lane, w);
-    };
-    acc_t acc[4], acc2[4];
-    T* tile = M + (size_t)r0 * Tp + (size_t)k * TB;
-    if (k <= js - 3 || js == 1) {
-      load_acc<T>(acc, tile, Tp, nrows, lane, w);
-      neg(acc);
-      pending(acc, k, nullptr, 0);
-      if (js == 1) {
-        solve(acc, k, acc2);
-        neg(acc2);
-        store_acc<T>(acc2, tile, Tp, nrows, lane, w);
-      } else {
-        neg(acc);
-        store_acc<T>(acc, tile, Tp, nrows, lane, w);
-      }
-      return;
-    }
-    // k = js - 2: F_{js-1} (stored here), then Y_k -= F_{js-1} L_{js-1,k}
-    // and the solve of column k
-    T* tile1 = M + (size_t)r0 * Tp + (size_t)(js - 1) * TB;
-    load_acc<T>(acc, tile1, Tp, nrows, lane, w);
-    load_acc<T>(acc2, tile, Tp, nrows, lane, w);
-    neg(acc);
-    neg(acc2);
-    pending(acc, js - 1, acc2, k);
-    acc_t f1[4];
-    solve(acc, js - 1, f1);
-    neg(f1);  // F_{js-1}
-    store_acc<T>(f1, tile1, Tp, nrows, lane, w);
-    fetch_block<T>(rb, V + (size_t)(js - 1) * TB * Tp + (size_t)k * TB, Tp, TB, tid);
-    __syncthreads();
-    acc_to_lds_t<T>(f1, S0, lane, w);  // A = F_{js-1}^T
-    put_block<T, false>(S1, rb, tid);
-    __syncthreads();
-    tile_mma64<T>(acc2, S0, S1, lane, w);
-    solve(acc2, k, f1);
-    neg(f1);
-    store_acc<T>(f1, tile, Tp, nrows, lane, w);
-    return;
-  }
-  if constexpr (MODE != STEP_CHOL && MODE != STEP_BWD2) {
+  if constexpr (MODE != STEP_CHOL) {
     constexpr bool FWD = MODE != STEP_BWD;
     int js, lim, kext;  // forward: lim = panel start; backward: lim = panel end
     if (FWD) chol_range(nblk, cfg.pw, cfg.pf, cfg.tf, js, lim, kext);
@@ -756,13 +650,181 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
   }
 }
 
+// ------------------------------------------------- dataflow backward solve
+// The rows of F = G L^{-1} are independent, so each 64-row tile of F is its
+// own chain over the block columns, from the last to the first:
+//
+//   F_k = (G_k - sum_{i > k} F_i L_ik) L_kk^{-1} = (...) X_k^T,
+//
+// (X_k = L_kk^{-T}, stored by the factorisation).  One launch holds every
+// (row tile, block column) pair; the workgroup of (rt, k) takes the
+// products with F_i as their ready flags appear, highest i first, and
+// publishes its own F_k when it is stored.  Workgroups are numbered from
+// the last column down, so every wait is on a lower workgroup id: those are
+// dispatched first and never wait on a higher one, hence the launch cannot
+// deadlock.  A wait still gives up after spin_limit polls (setting
+// FLAG_SOLVE_STALL, which every other wait of the problem sees and follows)
+// so the grid always drains.
+//
+// The F tiles pass between workgroups through device-coherent accesses
+// (agent-scope relaxed atomics, which bypass the per-XCD L2 state), so no
+// L2-wide write-back or invalidation is needed: the producer waits for its
+// stores to be acknowledged before it sets the flag, and the consumer's
+// reads are issued after it has seen the flag.
+constexpr int FLOW_SPIN_LIMIT = 1 << 20;
+
+template <typename T>
+struct Bits;
+template <>
+struct Bits<double> {
+  typedef unsigned long long type;
+};
+template <>
+struct Bits<float> {
+  typedef unsigned int type;
+};
+template <typename T>
+__device__ __forceinline__ T coherent_load(const T* p) {
+  typedef typename Bits<T>::type U;
+  const U u = __hip_atomic_load((const U*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_bit_cast(T, u);
+}
+template <typename T>
+__device__ __forceinline__ void coherent_store(T* p, T v) {
+  typedef typename Bits<T>::type U;
+  __hip_atomic_store((U*)p, __builtin_bit_cast(U, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// fetch_block / store_acc through device-coherent accesses
+template <typename T>
+__device__ __forceinline__ void fetch_block_coherent(T v[16], const T* g, size_t ld, int nrows, int tid) {
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int idx = tid + 256 * e;
+    v[e] = (idx >> 6) < nrows ? coherent_load<T>(g + (size_t)(idx >> 6) * ld + (idx & 63)) : T(0);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void store_acc_coherent(const typename Acc4<T>::type acc[4], T* g, size_t ld, int nrows,
+                                                   int lane, int w) {
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = acc_row<T>(lane, w, r);
+      if (row < nrows) coherent_store<T>(g + (size_t)row * ld + acc_col(lane, tj), acc[tj][r]);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void flow_reset_kernel(const StepProb<T>* probs) {
+  const StepProb<T>& q = probs[blockIdx.x];
+  const int cnt = ((q.n + TB - 1) / TB) * q.nblk;
+  const gptr<int32_t> f = as_global(q.flow);
+  for (int e = threadIdx.x; e < cnt; e += 256) f[e] = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void bwd_flow_kernel(const StepProb<T>* probs, const int* offs, int nprob,
+                                                       int spin_limit) {
+  typedef typename Acc4<T>::type acc_t;
+  __shared__ T S0[TB * LDT];
+  __shared__ T S1[TB * LDT];
+  __shared__ int stalled;
+  int pid = 0;
+  while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
+  const StepProb<T> q = probs[pid];
+  DevState* const st = q.st;
+  // uniform per problem and unchanged during the launch: all or none of a
+  // problem's workgroups take part
+  if (st->done) return;
+  const int nblk = q.nblk, Tp = nblk * TB;
+  const int nrt = (q.n + TB - 1) / TB;
+  const int bid = blockIdx.x - offs[pid];  // no XCD remap: the id order is the dependency order
+  const int rt = bid % nrt, k = nblk - 1 - bid / nrt;
+  const int r0 = rt * TB, nrows = min(TB, q.n - r0);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int32_t* const flag = q.flow + (size_t)rt * nblk;
+  T* const tile = q.M + (size_t)r0 * Tp + (size_t)k * TB;
+  acc_t acc[4];
+  T rf[16], rl[16], rx[16];
+  // the accumulators hold -G_k so that every product adds in place
+  load_acc<T>(acc, tile, Tp, nrows, lane, w);
+  fetch_block<T>(rx, q.ldiag + (size_t)k * TB * TB, TB, TB, tid);
+  if (k + 1 < nblk) fetch_block<T>(rl, q.V + (size_t)(nblk - 1) * TB * Tp + (size_t)k * TB, Tp, TB, tid);
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) acc[tj] = -acc[tj];
+  // Waits until F_i of this row tile is published; false (for every wave)
+  // once a wait of the problem has stalled.  The barrier also means every
+  // wave is past its reads of S0 / S1 for the previous product.
+  auto wait_ready = [&](int i) -> bool {
+    if (tid == 0) {
+      int spins = 0, bad = 0;
+      while (__hip_atomic_load(flag + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        if ((__hip_atomic_load(&st->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SOLVE_STALL) ||
+            ++spins > spin_limit) {
+          __hip_atomic_fetch_or(&st->flags, (int)FLAG_SOLVE_STALL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          bad = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      stalled = bad;
+    }
+    __syncthreads();
+    return !stalled;
+  };
+  for (int i = nblk - 1; i > k + 1; --i) {
+    if (!wait_ready(i)) return;
+    fetch_block_coherent<T>(rf, q.M + (size_t)r0 * Tp + (size_t)i * TB, Tp, nrows, tid);
+    put_block<T, false>(S1, rl, tid);  // L_ik
+    fetch_block<T>(rl, q.V + (size_t)(i - 1) * TB * Tp + (size_t)k * TB, Tp, TB, tid);  // i - 1 > k
+    put_block<T, true>(S0, rf, tid);  // F_i^T
+    __syncthreads();
+    tile_mma64<T>(acc, S0, S1, lane, w);  // acc += F_i L_ik
+  }
+  // f = acc X_k^T with the columns beyond k + 1; the last column then
+  // enters as F_{k+1} P with P = L_{k+1,k} X_k^T formed while it is still
+  // on its way, so one product follows the last wait.
+  if (k + 1 < nblk) __syncthreads();  // every wave is past its reads of S0 / S1
+  acc_to_lds_t<T>(acc, S0, lane, w);
+  put_block<T, true>(S1, rx, tid);  // X_k^T
+  __syncthreads();
+  acc_t f[4];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) f[tj] = acc_t{0, 0, 0, 0};
+  tile_mma64<T>(f, S0, S1, lane, w);
+  if (k + 1 < nblk) {
+    __syncthreads();
+    put_block<T, true>(S0, rl, tid);  // L_{k+1,k}^T
+    __syncthreads();
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[tj] = acc_t{0, 0, 0, 0};
+    tile_mma64<T>(acc, S0, S1, lane, w);  // P
+    __syncthreads();
+    acc_to_lds<T>(acc, S1, lane, w);  // B operand P
+    if (!wait_ready(k + 1)) return;
+    fetch_block_coherent<T>(rf, q.M + (size_t)r0 * Tp + (size_t)(k + 1) * TB, Tp, nrows, tid);
+    put_block<T, true>(S0, rf, tid);  // F_{k+1}^T
+    __syncthreads();
+    tile_mma64<T>(f, S0, S1, lane, w);
+  }
+  // f = -(G_k - sum_{i > k} F_i L_ik) X_k^T = -F_k
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) f[tj] = -f[tj];
+  store_acc_coherent<T>(f, tile, Tp, nrows, lane, w);
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores of F_k are acknowledged
+  __syncthreads();
+  if (tid == 0) __hip_atomic_store(flag + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 int step_tiles(int mode, int nblk, int n, StepCfg c) {
   const int nrt = (n + TB - 1) / TB;
   switch (mode) {
     case STEP_CHOL: return chol_tiles(nblk, c.pw, c.pc, c.tc);
     case STEP_FWD: return fwd_tiles(nblk, nrt, c.pw, c.pf, c.tf);
     case STEP_CHOL_FWD: return chol_tiles(nblk, c.pw, c.pc, c.tc) + fwd_tiles(nblk, nrt, c.pw, c.pf, c.tf);
-    case STEP_BWD2: return bwd2_tiles(nblk, nrt, c.tf);
+    case STEP_FLOW_RESET: return 1;
+    case STEP_BWD_FLOW: return nrt * nblk;
     default: return bwd_tiles(nblk, nrt, c.pw, c.pf, c.tf);
   }
 }
@@ -782,8 +844,11 @@ void step_group(hipStream_t s, int mode, const StepProb<T>* probs, const int* of
     case STEP_BWD:
       hipLaunchKernelGGL((step_kernel<T, STEP_BWD>), grid, block, 0, s, probs, offs, nprob, cfg, retry_pass);
       break;
-    case STEP_BWD2:
-      hipLaunchKernelGGL((step_kernel<T, STEP_BWD2>), grid, block, 0, s, probs, offs, nprob, cfg, retry_pass);
+    case STEP_FLOW_RESET:  // one workgroup per problem
+      hipLaunchKernelGGL((flow_reset_kernel<T>), dim3(nprob), block, 0, s, probs);
+      break;
+    case STEP_BWD_FLOW:
+      hipLaunchKernelGGL((bwd_flow_kernel<T>), grid, block, 0, s, probs, offs, nprob, FLOW_SPIN_LIMIT);
       break;
     default:
       hipLaunchKernelGGL((step_kernel<T, STEP_CHOL_FWD>), grid, block, 0, s, probs, offs, nprob, cfg,
@@ -859,9 +924,9 @@ std::vector<SolveItem> solve_schedule(int sched, int max_nblk, int pw) {
       break;
     default:
       if (P == 1) {
-        // one level: the last block column, then two columns per launch
-        step(STEP_BWD, -1, 0, 0, 0);
-        for (int t = 1; t <= max_nblk / 2; ++t) step(STEP_BWD2, -1, 0, 0, t);
+        // one level: the whole solve as one dataflow launch
+        step(STEP_FLOW_RESET, -1, 0, 0, 0);
+        step(STEP_BWD_FLOW, -1, 0, 0, 0);
         break;
       }
       for (int p = P - 1; p >= 0; --p) {

@@ -25,6 +25,7 @@ __device__ __forceinline__ gptr<T> as_global(T* p) {
 enum {
   FLAG_NOT_SPD = 1,      // a Cholesky pivot was <= 0 or not finite
   FLAG_NONFINITE = 2,    // a non-finite value reached the fit
+  FLAG_SOLVE_STALL = 4,  // a wait of the dataflow solve passed its spin limit
 };
 
 // Per-plan device state (lives in the caller's workspace).

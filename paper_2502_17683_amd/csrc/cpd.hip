@@ -52,6 +52,7 @@ struct Bufs {
   T* ldiag;
   T* diagL;
   T* lam;
+  int32_t* flow;  // ready flags of the dataflow backward solve
 };
 
 struct Prob {
@@ -212,6 +213,7 @@ void carve_typed(Layout& L, Prob& q, Bufs<T>& b, bool own_inputs) {
   b.ldiag = (T*)L.take(sizeof(T) * (size_t)q.nblk * 64 * 64);
   b.diagL = (T*)L.take(sizeof(T) * (size_t)Tp);
   b.lam = (T*)L.take(sizeof(T) * (size_t)Tp);
+  b.flow = (int32_t*)L.take(sizeof(int32_t) * (size_t)((q.nmax + 63) / 64) * q.nblk);
 }
 
 // Split-BF16 buffers; X and Z splits are shared between problems (and
@@ -442,7 +444,7 @@ void build_typed(TableBuilder& tb, cpd_plan_s* p, Bufs<T> Prob::*bufs, bool gate
             v->back().want = 1;
           }
       }
-      sp.push_back({b.V, b.ldiag, b.diagL, b.Msol, q.st, q.nblk, q.n[n]});
+      sp.push_back({b.V, b.ldiag, b.diagL, b.Msol, q.st, q.nblk, q.n[n], b.flow});
       const T* g[3];
       int c = 0;
       for (int m = 0; m < 4; ++m)
@@ -973,6 +975,7 @@ bool any_promote(const cpd_plan_s* p) {
   return false;
 }
 int status_from_flags(int flags) {
+  if (flags & FLAG_SOLVE_STALL) return CPD_ERR_HIP;
   if (flags & FLAG_NOT_SPD) return CPD_ERR_NOT_SPD;
   if (flags & FLAG_NONFINITE) return CPD_ERR_NONFINITE;
   return CPD_OK;

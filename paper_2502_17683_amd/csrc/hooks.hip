@@ -56,7 +56,7 @@ size_t solve_ws(int R, int n) {
   const int nblk = (R + 63) / 64, Tp = nblk * 64;
   return al(sizeof(DevState)) + al(sizeof(T) * (size_t)Tp * Tp) + al(sizeof(T) * (size_t)nblk * 4096) +
          al(sizeof(T) * Tp) + al(sizeof(T) * (size_t)n * Tp) + al(sizeof(StepProb<T>)) + al(sizeof(int) * 2) +
-         al(sizeof(GemmArgs<T>));
+         al(sizeof(GemmArgs<T>)) + al(sizeof(int32_t) * (size_t)((n + 63) / 64) * nblk);
 }
 
 // One-problem run of the blocked factorisation, forward and backward solves
@@ -73,11 +73,12 @@ cpd_status solve_impl(int R, int n, const T* V, const T* M, T* F, void* ws, hipS
   T* Mp = (T*)b; b += al(sizeof(T) * (size_t)n * Tp);
   StepProb<T>* prob = (StepProb<T>*)b; b += al(sizeof(StepProb<T>));
   int* offs = (int*)b; b += al(sizeof(int) * 2);
-  GemmArgs<T>* gtab = (GemmArgs<T>*)b;
+  GemmArgs<T>* gtab = (GemmArgs<T>*)b; b += al(sizeof(GemmArgs<T>));
+  int32_t* flow = (int32_t*)b;
   hipLaunchKernelGGL(init_state, dim3(1), dim3(64), 0, s, st);
   hipLaunchKernelGGL((pad_square<T>), dim3(grid_of((size_t)Tp * Tp)), dim3(256), 0, s, V, R, Tp, Vp);
   hipLaunchKernelGGL((pad_rows<T>), dim3(grid_of((size_t)n * Tp)), dim3(256), 0, s, M, n, R, Tp, Mp);
-  StepProb<T> hp{Vp, ldiag, diagL, Mp, st, nblk, n};
+  StepProb<T> hp{Vp, ldiag, diagL, Mp, st, nblk, n, flow};
   if (hipMemcpyAsync(prob, &hp, sizeof(hp), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
   for (int sched : {SCHED_CHOL, SCHED_FWD, SCHED_BWD}) {
     for (const SolveItem& it : solve_schedule(sched, nblk, pw)) {
@@ -108,6 +109,7 @@ cpd_status solve_impl(int R, int n, const T* V, const T* M, T* F, void* ws, hipS
   if (hipMemcpyAsync(&h, st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess) return CPD_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return CPD_ERR_HIP;
   if (failed) *failed = h.chol_fail;
+  if (h.flags & FLAG_SOLVE_STALL) return CPD_ERR_HIP;
   return h.chol_fail ? CPD_ERR_NOT_SPD : CPD_OK;
 }
 }  // namespace

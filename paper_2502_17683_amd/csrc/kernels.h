@@ -94,8 +94,16 @@ struct StepProb {
   DevState* st;
   int nblk;
   int n;
+  int32_t* flow;  // ready flags of the dataflow backward solve, ceil(n / 64) x nblk
 };
-enum StepMode { STEP_CHOL = 0, STEP_FWD = 1, STEP_BWD = 2, STEP_CHOL_FWD = 3, STEP_BWD2 = 4 };
+enum StepMode {
+  STEP_CHOL = 0,
+  STEP_FWD = 1,
+  STEP_BWD = 2,
+  STEP_CHOL_FWD = 3,
+  STEP_FLOW_RESET = 4,  // clears the ready flags (one workgroup per problem)
+  STEP_BWD_FLOW = 5     // the whole one-level backward solve as one dataflow launch
+};
 
 // Two-level blocking: the 64-wide block columns are grouped into panels of
 // pw blocks.  Inside a panel the step kernel works one block column per
@@ -142,9 +150,8 @@ bool panel_gemm(int kind, const StepProb<T>& q, int pw, int p, GemmArgs<T>& g);
 //                   forward update of panel p - 1.  One-level (pw >=
 //                   max_nblk): one block column behind.
 //   SCHED_FWD       forward solve alone;  SCHED_BWD  backward solve (panels
-//                   from the last one down; one level: after the launch
-//                   that solves the last block column, STEP_BWD2 launches
-//                   that solve two block columns each).
+//                   from the last one down; one level: a flag reset and one
+//                   dataflow launch, STEP_BWD_FLOW).
 enum SolveSched { SCHED_CHOL = 0, SCHED_CHOL_FWD = 1, SCHED_FWD = 2, SCHED_BWD = 3 };
 struct SolveItem {
   int mode;
