@@ -817,6 +817,221 @@ __global__ __launch_bounds__(256, 2) void bwd_flow_kernel(const StepProb<T>* pro
   if (tid == 0) __hip_atomic_store(flag + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ------------------------- dataflow factorisation with the forward solve
+// One launch holds, block column by block column, the lower tiles (i, k) of
+// the factorisation and the tiles (rt, k) of the forward solve G L^T = M:
+//
+//   L_ik = (A_ik - sum_{j<k} L_ij L_kj^T) L_kk^{-T},
+//   G_k  = (M_k  - sum_{j<k} G_j  L_kj^T) X_k,        X_k = L_kk^{-T}.
+//
+// A workgroup takes the products of the earlier columns as their ready
+// flags appear.  As in the per-step form, every workgroup of column k
+// factors the diagonal block itself, so the chain from one column to the
+// next is a single hop: the diagonal workgroup publishes D_k updated
+// through column k - 2 early, and each workgroup applies column k - 1
+// (the same product in every workgroup, so all hold the same L_kk),
+// factors, and solves its tile.  The diagonal workgroup also forms and
+// publishes X_k for the forward solve.  Every wait is on a lower workgroup
+// id (columns in order; in a column the diagonal tile first, the forward
+// tiles last), so the launch cannot deadlock; waits are bounded as in the
+// backward solve.
+template <typename T>
+__device__ __forceinline__ void load_acc_coherent(typename Acc4<T>::type acc[4], const T* g, size_t ld, int lane,
+                                                  int w) {
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[tj][r] = coherent_load<T>(g + (size_t)acc_row<T>(lane, w, r) * ld + acc_col(lane, tj));
+}
+template <typename T>
+__device__ __forceinline__ void store_b4_coherent(const T s[16], T* g, size_t ld, int g4, int j) {
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) coherent_store<T>(g + (size_t)(4 * g4 + ii) * ld + j + 16 * v, s[4 * ii + v]);
+}
+__host__ __device__ inline int chol_fwd_flow_tiles(int nblk, int nrt) { return nblk * (nblk + 1) / 2 + nrt * nblk; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void cflow_reset_kernel(const StepProb<T>* probs) {
+  const StepProb<T>& q = probs[blockIdx.x];
+  const int nf = ((q.n + TB - 1) / TB) * q.nblk, nc = (q.nblk + 2) * q.nblk;
+  const gptr<int32_t> f = as_global(q.flow), c = as_global(q.cflow);
+  for (int e = threadIdx.x; e < nf; e += 256) f[e] = 0;
+  for (int e = threadIdx.x; e < nc; e += 256) c[e] = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>* probs, const int* offs,
+                                                               int nprob, int spin_limit) {
+  typedef typename Acc4<T>::type acc_t;
+  __shared__ T S0[TB * LDT];
+  __shared__ T S1[TB * LDT];
+  __shared__ __attribute__((aligned(16))) T colbuf[8 * TB];
+  __shared__ T invd[TB];
+  __shared__ int stalled;
+  int pid = 0;
+  while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
+  const StepProb<T> q = probs[pid];
+  DevState* const st = q.st;
+  // uniform per problem and unchanged during the launch
+  if (st->done || st->chol_fail) return;
+  const int nblk = q.nblk, Tp = nblk * TB, nrt = (q.n + TB - 1) / TB;
+  int bid = blockIdx.x - offs[pid];
+  int k = 0;
+  while (bid >= nblk - k + nrt) {
+    bid -= nblk - k + nrt;
+    ++k;
+  }
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int sr = tid >> 2, q0 = tid & 3;   // strip layout (diagonal factorisation)
+  const int bg = tid >> 4, bj = tid & 15;  // block-4 layout (triangular solves)
+  int32_t* const lfl = q.cflow;                // [i nblk + j]: L_ij stored
+  int32_t* const dfl = q.cflow + nblk * nblk;  // [k]: D_k through column k - 2 stored
+  int32_t* const xfl = dfl + nblk;             // [k]: X_k stored
+  auto spin = [&](const int32_t* f) -> bool {
+    int spins = 0;
+    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      if ((__hip_atomic_load(&st->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SOLVE_STALL) ||
+          ++spins > spin_limit) {
+        __hip_atomic_fetch_or(&st->flags, (int)FLAG_SOLVE_STALL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+  };
+  // waits for one or two flags; false (for every wave) once the problem has
+  // stalled.  The barrier also means every wave is past its reads of S0 / S1.
+  auto wait = [&](const int32_t* a, const int32_t* b) -> bool {
+    if (tid == 0) stalled = !(spin(a) && (b == nullptr || spin(b)));
+    __syncthreads();
+    return !stalled;
+  };
+  auto publish = [&](int32_t* f) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores are acknowledged
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  auto blk = [&](int i, int j) { return q.V + (size_t)i * TB * Tp + (size_t)j * TB; };
+  acc_t acc[4], p[4];
+  T ra[16], rb[16];
+
+  if (bid < nblk - k) {
+    // ---- factorisation tile (i, k)
+    const int i = k + bid;
+    const bool diag = i == k;
+    T* const tile = blk(i, k);
+    load_acc<T>(acc, tile, Tp, TB, lane, w);  // A_ik, written before the launch
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
+    for (int j = 0; j + 1 < k; ++j) {  // columns j <= k - 2
+      if (!wait(lfl + i * nblk + j, diag ? nullptr : lfl + k * nblk + j)) return;
+      fetch_block_coherent<T>(ra, blk(i, j), Tp, TB, tid);
+      if (!diag) fetch_block_coherent<T>(rb, blk(k, j), Tp, TB, tid);
+      put_block<T, true>(S0, ra, tid);
+      if (!diag) put_block<T, true>(S1, rb, tid);
+      __syncthreads();
+      tile_mma64<T>(p, S0, diag ? S0 : S1, lane, w);  // += L_ij L_kj^T
+    }
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[tj] -= p[tj];
+    acc_t dd[4];
+    if (diag) {
+      if (k >= 2) {
+        store_acc_coherent<T>(acc, q.dpart + (size_t)k * TB * TB, TB, TB, lane, w);
+        publish(dfl + k);
+      }
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) dd[tj] = acc[tj];
+    } else if (k >= 2) {
+      if (!wait(dfl + k, nullptr)) return;
+      load_acc_coherent<T>(dd, q.dpart + (size_t)k * TB * TB, TB, lane, w);
+    } else {
+      load_acc<T>(dd, blk(k, k), Tp, TB, lane, w);  // A_kk: no earlier columns to apply
+    }
+    if (k >= 1) {
+      // column k - 1: the own tile and D_k
+      if (!wait(lfl + i * nblk + k - 1, diag ? nullptr : lfl + k * nblk + k - 1)) return;
+      __builtin_amdgcn_s_setprio(3);  // the chain
+      fetch_block_coherent<T>(rb, blk(k, k - 1), Tp, TB, tid);
+      if (!diag) fetch_block_coherent<T>(ra, blk(i, k - 1), Tp, TB, tid);
+      put_block<T, true>(S1, rb, tid);
+      if (!diag) put_block<T, true>(S0, ra, tid);
+      __syncthreads();
+      if (!diag) {
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
+        tile_mma64<T>(p, S0, S1, lane, w);
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) acc[tj] -= p[tj];
+      }
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
+      tile_mma64<T>(p, S1, S1, lane, w);
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) dd[tj] -= p[tj];
+    }
+    __syncthreads();  // every wave is past its reads of S0 / S1
+    acc_to_lds<T>(dd, S1, lane, w);
+    if (!diag) acc_to_lds<T>(acc, S0, lane, w);
+    __syncthreads();
+    T d[16];
+    lds_to_strip<T>(S1, d, sr, q0);
+    __syncthreads();
+    const bool ok = strip_potrf4<T>(d, S1, invd, colbuf, sr, q0);  // S1 = L_kk
+    T s[16];
+    if (diag) {
+      if (!ok && tid == 0) atomicExch(&st->chol_fail, 1);
+      if (tid < TB) as_global(q.diagL)[k * TB + tid] = S1[tid * LDT + tid];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) s[4 * ii + v] = (4 * bg + ii == bj + 16 * v) ? T(1) : T(0);
+      b4_fwd<T>(s, S1, invd, bj);  // X_k
+      store_b4_coherent<T>(s, q.ldiag + (size_t)k * TB * TB, TB, bg, bj);
+      publish(xfl + k);
+      return;
+    }
+    lds_to_b4<T>(S0, s, bg, bj);
+    b4_fwd<T>(s, S1, invd, bj);  // L_ik
+    store_b4_coherent<T>(s, tile, Tp, bg, bj);
+    publish(lfl + i * nblk + k);
+    return;
+  }
+
+  // ---- forward-solve tile (rt, k)
+  const int rt = bid - (nblk - k);
+  const int r0 = rt * TB, nrows = min(TB, q.n - r0);
+  int32_t* const gfl = q.flow + (size_t)rt * nblk;
+  T* const tile = q.M + (size_t)r0 * Tp + (size_t)k * TB;
+  load_acc<T>(acc, tile, Tp, nrows, lane, w);  // M_k, written before the launch
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
+  for (int j = 0; j < k; ++j) {
+    if (!wait(gfl + j, lfl + k * nblk + j)) return;
+    fetch_block_coherent<T>(ra, q.M + (size_t)r0 * Tp + (size_t)j * TB, Tp, nrows, tid);  // G_j
+    fetch_block_coherent<T>(rb, blk(k, j), Tp, TB, tid);                                 // L_kj
+    put_block<T, true>(S0, ra, tid);
+    put_block<T, true>(S1, rb, tid);
+    __syncthreads();
+    tile_mma64<T>(p, S0, S1, lane, w);  // += G_j L_kj^T
+  }
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) acc[tj] -= p[tj];
+  if (!wait(xfl + k, nullptr)) return;
+  __builtin_amdgcn_s_setprio(3);
+  fetch_block_coherent<T>(ra, q.ldiag + (size_t)k * TB * TB, TB, TB, tid);
+  acc_to_lds_t<T>(acc, S0, lane, w);
+  put_block<T, false>(S1, ra, tid);  // X_k
+  __syncthreads();
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
+  tile_mma64<T>(p, S0, S1, lane, w);  // G_k
+  store_acc_coherent<T>(p, tile, Tp, nrows, lane, w);
+  publish(gfl + k);
+}
+
 int step_tiles(int mode, int nblk, int n, StepCfg c) {
   const int nrt = (n + TB - 1) / TB;
   switch (mode) {
@@ -825,6 +1040,8 @@ int step_tiles(int mode, int nblk, int n, StepCfg c) {
     case STEP_CHOL_FWD: return chol_tiles(nblk, c.pw, c.pc, c.tc) + fwd_tiles(nblk, nrt, c.pw, c.pf, c.tf);
     case STEP_FLOW_RESET: return 1;
     case STEP_BWD_FLOW: return nrt * nblk;
+    case STEP_CFLOW_RESET: return 1;
+    case STEP_CHOL_FWD_FLOW: return chol_fwd_flow_tiles(nblk, nrt);
     default: return bwd_tiles(nblk, nrt, c.pw, c.pf, c.tf);
   }
 }
@@ -849,6 +1066,12 @@ void step_group(hipStream_t s, int mode, const StepProb<T>* probs, const int* of
       break;
     case STEP_BWD_FLOW:
       hipLaunchKernelGGL((bwd_flow_kernel<T>), grid, block, 0, s, probs, offs, nprob, FLOW_SPIN_LIMIT);
+      break;
+    case STEP_CFLOW_RESET:  // one workgroup per problem
+      hipLaunchKernelGGL((cflow_reset_kernel<T>), dim3(nprob), block, 0, s, probs);
+      break;
+    case STEP_CHOL_FWD_FLOW:
+      hipLaunchKernelGGL((chol_fwd_flow_kernel<T>), grid, block, 0, s, probs, offs, nprob, FLOW_SPIN_LIMIT);
       break;
     default:
       hipLaunchKernelGGL((step_kernel<T, STEP_CHOL_FWD>), grid, block, 0, s, probs, offs, nprob, cfg,
@@ -907,8 +1130,9 @@ std::vector<SolveItem> solve_schedule(int sched, int max_nblk, int pw) {
       break;
     case SCHED_CHOL_FWD:
       if (P == 1) {
-        // one level: forward step t - 1 rides with factorisation step t
-        for (int t = 0; t <= max_nblk; ++t) step(STEP_CHOL_FWD, 0, t, 0, t - 1);
+        // one level: one dataflow launch
+        step(STEP_CFLOW_RESET, -1, 0, -1, 0);
+        step(STEP_CHOL_FWD_FLOW, -1, 0, -1, 0);
         break;
       }
       for (int p = 0; p <= P; ++p) {

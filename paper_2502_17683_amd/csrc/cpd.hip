@@ -52,7 +52,9 @@ struct Bufs {
   T* ldiag;
   T* diagL;
   T* lam;
-  int32_t* flow;  // ready flags of the dataflow backward solve
+  int32_t* flow;   // ready flags of the dataflow solves
+  int32_t* cflow;  // ready flags of the dataflow factorisation
+  T* dpart;        // partly updated diagonal blocks of the dataflow factorisation
 };
 
 struct Prob {
@@ -214,6 +216,8 @@ void carve_typed(Layout& L, Prob& q, Bufs<T>& b, bool own_inputs) {
   b.diagL = (T*)L.take(sizeof(T) * (size_t)Tp);
   b.lam = (T*)L.take(sizeof(T) * (size_t)Tp);
   b.flow = (int32_t*)L.take(sizeof(int32_t) * (size_t)((q.nmax + 63) / 64) * q.nblk);
+  b.cflow = (int32_t*)L.take(sizeof(int32_t) * (size_t)(q.nblk + 2) * q.nblk);
+  b.dpart = (T*)L.take(sizeof(T) * (size_t)q.nblk * 64 * 64);
 }
 
 // Split-BF16 buffers; X and Z splits are shared between problems (and
@@ -444,7 +448,7 @@ void build_typed(TableBuilder& tb, cpd_plan_s* p, Bufs<T> Prob::*bufs, bool gate
             v->back().want = 1;
           }
       }
-      sp.push_back({b.V, b.ldiag, b.diagL, b.Msol, q.st, q.nblk, q.n[n], b.flow});
+      sp.push_back({b.V, b.ldiag, b.diagL, b.Msol, q.st, q.nblk, q.n[n], b.flow, b.cflow, b.dpart});
       const T* g[3];
       int c = 0;
       for (int m = 0; m < 4; ++m)

@@ -56,7 +56,8 @@ size_t solve_ws(int R, int n) {
   const int nblk = (R + 63) / 64, Tp = nblk * 64;
   return al(sizeof(DevState)) + al(sizeof(T) * (size_t)Tp * Tp) + al(sizeof(T) * (size_t)nblk * 4096) +
          al(sizeof(T) * Tp) + al(sizeof(T) * (size_t)n * Tp) + al(sizeof(StepProb<T>)) + al(sizeof(int) * 2) +
-         al(sizeof(GemmArgs<T>)) + al(sizeof(int32_t) * (size_t)((n + 63) / 64) * nblk);
+         al(sizeof(GemmArgs<T>)) + al(sizeof(int32_t) * (size_t)((n + 63) / 64) * nblk) +
+         al(sizeof(int32_t) * (size_t)(nblk + 2) * nblk) + al(sizeof(T) * (size_t)nblk * 4096);
 }
 
 // One-problem run of the blocked factorisation, forward and backward solves
@@ -74,13 +75,15 @@ cpd_status solve_impl(int R, int n, const T* V, const T* M, T* F, void* ws, hipS
   StepProb<T>* prob = (StepProb<T>*)b; b += al(sizeof(StepProb<T>));
   int* offs = (int*)b; b += al(sizeof(int) * 2);
   GemmArgs<T>* gtab = (GemmArgs<T>*)b; b += al(sizeof(GemmArgs<T>));
-  int32_t* flow = (int32_t*)b;
+  int32_t* flow = (int32_t*)b; b += al(sizeof(int32_t) * (size_t)((n + 63) / 64) * nblk);
+  int32_t* cflow = (int32_t*)b; b += al(sizeof(int32_t) * (size_t)(nblk + 2) * nblk);
+  T* dpart = (T*)b;
   hipLaunchKernelGGL(init_state, dim3(1), dim3(64), 0, s, st);
   hipLaunchKernelGGL((pad_square<T>), dim3(grid_of((size_t)Tp * Tp)), dim3(256), 0, s, V, R, Tp, Vp);
   hipLaunchKernelGGL((pad_rows<T>), dim3(grid_of((size_t)n * Tp)), dim3(256), 0, s, M, n, R, Tp, Mp);
-  StepProb<T> hp{Vp, ldiag, diagL, Mp, st, nblk, n, flow};
+  StepProb<T> hp{Vp, ldiag, diagL, Mp, st, nblk, n, flow, cflow, dpart};
   if (hipMemcpyAsync(prob, &hp, sizeof(hp), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
-  for (int sched : {SCHED_CHOL, SCHED_FWD, SCHED_BWD}) {
+  for (int sched : {SCHED_CHOL_FWD, SCHED_BWD}) {
     for (const SolveItem& it : solve_schedule(sched, nblk, pw)) {
       // tables are passed through a tiny per-launch upload (this hook is not
       // performance-critical)

@@ -94,15 +94,19 @@ struct StepProb {
   DevState* st;
   int nblk;
   int n;
-  int32_t* flow;  // ready flags of the dataflow backward solve, ceil(n / 64) x nblk
+  int32_t* flow;   // ready flags of the dataflow solves, ceil(n / 64) x nblk
+  int32_t* cflow;  // ready flags of the dataflow factorisation, nblk^2 + 2 nblk
+  T* dpart;        // diagonal blocks updated through column k - 2, nblk x 64 x 64
 };
 enum StepMode {
   STEP_CHOL = 0,
   STEP_FWD = 1,
   STEP_BWD = 2,
   STEP_CHOL_FWD = 3,
-  STEP_FLOW_RESET = 4,  // clears the ready flags (one workgroup per problem)
-  STEP_BWD_FLOW = 5     // the whole one-level backward solve as one dataflow launch
+  STEP_FLOW_RESET = 4,     // clears the solve's ready flags (one workgroup per problem)
+  STEP_BWD_FLOW = 5,       // the whole one-level backward solve as one dataflow launch
+  STEP_CFLOW_RESET = 6,    // clears the factorisation's and the solve's ready flags
+  STEP_CHOL_FWD_FLOW = 7   // one-level factorisation + forward solve as one dataflow launch
 };
 
 // Two-level blocking: the 64-wide block columns are grouped into panels of
