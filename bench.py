@@ -201,14 +201,14 @@ def main():
     tflops = {p: mtt / (mttkrp_ms(kt[p]) * 1e-3) / 1e12 for p in kt}
     core_ms = kt["mixed"]["core"]
     core_achieved = fl_core / (core_ms * 1e-3)
-    # dominant kernel of the mixed sweep: the fused Cholesky + forward-solve
-    # step (nblk + 1 launches per mode update, FP64 matrix cores): Cholesky
-    # R^3 / 3 flops plus the forward triangular solve of n rows, n R^2
-    nblk = (Rc + 63) // 64
+    # dominant kernel of the mixed sweep: the dataflow Cholesky factorisation
+    # fused with the forward solve (one launch per mode update, after a flag
+    # reset of ~5 us that stays in the timing; FP64 matrix cores): R^3 / 3
+    # flops plus the forward triangular solve of n rows, n R^2
     fl_factor_fwd = Rc ** 3 / 3.0 + 1.0 * N * Rc * Rc
-    launches = nblk + 1
-    per_launch_ms = kt["mixed"]["factor_fwd"] / launches
-    fac_achieved = (fl_factor_fwd / launches) / (per_launch_ms * 1e-3)
+    launches = 1
+    per_launch_ms = kt["mixed"]["factor_fwd"] - kt["mixed"]["form_v"]
+    fac_achieved = fl_factor_fwd / (per_launch_ms * 1e-3)
     sweep_ms = {p: 4 * (k["projection"] + k["backprojection"] + k["gram"] + k["solve"]) + 2 * k["core"]
                 for p, k in kt.items()}
 
@@ -254,11 +254,11 @@ def main():
         "f_ref": f_ref, "target_fit": target,
         "mttkrp_tflops": tflops,
         "kernel_ms": kt,
-        "roofline": {"bound": "mfma", "kernel": "step_kernel<double, STEP_CHOL_FWD> (Cholesky step "
-                                                  "fused with the forward triangular solve, FP64)",
+        "roofline": {"bound": "mfma", "kernel": "chol_fwd_flow_kernel<double> (dataflow Cholesky "
+                                                  "factorisation fused with the forward solve, FP64)",
                      "achieved": fac_achieved / 1e12, "peak": MFMA_PEAK["f64"] / 1e12,
                      "unit": "TFLOP/s", "frac": fac_achieved / MFMA_PEAK["f64"],
-                     "traffic": measured_traffic("step_kernel<double,3>"),
+                     "traffic": measured_traffic("chol_fwd_flow_kernel<double>"),
                      "avg_launch_us": per_launch_ms * 1e3, "launches_per_mode": launches},
         "roofline_core_product": {"bound": "mfma", "kernel": "gemm_split_kernel<true,false> (core product, "
                                                             "split BF16, useful flops)",

@@ -174,14 +174,16 @@ cpd_status cpd_mttkrp(cpd_plan p, int32_t mode, double* M_dev);
 
 /* Measurement hook: average device time (ms, hipEvents on the plan's
  * stream, `reps` back-to-back repetitions after one warm-up) of each kernel
- * family of the sweep at the plan's shapes, for mode 0 (ms_out: 7 doubles):
+ * family of the sweep at the plan's shapes, for mode 0 (ms_out: 8 doubles):
  *   [0] projection X^T F,  [1] core product Z (W o W),
  *   [2] back-projection X (W o Y),  [3] Gram F^T F (lower triangle),
  *   [4] whole normal-equation solve (V, factorisation fused with the
  *       forward triangular solve, backward solve, normalisation),
- *   [5] V + factorisation/forward solve (nblk + 1 launches of the fused
- *       step kernel), [6] backward solve (nblk launches),
- *   with nblk = ceil(r_cp / 64).
+ *   [5] V + factorisation/forward solve, [6] backward solve,
+ *   [7] V alone (the Hadamard product of the Grams).
+ *   For a one-level solve (r_cp up to the panel threshold) the
+ *   factorisation/forward solve and the backward solve are one dataflow
+ *   launch each, after a flag reset.
  * Overwrites the plan's intermediate buffers and resets its stopping state:
  * re-initialise the plan before using it again.  Synchronises. */
 cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out);

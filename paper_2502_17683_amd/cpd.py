@@ -166,12 +166,12 @@ class CPD:
 
     def kernel_times(self, reps=5):
         """Average ms of (projection, core product, back-projection, Gram,
-        solve, factorisation + forward solve, backward solve) at this plan's
-        shapes.  Invalidates the plan's state."""
-        out = (ctypes.c_double * 7)()
+        solve, V + factorisation + forward solve, backward solve, V) at this
+        plan's shapes.  Invalidates the plan's state."""
+        out = (ctypes.c_double * 8)()
         check(self.lib.cpd_kernel_times(self.plan, int(reps), out), "cpd_kernel_times")
         return dict(zip(("projection", "core", "backprojection", "gram", "solve", "factor_fwd",
-                         "solve_bwd"), list(out)))
+                         "solve_bwd", "form_v"), list(out)))
 
     def close(self):
         if getattr(self, "plan", None) is not None and self.plan.value:
@@ -281,10 +281,10 @@ class CPDBatch:
         return {k: getattr(st, k) for k, _ in CpdStats._fields_}
 
     def kernel_times(self, reps=5):
-        out = (ctypes.c_double * 7)()
+        out = (ctypes.c_double * 8)()
         check(self.lib.cpd_kernel_times(self.plan, int(reps), out), "cpd_kernel_times")
         return dict(zip(("projection", "core", "backprojection", "gram", "solve", "factor_fwd",
-                         "solve_bwd"), list(out)))
+                         "solve_bwd", "form_v"), list(out)))
 
     def autotune_log(self):
         n = self.lib.cpd_autotune_log(self.plan, None, 0)

@@ -1418,8 +1418,13 @@ cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out) {
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   const bool f32 = p->prec == CPD_FP32;
-  for (int which = 0; which < 7; ++which) {
+  for (int which = 0; which < 8; ++which) {
     auto body = [&]() {
+      if (which == 7) {
+        if (f32) form_v_group<float>(s, (const FormVArgs<float>*)p->formv[0], p->count, p->maxTp, 0);
+        else form_v_group<double>(s, (const FormVArgs<double>*)p->formv[0], p->count, p->maxTp, 0);
+        return;
+      }
       if (which >= 4) {
         // normal-equation solve of mode 0: V, factorisation fused with the
         // forward solve, backward solve, normalisation
