@@ -43,7 +43,7 @@ def mttkrp_flops(n, r_thc, r_cp):
     return 4.0 * r_thc * r_cp * sum(n) + 4.0 * r_thc * r_thc * r_cp
 
 
-def measured_traffic(kernel, profile="step_kernel_chol_fwd_traffic_n800_r4000.md"):
+def measured_traffic(kernel, profile="chol_fwd_flow_traffic_n800_r4000.md"):
     """HBM bytes per launch of `kernel` from a committed PMC summary, or
     None once the kernel's source has changed since the counters were taken."""
     import hashlib
