@@ -723,24 +723,35 @@ __global__ __launch_bounds__(256) void flow_reset_kernel(const StepProb<T>* prob
   for (int e = threadIdx.x; e < cnt; e += 256) f[e] = 0;
 }
 
+// Segment of a grouped dataflow launch holding workgroup bx (see
+// flow_segments): problem, block column, and the index inside the segment.
+__device__ __forceinline__ void flow_segment(const int* seg, int nseg, int bx, int& pid, int& k, int& bid) {
+  int lo = 0, hi = nseg - 1;  // the last segment starting at or before bx
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seg[3 * mid] <= bx) lo = mid;
+    else hi = mid - 1;
+  }
+  pid = seg[3 * lo + 1];
+  k = seg[3 * lo + 2];
+  bid = bx - seg[3 * lo];
+}
+
 template <typename T>
-__global__ __launch_bounds__(256, 2) void bwd_flow_kernel(const StepProb<T>* probs, const int* offs, int nprob,
+__global__ __launch_bounds__(256, 2) void bwd_flow_kernel(const StepProb<T>* probs, const int* seg, int nseg,
                                                        int spin_limit) {
   typedef typename Acc4<T>::type acc_t;
   __shared__ T S0[TB * LDT];
   __shared__ T S1[TB * LDT];
   __shared__ int stalled;
-  int pid = 0;
-  while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
+  int pid, k, rt;  // no XCD remap: the id order is the dependency order
+  flow_segment(seg, nseg, blockIdx.x, pid, k, rt);
   const StepProb<T> q = probs[pid];
   DevState* const st = q.st;
   // uniform per problem and unchanged during the launch: all or none of a
   // problem's workgroups take part
   if (st->done) return;
   const int nblk = q.nblk, Tp = nblk * TB;
-  const int nrt = (q.n + TB - 1) / TB;
-  const int bid = blockIdx.x - offs[pid];  // no XCD remap: the id order is the dependency order
-  const int rt = bid % nrt, k = nblk - 1 - bid / nrt;
   const int r0 = rt * TB, nrows = min(TB, q.n - r0);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int32_t* const flag = q.flow + (size_t)rt * nblk;
@@ -862,27 +873,24 @@ __global__ __launch_bounds__(256) void cflow_reset_kernel(const StepProb<T>* pro
 }
 
 template <typename T>
-__global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>* probs, const int* offs,
-                                                               int nprob, int spin_limit) {
+__global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>* probs, const int* seg,
+                                                               int nseg, int spin_limit) {
   typedef typename Acc4<T>::type acc_t;
   __shared__ T S0[TB * LDT];
   __shared__ T S1[TB * LDT];
   __shared__ __attribute__((aligned(16))) T colbuf[8 * TB];
   __shared__ T invd[TB];
   __shared__ int stalled;
-  int pid = 0;
-  while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
+  int pid, k, bid;
+  flow_segment(seg, nseg, blockIdx.x, pid, k, bid);
   const StepProb<T> q = probs[pid];
   DevState* const st = q.st;
-  // uniform per problem and unchanged during the launch
-  if (st->done || st->chol_fail) return;
+  // Uniform per problem and unchanged during the launch: all or none of a
+  // problem's workgroups take part.  (chol_fail is not a valid gate here:
+  // this launch sets it, and a workgroup that left on it would never
+  // publish its flags.  A failed problem's tiles are discarded later.)
+  if (st->done) return;
   const int nblk = q.nblk, Tp = nblk * TB, nrt = (q.n + TB - 1) / TB;
-  int bid = blockIdx.x - offs[pid];
-  int k = 0;
-  while (bid >= nblk - k + nrt) {
-    bid -= nblk - k + nrt;
-    ++k;
-  }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int sr = tid >> 2, q0 = tid & 3;   // strip layout (diagonal factorisation)
   const int bg = tid >> 4, bj = tid & 15;  // block-4 layout (triangular solves)
@@ -1032,6 +1040,26 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
   publish(gfl + k);
 }
 
+std::vector<int> flow_segments(int mode, const std::vector<int>& nblk, const std::vector<int>& n) {
+  std::vector<int> seg;
+  int start = 0, cmax = 0;
+  for (int b : nblk) cmax = b > cmax ? b : cmax;
+  for (int c = 0; c < cmax; ++c)
+    for (size_t p = 0; p < nblk.size(); ++p) {
+      if (c >= nblk[p]) continue;
+      const int nrt = (n[p] + TB - 1) / TB;
+      const int k = mode == STEP_BWD_FLOW ? nblk[p] - 1 - c : c;
+      seg.push_back(start);
+      seg.push_back((int)p);
+      seg.push_back(k);
+      start += mode == STEP_BWD_FLOW ? nrt : nblk[p] - k + nrt;
+    }
+  seg.push_back(start);
+  seg.push_back(-1);
+  seg.push_back(-1);
+  return seg;
+}
+
 int step_tiles(int mode, int nblk, int n, StepCfg c) {
   const int nrt = (n + TB - 1) / TB;
   switch (mode) {
@@ -1064,13 +1092,13 @@ void step_group(hipStream_t s, int mode, const StepProb<T>* probs, const int* of
     case STEP_FLOW_RESET:  // one workgroup per problem
       hipLaunchKernelGGL((flow_reset_kernel<T>), dim3(nprob), block, 0, s, probs);
       break;
-    case STEP_BWD_FLOW:
+    case STEP_BWD_FLOW:  // offs: segment table, nprob: its segment count
       hipLaunchKernelGGL((bwd_flow_kernel<T>), grid, block, 0, s, probs, offs, nprob, FLOW_SPIN_LIMIT);
       break;
     case STEP_CFLOW_RESET:  // one workgroup per problem
       hipLaunchKernelGGL((cflow_reset_kernel<T>), dim3(nprob), block, 0, s, probs);
       break;
-    case STEP_CHOL_FWD_FLOW:
+    case STEP_CHOL_FWD_FLOW:  // offs: segment table, nprob: its segment count
       hipLaunchKernelGGL((chol_fwd_flow_kernel<T>), grid, block, 0, s, probs, offs, nprob, FLOW_SPIN_LIMIT);
       break;
     default:

@@ -88,7 +88,8 @@ struct GroupOp {
 struct SolveLaunch {
   int mode = -1;          // StepMode, or -1 for the GEMM
   StepCfg cfg{1, -1, 0, -1, 0};
-  int* offs = nullptr;    // device, nprob + 1 prefix sums (step launches)
+  int* offs = nullptr;    // device, nprob + 1 prefix sums (step launches) or segment table
+  int nseg = 0;           // segments of a dataflow launch (0: prefix sums)
   int total = 0;
   GroupOp gemm;
 };
@@ -386,7 +387,17 @@ std::vector<SolveLaunch> build_sched(TableBuilder& tb, int sched, int max_nblk, 
     SolveLaunch L;
     L.mode = it.mode;
     L.cfg = it.cfg;
-    if (it.mode >= 0) {
+    if (it.mode >= 0 && is_flow_mode(it.mode)) {
+      std::vector<int> nb, nr;
+      for (auto& q : sp) {
+        nb.push_back(q.nblk);
+        nr.push_back(q.n);
+      }
+      const std::vector<int> seg = flow_segments(it.mode, nb, nr);
+      L.nseg = (int)seg.size() / 3 - 1;
+      L.total = seg[3 * L.nseg];
+      L.offs = (int*)tb.put(seg);
+    } else if (it.mode >= 0) {
       std::vector<int> offs(1, 0);
       for (auto& q : sp) offs.push_back(offs.back() + step_tiles(it.mode, q.nblk, q.n, it.cfg));
       L.total = offs.back();
@@ -750,7 +761,7 @@ void run_sched(cpd_plan_s* p, hipStream_t s, int n, const std::vector<SolveLaunc
   const StepProb<T>* probs = (const StepProb<T>*)p->steps[n].probs;
   for (const SolveLaunch& L : sched) {
     if (L.mode < 0) run_gemm<T>(p, s, L.gemm);
-    else step_group<T>(s, L.mode, probs, L.offs, p->count, L.total, L.cfg, retry_pass);
+    else step_group<T>(s, L.mode, probs, L.offs, L.nseg > 0 ? L.nseg : p->count, L.total, L.cfg, retry_pass);
   }
 }
 

@@ -55,7 +55,7 @@ template <typename T>
 size_t solve_ws(int R, int n) {
   const int nblk = (R + 63) / 64, Tp = nblk * 64;
   return al(sizeof(DevState)) + al(sizeof(T) * (size_t)Tp * Tp) + al(sizeof(T) * (size_t)nblk * 4096) +
-         al(sizeof(T) * Tp) + al(sizeof(T) * (size_t)n * Tp) + al(sizeof(StepProb<T>)) + al(sizeof(int) * 2) +
+         al(sizeof(T) * Tp) + al(sizeof(T) * (size_t)n * Tp) + al(sizeof(StepProb<T>)) + al(sizeof(int) * 3 * (nblk + 1)) +
          al(sizeof(GemmArgs<T>)) + al(sizeof(int32_t) * (size_t)((n + 63) / 64) * nblk) +
          al(sizeof(int32_t) * (size_t)(nblk + 2) * nblk) + al(sizeof(T) * (size_t)nblk * 4096);
 }
@@ -73,7 +73,7 @@ cpd_status solve_impl(int R, int n, const T* V, const T* M, T* F, void* ws, hipS
   T* diagL = (T*)b; b += al(sizeof(T) * Tp);
   T* Mp = (T*)b; b += al(sizeof(T) * (size_t)n * Tp);
   StepProb<T>* prob = (StepProb<T>*)b; b += al(sizeof(StepProb<T>));
-  int* offs = (int*)b; b += al(sizeof(int) * 2);
+  int* offs = (int*)b; b += al(sizeof(int) * 3 * (nblk + 1));
   GemmArgs<T>* gtab = (GemmArgs<T>*)b; b += al(sizeof(GemmArgs<T>));
   int32_t* flow = (int32_t*)b; b += al(sizeof(int32_t) * (size_t)((n + 63) / 64) * nblk);
   int32_t* cflow = (int32_t*)b; b += al(sizeof(int32_t) * (size_t)(nblk + 2) * nblk);
@@ -88,10 +88,17 @@ cpd_status solve_impl(int R, int n, const T* V, const T* M, T* F, void* ws, hipS
       // tables are passed through a tiny per-launch upload (this hook is not
       // performance-critical)
       if (it.mode >= 0) {
-        int ho[2] = {0, step_tiles(it.mode, nblk, n, it.cfg)};
-        if (hipMemcpyAsync(offs, ho, sizeof(ho), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
+        std::vector<int> tab = {0, step_tiles(it.mode, nblk, n, it.cfg)};
+        int cnt = 1, total = tab[1];
+        if (is_flow_mode(it.mode)) {
+          tab = flow_segments(it.mode, {nblk}, {n});
+          cnt = (int)tab.size() / 3 - 1;
+          total = tab[3 * cnt];
+        }
+        if (hipMemcpyAsync(offs, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+          return CPD_ERR_HIP;
         if (hipStreamSynchronize(s) != hipSuccess) return CPD_ERR_HIP;
-        step_group<T>(s, it.mode, prob, offs, 1, ho[1], it.cfg, 0);
+        step_group<T>(s, it.mode, prob, offs, cnt, total, it.cfg, 0);
         continue;
       }
       for (int h = 0; h < 2; ++h) {

@@ -130,6 +130,18 @@ struct StepCfg {
 inline int panel_count(int nblk, int pw) { return (nblk + pw - 1) / pw; }
 // Workgroups of problem (nblk, n) in a launch of `mode` with `cfg`.
 int step_tiles(int mode, int nblk, int n, StepCfg cfg);
+// Workgroup order of a grouped dataflow launch (STEP_CHOL_FWD_FLOW,
+// STEP_BWD_FLOW) over problems of nblk[p] blocks and n[p] rows: segments of
+// one (problem, block column), block column by block column across the
+// problems (ascending for the factorisation, from each problem's last
+// column down for the backward solve), so every problem advances at the
+// same pace and every wait is on a lower workgroup id.  Int triples
+// (first workgroup, problem, column), then (total workgroups, -1, -1).
+std::vector<int> flow_segments(int mode, const std::vector<int>& nblk, const std::vector<int>& n);
+inline bool is_flow_mode(int mode) { return mode == STEP_CHOL_FWD_FLOW || mode == STEP_BWD_FLOW; }
+// Launches one step of `mode`.  offs: nprob + 1 prefix sums of the
+// problems' workgroups, or for a dataflow mode the segment table, with
+// nprob its segment count.
 template <typename T>
 void step_group(hipStream_t s, int mode, const StepProb<T>* probs, const int* offs, int nprob, int total_tiles,
                 StepCfg cfg, int retry_pass);

@@ -94,6 +94,26 @@ def test_spd_solve_detects_indefinite():
     assert failed
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_spd_solve_early_failure_at_large_size(fp32):
+    """A pivot that fails in the first block column while most workgroups
+    of the dataflow launch have not started: the failure is reported as
+    not-SPD, never as a stalled launch (every workgroup still publishes)."""
+    from paper_2502_17683_amd import CpdError, test_solve
+    R, n = 3000, 200
+    say(f"solve early failure R={R} n={n} fp32={fp32}")
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((R, R + 5))
+    V = A @ A.T / R + 0.5 * np.eye(R)
+    V[5, 5] = -1.0
+    dt = torch.float32 if fp32 else torch.float64
+    try:
+        _, failed = test_solve(to_dev(V, dt), to_dev(rng.standard_normal((n, R)), dt))
+    except CpdError as e:  # a stall would come back as a HIP error
+        pytest.fail(f"solve reported {e}")
+    assert failed
+
+
 @pytest.mark.parametrize("M,N,K", [(37, 29, 50), (256, 130, 300), (800, 1000, 1024)])
 @pytest.mark.parametrize("pair", [False, True])
 @pytest.mark.parametrize("bm", [64, 128])
