@@ -435,6 +435,14 @@ cpd_status cpd_test_gemm(int32_t fp32, int32_t M, int32_t N, int32_t K, const vo
  *   panels of `panel` blocks (0: one level).  Sync; returns CPD_ERR_NOT_SPD
  *   (and *failed = 1) on a non-positive pivot. */
 size_t cpd_test_solve_workspace(int32_t fp32, int32_t R, int32_t n);
+/* cpd_test_flow_spin_limit: sets how many polls a wait of the dataflow
+ *   factorisation and solves makes before it gives up (negative: restore
+ *   the default, 2^20), for launches enqueued afterwards in this process;
+ *   returns the previous value.  A wait that gives up makes the whole
+ *   problem's launch end early and the call report CPD_ERR_HIP (the plan
+ *   needs cpd_init again).  For failure-path tests only: the default never
+ *   gives up on a working device.  Not thread-safe. */
+int32_t cpd_test_flow_spin_limit(int32_t polls);
 cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, const void* M, void* F,
                           void* workspace, size_t ws_bytes, void* stream, int32_t* failed, int32_t panel);
 /* cpd_test_gemm_split: C (M x N, FP64) = A B^T from FP64 A (M x K) and

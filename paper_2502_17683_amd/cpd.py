@@ -329,6 +329,12 @@ def test_gemm(A, B1, B2=None, a_t=False, b_t=False):
     return C
 
 
+def test_flow_spin_limit(polls):
+    """Polls a dataflow-solve wait makes before giving up (negative: the
+    default); returns the previous value.  Failure-path tests only."""
+    return int(_lib.load().cpd_test_flow_spin_limit(int(polls)))
+
+
 def test_solve(V, M, panel=0):
     """F = M V^{-1} through the library's blocked Cholesky and solves
     (panels of `panel` 64-wide blocks; 0: one level)."""

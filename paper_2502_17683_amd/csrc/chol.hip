@@ -672,6 +672,12 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
 // stores to be acknowledged before it sets the flag, and the consumer's
 // reads are issued after it has seen the flag.
 constexpr int FLOW_SPIN_LIMIT = 1 << 20;
+static int g_flow_spin_limit = FLOW_SPIN_LIMIT;  // host side, lowered only by a test hook
+int set_flow_spin_limit(int polls) {
+  const int prev = g_flow_spin_limit;
+  g_flow_spin_limit = polls < 0 ? FLOW_SPIN_LIMIT : polls;
+  return prev;
+}
 
 template <typename T>
 struct Bits;
@@ -1093,13 +1099,13 @@ void step_group(hipStream_t s, int mode, const StepProb<T>* probs, const int* of
       hipLaunchKernelGGL((flow_reset_kernel<T>), dim3(nprob), block, 0, s, probs);
       break;
     case STEP_BWD_FLOW:  // offs: segment table, nprob: its segment count
-      hipLaunchKernelGGL((bwd_flow_kernel<T>), grid, block, 0, s, probs, offs, nprob, FLOW_SPIN_LIMIT);
+      hipLaunchKernelGGL((bwd_flow_kernel<T>), grid, block, 0, s, probs, offs, nprob, g_flow_spin_limit);
       break;
     case STEP_CFLOW_RESET:  // one workgroup per problem
       hipLaunchKernelGGL((cflow_reset_kernel<T>), dim3(nprob), block, 0, s, probs);
       break;
     case STEP_CHOL_FWD_FLOW:  // offs: segment table, nprob: its segment count
-      hipLaunchKernelGGL((chol_fwd_flow_kernel<T>), grid, block, 0, s, probs, offs, nprob, FLOW_SPIN_LIMIT);
+      hipLaunchKernelGGL((chol_fwd_flow_kernel<T>), grid, block, 0, s, probs, offs, nprob, g_flow_spin_limit);
       break;
     default:
       hipLaunchKernelGGL((step_kernel<T, STEP_CHOL_FWD>), grid, block, 0, s, probs, offs, nprob, cfg,

@@ -149,6 +149,8 @@ size_t cpd_test_solve_workspace(int32_t fp32, int32_t R, int32_t n) {
   return fp32 ? solve_ws<float>(R, n) : solve_ws<double>(R, n);
 }
 
+int32_t cpd_test_flow_spin_limit(int32_t polls) { return set_flow_spin_limit(polls); }
+
 cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, const void* M, void* F,
                           void* workspace, size_t ws_bytes, void* stream, int32_t* failed, int32_t panel) {
   if (panel < 0) return CPD_ERR_INVALID_ARG;

@@ -139,6 +139,9 @@ int step_tiles(int mode, int nblk, int n, StepCfg cfg);
 // (first workgroup, problem, column), then (total workgroups, -1, -1).
 std::vector<int> flow_segments(int mode, const std::vector<int>& nblk, const std::vector<int>& n);
 inline bool is_flow_mode(int mode) { return mode == STEP_CHOL_FWD_FLOW || mode == STEP_BWD_FLOW; }
+// Polls a dataflow wait makes before it gives up (negative: the default);
+// returns the previous value.  Applies to launches enqueued afterwards.
+int set_flow_spin_limit(int polls);
 // Launches one step of `mode`.  offs: nprob + 1 prefix sums of the
 // problems' workgroups, or for a dataflow mode the segment table, with
 // nprob its segment count.

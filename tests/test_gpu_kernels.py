@@ -114,6 +114,36 @@ def test_spd_solve_early_failure_at_large_size(fp32):
     assert failed
 
 
+def test_dataflow_wait_gives_up_and_recovers():
+    """With a wait limit of zero polls, every dataflow wait that is not
+    ready at once gives up: the launch still ends and the call returns
+    either the right solution or CPD_ERR_HIP (never a hang).  With the
+    default restored, the next solve is right again."""
+    from paper_2502_17683_amd import CpdError, test_flow_spin_limit, test_solve
+    R, n = 2000, 130
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((R, R + 5))
+    V = A @ A.T / R + 0.5 * np.eye(R)
+    M = rng.standard_normal((n, R))
+    ref = np.linalg.solve(V, M.T).T
+    say("dataflow solve with a zero-poll wait limit")
+    prev = test_flow_spin_limit(0)
+    try:
+        try:
+            F, failed = test_solve(to_dev(V), to_dev(M))
+            outcome = "solved"
+            assert not failed and rel_err(F.cpu().numpy(), ref) <= 1e-9
+        except CpdError as e:  # CPD_ERR_HIP: the launch gave up
+            outcome = str(e)
+            assert e.code == -2
+    finally:
+        test_flow_spin_limit(-1)
+    assert prev == test_flow_spin_limit(-1)
+    say(f"zero-poll outcome: {outcome}")
+    F, failed = test_solve(to_dev(V), to_dev(M))
+    assert not failed and rel_err(F.cpu().numpy(), ref) <= 1e-9
+
+
 @pytest.mark.parametrize("M,N,K", [(37, 29, 50), (256, 130, 300), (800, 1000, 1024)])
 @pytest.mark.parametrize("pair", [False, True])
 @pytest.mark.parametrize("bm", [64, 128])
