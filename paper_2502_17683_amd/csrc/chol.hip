@@ -657,12 +657,13 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
 //   F_k = (G_k - sum_{i > k} F_i L_ik) L_kk^{-1} = (...) X_k^T,
 //
 // (X_k = L_kk^{-T}, stored by the factorisation).  One launch holds every
-// (row tile, block column) pair; the workgroup of (rt, k) takes the
-// products with F_i as their ready flags appear, highest i first, and
-// publishes its own F_k when it is stored.  Workgroups are numbered from
-// the last column down, so every wait is on a lower workgroup id: those are
-// dispatched first and never wait on a higher one, hence the launch cannot
-// deadlock.  A wait still gives up after spin_limit polls (setting
+// (row tile, block column) pair of every problem; the workgroup of (rt, k)
+// takes the products with F_i as their ready flags appear, highest i
+// first, and publishes its own F_k when it is stored.  Workgroups are
+// numbered from each problem's last column down (flow_segments), so every
+// wait is on a lower workgroup id: those are dispatched first and never
+// wait on a higher one, hence the launch cannot deadlock.  A wait still
+// gives up after spin_limit polls (setting
 // FLAG_SOLVE_STALL, which every other wait of the problem sees and follows)
 // so the grid always drains.
 //
