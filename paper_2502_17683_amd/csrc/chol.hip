@@ -181,9 +181,11 @@ __device__ __forceinline__ void b4_bwd(T s[16], const T* L, const T* invd, int j
 // is in LDS (row-major, stride LDT, zero above the diagonal) and invd[c] =
 // 1 / L[c][c].  Returns false if a pivot was not positive (the factor is
 // then finite garbage).
-template <typename T, int B>
+// PANEL: the thread also carries row r of a tile below the block in e[16]
+// (same layout) through every column step, which solves it against L^T.
+template <typename T, int B, bool PANEL = false>
 struct Potrf4 {
-  __device__ __forceinline__ static void run(T d[16], T* cb, T* invd, int r, int q0, bool& ok) {
+  __device__ __forceinline__ static void run(T d[16], T e[16], T* cb, T* invd, int r, int q0, bool& ok) {
     if constexpr (B < 16) {
       T* c = cb + (B & 1) * 4 * TB;
       c[r * 4 + q0] = d[B];
@@ -239,6 +241,29 @@ struct Potrf4 {
         for (int m = q + 1; m < 4; ++m) v -= wv[m] * Ld[m][q];
         wv[q] = v * il[q];
       }
+      // the tile row: yt = its 4 entries solved against Ld^T, wt = yt Ld^{-1}
+      T yt[4], wt[4];
+      if constexpr (PANEL) {
+        T at[4];
+        at[0] = qb<0>(e[B]);
+        at[1] = qb<1>(e[B]);
+        at[2] = qb<2>(e[B]);
+        at[3] = qb<3>(e[B]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          T v = at[q];
+#pragma unroll
+          for (int m = 0; m < q; ++m) v -= yt[m] * Ld[q][m];
+          yt[q] = v * il[q];
+        }
+#pragma unroll
+        for (int q = 3; q >= 0; --q) {
+          T v = yt[q];
+#pragma unroll
+          for (int m = q + 1; m < 4; ++m) v -= wt[m] * Ld[m][q];
+          wt[q] = v * il[q];
+        }
+      }
       // trailing columns of this thread, A[k][c0..c0+3] = c[k][0..3] read
       // two columns ahead
       T ca[4], cn[4];
@@ -261,6 +286,10 @@ struct Potrf4 {
         // keep the updates in order: otherwise every column's reads are
         // hoisted at once and the tile spills
         if constexpr (sizeof(T) == 8) __asm__ volatile("" : "+v"(d[u]));
+        if constexpr (PANEL) {
+          e[u] -= wt[0] * ca[0] + wt[1] * ca[1] + wt[2] * ca[2] + wt[3] * ca[3];
+          if constexpr (sizeof(T) == 8) __asm__ volatile("" : "+v"(e[u]));
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           ca[q] = cn[q];
@@ -269,20 +298,33 @@ struct Potrf4 {
       }
       // own entry of the block column: L[r][c0 + q0] = y[q0]
       d[B] = q0 == 0 ? y[0] : q0 == 1 ? y[1] : q0 == 2 ? y[2] : y[3];
-      Potrf4<T, B + 1>::run(d, cb, invd, r, q0, ok);
+      if constexpr (PANEL) e[B] = q0 == 0 ? yt[0] : q0 == 1 ? yt[1] : q0 == 2 ? yt[2] : yt[3];
+      Potrf4<T, B + 1, PANEL>::run(d, e, cb, invd, r, q0, ok);
     }
   }
 };
 template <typename T>
 __device__ __forceinline__ bool strip_potrf4(T d[16], T* L, T* invd, T* cb /* 2 x 64 x 4 */, int r, int q0) {
   bool ok = true;
-  Potrf4<T, 0>::run(d, cb, invd, r, q0, ok);
+  Potrf4<T, 0>::run(d, d, cb, invd, r, q0, ok);
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int q = q0 + 4 * u;
     L[r * LDT + q] = q <= r ? d[u] : T(0);
   }
   __syncthreads();
+  return ok;
+}
+
+// The factorisation of the diagonal block in d (as strip_potrf4, but L is
+// left in d and not written to LDS) with row r of a tile below it carried in
+// e: on return e holds that row of the tile solved against L^T, that is of
+// A L^{-T}, in the strip layout.  The block's values are bitwise those of
+// strip_potrf4.  Returns false if a pivot was not positive.
+template <typename T>
+__device__ __forceinline__ bool strip_potrf4_panel(T d[16], T e[16], T* invd, T* cb, int r, int q0) {
+  bool ok = true;
+  Potrf4<T, 0, true>::run(d, e, cb, invd, r, q0, ok);
   return ok;
 }
 
@@ -847,8 +889,9 @@ __global__ __launch_bounds__(256, 2) void bwd_flow_kernel(const StepProb<T>* pro
 // factors the diagonal block itself, so the chain from one column to the
 // next is a single hop: the diagonal workgroup publishes D_k updated
 // through column k - 2 early, and each workgroup applies column k - 1
-// (the same product in every workgroup, so all hold the same L_kk),
-// factors, and solves its tile.  The diagonal workgroup also forms and
+// (the same product in every workgroup, so all hold the same L_kk) and
+// factors D_k with its tile's rows carried through the same column steps,
+// which solves the tile.  The diagonal workgroup also forms and
 // publishes X_k for the forward solve.  Every wait is on a lower workgroup
 // id (columns in order; in a column the diagonal tile first, the forward
 // tiles last), so the launch cannot deadlock; waits are bounded as in the
@@ -993,25 +1036,40 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
     __syncthreads();
     T d[16];
     lds_to_strip<T>(S1, d, sr, q0);
+    if constexpr (sizeof(T) == 8) {
+      if (!diag) {
+        // the tile's rows ride through the factorisation of D_k: L_ik comes
+        // out of the same column steps, with no separate substitution
+        // (FP64 only: the FP32 instance spills with the second strip)
+        T e[16];
+        lds_to_strip<T>(S0, e, sr, q0);
+        strip_potrf4_panel<T>(d, e, invd, colbuf, sr, q0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) coherent_store<T>(tile + (size_t)sr * Tp + q0 + 4 * u, e[u]);
+        publish(lfl + i * nblk + k);
+        return;
+      }
+    }
     __syncthreads();
     const bool ok = strip_potrf4<T>(d, S1, invd, colbuf, sr, q0);  // S1 = L_kk
     T s[16];
-    if (diag) {
-      if (!ok && tid == 0) atomicExch(&st->chol_fail, 1);
-      if (tid < TB) as_global(q.diagL)[k * TB + tid] = S1[tid * LDT + tid];
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) s[4 * ii + v] = (4 * bg + ii == bj + 16 * v) ? T(1) : T(0);
-      b4_fwd<T>(s, S1, invd, bj);  // X_k
-      store_b4_coherent<T>(s, q.ldiag + (size_t)k * TB * TB, TB, bg, bj);
-      publish(xfl + k);
+    if (!diag) {  // FP32: the tile by substitution with L_kk
+      lds_to_b4<T>(S0, s, bg, bj);
+      b4_fwd<T>(s, S1, invd, bj);
+      store_b4_coherent<T>(s, tile, Tp, bg, bj);
+      publish(lfl + i * nblk + k);
       return;
     }
-    lds_to_b4<T>(S0, s, bg, bj);
-    b4_fwd<T>(s, S1, invd, bj);  // L_ik
-    store_b4_coherent<T>(s, tile, Tp, bg, bj);
-    publish(lfl + i * nblk + k);
+    // the diagonal workgroup: L_kk, and X_k = L_kk^{-T} for the forward solve
+    if (!ok && tid == 0) atomicExch(&st->chol_fail, 1);
+    if (tid < TB) as_global(q.diagL)[k * TB + tid] = S1[tid * LDT + tid];
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) s[4 * ii + v] = (4 * bg + ii == bj + 16 * v) ? T(1) : T(0);
+    b4_fwd<T>(s, S1, invd, bj);  // X_k
+    store_b4_coherent<T>(s, q.ldiag + (size_t)k * TB * TB, TB, bg, bj);
+    publish(xfl + k);
     return;
   }
 
