@@ -47,7 +47,10 @@ typedef int32_t cpd_status;
 enum {
   CPD_OK = 0,
   CPD_ERR_INVALID_ARG = -1, /* bad sizes, null pointers, unsupported option  */
-  CPD_ERR_HIP = -2,         /* a HIP runtime call failed                      */
+  CPD_ERR_HIP = -2,         /* a HIP runtime call failed, or a wait of the
+                               dataflow factorisation/solves gave up (the
+                               device made no progress; the plan needs
+                               cpd_init / cpd_batch_init again)              */
   CPD_ERR_NOT_SPD = -3,     /* normal matrix not positive definite (after the
                                damped retry, if enabled)                      */
   CPD_ERR_NONFINITE = -4,   /* NaN/Inf reached the fit or ||G||^2 <= 0        */

@@ -1513,7 +1513,7 @@ const char* cpd_status_string(cpd_status s) {
   switch (s) {
     case CPD_OK: return "ok";
     case CPD_ERR_INVALID_ARG: return "invalid argument";
-    case CPD_ERR_HIP: return "HIP runtime error";
+    case CPD_ERR_HIP: return "HIP runtime error (or a dataflow solve wait gave up)";
     case CPD_ERR_NOT_SPD: return "normal matrix not positive definite";
     case CPD_ERR_NONFINITE: return "non-finite value in the fit";
     case CPD_ERR_WORKSPACE: return "workspace missing or too small";
