@@ -17,7 +17,10 @@ tiny mode sizes (the tensor has n0*n1*n2*n3 entries).
   Details), here by explicit reconstruction -- deliberately a different
   formula from the matrix-free one.
 * Stopping: relative change of the fit below ``tol`` (Computational
-  Details use 1e-3), or fit below ``fit_floor``, or ``max_sweeps``.
+  Details use 1e-3), or fit below ``fit_floor``, or ``max_sweeps``.  With
+  ``fit_every`` = k > 1 the rule is looked at only after sweeps k, 2k, ...
+  and the change is measured against the fit k sweeps earlier (the
+  cadence at which the mixed-precision path evaluates its fit).
 
 Readings where the paper is silent: modes are updated in order 0,1,2,3;
 columns are normalised to unit 2-norm after every update and the weights
@@ -96,7 +99,23 @@ def _normalise(F):
     return F / safe[None, :], lam
 
 
-def dense_cp_als(G, init, max_sweeps, tol=1e-4, fit_floor=1e-7, allow_fallback=True):
+def _stop(fits, tol, fit_floor, fit_every):
+    """The stopping rule of the module header, looked at after every
+    fit_every-th sweep only: the fit is at or below fit_floor, or its
+    change since the previous such sweep is at most tol times that
+    earlier fit."""
+    k = len(fits)
+    if k % fit_every:
+        return False
+    if fits[k - 1] <= fit_floor:
+        return True
+    if k - fit_every < 1:
+        return False
+    earlier = fits[k - 1 - fit_every]
+    return abs(fits[k - 1] - earlier) <= tol * earlier
+
+
+def dense_cp_als(G, init, max_sweeps, tol=1e-4, fit_floor=1e-7, allow_fallback=True, fit_every=1):
     """Run CP-ALS on the dense tensor G from the given initial factors.
 
     Returns dict(fits=[...], lam=..., F=[...], fallbacks=int).
@@ -114,10 +133,7 @@ def dense_cp_als(G, init, max_sweeps, tol=1e-4, fit_floor=1e-7, allow_fallback=T
             Fn, damped = _normal_solve(V, M, allow_fallback)
             fallbacks += int(damped)
             F[n], lam = _normalise(Fn)
-        f = dense_fit(G, lam, F)
-        fits.append(f)
-        if f <= fit_floor:
-            break
-        if len(fits) >= 2 and abs(fits[-1] - fits[-2]) <= tol * fits[-2]:
+        fits.append(dense_fit(G, lam, F))
+        if _stop(fits, tol, fit_floor, fit_every):
             break
     return dict(fits=fits, lam=lam, F=F, fallbacks=fallbacks)

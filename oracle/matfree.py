@@ -147,14 +147,30 @@ class MatFreeCPALS:
         return self.fit()
 
 
-def mf_cp_als(X, Z, init, max_sweeps, tol=1e-4, fit_floor=1e-7, allow_fallback=True):
-    """Matrix-free CP-ALS with the stopping rule of oracle/dense.py."""
+def stops(fits, tol, fit_floor, fit_every=1):
+    """Stopping rule (Computational Details: relative change in fit below a
+    tolerance), read as in oracle/dense.py and checked after the sweep that
+    produced fits[-1].  The rule is looked at on every fit_every-th sweep
+    only; there it fires when the fit is at or below fit_floor, or when it
+    changed by at most tol relative to the fit of the previous such sweep
+    (fit_every sweeps earlier)."""
+    k = len(fits)
+    if k == 0 or k % fit_every:
+        return False
+    if fits[-1] <= fit_floor:
+        return True
+    if k <= fit_every:
+        return False
+    prev = fits[-1 - fit_every]
+    return abs(fits[-1] - prev) <= tol * prev
+
+
+def mf_cp_als(X, Z, init, max_sweeps, tol=1e-4, fit_floor=1e-7, allow_fallback=True, fit_every=1):
+    """Matrix-free CP-ALS with the stopping rule ``stops``."""
     st = MatFreeCPALS(X, Z, init, allow_fallback)
     fits = []
     for _ in range(max_sweeps):
         fits.append(st.sweep())
-        if fits[-1] <= fit_floor:
-            break
-        if len(fits) >= 2 and abs(fits[-1] - fits[-2]) <= tol * fits[-2]:
+        if stops(fits, tol, fit_floor, fit_every):
             break
     return dict(fits=fits, lam=st.lam, F=st.F, fallbacks=st.fallbacks, state=st)

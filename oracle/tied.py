@@ -109,14 +109,22 @@ class TiedCPALS:
         return np.sqrt(max(self.norm2 - 2.0 * inner + model2, 0.0)) / np.sqrt(self.norm2)
 
 
-def tied_cp_als(X, Z, init, max_sweeps, tol=1e-4, fit_floor=1e-7, allow_fallback=True):
+def _rule_fires(fits, tol, fit_floor, fit_every):
+    # the stopping rule of oracle/dense.py, looked at every fit_every sweeps
+    k = len(fits)
+    if k % fit_every != 0:
+        return False
+    if fits[-1] <= fit_floor:
+        return True
+    return k > fit_every and abs(fits[-1] - fits[-1 - fit_every]) <= tol * fits[-1 - fit_every]
+
+
+def tied_cp_als(X, Z, init, max_sweeps, tol=1e-4, fit_floor=1e-7, allow_fallback=True, fit_every=1):
     """Tied CP-ALS with the stopping rule of oracle/dense.py."""
     st = TiedCPALS(X, Z, init, allow_fallback)
     fits = []
     for _ in range(max_sweeps):
         fits.append(st.sweep())
-        if fits[-1] <= fit_floor:
-            break
-        if len(fits) >= 2 and abs(fits[-1] - fits[-2]) <= tol * fits[-2]:
+        if _rule_fires(fits, tol, fit_floor, fit_every):
             break
     return dict(fits=fits, lam=st.lam, F=st.F, fallbacks=st.fallbacks, state=st)
