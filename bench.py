@@ -10,13 +10,18 @@ Protocol
   2. Warm-up (untimed): --warmup mixed runs to the target.
   3. Timed: --steps runs of the mixed-precision path, each from cpd_init
      (inputs already in HBM) to the end of the first sweep whose fit --
-     evaluated in FP64 -- is <= f*.  value = mean seconds per run.
-     One timed FP64 run to the same target gives the FP64 time-to-fit.
+     evaluated in FP64 -- is <= f*.  value = median seconds per run (null
+     if any run missed the target), with the spread.  Three timed FP64 runs
+     to the same target give the FP64 time-to-fit (median).
+     Untimed: one split-BF16 run with the fit evaluated every sweep gives
+     the per-sweep fit error |f_mixed - f_fp64| / f_fp64 against the
+     reference trajectory.
   4. Kernel times (hipEvents on the plan's stream) of the projection, core
      product, back-projection, Gram and solve at this shape give MTTKRP
      TFLOP/s for both precisions and the roofline of the dominant kernel.
   5. CPU baseline: the matrix-free NumPy oracle on the host, a bounded
-     sample of sweeps, extrapolated to the FP64 sweep count.
+     sample of sweeps (all threads, and one sweep on one thread),
+     extrapolated to the FP64 sweep count.
 
 Prints one JSON line.
 """
@@ -65,7 +70,9 @@ def measured_traffic(kernel, profile="chol_fwd_flow_traffic_n800_r4000.md"):
 
 
 def run_to_target(make, target, max_sweeps, chunk=1):
-    """Wall time (s) from plan creation to the sweep that reaches target."""
+    """Wall time (s) from plan creation to the sweep that reaches target,
+    plus the sweep count, whether the target was reached, the last evaluated
+    fit and whether the precision guard moved the run to FP64 products."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -84,8 +91,25 @@ def run_to_target(make, target, max_sweeps, chunk=1):
                 break
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    st = cpd.stats()
     cpd.close()
-    return t, sweeps, reached, last
+    return t, sweeps, reached, last, int(st["fp64_path"])
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def spread(xs):
+    a = np.asarray(xs, dtype=np.float64)
+    return {"median": float(np.median(a)), "min": float(a.min()), "max": float(a.max()),
+            "p25": float(np.percentile(a, 25)), "p75": float(np.percentile(a, 75)), "n": int(a.size)}
 
 
 def main():
@@ -96,11 +120,12 @@ def main():
     ap.add_argument("--n", type=int, default=800)
     ap.add_argument("--r-thc", type=int, default=4000)
     ap.add_argument("--r-cp", type=int, default=4000)
-    ap.add_argument("--ref-sweeps", type=int, default=100)
+    ap.add_argument("--ref-sweeps", type=int, default=200)
     ap.add_argument("--max-sweeps", type=int, default=400)
     ap.add_argument("--fit-every", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--cpu-sweeps", type=int, default=3)
+    ap.add_argument("--cpu-sweeps-1t", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--init", choices=("normal", "uniform"), default="normal",
                     help="initial factors: N(0,1)/sqrt(n) (default) or the paper's U[-1,1]")
@@ -171,21 +196,42 @@ def main():
     log(f"[bench] f_ref={f_ref:.8f} target={target:.8f} (first fit {ref_fits[0]:.6f})")
 
     # 2./3. time-to-fit
+    mk_mixed = lambda: make("mixed", fit_every=args.fit_every)
     for w in range(args.warmup):
-        t, s, ok, last = run_to_target(lambda: make("mixed", fit_every=args.fit_every), target,
-                                       args.max_sweeps, args.fit_every)
-        log(f"[bench] warmup {w}: mixed {t:.3f}s sweeps={s} reached={ok} last_fit={last}")
-    times, sweeps_m, reached_m, last_m = [], [], [], []
+        t, s, ok, last, p64 = run_to_target(mk_mixed, target, args.max_sweeps, args.fit_every)
+        log(f"[bench] warmup {w}: mixed {t:.3f}s sweeps={s} reached={ok} last_fit={last} fp64_path={p64}")
+    times, sweeps_m, reached_m, last_m, path_m = [], [], [], [], []
     for k in range(args.steps):
-        t, s, ok, last = run_to_target(lambda: make("mixed", fit_every=args.fit_every), target,
-                                       args.max_sweeps, args.fit_every)
+        t, s, ok, last, p64 = run_to_target(mk_mixed, target, args.max_sweeps, args.fit_every)
         times.append(t)
         sweeps_m.append(s)
         reached_m.append(ok)
         last_m.append(last)
-        log(f"[bench] step {k}: mixed {t:.3f}s sweeps={s} reached={ok} last_fit={last}")
-    t64, s64, ok64, last64 = run_to_target(lambda: make("fp64"), target, args.max_sweeps, 1)
-    log(f"[bench] fp64 run: {t64:.3f}s sweeps={s64} reached={ok64} last_fit={last64}")
+        path_m.append(p64)
+        log(f"[bench] step {k}: mixed {t:.3f}s sweeps={s} reached={ok} last_fit={last} fp64_path={p64}")
+    t64s = []
+    for k in range(3):
+        t64, s64, ok64, last64, _ = run_to_target(lambda: make("fp64"), target, args.max_sweeps, 1)
+        t64s.append(t64)
+        log(f"[bench] fp64 run {k}: {t64:.3f}s sweeps={s64} reached={ok64} last_fit={last64}")
+    t64 = float(np.median(t64s))
+
+    # per-sweep fit error of split BF16 against the FP64 reference trajectory
+    # (same start; the split run evaluates its fit in FP64 every sweep)
+    em = make("mixed", fit_every=1)
+    mfits = em.sweep(args.ref_sweeps)
+    em_path = int(em.stats()["fp64_path"])
+    em.close()
+    nerr = min(len(mfits), len(ref_fits))
+    err = np.abs(np.array(mfits[:nerr]) - np.array(ref_fits[:nerr])) / np.array(ref_fits[:nerr])
+    fit_err = {"per_sweep": [float(e) for e in err],
+               "max_first_10": float(err[:10].max()), "max_first_50": float(err[:50].max()),
+               "max_all": float(err.max()), "final": float(err[-1]),
+               "final_fit_mixed": float(mfits[nerr - 1]), "final_fit_fp64": float(ref_fits[nerr - 1]),
+               "fp64_path": em_path}
+    log(f"[bench] per-sweep |f_mixed - f_fp64| / f_fp64: first 10 <= {fit_err['max_first_10']:.2e}, "
+        f"first 50 <= {fit_err['max_first_50']:.2e}, all {nerr} <= {fit_err['max_all']:.2e}, "
+        f"final {fit_err['final']:.2e}")
 
     # 4. kernel times
     kt = {}
@@ -217,19 +263,31 @@ def main():
     if not args.no_cpu:
         from oracle import matfree
         import multiprocessing
+        from threadpoolctl import threadpool_limits
         cores = int(os.environ.get("OMP_NUM_THREADS", multiprocessing.cpu_count()))
-        log(f"[bench] CPU oracle: {args.cpu_sweeps} sweeps on {cores} threads")
+        log(f"[bench] CPU oracle: {args.cpu_sweeps} sweeps on {cores} threads, "
+            f"{args.cpu_sweeps_1t} on one thread ({cpu_model()})")
         st = matfree.MatFreeCPALS([X] * 4, Z, init)
-        t0 = time.perf_counter()
-        for _ in range(args.cpu_sweeps):
-            st.sweep()
-        dt = (time.perf_counter() - t0) / args.cpu_sweeps
+        with threadpool_limits(cores):
+            t0 = time.perf_counter()
+            for _ in range(args.cpu_sweeps):
+                st.sweep()
+            dt = (time.perf_counter() - t0) / args.cpu_sweeps
+        dt1 = None
+        if args.cpu_sweeps_1t > 0:
+            with threadpool_limits(1):
+                t0 = time.perf_counter()
+                for _ in range(args.cpu_sweeps_1t):
+                    st.sweep()
+                dt1 = (time.perf_counter() - t0) / args.cpu_sweeps_1t
         cpu = {"value": dt * s64, "unit": "s", "cores": cores, "kind": "oracle",
                "sample": f"{args.cpu_sweeps} matrix-free FP64 NumPy sweeps at N={N}, R_thc={Rt}, "
                          f"R_cp={Rc} ({dt:.2f} s/sweep, set-up excluded), extrapolated to the "
-                         f"{s64} sweeps the FP64 GPU run needed"}
+                         f"{s64} sweeps the FP64 GPU run needed",
+               "cpu_model": cpu_model(), "s_per_sweep": dt, "s_per_sweep_1thread": dt1,
+               "sweeps_1thread": args.cpu_sweeps_1t}
 
-    value = float(np.mean(times))
+    value = float(np.median(times)) if all(reached_m) else None
     out = {
         "metric": "CP-ALS time-to-fit 1e-4 (s) and MTTKRP TFLOP/s, mixed vs FP64, 1 MI355X",
         "value": value,
@@ -237,7 +295,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": value * 1e3,
+        "ms_per_step": value * 1e3 if value is not None else None,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -247,10 +305,13 @@ def main():
                                f"seed {args.seed}, target fit = FP64 best over "
                                f"{args.ref_sweeps} sweeps x (1+1e-4)",
                    "n": N, "r_thc": Rt, "r_cp": Rc, "fit_every": args.fit_every, "init": args.init},
+        "time_to_fit_s": {"mixed": spread(times), "fp64": spread(t64s)},
         "fp64_time_to_fit_s": t64,
-        "speedup_vs_fp64": t64 / value if value > 0 else None,
+        "speedup_vs_fp64": t64 / value if value else None,
         "sweeps_to_fit": {"mixed": sweeps_m, "fp64": s64},
         "reached": {"mixed": reached_m, "fp64": ok64},
+        "fp64_path_timed_runs": path_m,
+        "fit_error_vs_fp64": fit_err,
         "f_ref": f_ref, "target_fit": target,
         "mttkrp_tflops": tflops,
         "kernel_ms": kt,

@@ -82,15 +82,19 @@ typedef struct {
   const double* init[4];  /* DEVICE n[m] x r_cp initial factors (required); their
                              columns are normalised to unit 2-norm at init        */
   int32_t precision;      /* cpd_precision                                        */
-  double tol;             /* stop when |f_k - f_{k-1}| <= tol f_{k-1}             */
+  double tol;             /* stop when |f_k - f_{k-fit_every}| <= tol f_{k-fit_every}
+                             (Computational Details: relative change in fit) */
   double fit_floor;       /* ... or when f_k <= fit_floor (0 disables)            */
   int32_t chol_fallback;  /* 1: one damped retry V + mu I, mu = 1e-12 tr(V)/R_cp,
                              on a non-positive pivot; 0: fail with NOT_SPD       */
   int32_t use_graph;      /* 1: replay each sweep as a captured hipGraph          */
-  int32_t fit_every;      /* CPD_MIXED_BF16 only: evaluate the fit (in FP64, with
-                             an FP64 mode-3 MTTKRP) and the stopping rule every
-                             fit_every sweeps (<= 1: every sweep); other
-                             precisions evaluate it every sweep               */
+  int32_t fit_every;      /* cadence k of the stopping rule (<= 1: every sweep):
+                             the rule is looked at after sweeps k, 2k, ... and
+                             compares the fit with the fit k sweeps earlier, in
+                             every precision.  CPD_MIXED_BF16 also evaluates
+                             the fit itself (in FP64, with an FP64 mode-3
+                             MTTKRP) only on those sweeps; FP64 and FP32
+                             evaluate it every sweep                          */
   int32_t autotune;       /* 1: time both GEMM tile shapes of every grouped
                              FP64/FP32 product at init and keep the faster
                              (cached per process by shape); 0: heuristic      */
@@ -144,29 +148,40 @@ size_t cpd_workspace_size(const cpd_desc* d);
  * host-side plan to be released with cpd_destroy. */
 cpd_status cpd_init(const cpd_desc* d, cpd_plan* out);
 
-/* Runs up to nsweeps ALS sweeps (modes 0,1,2,3 in order, then the fit and
- * the stopping rule).  Sweeps after convergence are no-ops on the device.
+/* Runs up to nsweeps ALS sweeps (Section 2.1: alternating least squares on
+ * eq. lossF; modes 0,1,2,3 in order, each mode update the projection, the
+ * core product, the back-projection and the normal-equation solve with
+ * V_n = o_{m != n} F_m^T F_m), then the fit and the stopping rule
+ * (Computational Details: fit ||T - T~|| / ||T||, relative change in fit
+ * below tol).  Sweeps after convergence are no-ops on the device.
  * If fits_host or n_run is non-NULL the call synchronises after every sweep,
  * stops at convergence, writes the fit of each sweep run to fits_host
  * (length >= nsweeps) and the number of sweeps run to *n_run; otherwise it
  * only enqueues the work. */
 cpd_status cpd_sweep(cpd_plan p, int32_t nsweeps, double* fits_host, int32_t* n_run);
 
-/* Synchronises the plan's stream and returns the last fit (-1 if none). */
+/* Synchronises the plan's stream and returns the last fit (-1 if none):
+ * the paper's ||T - T~|| / ||T|| (Computational Details), computed
+ * matrix-free from ||G||^2, <G, G~> and ||G~||^2 (eq. lossF). */
 cpd_status cpd_fit(cpd_plan p, double* fit_host);
 
 /* Copies the current factors (DEVICE n[m] x r_cp each, dense) and the
- * weights lambda (DEVICE r_cp) out; async.  Any pointer may be NULL. */
+ * weights lambda (DEVICE r_cp) out -- the CPD of eq. cp4 with unit-norm
+ * columns; async.  Any pointer may be NULL. */
 cpd_status cpd_get_factors(cpd_plan p, double* const F_dev[4], double* lambda_dev);
 
 /* Restores factors and weights written by cpd_get_factors (checkpoint
- * resume): recomputes the projections and Grams from them and sets the
+ * resume of the ALS iteration of Section 2.1, whose state between sweeps
+ * is exactly the factors and weights of eq. cp4): recomputes the
+ * projections and Grams from them and sets the
  * previous fit used by the stopping rule to prev_fit (< 0: none) and the
  * sweep counter to sweeps.  Async. */
 cpd_status cpd_set_factors(cpd_plan p, const double* const F_dev[4], const double* lambda_dev,
                            double prev_fit, int32_t sweeps);
 
-/* Synchronises and fills *out. */
+/* Synchronises and fills *out: sweep count, stopping state, the fit and
+ * its terms ||G||^2, <G, G~>, ||G~||^2 (Computational Details; eq. lossF),
+ * damped retries of the Cholesky of V_n and its condition estimate. */
 cpd_status cpd_stats(cpd_plan p, cpd_stats_t* out);
 
 /* Test hook: the matrix-free MTTKRP of `mode` from the current factors,

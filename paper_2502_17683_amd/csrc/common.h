@@ -45,6 +45,7 @@ struct DevState {
   int32_t promote;       // set by the precision guard in the sweep that promoted
   int32_t fallbacks_start;  // fallbacks at the start of the sweep
   double cond_max;       // largest (max L_ii / min L_ii)^2 seen in the sweep
+  double fit_rule;       // fit at the last sweep the stopping rule looked at (-1: none)
 };
 
 // Tile (tm, tn) of linear index bid in groups of G tile rows: a group runs

@@ -809,7 +809,8 @@ void enqueue_sweep_tied(cpd_plan_s* p, hipStream_t s, bool fast) {
   }
   run_gemm<T>(p, s, p->back[3]);
   tied_inner_group<T>(s, (const NormArgs<T>*)p->tinner, p->count, p->maxR);
-  fit_group<T>(s, (const FitArgs<T>*)p->fit, p->count, p->maxR, HIST_CAP, p->tol, p->fit_floor, 0, 0.0);
+  fit_group<T>(s, (const FitArgs<T>*)p->fit, p->count, p->maxR, HIST_CAP, p->tol, p->fit_floor, 0, 0.0,
+               p->fit_every);
 }
 
 template <typename T>
@@ -826,7 +827,8 @@ void enqueue_sweep_typed(cpd_plan_s* p, hipStream_t s, bool fast) {
     run_gemm<T>(p, s, p->gram[n]);
     run_gemm<T>(p, s, p->proj[n]);
   }
-  fit_group<T>(s, (const FitArgs<T>*)p->fit, p->count, p->maxR, HIST_CAP, p->tol, p->fit_floor, 0, 0.0);
+  fit_group<T>(s, (const FitArgs<T>*)p->fit, p->count, p->maxR, HIST_CAP, p->tol, p->fit_floor, 0, 0.0,
+               p->fit_every);
 }
 
 // Mixed precision: the three MTTKRP products in split BF16, everything
@@ -871,8 +873,9 @@ void enqueue_sweep_mixed(cpd_plan_s* p, hipStream_t s, bool fit_sweep, bool fast
     mixed_refresh_mode(p, s, n);
   }
   if (fit_sweep)
+    // fit sweeps are exactly the sweeps the stopping rule looks at
     fit_group<double>(s, (const FitArgs<double>*)p->fit, p->count, p->maxR, HIST_CAP, p->tol, p->fit_floor, 1,
-                      p->cond_limit);
+                      p->cond_limit, 1);
   else
     sweep_tick_group(s, (DevState* const*)p->sts, p->count, 1, p->cond_limit);
 }
@@ -927,6 +930,7 @@ __global__ void dense_to_strided_f32(const double* src, int rows, int cols, int 
 __global__ void state_set_kernel(DevState* st, double prev_fit, int sweeps) {
   if (threadIdx.x == 0) {
     st->fit_prev = prev_fit;
+    st->fit_rule = prev_fit;
     st->sweeps = sweeps;
     st->done = 0;
     st->flags = 0;
@@ -982,6 +986,11 @@ bool all_done(const cpd_plan_s* p) {
 bool any_chol_fail(const cpd_plan_s* p) {
   for (int i = 0; i < p->count; ++i)
     if (p->host_states[i].chol_fail) return true;
+  return false;
+}
+bool any_stall(const cpd_plan_s* p) {
+  for (int i = 0; i < p->count; ++i)
+    if (p->host_states[i].flags & FLAG_SOLVE_STALL) return true;
   return false;
 }
 bool any_promote(const cpd_plan_s* p) {
@@ -1216,6 +1225,13 @@ int batch_sweep(cpd_plan_s* p, int nsweeps, double* fits_host, int32_t* n_run) {
     rc = launch_sweep(p, fit, true);
     if (rc == CPD_OK) rc = read_states(p);
     if (rc != CPD_OK) return rc;
+    if (any_stall(p)) {
+      // a dataflow wait gave up: the problem is marked done on the device
+      // and the call reports CPD_ERR_HIP without running further sweeps
+      p->launched += 1;
+      ++ran;
+      break;
+    }
     // Replays: a failed pivot reruns the sweep with the damped-retry graph;
     // a precision promotion reruns it with the promoted problems on the
     // FP64 path.  Each problem can be promoted once, so this terminates.

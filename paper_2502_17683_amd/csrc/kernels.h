@@ -208,7 +208,7 @@ struct FitArgs {
 };
 template <typename T>
 void fit_group(hipStream_t s, const FitArgs<T>* tab, int nprob, int max_R, int hist_cap, double tol,
-               double fit_floor, int guard, double cond_limit);
+               double fit_floor, int guard, double cond_limit, int rule_every);
 // Non-fit sweep of a split-BF16 plan: sweep counter and precision guard.
 void sweep_tick_group(hipStream_t s, DevState* const* st_tab, int nprob, int guard, double cond_limit);
 // Precision guard bookkeeping (split-BF16 plans):

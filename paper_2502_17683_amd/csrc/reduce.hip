@@ -211,7 +211,8 @@ __device__ __forceinline__ bool guard_trips(const DevState* st, double fit, doub
 
 template <typename T>
 __global__ __launch_bounds__(256) void fit_final_kernel(const FitArgs<T>* tab, int hist_cap, double tol,
-                                                        double fit_floor, int guard, double cond_limit) {
+                                                        double fit_floor, int guard, double cond_limit,
+                                                        int rule_every) {
   __shared__ double pa[256];
   __shared__ double pb[256];
   const FitArgs<T> a = tab[blockIdx.x];
@@ -245,30 +246,39 @@ __global__ __launch_bounds__(256) void fit_final_kernel(const FitArgs<T>* tab, i
     a.fit_hist[k % hist_cap] = fit;
     st->sweeps = k + 1;
     const double prev = st->fit_prev;
+    // Stopping rule, looked at on every rule_every-th sweep: the fit is at
+    // or below the floor, or it changed by at most tol relative to the fit
+    // of the previous rule sweep.  Failures stop the problem at once.
+    const bool rule = (k + 1) % rule_every == 0;
+    const double ref = st->fit_rule;
     if (guard && guard_trips(st, fit, prev, cond_limit)) {
       st->path = 1;
       st->promote = 1;
-    } else if (fit <= fit_floor || (prev >= 0.0 && fabs(fit - prev) <= tol * prev) || !isfinite(fit) ||
-               (st->flags & FLAG_NOT_SPD)) {
+    } else if ((rule && (fit <= fit_floor || (ref >= 0.0 && fabs(fit - ref) <= tol * ref))) || !isfinite(fit) ||
+               (st->flags & (FLAG_NOT_SPD | FLAG_SOLVE_STALL))) {
       st->done = 1;
     }
+    if (rule) st->fit_rule = fit;
     st->fit_prev = fit;
   }
 }
 
 template <typename T>
 void fit_group(hipStream_t s, const FitArgs<T>* tab, int nprob, int max_R, int hist_cap, double tol,
-               double fit_floor, int guard, double cond_limit) {
+               double fit_floor, int guard, double cond_limit, int rule_every) {
+  if (rule_every < 1) rule_every = 1;
   hipLaunchKernelGGL((model_norm_rows_kernel<T>), dim3(max_R, nprob), dim3(256), 0, s, tab);
   hipLaunchKernelGGL((fit_final_kernel<T>), dim3(nprob), dim3(256), 0, s, tab, hist_cap, tol, fit_floor, guard,
-                     cond_limit);
+                     cond_limit, rule_every);
 }
 
 __global__ void sweep_tick_kernel(DevState* const* st_tab, int guard, double cond_limit) {
   DevState* st = st_tab[blockIdx.x];
   if (threadIdx.x == 0 && !st->done) {
     st->sweeps += 1;
-    if (guard && guard_trips(st, 0.0, -1.0, cond_limit)) {
+    if (st->flags & (FLAG_NOT_SPD | FLAG_SOLVE_STALL)) {
+      st->done = 1;  // a failed solve ends the problem (later sweeps are no-ops)
+    } else if (guard && guard_trips(st, 0.0, -1.0, cond_limit)) {
       st->path = 1;
       st->promote = 1;
     }
@@ -460,6 +470,7 @@ __global__ void state_reset_kernel(DevState* st, const double* norm2_src) {
   if (threadIdx.x == 0) {
     st->norm2 = *norm2_src;
     st->fit_prev = -1.0;
+    st->fit_rule = -1.0;
     st->inner = 0.0;
     st->model2 = 0.0;
     st->mu = 0.0;
@@ -533,7 +544,9 @@ template void retry_prepare_group<double>(hipStream_t, const FormVArgs<double>*,
 template void retry_prepare_group<float>(hipStream_t, const FormVArgs<float>*, int, int);
 template void normalise_group<double>(hipStream_t, const NormArgs<double>*, int, int);
 template void normalise_group<float>(hipStream_t, const NormArgs<float>*, int, int);
-template void fit_group<double>(hipStream_t, const FitArgs<double>*, int, int, int, double, double, int, double);
-template void fit_group<float>(hipStream_t, const FitArgs<float>*, int, int, int, double, double, int, double);
+template void fit_group<double>(hipStream_t, const FitArgs<double>*, int, int, int, double, double, int, double,
+                                int);
+template void fit_group<float>(hipStream_t, const FitArgs<float>*, int, int, int, double, double, int, double,
+                               int);
 
 }  // namespace thccp

@@ -55,6 +55,69 @@ def test_full_n800_split_mttkrp_error(big):
     assert err <= 1e-4
 
 
+def _split_mttkrp_bound_factor(n, r_thc):
+    """Relative bound, in units of the MTTKRP of absolute values, of the
+    split-BF16 MTTKRP (reading: hi = bf16(x), lo = bf16(x - hi), products
+    hi*hi + hi*lo + lo*hi, FP32 accumulation).  One split product of
+    length K is within u(K) = 3 * 2^-16 + K * 2^-24 of sum |a||b| (the
+    kernel-level bound); FP32 storage of W and Y and each FP32 Hadamard
+    product add 2^-24.  To first order, the projections (K = n) enter three
+    times (W_partner, and W_a, W_b through Y), the core and back-projection
+    products (K = r_thc) once each:
+        |M - M_ref| <= (3 u(n) + 2 u(r_thc) + 6 * 2^-24) |X|(|W|o|Z|(|W|o|W|))
+    with |W| = |X|^T |F|; a factor 1.001 covers the second-order terms."""
+    u = lambda K: 3 * 2.0 ** -16 + K * 2.0 ** -24
+    return 1.001 * (3 * u(n) + 2 * u(r_thc) + 6 * 2.0 ** -24)
+
+
+def test_full_n800_split_mttkrp_per_element_all_modes(big):
+    """Split-BF16 MTTKRP of every mode (both core products, Z and Z^T) at
+    N=800, R_thc=R_cp=4000, element by element against the oracle's FP64
+    matrix-free MTTKRP, within the derived bound times the oracle's MTTKRP
+    of absolute values."""
+    from paper_2502_17683_amd import CPD
+    X, Z, init = big
+    c = CPD(to_dev(X), to_dev(Z), 4000, [to_dev(f) for f in init], precision="mixed", tol=0.0, fit_floor=0.0)
+    Fn = [f / np.linalg.norm(f, axis=0) for f in init]
+    Xa, Za, Fa = np.abs(X), np.abs(Z), [np.abs(f) for f in Fn]
+    k = _split_mttkrp_bound_factor(800, 4000)
+    for n in range(4):
+        M = c.mttkrp(n).cpu().numpy()
+        ref = matfree.mttkrp([X] * 4, Z, Fn, n)
+        A = matfree.mttkrp([Xa] * 4, Za, Fa, n)
+        err = np.abs(M - ref)
+        ratio = float(np.max(err / (A + 1e-300)))
+        say(f"N=800 split-BF16 MTTKRP mode {n}: max |err| / |.|-MTTKRP {ratio:.2e} (bound {k:.2e}), "
+            f"rel Frobenius {np.linalg.norm(M - ref) / np.linalg.norm(ref):.2e}")
+        assert np.all(err <= k * A)
+    c.close()
+
+
+def test_full_n800_split_fit_per_sweep_vs_oracle(big):
+    """Split BF16 with the fit evaluated every sweep, against the oracle's
+    FP64 trajectory from the same start: the per-sweep relative fit error
+    stays within 1e-4 (the 'same fit' tolerance) over the first 8 sweeps.
+    The FP64 GPU run is checked beside it at 1e-10."""
+    from paper_2502_17683_amd import CPD
+    X, Z, init = big
+    S = 8
+    say(f"N=800 oracle trajectory, {S} sweeps")
+    ref = np.array(matfree.mf_cp_als([X] * 4, Z, init, S, tol=0.0, fit_floor=0.0)["fits"])
+    mk = lambda prec: CPD(to_dev(X), to_dev(Z), 4000, [to_dev(f) for f in init], precision=prec, tol=0.0,
+                          fit_floor=0.0, fit_every=1)
+    c = mk("mixed")
+    fm = np.array(c.sweep(S))
+    assert c.stats()["fp64_path"] == 0
+    c.close()
+    c = mk("fp64")
+    f64 = np.array(c.sweep(S))
+    c.close()
+    err = np.abs(fm - ref) / ref
+    say(f"N=800 split-BF16 per-sweep fit error vs oracle: {err}")
+    assert np.all(np.abs(f64 - ref) <= 1e-10 * ref)
+    assert np.all(err <= 1e-4)
+
+
 def test_full_n200_fp64_200_sweeps_match_oracle():
     """The N=200, R_thc=R_cp=1000 configuration over its 200 sweeps, every
     fit against the oracle."""
