@@ -95,9 +95,13 @@ typedef struct {
                              the fit itself (in FP64, with an FP64 mode-3
                              MTTKRP) only on those sweeps; FP64 and FP32
                              evaluate it every sweep                          */
-  int32_t autotune;       /* 1: time both GEMM tile shapes of every grouped
-                             FP64/FP32 product at init and keep the faster
-                             (cached per process by shape); 0: heuristic      */
+  int32_t autotune;       /* 1: time the candidate launch shapes of every
+                             grouped product at init and keep the fastest
+                             (cached per process by shape): FP64/FP32 tile
+                             edges 64/128; split BF16 128-column tiles of 64
+                             or 128 rows, or 128/256 x 256 tiles, the
+                             back-projection also with 2 or 4 K slices;
+                             0: heuristic                                   */
   int32_t solve_panel;    /* blocked Cholesky and triangular solves: 0 = one
                              level (each 64-wide step updates the whole
                              trailing matrix); k >= 1 = panels of k 64-wide
@@ -118,6 +122,9 @@ typedef struct {
                              NULL: computed from X and Z, which costs
                              O(r_thc^3) and three r_thc^2 buffers (supply it
                              for the DF form, where r_thc = n^2)              */
+  double fit_target;      /* stop the problem once an evaluated fit is at or
+                             below fit_target (time to a given fit; per
+                             problem in a batch); 0: off                     */
 } cpd_desc;
 
 typedef struct {
@@ -227,8 +234,10 @@ cpd_status cpd_batch_states(cpd_plan p, double* fits_host, int32_t* converged_ho
 int32_t cpd_batch_count(cpd_plan p);
 cpd_status cpd_batch_get_factors(cpd_plan p, int32_t idx, double* const F_dev[4], double* lambda_dev);
 cpd_status cpd_batch_stats(cpd_plan p, int32_t idx, cpd_stats_t* out);
-/* Autotuner decisions of the plan as "kind,M,N,K,...=tile" lines into buf
- * (NUL-terminated, truncated to len); returns the full length. */
+/* Autotuner decisions of the plan as "kind,M,N,K,...=shape" lines into buf
+ * (NUL-terminated, truncated to len); returns the full length.  FP64/FP32
+ * kinds: shape = tile edge; split-BF16 kinds (bf16core, bf16back, bf16proj):
+ * shape = bm + 1000 (bm x 256 tiles) + 10000 kparts. */
 int32_t cpd_autotune_log(cpd_plan p, char* buf, int32_t len);
 /* Laplace-transform row scaling of THC factors (eq. mp1_t and the THC-LT
  * amplitude after it): out[p, :] = exp(sign * eps[p] * t) * X[p, :] for
@@ -465,15 +474,17 @@ cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, con
                           void* workspace, size_t ws_bytes, void* stream, int32_t* failed, int32_t panel);
 /* cpd_test_gemm_split: C (M x N, FP64) = A B^T from FP64 A (M x K) and
  *   B (N x K) through the split-BF16 product (hi*hi + hi*lo + lo*hi, FP32
- *   accumulation).  With A2 != NULL the A operand is the FP32 product
- *   A o A2, split on the fly.  bm: row tile of the launch, 64 or 128 (0:
- *   the heuristic the sweep uses); other values return
- *   CPD_ERR_INVALID_ARG.  Uploads a one-entry argument table and
- *   synchronises before the launch. */
+ *   accumulation).  With A2 != NULL (B2 != NULL) the A (B) operand is the
+ *   FP32 product A o A2 (B o B2), split on the fly.  Launch shape: wide = 0:
+ *   128-column tiles with bm = 64 or 128 rows (0: the heuristic the sweep
+ *   uses), kparts = 1; wide = 1: bm x 256 tiles, bm = 128 or 256, with
+ *   kparts = 1..4 K slices (split-K, summed in order by a second launch).
+ *   Other values return CPD_ERR_INVALID_ARG.  Uploads a one-entry argument
+ *   table and synchronises before the launch. */
 size_t cpd_test_split_workspace(int32_t M, int32_t N, int32_t K);
 cpd_status cpd_test_gemm_split(int32_t M, int32_t N, int32_t K, const double* A, const double* A2,
-                               const double* B, double* C, void* workspace, size_t ws_bytes, void* stream,
-                               int32_t bm);
+                               const double* B, const double* B2, double* C, void* workspace, size_t ws_bytes,
+                               void* stream, int32_t bm, int32_t wide, int32_t kparts);
 /* cpd_test_mfma_probe: lane-layout probe of the 16x16x4 FP64 (fp32 = 0) or
  *   FP32 matrix instruction.  Probe p (of nprobe) feeds a[64p + lane] and
  *   b[64p + lane] to one wave with a zero accumulator and writes the four

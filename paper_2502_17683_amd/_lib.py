@@ -41,6 +41,7 @@ class CpdDesc(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("tied", i32),
         ("norm2", vp),
+        ("fit_target", ctypes.c_double),
     ]
 
 
@@ -102,7 +103,7 @@ EXPORTS = {
     "cpd_test_solve": (i32, [i32, i32, i32, vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(i32), i32]),
     "cpd_test_flow_spin_limit": (i32, [i32]),
     "cpd_test_split_workspace": (ctypes.c_size_t, [i32, i32, i32]),
-    "cpd_test_gemm_split": (i32, [i32, i32, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp, i32]),
+    "cpd_test_gemm_split": (i32, [i32, i32, i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp, i32, i32, i32]),
     "cpd_test_mfma_probe": (i32, [i32, i32, vp, vp, vp, vp]),
     "cpd_ws_workspace_size": (ctypes.c_size_t, [i32, i32, i32]),
     "cpd_ws_features": (i32, [i32, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),

@@ -35,7 +35,7 @@ class CPD:
 
     def __init__(self, X, Z, r_cp, init, precision="fp64", tol=1e-4, fit_floor=1e-7,
                  chol_fallback=True, use_graph=True, fit_every=1, autotune=False, solve_panel=0,
-                 device="cuda", tied=False, norm2=None):
+                 device="cuda", tied=False, norm2=None, fit_target=0.0):
         """tied: the particle-tied model F1 = F0, F3 = F2 (symmetric ALS;
         FP64/FP32 only; init[1] and init[3] are not used).  norm2: optional
         one-element device tensor holding ||G||^2 (skips its O(R_thc^3)
@@ -75,6 +75,7 @@ class CPD:
         d.tied = int(bool(tied))
         self.norm2 = None if norm2 is None else norm2.to(device=self.device, dtype=torch.float64).contiguous()
         d.norm2 = self.norm2.data_ptr() if self.norm2 is not None else None
+        d.fit_target = float(fit_target)
         d.stream = _stream(self.device).value
         need = self.lib.cpd_workspace_size(ctypes.byref(d))
         if need == 0:
@@ -164,6 +165,13 @@ class CPD:
         torch.cuda.current_stream(self.device).synchronize()
         return M
 
+    def autotune_log(self):
+        """The autotuner's decisions for this plan ("kind,dims=shape" lines)."""
+        n = self.lib.cpd_autotune_log(self.plan, None, 0)
+        buf = ctypes.create_string_buffer(max(n, 0) + 1)
+        self.lib.cpd_autotune_log(self.plan, buf, len(buf))
+        return buf.value.decode()
+
     def kernel_times(self, reps=5):
         """Average ms of (projection, core product, back-projection, Gram,
         solve, V + factorisation + forward solve, backward solve, V) at this
@@ -194,7 +202,8 @@ class CPDBatch:
     """
 
     def __init__(self, problems, precision="mixed", tol=1e-4, fit_floor=1e-7, chol_fallback=True,
-                 use_graph=True, fit_every=1, autotune=False, solve_panel=0, device="cuda", tied=False):
+                 use_graph=True, fit_every=1, autotune=False, solve_panel=0, device="cuda", tied=False,
+                 fit_targets=None):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.count = len(problems)
@@ -233,6 +242,7 @@ class CPDBatch:
             d.autotune = int(bool(autotune))
             d.solve_panel = int(solve_panel)
             d.tied = int(bool(tied))
+            d.fit_target = float(fit_targets[i]) if fit_targets is not None else 0.0
             d.stream = _stream(self.device).value
             self.shapes.append(([d.n[m] for m in range(4)], d.r_thc, d.r_cp))
         need = self.lib.cpd_batch_workspace_size(descs, self.count)
@@ -351,16 +361,18 @@ def test_solve(V, M, panel=0):
     return F, bool(failed.value)
 
 
-def test_gemm_split(A, B, A2=None, bm=0):
-    """C = A B^T (or (A o A2) B^T) through the split-BF16 GEMM (row tile bm:
-    64, 128, or 0 for the sweep's heuristic)."""
+def test_gemm_split(A, B, A2=None, bm=0, B2=None, wide=False, kparts=1):
+    """C = A B^T through the split-BF16 GEMM, with A (B) replaced by the
+    FP32 product A o A2 (B o B2) when given.  Launch shape: 128-column tiles
+    with bm = 64 or 128 rows (0: the sweep's heuristic), or with wide=True
+    bm x 256 tiles (bm = 128 or 256) and kparts K slices."""
     lib = _lib.load()
     M, K = A.shape
     N = B.shape[0]
     ws = torch.empty(lib.cpd_test_split_workspace(M, N, K), dtype=torch.uint8, device=A.device)
     C = torch.empty(M, N, dtype=torch.float64, device=A.device)
-    check(lib.cpd_test_gemm_split(M, N, K, _ptr(A), _ptr(A2), _ptr(B), _ptr(C), _ptr(ws), ws.numel(),
-                                  _stream(A.device), int(bm)), "cpd_test_gemm_split")
+    check(lib.cpd_test_gemm_split(M, N, K, _ptr(A), _ptr(A2), _ptr(B), _ptr(B2), _ptr(C), _ptr(ws), ws.numel(),
+                                  _stream(A.device), int(bm), int(bool(wide)), int(kparts)), "cpd_test_gemm_split")
     torch.cuda.current_stream(A.device).synchronize()
     return C
 

@@ -46,6 +46,7 @@ struct DevState {
   int32_t fallbacks_start;  // fallbacks at the start of the sweep
   double cond_max;       // largest (max L_ii / min L_ii)^2 seen in the sweep
   double fit_rule;       // fit at the last sweep the stopping rule looked at (-1: none)
+  double fit_target;     // stop once a fit is at or below this (0: off)
 };
 
 // Tile (tm, tn) of linear index bid in groups of G tile rows: a group runs

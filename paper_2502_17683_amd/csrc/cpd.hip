@@ -22,6 +22,7 @@
 namespace thccp {
 
 static const int HIST_CAP = 4096;
+static const int SPLIT_KPARTS_MAX = 4;  // split-K slices of the split-BF16 back-projection
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -72,6 +73,7 @@ struct Prob {
   double* partials;
   double* norm2;
   double* scratch64;
+  float* spart;  // split BF16: split-K partial products of the back-projection (4 x nmax x Tp)
 };
 
 // One grouped launch: device table + workgroup prefix sums.
@@ -82,6 +84,9 @@ struct GroupOp {
   int count = 0;         // table entries
   int bm = 64;
   bool a_t = false, b_t = false, had = false, apair = false, bpair = false;
+  bool wide = false;     // split BF16: bm x 256 tiles (gemm_split_wide_group)
+  int kparts = 1;        // split BF16, wide tiles: K slices (split-K) summed by a reduce launch
+  int maxm = 0, maxn = 0;
 };
 
 // One launch of a blocked solve: a step launch or a grouped panel GEMM.
@@ -175,7 +180,7 @@ int check_desc(const cpd_desc* d) {
     if (d->n[m] > (1 << 24)) return CPD_ERR_INVALID_ARG;
   if (d->precision != CPD_FP64 && d->precision != CPD_FP32 && d->precision != CPD_MIXED_BF16)
     return CPD_ERR_INVALID_ARG;
-  if (!(d->tol >= 0.0) || !(d->fit_floor >= 0.0)) return CPD_ERR_INVALID_ARG;
+  if (!(d->tol >= 0.0) || !(d->fit_floor >= 0.0) || !(d->fit_target >= 0.0)) return CPD_ERR_INVALID_ARG;
   return CPD_OK;
 }
 
@@ -262,6 +267,7 @@ void carve_mixed(Layout& L, Prob& q, SplitShare& sh) {
   mx.YT = (float*)L.take(4 * (size_t)Rc * mx.Rtp);
   mx.FTh = (__bf16*)L.take(2 * (size_t)Rc * mx.npad_max);
   mx.FTl = (__bf16*)L.take(2 * (size_t)Rc * mx.npad_max);
+  q.spart = (float*)L.take(4 * (size_t)SPLIT_KPARTS_MAX * q.nmax * q.Tp);
 }
 
 void carve_prob(Layout& L, Prob& q, int prec, SplitShare& sh) {
@@ -352,24 +358,111 @@ GroupOp gemm_op(TableBuilder& tb, const std::vector<GemmArgs<T>>& v, bool at, bo
   return op;
 }
 
-GroupOp split_op(TableBuilder& tb, const std::vector<SplitArgs>& v, bool apair, bool bpair) {
+// Launch shape of a split-BF16 grouped product, as one integer (the
+// autotune cache value): bm + 1000 wide + 10000 kparts.
+struct SplitCfg {
+  int bm = 128;
+  bool wide = false;
+  int kparts = 1;
+  int code() const { return bm + (wide ? 1000 : 0) + 10000 * kparts; }
+  static SplitCfg of(int c) {
+    SplitCfg g;
+    g.kparts = c / 10000;
+    c %= 10000;
+    g.wide = c >= 1000;
+    g.bm = c % 1000;
+    if (g.kparts < 1) g.kparts = 1;
+    return g;
+  }
+};
+
+long split_cfg_tiles(const std::vector<SplitArgs>& v, const SplitCfg& c) {
+  long t = 0;
+  for (auto& g : v)
+    t += (long)(c.wide ? split_wide_tile_count(g.M, g.N, c.bm) * c.kparts : split_tile_count(g.M, g.N, c.bm));
+  return t;
+}
+
+// Candidate launch shapes of a product; split-K only where a partial buffer
+// exists (the back-projection).
+std::vector<SplitCfg> split_candidates(bool splitk) {
+  std::vector<SplitCfg> c;
+  for (int bm : {64, 128}) c.push_back({bm, false, 1});
+  for (int bm : {128, 256}) {
+    c.push_back({bm, true, 1});
+    if (splitk)
+      for (int k = 2; k <= SPLIT_KPARTS_MAX; k *= 2) c.push_back({bm, true, k});
+  }
+  return c;
+}
+
+// Heuristic shape: wide 256 x 256 tiles when they alone cover most compute
+// units and K is long; for a short-M back-projection, wide tiles with
+// enough K slices to do so; otherwise the 128-column kernel with 64- or 128-row tiles (64 when
+// 128-row tiles would pad a quarter more rows, as in the Laplace batch, or
+// leave most compute units idle).
+SplitCfg split_default(const std::vector<SplitArgs>& v, bool splitk) {
+  const long w256 = split_cfg_tiles(v, {256, true, 1});
+  int kmin = 1 << 30;
+  for (auto& g : v) kmin = g.K < kmin ? g.K : kmin;
+  // long contractions only: with K = n (the projection) the 128-column
+  // kernel was measured faster
+  if (w256 >= 192 && kmin >= 2048) return {256, true, 1};
+  if (splitk) {
+    for (int k = 2; k <= SPLIT_KPARTS_MAX; k *= 2)
+      if (w256 * k >= 192) return {256, true, k};
+  }
+  long rows64 = 0, rows128 = 0;
+  for (auto& g : v) {
+    rows64 += (long)(g.M + 63) / 64 * 64;
+    rows128 += (long)(g.M + 127) / 128 * 128;
+  }
+  const long t128 = split_cfg_tiles(v, {128, false, 1});
+  return {(4 * rows128 >= 5 * rows64 || t128 < 128) ? 64 : 128, false, 1};
+}
+
+std::string split_key(const std::string& kind, const std::vector<SplitArgs>& v) {
+  std::vector<int> dims;
+  for (auto& g : v) {
+    dims.push_back(g.M);
+    dims.push_back(g.N);
+    dims.push_back(g.K);
+  }
+  return tune_key(kind, dims);
+}
+
+void split_apply(GroupOp& op, const std::vector<SplitArgs>& v, const SplitCfg& c, std::vector<int>* offs_out) {
+  op.bm = c.bm;
+  op.wide = c.wide;
+  op.kparts = c.kparts;
+  std::vector<int> offs(1, 0);
+  for (auto& g : v)
+    offs.push_back(offs.back() + (c.wide ? split_wide_tile_count(g.M, g.N, c.bm) * c.kparts
+                                         : split_tile_count(g.M, g.N, c.bm)));
+  op.total = offs.back();
+  if (offs_out) *offs_out = offs;
+}
+
+GroupOp split_op(TableBuilder& tb, const std::vector<SplitArgs>& v, bool apair, bool bpair, const std::string& kind,
+                 bool splitk) {
   GroupOp op;
   op.apair = apair;
   op.bpair = bpair;
   op.count = (int)v.size();
-  // 64-row tiles when 128-row ones would pad a quarter more rows (short M,
-  // as in the Laplace batch) or leave most compute units idle; otherwise
-  // 128 (fewer re-reads of the B operand)
-  long t128 = 0, rows64 = 0, rows128 = 0;
   for (auto& g : v) {
-    t128 += split_tile_count(g.M, g.N, 128);
-    rows64 += (long)(g.M + 63) / 64 * 64;
-    rows128 += (long)(g.M + 127) / 128 * 128;
+    if (g.M > op.maxm) op.maxm = g.M;
+    if (g.N > op.maxn) op.maxn = g.N;
   }
-  op.bm = (4 * rows128 >= 5 * rows64 || t128 < 128) ? 64 : 128;
-  std::vector<int> offs(1, 0);
-  for (auto& g : v) offs.push_back(offs.back() + split_tile_count(g.M, g.N, op.bm));
-  op.total = offs.back();
+  SplitCfg c = split_default(v, splitk);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(split_key(kind, v));
+    if (it != g_tune.end()) c = SplitCfg::of(it->second);
+  }
+  std::vector<int> offs;
+  split_apply(op, v, c, &offs);
+  // room for the prefix sums of any candidate shape (the autotuner rewrites them)
+  offs.resize(v.size() + 1 > offs.size() ? v.size() + 1 : offs.size());
   op.tab = tb.put(v);
   op.offs = (int*)tb.put(offs);
   return op;
@@ -582,19 +675,20 @@ void build_mixed(TableBuilder& tb, cpd_plan_s* p) {
         SplitOperand A{nullptr, nullptr, mx.WT[a], mx.WT[b], mx.Rtp};
         SplitOperand B = n == 0 ? SplitOperand{mx.Zh, mx.Zl, nullptr, nullptr, mx.Rtp}
                                 : SplitOperand{mx.ZTh, mx.ZTl, nullptr, nullptr, mx.Rtp};
-        core.push_back({Rc, Rt, mx.Rtp, A, B, mx.YT, nullptr, nullptr, mx.Rtp, done, &q.st->path, 0});
+        core.push_back({Rc, Rt, mx.Rtp, A, B, mx.YT, nullptr, nullptr, mx.Rtp, done, &q.st->path, 0, nullptr});
       }
       SplitOperand A{mx.Xh[n], mx.Xl[n], nullptr, nullptr, mx.Rtp};
       SplitOperand B{nullptr, nullptr, mx.WT[partner_of[n]], mx.YT, mx.Rtp};
-      back.push_back({q.n[n], Rc, mx.Rtp, A, B, nullptr, q.b64.Msol, nullptr, q.Tp, done, &q.st->path, 0});
+      back.push_back({q.n[n], Rc, mx.Rtp, A, B, nullptr, q.b64.Msol, nullptr, q.Tp, done, &q.st->path, 0, q.spart});
       SplitOperand PA{mx.FTh, mx.FTl, nullptr, nullptr, mx.npad_max};
       SplitOperand PB{mx.XTh[n], mx.XTl[n], nullptr, nullptr, mx.npad[n]};
-      proj.push_back({Rc, Rt, mx.npad[n], PA, PB, mx.WT[n], nullptr, nullptr, mx.Rtp, done, &q.st->path, 0});
+      proj.push_back({Rc, Rt, mx.npad[n], PA, PB, mx.WT[n], nullptr, nullptr, mx.Rtp, done, &q.st->path, 0,
+                      nullptr});
       ftt.push_back({q.b64.F[n], mx.FTh, mx.FTl, done, &q.st->path, q.n[n], Rc, q.Tp, mx.npad_max, mx.npad[n]});
     }
-    if (n == 0 || n == 2) p->score[n] = split_op(tb, core, true, false);
-    p->sback[n] = split_op(tb, back, false, true);
-    p->sproj[n] = split_op(tb, proj, false, false);
+    if (n == 0 || n == 2) p->score[n] = split_op(tb, core, true, false, "bf16core", false);
+    p->sback[n] = split_op(tb, back, false, true, "bf16back", true);
+    p->sproj[n] = split_op(tb, proj, false, false, "bf16proj", false);
     p->ftt[n] = tb.put(ftt);
   }
   // FP64 mode-3 MTTKRP for the fit of fit sweeps (split-path problems; a
@@ -754,7 +848,13 @@ void run_gemm(cpd_plan_s* p, hipStream_t s, const GroupOp& op) {
 }
 void run_split(cpd_plan_s* p, hipStream_t s, const GroupOp& op) {
   (void)p;
-  gemm_split_group(s, (const SplitArgs*)op.tab, op.offs, op.count, op.total, op.apair, op.bpair, op.bm);
+  const SplitArgs* tab = (const SplitArgs*)op.tab;
+  if (!op.wide) {
+    gemm_split_group(s, tab, op.offs, op.count, op.total, op.apair, op.bpair, op.bm);
+    return;
+  }
+  gemm_split_wide_group(s, tab, op.offs, op.count, op.total, op.apair, op.bpair, op.bm, op.kparts);
+  if (op.kparts > 1) gemm_split_reduce_group(s, tab, op.count, op.kparts, op.maxm, op.maxn);
 }
 template <typename T>
 void run_sched(cpd_plan_s* p, hipStream_t s, int n, const std::vector<SolveLaunch>& sched, int retry_pass) {
@@ -1040,7 +1140,7 @@ int rewind_sweep(cpd_plan_s* p) {
 // edges of every group once and records the faster in the process cache
 // (keyed by kind and shapes), which later table builds read.
 template <typename T>
-void autotune_ops(cpd_plan_s* p, hipStream_t s) {
+void autotune_ops(cpd_plan_s* p, hipStream_t s, bool gram_only = false) {
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1097,10 +1197,70 @@ void autotune_ops(cpd_plan_s* p, hipStream_t s) {
   };
   const std::string kind = sizeof(T) == 8 ? "f64" : "f32";
   for (int n = 0; n < 4; ++n) {
-    if (n == 0 || n == 2) tune(p->core[n], kind + "core");
-    tune(p->back[n], kind + "back");
+    if (!gram_only && (n == 0 || n == 2)) tune(p->core[n], kind + "core");
+    if (!gram_only) tune(p->back[n], kind + "back");
     tune(p->gram[n], kind + "gram");
-    tune(p->proj[n], kind + "proj");
+    if (!gram_only) tune(p->proj[n], kind + "proj");
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+// Launch-shape autotuning of the split-BF16 grouped products (core,
+// back-projection, projection): every candidate shape (128-column tiles
+// with 64 or 128 rows; wide bm x 256 tiles with bm = 128 or 256; for the
+// back-projection also 2 or 4 K slices) is timed once on the plan's own
+// tables and the fastest is kept in the process cache.
+void autotune_split(cpd_plan_s* p, hipStream_t s) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return;
+  }
+  auto tune = [&](GroupOp& op, const std::string& kind, bool splitk) {
+    if (op.total == 0 || !op.tab) return;
+    std::vector<SplitArgs> host(op.count);
+    if (hipMemcpy(host.data(), op.tab, sizeof(SplitArgs) * op.count, hipMemcpyDeviceToHost) != hipSuccess) return;
+    const std::string key = split_key(kind, host);
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) {
+        p->tune_log.push_back({key, it->second});
+        return;
+      }
+    }
+    float best = 1e30f;
+    SplitCfg best_c = SplitCfg::of(op.bm + (op.wide ? 1000 : 0) + 10000 * op.kparts);
+    for (const SplitCfg& c : split_candidates(splitk)) {
+      GroupOp t = op;
+      std::vector<int> offs;
+      split_apply(t, host, c, &offs);
+      if (t.total <= 0) continue;
+      if (hipMemcpy(op.offs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice) != hipSuccess) return;
+      float ms = 0.f;
+      for (int w = 0; w < 2; ++w) {  // second pass is the timed one
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < 3; ++r) run_split(p, s, t);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
+      }
+      if (hipGetLastError() != hipSuccess) return;
+      if (ms < best) {
+        best = ms;
+        best_c = c;
+      }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best_c.code();
+    p->tune_log.push_back({key, best_c.code()});
+  };
+  for (int n = 0; n < 4; ++n) {
+    if (n == 0 || n == 2) tune(p->score[n], "bf16core", false);
+    tune(p->sback[n], "bf16back", true);
+    tune(p->sproj[n], "bf16proj", false);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1148,11 +1308,17 @@ int plan_create(const cpd_desc* descs, int count, void* workspace, size_t ws_byt
   hipStream_t s = p->stream;
   fill_bytes(s, workspace, p->tables_off);
   rc = upload_tables(p, s);
-  if (rc == CPD_OK && p->autotune && p->prec != CPD_MIXED_BF16) {
+  if (rc == CPD_OK && p->autotune) {
     // tuning launches write the plan's intermediate buffers; they are
-    // cleared again below and recomputed by the set-up
+    // cleared again below and recomputed by the set-up.  Split-BF16 plans
+    // tune their split products and the FP64 Gram (their other FP64
+    // products run only for problems the precision guard promotes).
     if (p->prec == CPD_FP64) autotune_ops<double>(p, s);
-    else autotune_ops<float>(p, s);
+    else if (p->prec == CPD_FP32) autotune_ops<float>(p, s);
+    else {
+      autotune_split(p, s);
+      autotune_ops<double>(p, s, true);
+    }
     rc = upload_tables(p, s);
     fill_bytes(s, workspace, p->tables_off);
   }
@@ -1179,7 +1345,7 @@ int plan_create(const cpd_desc* descs, int count, void* workspace, size_t ws_byt
       for (int m = 0; m < 4; ++m)
         copy_normalised_init(s, q.d.init[p->tied ? m & 2 : m], q.n[m], q.Rc, q.Tp, q.b64.F[m]);
     }
-    state_reset(s, q.st, q.norm2);
+    state_reset(s, q.st, q.norm2, q.d.fit_target > 0.0 ? q.d.fit_target : 0.0);
   }
   if (rc == CPD_OK) rc = refresh_all(p, s);
   if (rc == CPD_OK && hipGetLastError() != hipSuccess) rc = CPD_ERR_HIP;

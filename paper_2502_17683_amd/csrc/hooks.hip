@@ -165,50 +165,62 @@ cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, con
 size_t cpd_test_split_workspace(int32_t M, int32_t N, int32_t K) {
   if (M <= 0 || N <= 0 || K <= 0) return 0;
   const size_t Kp = (K + 31) / 32 * 32;
-  return 4 * al(2 * (size_t)M * Kp) + 4 * al(2 * (size_t)N * Kp) + 2 * al(4 * (size_t)M * Kp) +
-         al(sizeof(SplitArgs)) + al(2 * sizeof(int));
+  return 2 * al(2 * (size_t)M * Kp) + 2 * al(2 * (size_t)N * Kp) + 2 * al(4 * (size_t)M * Kp) +
+         2 * al(4 * (size_t)N * Kp) + al(4 * (size_t)4 * M * N) + al(sizeof(SplitArgs)) + al(2 * sizeof(int));
 }
 
-// C (M x N, dense) = A B^T with A (M x K), B (N x K) dense FP64; when A2 is
-// non-null the A operand is the FP32 element-wise product A o A2 (split on
-// the fly), as in the fused core product.
+// C (M x N, dense) = A B^T with A (M x K), B (N x K) dense FP64; when A2
+// (B2) is non-null the A (B) operand is the FP32 element-wise product
+// A o A2 (B o B2), split on the fly, as in the fused core product and
+// back-projection.  bm/wide/kparts select the launch shape.
 cpd_status cpd_test_gemm_split(int32_t M, int32_t N, int32_t K, const double* A, const double* A2,
-                               const double* B, double* C, void* workspace, size_t ws_bytes, void* stream,
-                               int32_t bm) {
+                               const double* B, const double* B2, double* C, void* workspace, size_t ws_bytes,
+                               void* stream, int32_t bm, int32_t wide, int32_t kparts) {
   if (M <= 0 || N <= 0 || K <= 0 || !A || !B || !C) return CPD_ERR_INVALID_ARG;
-  if (bm == 0) bm = split_default_bm(M, N);
-  if (bm != 64 && bm != 128) return CPD_ERR_INVALID_ARG;
+  if (wide) {
+    if ((bm != 128 && bm != 256) || kparts < 1 || kparts > 4) return CPD_ERR_INVALID_ARG;
+  } else {
+    if (bm == 0) bm = split_default_bm(M, N);
+    if ((bm != 64 && bm != 128) || kparts != 1) return CPD_ERR_INVALID_ARG;
+  }
   if (!workspace || ws_bytes < cpd_test_split_workspace(M, N, K)) return CPD_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   const int Kp = (K + 31) / 32 * 32;
   char* b = (char*)workspace;
   __bf16* Ah = (__bf16*)b; b += al(2 * (size_t)M * Kp);
   __bf16* Al = (__bf16*)b; b += al(2 * (size_t)M * Kp);
-  b += 2 * al(2 * (size_t)M * Kp);
   __bf16* Bh = (__bf16*)b; b += al(2 * (size_t)N * Kp);
   __bf16* Bl = (__bf16*)b; b += al(2 * (size_t)N * Kp);
-  b += 2 * al(2 * (size_t)N * Kp);
   float* Ap = (float*)b; b += al(4 * (size_t)M * Kp);
   float* Aq = (float*)b; b += al(4 * (size_t)M * Kp);
+  float* Bp = (float*)b; b += al(4 * (size_t)N * Kp);
+  float* Bq = (float*)b; b += al(4 * (size_t)N * Kp);
+  float* part = (float*)b; b += al(4 * (size_t)4 * M * N);
   SplitArgs* tab = (SplitArgs*)b; b += al(sizeof(SplitArgs));
   int* offs = (int*)b;
-  split_rows_f64(s, B, N, K, K, Bh, Bl, Kp, Kp);
-  SplitOperand opB{Bh, Bl, nullptr, nullptr, Kp};
-  SplitOperand opA;
-  if (A2) {
-    hipLaunchKernelGGL(to_f32_padded, dim3(grid_of((size_t)M * Kp)), dim3(256), 0, s, A, M, K, Ap, Kp);
-    hipLaunchKernelGGL(to_f32_padded, dim3(grid_of((size_t)M * Kp)), dim3(256), 0, s, A2, M, K, Aq, Kp);
-    opA = SplitOperand{nullptr, nullptr, Ap, Aq, Kp};
-  } else {
-    split_rows_f64(s, A, M, K, K, Ah, Al, Kp, Kp);
-    opA = SplitOperand{Ah, Al, nullptr, nullptr, Kp};
-  }
-  const SplitArgs ha{M, N, Kp, opA, opB, nullptr, C, nullptr, N, nullptr, nullptr, 0};
-  const int ho[2] = {0, split_tile_count(M, N, bm)};
+  auto operand = [&](const double* X, const double* X2, int rows, __bf16* h, __bf16* l, float* p, float* q) {
+    if (X2) {
+      hipLaunchKernelGGL(to_f32_padded, dim3(grid_of((size_t)rows * Kp)), dim3(256), 0, s, X, rows, K, p, Kp);
+      hipLaunchKernelGGL(to_f32_padded, dim3(grid_of((size_t)rows * Kp)), dim3(256), 0, s, X2, rows, K, q, Kp);
+      return SplitOperand{nullptr, nullptr, p, q, Kp};
+    }
+    split_rows_f64(s, X, rows, K, K, h, l, Kp, Kp);
+    return SplitOperand{h, l, nullptr, nullptr, Kp};
+  };
+  const SplitOperand opA = operand(A, A2, M, Ah, Al, Ap, Aq);
+  const SplitOperand opB = operand(B, B2, N, Bh, Bl, Bp, Bq);
+  const SplitArgs ha{M, N, Kp, opA, opB, nullptr, C, nullptr, N, nullptr, nullptr, 0, part};
+  const int tiles = wide ? split_wide_tile_count(M, N, bm) * kparts : split_tile_count(M, N, bm);
+  const int ho[2] = {0, tiles};
   if (hipMemcpyAsync(tab, &ha, sizeof(ha), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
   if (hipMemcpyAsync(offs, ho, sizeof(ho), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return CPD_ERR_HIP;  // host copies of ha/ho go out of scope
-  gemm_split_group(s, tab, offs, 1, ho[1], opA.p != nullptr, false, bm);
+  if (wide) {
+    gemm_split_wide_group(s, tab, offs, 1, tiles, A2 != nullptr, B2 != nullptr, bm, kparts);
+    gemm_split_reduce_group(s, tab, 1, kparts, M, N);
+  } else {
+    gemm_split_group(s, tab, offs, 1, tiles, A2 != nullptr, B2 != nullptr, bm);
+  }
   return hipGetLastError() == hipSuccess ? CPD_OK : CPD_ERR_HIP;
 }
 

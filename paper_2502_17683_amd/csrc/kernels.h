@@ -243,7 +243,7 @@ void hadamard_inplace_f64(hipStream_t s, double* A, const double* B, size_t coun
 void transposed_dot_f64(hipStream_t s, const double* P, const double* Q, int R, int ld, double* partials,
                         double* out);
 void fill_bytes(hipStream_t s, void* p, size_t bytes);
-void state_reset(hipStream_t s, DevState* st, double* norm2_src);
+void state_reset(hipStream_t s, DevState* st, double* norm2_src, double fit_target);
 void cast_f64_to_f32(hipStream_t s, const double* a, float* b, size_t count);
 void copy_normalised_init(hipStream_t s, const double* src, int n, int R, int ld, double* dst);
 void lt_scale_rows(hipStream_t s, const double* X, const double* eps, int n, int r, double t, double sign,

@@ -48,6 +48,7 @@ struct SplitArgs {
   const int32_t* done;
   const int32_t* gate;  // skip unless *gate == want (per-problem precision path)
   int32_t want;
+  float* part;          // split-K launches: kparts x M x ldc FP32 partial products
 };
 // Tiles of one product with row tile bm (128, or 64 for short M or when
 // the 128-row tiles would leave most compute units idle: split_default_bm).
@@ -56,6 +57,17 @@ int split_default_bm(int M, int N);
 // Grouped launch: all problems share (A pair?, B pair?) and the row tile bm.
 void gemm_split_group(hipStream_t s, const SplitArgs* tab, const int* offs, int nprob, int total_tiles,
                       bool apair, bool bpair, int bm);
+
+// Wide tiles: bm x 256 per workgroup (bm = 128 or 256), each of the four
+// waves holding a (bm/2) x 128 accumulator block, for products large
+// enough to fill the compute units with them.  With kparts > 1 the K range
+// is cut into kparts slices (split-K): each workgroup writes its partial
+// product to SplitArgs::part and gemm_split_reduce_group sums the slices in
+// order into C (deterministic).
+int split_wide_tile_count(int M, int N, int bm);
+void gemm_split_wide_group(hipStream_t s, const SplitArgs* tab, const int* offs, int nprob, int total_tiles,
+                           bool apair, bool bpair, int bm, int kparts);
+void gemm_split_reduce_group(hipStream_t s, const SplitArgs* tab, int nprob, int kparts, int max_m, int max_n);
 
 // dst (cols x ldd) = split(src^T): dst[c][r] for c < cols, r < dcols
 // (r >= rows written as 0).

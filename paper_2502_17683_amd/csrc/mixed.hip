@@ -66,6 +66,15 @@ struct Stage<false, C> {
       ok |= (uint32_t)v << c;
     }
   }
+  // one chunk of a later k-tile into the same registers (the row, hence
+  // its validity bit, does not depend on the k-tile)
+  __device__ __forceinline__ void load_chunk(const SplitOperand& op, int rows, int r0, int k0, int tid, int c) {
+    const gptr<const __bf16> hi = as_global(op.hi), lo = as_global(op.lo);
+    const int gr = r0 + ((tid + 256 * c) >> 2);
+    const size_t off = (size_t)(gr < rows ? gr : r0) * op.ld + k0 + (tid & 3) * 8;
+    h[c] = *(const gptr<const u4_t>)(hi + off);
+    l[c] = *(const gptr<const u4_t>)(lo + off);
+  }
   __device__ __forceinline__ void get(int c, u4_t& H, u4_t& L) {
     u4_t x = h[c], y = l[c];
     asm volatile("" : "+v"(x), "+v"(y));
@@ -93,6 +102,16 @@ struct Stage<true, C> {
         q[c][u] = *(const gptr<const f4_t>)(Q + off + 4 * u);
       }
       ok |= (uint32_t)v << c;
+    }
+  }
+  __device__ __forceinline__ void load_chunk(const SplitOperand& op, int rows, int r0, int k0, int tid, int c) {
+    const gptr<const float> P = as_global(op.p), Q = as_global(op.q);
+    const int gr = r0 + ((tid + 256 * c) >> 2);
+    const size_t off = (size_t)(gr < rows ? gr : r0) * op.ld + k0 + (tid & 3) * 8;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      p[c][u] = *(const gptr<const f4_t>)(P + off + 4 * u);
+      q[c][u] = *(const gptr<const f4_t>)(Q + off + 4 * u);
     }
   }
   __device__ __forceinline__ void get(int c, u4_t& H, u4_t& L) {
@@ -242,6 +261,219 @@ void gemm_split_group(hipStream_t s, const SplitArgs* tab, const int* offs, int 
   THCCP_SPLIT_CASE(false, true)
   THCCP_SPLIT_CASE(true, true)
 #undef THCCP_SPLIT_CASE
+}
+
+// ------------------------------------------------------------ wide tiles
+// BM x 256 tiles, 2 x 2 waves of (BM / 2) x 128: each LDS fragment read
+// feeds 3 * BM / 32 (A) or 24 (B) matrix-core products, against 3 x 4 in
+// the 128 x 128 kernel above.  LDS rows are 32 bf16 (64 bytes) with no
+// padding; the 16-byte chunk c of row r is stored at chunk
+// c ^ (((r >> 1) ^ (r >> 3)) & 3), so the 16 lanes of a fragment read (rows
+// r0..r0+15, one chunk) and the 16 lanes of a staging store (rows
+// r0..r0+3, all chunks) touch distinct 16-byte bank groups, in every
+// aligned group of 8 lanes as well.
+namespace {
+constexpr int WBN = 256;
+__device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ (((row >> 1) ^ (row >> 3)) & 3); }
+}  // namespace
+
+template <bool APAIR, bool BPAIR, int BM>
+__global__ __launch_bounds__(256, 1) void gemm_split_wide_kernel(const SplitArgs* tab, const int* offs, int nprob,
+                                                                  int kparts) {
+  constexpr int CA = BM / 64, CB = WBN / 64;
+  constexpr int TI = BM / 32;  // 16-row MFMA tiles per wave
+  constexpr int TJ = 8;        // 16-column MFMA tiles per wave
+  constexpr int SA = BM * SBK, SB = WBN * SBK;  // bf16 per half-operand per stage
+  constexpr int STAGE = 2 * SA + 2 * SB;
+  __shared__ __attribute__((aligned(16))) __bf16 lds[2 * STAGE];
+  int pid = 0;
+  while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
+  const SplitArgs a = tab[pid];
+  if (a.done && *a.done) return;
+  if (a.gate && *a.gate != a.want) return;
+  const int tiles_n = (a.N + WBN - 1) / WBN, tiles_m = (a.M + BM - 1) / BM;
+  const int ntiles = tiles_m * tiles_n;
+  const int local = blockIdx.x - offs[pid];
+  const int kp = local / ntiles;
+  const int bid = xcd_remap(local - kp * ntiles, ntiles);
+  int tm, tn;
+  grouped_tile(bid, tiles_m, tiles_n, 4, tm, tn);
+  const int m0 = tm * BM, n0 = tn * WBN;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int nk_all = a.K / SBK;
+  const int kt0 = (int)((long)nk_all * kp / kparts), kt1 = (int)((long)nk_all * (kp + 1) / kparts);
+
+  Stage<APAIR, CA> sa;
+  Stage<BPAIR, CB> sb;
+  f4_t acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+  // staging store of chunk c: thread tid owns rows (tid + 256 c) >> 2, chunk
+  // tid & 3, of both operands
+  auto store_chunk = [&](int st, int c) {
+    __bf16* Ah = lds + st * STAGE;
+    __bf16* Al = Ah + SA;
+    __bf16* Bh = Al + SA;
+    __bf16* Bl = Bh + SB;
+    const int row = (tid + 256 * c) >> 2;
+    const int off = row * SBK + 8 * swz(row, tid & 3);
+    u4_t h, l;
+    if (c < CA) {
+      sa.get(c, h, l);
+      *(u4_t*)&Ah[off] = h;
+      *(u4_t*)&Al[off] = l;
+    }
+    sb.get(c, h, l);
+    *(u4_t*)&Bh[off] = h;
+    *(u4_t*)&Bl[off] = l;
+  };
+
+  // The staging registers hold the k-tile after the one being stored: each
+  // chunk of k-tile kt + 2 is loaded as soon as its registers have been
+  // stored to LDS (for k-tile kt + 1, during the products of kt), so the
+  // loads have about one and a half k-tiles of products to arrive in.
+  if (kt0 < kt1) {
+    sa.load(a.A, a.M, m0, kt0 * SBK, tid);
+    sb.load(a.B, a.N, n0, kt0 * SBK, tid);
+#pragma unroll
+    for (int c = 0; c < CB; ++c) store_chunk(0, c);
+    if (kt0 + 1 < kt1) {
+      sa.load(a.A, a.M, m0, (kt0 + 1) * SBK, tid);
+      sb.load(a.B, a.N, n0, (kt0 + 1) * SBK, tid);
+    }
+  }
+  __syncthreads();
+  const int fch = lane >> 4;  // fragment chunk: k offset 8 * fch
+  for (int kt = kt0; kt < kt1; ++kt) {
+    const int cur = (kt - kt0) & 1;
+    const bool more = kt + 1 < kt1, more2 = kt + 2 < kt1;
+    const __bf16* Ah = lds + cur * STAGE;
+    const __bf16* Al = Ah + SA;
+    const __bf16* Bh = Al + SA;
+    const __bf16* Bl = Bh + SB;
+    bf16x8_t ah[TI], al[TI];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+      const int row = wm * (BM / 2) + i * 16 + (lane & 15);
+      const int off = row * SBK + 8 * swz(row, fch);
+      ah[i] = *(const bf16x8_t*)&Ah[off];
+      al[i] = *(const bf16x8_t*)&Al[off];
+    }
+    auto bfrag = [&](int j, bf16x8_t& h, bf16x8_t& l) {
+      const int col = wn * 128 + j * 16 + (lane & 15);
+      const int off = col * SBK + 8 * swz(col, fch);
+      h = *(const bf16x8_t*)&Bh[off];
+      l = *(const bf16x8_t*)&Bl[off];
+    };
+    bf16x8_t bh, bl;
+    bfrag(0, bh, bl);
+    // software pipeline over the 8 column tiles: the fragments of tile
+    // j + 1 are read while tile j's products run; the staging stores of the
+    // next k-tile are spread over the last column tiles
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      bf16x8_t nh, nl;
+      if (j + 1 < TJ) bfrag(j + 1, nh, nl);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+      }
+      // (the other stage was last read in the previous iteration, which
+      // every wave finished before the barrier that ended it)
+      if (more && j >= TJ - CB) {
+        const int c = j - (TJ - CB);
+        store_chunk(cur ^ 1, c);
+        if (more2) {
+          if (c < CA) sa.load_chunk(a.A, a.M, m0, (kt + 2) * SBK, tid, c);
+          sb.load_chunk(a.B, a.N, n0, (kt + 2) * SBK, tid, c);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (j + 1 < TJ) {
+        bh = nh;
+        bl = nl;
+      }
+    }
+    __syncthreads();
+  }
+
+  const bool partial = kparts > 1;
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * (BM / 2) + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * 128 + j * 16 + (lane & 15);
+        if (row < a.M && col < a.N) {
+          const size_t off = (size_t)row * a.ldc + col;
+          if (partial) {
+            as_global(a.part)[(size_t)kp * a.M * a.ldc + off] = acc[i][j][r];
+          } else {
+            if (a.C32) as_global(a.C32)[off] = acc[i][j][r];
+            if (a.C64) as_global(a.C64)[off] = (double)acc[i][j][r];
+            if (a.C64b) as_global(a.C64b)[off] = (double)acc[i][j][r];
+          }
+        }
+      }
+}
+
+// C = sum over the kparts slices, in slice order (FP32 sums, as the
+// accumulation inside one slice).  blockIdx.y selects the problem.
+__global__ __launch_bounds__(256) void split_reduce_kernel(const SplitArgs* tab, int kparts) {
+  const SplitArgs a = tab[blockIdx.y];
+  if (a.done && *a.done) return;
+  if (a.gate && *a.gate != a.want) return;
+  const size_t total = (size_t)a.M * a.N;
+  const size_t slice = (size_t)a.M * a.ldc;
+  const gptr<const float> P = as_global((const float*)a.part);
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    const size_t r = e / a.N, c = e % a.N;
+    const size_t off = r * a.ldc + c;
+    float v = P[off];
+    for (int k = 1; k < kparts; ++k) v += P[k * slice + off];
+    if (a.C32) as_global(a.C32)[off] = v;
+    if (a.C64) as_global(a.C64)[off] = (double)v;
+    if (a.C64b) as_global(a.C64b)[off] = (double)v;
+  }
+}
+
+int split_wide_tile_count(int M, int N, int bm) { return ((M + bm - 1) / bm) * ((N + WBN - 1) / WBN); }
+
+void gemm_split_wide_group(hipStream_t s, const SplitArgs* tab, const int* offs, int nprob, int total_tiles,
+                           bool apair, bool bpair, int bm, int kparts) {
+  if (total_tiles <= 0) return;
+  if (kparts < 1) kparts = 1;
+  dim3 grid(total_tiles), block(256);
+#define THCCP_WIDE_CASE(AP, BP)                                                                              \
+  if (apair == AP && bpair == BP) {                                                                         \
+    if (bm == 128)                                                                                          \
+      hipLaunchKernelGGL((gemm_split_wide_kernel<AP, BP, 128>), grid, block, 0, s, tab, offs, nprob, kparts); \
+    else                                                                                                    \
+      hipLaunchKernelGGL((gemm_split_wide_kernel<AP, BP, 256>), grid, block, 0, s, tab, offs, nprob, kparts); \
+    return;                                                                                                 \
+  }
+  THCCP_WIDE_CASE(false, false)
+  THCCP_WIDE_CASE(true, false)
+  THCCP_WIDE_CASE(false, true)
+  THCCP_WIDE_CASE(true, true)
+#undef THCCP_WIDE_CASE
+}
+
+void gemm_split_reduce_group(hipStream_t s, const SplitArgs* tab, int nprob, int kparts, int max_m, int max_n) {
+  if (kparts <= 1 || nprob <= 0) return;
+  size_t blocks = ((size_t)max_m * max_n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)blocks, nprob), dim3(256), 0, s, tab, kparts);
 }
 
 // ------------------------------------------------------------- splitting

@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void fit_final_kernel(const FitArgs<T>* tab, i
       st->path = 1;
       st->promote = 1;
     } else if ((rule && (fit <= fit_floor || (ref >= 0.0 && fabs(fit - ref) <= tol * ref))) || !isfinite(fit) ||
-               (st->flags & (FLAG_NOT_SPD | FLAG_SOLVE_STALL))) {
+               fit <= st->fit_target || (st->flags & (FLAG_NOT_SPD | FLAG_SOLVE_STALL))) {
       st->done = 1;
     }
     if (rule) st->fit_rule = fit;
@@ -466,9 +466,10 @@ void fill_bytes(hipStream_t s, void* p, size_t bytes) {
   hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(256), 0, s, (uint32_t*)p, words);
 }
 
-__global__ void state_reset_kernel(DevState* st, const double* norm2_src) {
+__global__ void state_reset_kernel(DevState* st, const double* norm2_src, double fit_target) {
   if (threadIdx.x == 0) {
     st->norm2 = *norm2_src;
+    st->fit_target = fit_target;
     st->fit_prev = -1.0;
     st->fit_rule = -1.0;
     st->inner = 0.0;
@@ -490,8 +491,8 @@ __global__ void state_reset_kernel(DevState* st, const double* norm2_src) {
     }
   }
 }
-void state_reset(hipStream_t s, DevState* st, double* norm2_src) {
-  hipLaunchKernelGGL(state_reset_kernel, dim3(1), dim3(64), 0, s, st, norm2_src);
+void state_reset(hipStream_t s, DevState* st, double* norm2_src, double fit_target) {
+  hipLaunchKernelGGL(state_reset_kernel, dim3(1), dim3(64), 0, s, st, norm2_src, fit_target);
 }
 
 __global__ void cast_d2f_kernel(const double* a, float* b, size_t n) {

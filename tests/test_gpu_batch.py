@@ -110,3 +110,55 @@ def test_lt_workload_runs():
         f"promoted to FP64: {[meta[i] for i in promoted]}")
     assert np.all(np.isfinite(fb))
     assert np.all(fb[:, -1] <= fb[:, 0] * (1 + 1e-6))
+
+
+def test_split_autotune_on_the_laplace_batch():
+    """The autotuner on a split-BF16 batch of the full Laplace workload's
+    sizes: every split product kind gets a decision, the decision is one of
+    the candidate launch shapes, and the tuned plan's fits (FP64-evaluated)
+    equal the untuned plan's within the split rounding (different launch
+    shapes only change the FP32 accumulation order)."""
+    from paper_2502_17683_amd import CPDBatch
+    from synth import LT_SYSTEMS
+    systems = [make_lt_system(o, v, i) for i, (o, v) in enumerate(LT_SYSTEMS)]
+    problems, _ = _problems(systems, (0.01, 0.3))
+    a = CPDBatch(problems, precision="mixed", tol=0.0, fit_floor=0.0, autotune=True)
+    log = a.autotune_log()
+    say(f"split autotune log:\n{log}")
+    kinds = {line.split(",")[0]: int(line.split("=")[1]) for line in log.splitlines() if line}
+    for k in ("bf16core", "bf16back", "bf16proj", "f64gram"):
+        assert k in kinds
+    valid = {64 + 10000, 128 + 10000} | {bm + 1000 + 10000 * kp for bm in (128, 256) for kp in (1, 2, 4)}
+    assert all(v in valid for k, v in kinds.items() if k.startswith("bf16"))
+    fa = a.sweep(6)
+    a.close()
+    b = CPDBatch(problems, precision="mixed", tol=0.0, fit_floor=0.0, autotune=False)
+    fb = b.sweep(6)
+    b.close()
+    for x, y in zip(fa, fb):
+        x, y = np.array(x), np.array(y)
+        assert np.all(np.abs(x - y) <= 1e-4 * y)
+
+
+def test_fit_target_stops_each_problem_at_its_target():
+    """cpd_desc.fit_target: each problem of an FP64 batch stops at the first
+    sweep whose fit is at or below its own target (here the oracle's fit
+    after 3, 7 and 11 sweeps), and its fits up to there follow the oracle."""
+    from paper_2502_17683_amd import CPDBatch
+    from synth import make_thc
+    stops = (3, 7, 11)
+    probs, refs = [], []
+    for k, (n, rt, rc) in enumerate(((16, 64, 40), (24, 96, 50), (20, 80, 60))):
+        X, Z = make_thc(n, rt, 30 + k)
+        init = init_factors([n] * 4, rc, 1030 + k)
+        probs.append(dict(X=to_dev(X), Z=to_dev(Z), r_cp=rc, init=[to_dev(f) for f in init]))
+        refs.append(matfree.mf_cp_als([X] * 4, Z, init, 20, tol=0.0, fit_floor=0.0)["fits"])
+    targets = [refs[i][stops[i] - 1] * (1 + 1e-12) for i in range(3)]
+    b = CPDBatch(probs, precision="fp64", tol=0.0, fit_floor=0.0, fit_targets=targets)
+    fits = b.sweep(20)
+    _, done, sweeps = b.states()
+    say(f"fit_target stops: {list(sweeps)}")
+    for i in range(3):
+        assert done[i] and sweeps[i] == stops[i]
+        np.testing.assert_allclose(fits[i], refs[i][:stops[i]], rtol=1e-10)
+    b.close()

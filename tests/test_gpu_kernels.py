@@ -144,23 +144,35 @@ def test_dataflow_wait_gives_up_and_recovers():
     assert not failed and rel_err(F.cpu().numpy(), ref) <= 1e-9
 
 
-@pytest.mark.parametrize("M,N,K", [(37, 29, 50), (256, 130, 300), (800, 1000, 1024)])
-@pytest.mark.parametrize("pair", [False, True])
-@pytest.mark.parametrize("bm", [64, 128])
-def test_gemm_split_error_bound(M, N, K, pair, bm):
+SPLIT_SHAPES = [(64, False, 1), (128, False, 1), (128, True, 1), (256, True, 1), (256, True, 2), (128, True, 4)]
+
+
+@pytest.mark.parametrize("M,N,K", [(37, 29, 50), (256, 130, 300), (800, 1000, 1024), (300, 520, 4000)])
+@pytest.mark.parametrize("pair", ["none", "A", "B"])
+@pytest.mark.parametrize("bm,wide,kparts", SPLIT_SHAPES)
+def test_gemm_split_error_bound(M, N, K, pair, bm, wide, kparts):
     """Split-BF16 product: every element within the bound of one correction
     pass (dropped lo*lo term and the two bf16 roundings, ~3 * 2^-16 of
-    sum |a||b|) plus FP32 accumulation (K * 2^-24 of sum |a||b|)."""
+    sum |a||b|) plus FP32 accumulation (K * 2^-24 of sum |a||b|), in every
+    launch shape (128-column tiles; bm x 256 tiles; K slices summed in
+    FP32, still within K * 2^-24), with the FP32 pair product on either
+    operand."""
     from paper_2502_17683_amd import test_gemm_split
-    say(f"split M={M} N={N} K={K} pair={pair} bm={bm}")
+    if (M, N, K) == (300, 520, 4000) and pair == "none" and not (wide and kparts > 1):
+        pytest.skip("long-K case: run with split-K shapes and pair operands")
+    say(f"split M={M} N={N} K={K} pair={pair} bm={bm} wide={wide} kparts={kparts}")
     rng = np.random.default_rng(M + N + K)
     A = rng.standard_normal((M, K))
-    A2 = rng.standard_normal((M, K)) if pair else None
     B = rng.standard_normal((N, K))
-    C = test_gemm_split(to_dev(A), to_dev(B), to_dev(A2) if pair else None, bm=bm).cpu().numpy()
-    Aop = (A.astype(np.float32) * A2.astype(np.float32)).astype(np.float64) if pair else A
-    ref = Aop @ B.T
-    scale = np.abs(Aop) @ np.abs(B).T
+    A2 = rng.standard_normal((M, K)) if pair == "A" else None
+    B2 = rng.standard_normal((N, K)) if pair == "B" else None
+    C = test_gemm_split(to_dev(A), to_dev(B), to_dev(A2) if A2 is not None else None, bm=bm,
+                        B2=to_dev(B2) if B2 is not None else None, wide=wide, kparts=kparts).cpu().numpy()
+    f32 = lambda X, X2: (X.astype(np.float32) * X2.astype(np.float32)).astype(np.float64)
+    Aop = f32(A, A2) if A2 is not None else A
+    Bop = f32(B, B2) if B2 is not None else B
+    ref = Aop @ Bop.T
+    scale = np.abs(Aop) @ np.abs(Bop).T
     bound = (3 * 2.0 ** -16 + K * 2.0 ** -24) * scale
     assert np.all(np.abs(C - ref) <= bound)
     # and it really is better than a single bf16 pass
