@@ -374,6 +374,21 @@ size_t cpd_ws_workspace_size(int32_t n0, int32_t r_thc, int32_t r_cp);
 cpd_status cpd_ws_features(int32_t n0, int32_t r_thc, const double* X0, const double* Z, float* feat,
                            double* heur, void* workspace, size_t workspace_bytes, void* stream);
 
+/* cpd_ws_features without a workspace, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops).  Same
+ * arguments, results and ordering as cpd_ws_features; its scratch (S and
+ * the raw features, 8 r_thc^2 + 64 r_thc bytes) lives in a static device
+ * array of the library, one per GPU, which the process holds from the first
+ * call on that GPU to its end (33.7 MB).  Limit: r_thc <= 2048 (larger:
+ * CPD_ERR_INVALID_ARG).  Calls on the same GPU share the array: calls whose
+ * work overlaps on the device (different streams, or threads) race; calls
+ * ordered on one stream do not.  The stream must belong to the current
+ * device.  No device memory is allocated or freed.  Errors:
+ * CPD_ERR_INVALID_ARG, CPD_ERR_HIP (the scratch address could not be
+ * looked up, or a launch failed). */
+cpd_status cpd_ws_features_noalloc(int32_t n0, int32_t r_thc, const double* X0, const double* Z, float* feat,
+                                   double* heur, void* stream);
+
 /* Initial factors from scores: grid points ranked by s (descending; ties:
  * smaller P first); for the top r_cp points P_k
  *   init[m][:, k] = exp(ell[P_k]) (X[m][:, P_k]

@@ -107,6 +107,7 @@ EXPORTS = {
     "cpd_test_mfma_probe": (i32, [i32, i32, vp, vp, vp, vp]),
     "cpd_ws_workspace_size": (ctypes.c_size_t, [i32, i32, i32]),
     "cpd_ws_features": (i32, [i32, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+    "cpd_ws_features_noalloc": (i32, [i32, i32, vp, vp, vp, vp, vp]),
     "cpd_ws_select_init": (i32, [ctypes.POINTER(i32), i32, i32, vp * 4, vp, vp, i32, ctypes.POINTER(vp * 4),
                                  ctypes.c_double, vp * 4, vp, ctypes.c_size_t, vp]),
     "cpd_ws_labels": (i32, [ctypes.POINTER(i32), i32, i32, vp * 4, vp * 4, vp, vp, vp, vp, vp,

@@ -30,6 +30,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/thccp.h"
 #include "common.h"
 #include "kernels.h"
@@ -714,6 +716,37 @@ void rowred(hipStream_t s, const float* L, int ldl, const int* lidx, int T, cons
   hipLaunchKernelGGL(rowred_final_kernel, dim3((nout + 255) / 256), dim3(256), 0, s, part, nchunk, T, C, gW, gb);
 }
 
+// Scratch of the allocation-free feature entry point: S = X0^T X0
+// (r_thc^2 doubles) and the raw features (r_thc x 8 doubles) for
+// r_thc <= WS_NOALLOC_MAX_RTHC.  One copy per GPU, alive until the process
+// ends; host code uses only the device address of this array looked up with
+// hipGetSymbolAddress, once per device (the name itself is a host-side
+// stand-in, not a device address).
+constexpr int WS_NOALLOC_MAX_RTHC = 2048;
+constexpr size_t al_c(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t WS_NOALLOC_BYTES =
+    al_c(sizeof(double) * (size_t)WS_NOALLOC_MAX_RTHC * WS_NOALLOC_MAX_RTHC) +
+    al_c(sizeof(double) * (size_t)WS_NOALLOC_MAX_RTHC * D_IN);
+static __device__ __align__(256) char feat_scratch[WS_NOALLOC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of feat_scratch on the current device (looked up on the
+// first call per device); nullptr if the lookup fails.
+void* scratch_of_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(feat_scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_dev[dev] = ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -731,6 +764,16 @@ cpd_status cpd_ws_features(int32_t n0, int32_t r_thc, const double* X0, const do
   if (n0 <= 0 || r_thc <= 0 || !X0 || !Z || !feat || !workspace) return CPD_ERR_INVALID_ARG;
   if (workspace_bytes < feat_bytes(r_thc)) return CPD_ERR_WORKSPACE;
   Carve c{(char*)workspace};
+  return enqueue_features((hipStream_t)stream, n0, r_thc, X0, Z, feat, heur, carve_feat(c, r_thc));
+}
+
+cpd_status cpd_ws_features_noalloc(int32_t n0, int32_t r_thc, const double* X0, const double* Z, float* feat,
+                                   double* heur, void* stream) {
+  if (n0 <= 0 || r_thc <= 0 || !X0 || !Z || !feat) return CPD_ERR_INVALID_ARG;
+  if (r_thc > WS_NOALLOC_MAX_RTHC) return CPD_ERR_INVALID_ARG;
+  void* ws = scratch_of_current_device();
+  if (!ws) return CPD_ERR_HIP;
+  Carve c{(char*)ws};
   return enqueue_features((hipStream_t)stream, n0, r_thc, X0, Z, feat, heur, carve_feat(c, r_thc));
 }
 

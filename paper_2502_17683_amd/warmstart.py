@@ -65,6 +65,21 @@ def ws_features(X0, Z, device="cuda"):
     return feat, heur
 
 
+def ws_features_noalloc(X0, Z, device="cuda"):
+    """ws_features through the allocation-free entry point (static device
+    scratch inside the library; r_thc <= 2048)."""
+    lib = _lib.load()
+    dev = torch.device(device)
+    X0 = _dev_f64(X0, dev)
+    Z = _dev_f64(Z, dev)
+    n0, r_thc = X0.shape
+    feat = torch.empty(r_thc, N_FEATURES, dtype=torch.float32, device=dev)
+    heur = torch.empty(r_thc, dtype=torch.float64, device=dev)
+    check(lib.cpd_ws_features_noalloc(n0, r_thc, _ptr(X0), _ptr(Z), _ptr(feat), _ptr(heur), _stream(dev)),
+          "cpd_ws_features_noalloc")
+    return feat, heur
+
+
 def ws_select_init(X, s, ell, r_cp, stride=1, noise=None, sigma=0.0, device="cuda"):
     """Initial factors from the top-r_cp grid points by score s (float32),
     optionally blended with the random guess `noise` (four n_m x r_cp)."""
