@@ -129,7 +129,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--init", choices=("normal", "uniform"), default="normal",
                     help="initial factors: N(0,1)/sqrt(n) (default) or the paper's U[-1,1]")
-    ap.add_argument("--workload", choices=("mixed", "lt", "warmstart", "exchange", "tied", "df", "combined"),
+    ap.add_argument("--workload", choices=("mixed", "lt", "warmstart", "exchange", "tied", "df", "combined",
+                                           "kernels"),
                     default="mixed",
                     help="mixed: the headline time-to-fit line (default); lt: the batched "
                          "Laplace-transform CPDs; warmstart: train and evaluate the learned warm start; "
@@ -137,13 +138,15 @@ def main():
                          "tied: the particle-tied CPD (symmetric ALS) against the four-factor one, FP64; "
                          "df: DF-based against THC-based CP-ALS, FP64, growing n; combined: the 48 "
                          "Laplace CPDs in split BF16 from the learned warm start, each to its FP64 "
-                         "reference fit, against FP64 from the random start")
+                         "reference fit, against FP64 from the random start; kernels: only the "
+                         "per-kernel timing hook of both precisions at the headline shape (a short run for "
+                         "hardware counters)")
     ap.add_argument("--lt-sweeps", type=int, default=40)
     ap.add_argument("--accuracy-sweeps", type=int, default=100,
                     help="exchange workload: CP-ALS sweep cap for the accuracy comparison (0: skip)")
-    ap.add_argument("--ws-train", type=int, default=512)
-    ap.add_argument("--ws-heldout", type=int, default=32)
-    ap.add_argument("--ws-heldout-large", type=int, default=4)
+    ap.add_argument("--ws-train", type=int, default=2000)
+    ap.add_argument("--ws-heldout", type=int, default=200)
+    ap.add_argument("--ws-heldout-large", type=int, default=200)
     ap.add_argument("--ws-budget", type=int, default=200)
     ap.add_argument("--comb-train-sets", type=int, default=4,
                     help="combined workload: training Laplace batches (3 systems x 16 points each)")
@@ -178,6 +181,8 @@ def main():
         return bench_df(args)
     if args.workload == "combined":
         return bench_combined(args)
+    if args.workload == "kernels":
+        return bench_kernels(args)
 
     import torch
     from paper_2502_17683_amd import CPD
@@ -749,7 +754,14 @@ def bench_warmstart(args):
     t_gen = time.perf_counter() - t0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    data = training_set(train, sweeps=300, tol=1e-4, chunk=64)
+    parts = []
+    for a in range(0, len(train), 256):
+        parts.append(training_set(train[a:a + 256], sweeps=300, tol=1e-4, chunk=64))
+        torch.cuda.synchronize()
+        log(f"[bench-ws] labelled {min(a + 256, len(train))}/{len(train)} training CPDs "
+            f"({time.perf_counter() - t0:.1f}s)")
+    data = tuple(torch.cat([q[i] for q in parts]) for i in range(4))
+    del parts
     torch.cuda.synchronize()
     t_label = time.perf_counter() - t0
     del train
@@ -764,55 +776,69 @@ def bench_warmstart(args):
     log(f"[bench-ws] generated {args.ws_train} inputs in {t_gen:.1f}s, labelled in {t_label:.1f}s, "
         f"trained {len(losses)} steps in {t_train:.2f}s, loss {losses[0]:.3f} -> {losses[-1]:.3f}")
 
-    def evaluate(n, r_thc, r_cp, seeds, budget):
-        rows = []
-        for seed in seeds:
-            X, Z = make_thc(n, r_thc, seed)
-            rnd = init_factors([n] * 4, r_cp, seed + 1000)
-            Xd, Zd = torch.as_tensor(X, device=dev), torch.as_tensor(Z, device=dev)
-            rd = [torch.as_tensor(f, device=dev) for f in rnd]
-            ref = CPD(Xd, Zd, r_cp, rd, precision="fp64", tol=0.0, fit_floor=0.0)
-            target = min(ref.sweep(budget)) * (1 + 1e-4)
+    def evaluate(n, r_thc, r_cp, seeds, budget, chunk):
+        """Held-out problems in batches of `chunk`: the FP64 random start's
+        best fit over `budget` sweeps x (1 + 1e-4) is each problem's target
+        (untimed reference); then the random, learned and heuristic starts
+        each run as one FP64 batch whose problems stop on the device at their
+        targets (timed, warm-start inference included).  Returns per kind
+        the sweeps each problem needed (None: missed within the budget) and
+        the summed wall time."""
+        seeds = list(seeds)
+        sweeps = {k: [] for k in ("random", "learned", "heuristic")}
+        secs = {k: 0.0 for k in sweeps}
+        for a in range(0, len(seeds), chunk):
+            part = seeds[a:a + chunk]
+            base = []
+            for seed in part:
+                X, Z = make_thc(n, r_thc, seed)
+                rnd = init_factors([n] * 4, r_cp, seed + 1000)
+                base.append({"X": torch.as_tensor(X, device=dev), "Z": torch.as_tensor(Z, device=dev),
+                             "r_cp": r_cp, "init": [torch.as_tensor(f, device=dev) for f in rnd]})
+            ref = CPDBatch(base, precision="fp64", tol=0.0, fit_floor=0.0)
+            rf = ref.sweep(budget)
             ref.close()
-            row = {"seed": seed}
-            for kind in ("random", "learned", "heuristic"):
+            targets = [min(f) * (1.0 + 1e-4) for f in rf]
+            for kind in sweeps:
                 torch.cuda.synchronize()
                 t = time.perf_counter()
-                if kind == "random":
-                    init, src = rd, "random"
-                else:
-                    init, src = ws_init(Xd, Zd, r_cp, packed=packed if kind == "learned" else None, noise=rd)
-                c = CPD(Xd, Zd, r_cp, init, precision="fp64", tol=0.0, fit_floor=0.0)
-                sweeps, hit = 0, False
-                while sweeps < budget and not hit:
-                    f = c.sweep(1)
-                    sweeps += 1
-                    hit = f[-1] <= target
+                probs = base
+                if kind != "random":
+                    probs = [dict(b, init=ws_init(b["X"], b["Z"], r_cp, packed=packed if kind == "learned" else None,
+                                                  noise=b["init"])[0]) for b in base]
+                bt = CPDBatch(probs, precision="fp64", tol=0.0, fit_floor=0.0, fit_targets=targets)
+                bt.sweep(budget)
+                last, _, sw = bt.states()
+                bt.close()
                 torch.cuda.synchronize()
-                row[kind] = {"sweeps": sweeps if hit else None, "seconds": time.perf_counter() - t,
-                             "source": src}
-                c.close()
-            rows.append(row)
-            log(f"[bench-ws] N={n} seed {seed}: " + ", ".join(
-                f"{k} {row[k]['sweeps']} sw {row[k]['seconds']:.3f}s" for k in ("random", "learned", "heuristic")))
-        return rows
+                secs[kind] += time.perf_counter() - t
+                sweeps[kind] += [int(sw[i]) if last[i] <= targets[i] else None for i in range(len(part))]
+            log(f"[bench-ws] N={n}: {a + len(part)}/{len(seeds)} held-out problems; median sweeps so far " +
+                ", ".join(f"{k} {np.median([x if x is not None else budget + 1 for x in v]):.1f}"
+                          for k, v in sweeps.items()))
+            del base
+        return sweeps, secs
 
-    def summary(rows, budget):
+    def summary(res, budget):
+        sweeps, secs = res
         out = {}
-        for kind in ("random", "learned", "heuristic"):
-            sw = [r[kind]["sweeps"] if r[kind]["sweeps"] is not None else budget + 1 for r in rows]
-            tt = [r[kind]["seconds"] for r in rows]
-            out[kind] = {"median_sweeps": float(np.median(sw)), "reached": int(sum(s <= budget for s in sw)),
-                         "median_seconds": float(np.median(tt))}
-        out["speedup_median_seconds_learned_vs_random"] = (out["random"]["median_seconds"]
-                                                          / out["learned"]["median_seconds"])
+        for kind, v in sweeps.items():
+            sw = [x if x is not None else budget + 1 for x in v]
+            out[kind] = {"median_sweeps": float(np.median(sw)), "mean_sweeps": float(np.mean(sw)),
+                         "reached": int(sum(x is not None for x in v)), "of": len(v),
+                         "wall_s_total": secs[kind], "wall_s_per_cpd": secs[kind] / max(len(v), 1)}
+        out["speedup_wall_learned_vs_random"] = secs["random"] / secs["learned"]
+        out["speedup_wall_learned_vs_heuristic"] = secs["heuristic"] / secs["learned"]
+        out["learned_fewer_or_equal_sweeps_than_heuristic"] = int(sum(
+            (l if l is not None else budget + 1) <= (h if h is not None else budget + 1)
+            for l, h in zip(sweeps["learned"], sweeps["heuristic"])))
         return out
 
-    small = evaluate(N, Rt, Rc, range(20000, 20000 + args.ws_heldout), args.ws_budget)
-    large = evaluate(400, 2000, 1600, range(20000, 20000 + args.ws_heldout_large), args.ws_budget)
+    small = evaluate(N, Rt, Rc, range(20000, 20000 + args.ws_heldout), args.ws_budget, 100)
+    large = evaluate(400, 2000, 1600, range(20000, 20000 + args.ws_heldout_large), args.ws_budget, 16)
     out = {
         "metric": "warm-start sweeps and wall time to the random start's best fit x (1+1e-4), 1 MI355X",
-        "value": summary(small, args.ws_budget)["learned"]["median_seconds"], "unit": "s", "n_gpus": 1,
+        "value": summary(small, args.ws_budget)["learned"]["wall_s_per_cpd"], "unit": "s", "n_gpus": 1,
         "higher_is_better": False, "data": "synthetic", "dtype": "f64 CP-ALS, f32 train / bf16 infer",
         "config": {"workload": f"train {args.ws_train} converged CPDs N=100 R_thc=500 R_cp=400 "
                                f"(seeds 10000+), held-out {args.ws_heldout} at N=100 and "
@@ -826,6 +852,33 @@ def bench_warmstart(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_kernels(args):
+    """Per-kernel times of the sweep's kernel families (cpd_kernel_times:
+    one warm-up and --steps repetitions each) for split BF16 and FP64 at the
+    headline shape; no time-to-fit runs.  Short enough to run under
+    hardware-counter collection."""
+    import torch
+    from paper_2502_17683_amd import CPD
+    from synth import make_thc, init_factors
+    N, Rt, Rc = args.n, args.r_thc, args.r_cp
+    dev = torch.device("cuda:0")
+    X, Z = make_thc(N, Rt, args.seed)
+    init = init_factors([N] * 4, Rc, args.seed + 1000)
+    Xd, Zd = torch.as_tensor(X, device=dev), torch.as_tensor(Z, device=dev)
+    Id = [torch.as_tensor(f, device=dev) for f in init]
+    kt = {}
+    for prec in ("mixed", "fp64"):
+        c = CPD(Xd, Zd, Rc, Id, precision=prec, tol=0.0, fit_floor=0.0)
+        kt[prec] = c.kernel_times(reps=max(args.steps, 1))
+        c.close()
+        log(f"[bench-kernels] {prec}: {kt[prec]}")
+    out = {"metric": "per-kernel time (ms) of the sweep's kernel families, 1 MI355X", "value": None, "unit": "ms",
+           "n_gpus": 1, "steps": args.steps, "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": f"THC CP-ALS kernel families, N={N}, R_thc={Rt}, R_cp={Rc}"},
+           "kernel_ms": kt}
+    print(json.dumps(out), flush=True)
+
+
 def bench_combined(args):
     """The three forms together on the batched Laplace workload (48 CPDs:
     (o,v) = (20,100), (40,200), (80,400) x 16 points): split BF16, started
@@ -836,7 +889,9 @@ def bench_combined(args):
     the device once it reaches its target (cpd_desc.fit_target).  The
     network is trained on converged CPDs of other Laplace systems of the
     same sizes (system seeds 100+), generated by the library itself; the
-    warm start's inference is inside the timed region.  Also reported: the
+    warm start's inference is inside the timed region.  A warm-started CPD
+    that has not reached its target after --comb-cap sweeps falls back to
+    the plain method (FP64 from the random start), also timed.  Also reported: the
     two forms alone (split BF16 from the random start, FP64 from the
     warm start)."""
     import torch
@@ -882,7 +937,7 @@ def bench_combined(args):
     log(f"[bench-comb] labelled {args.comb_train_sets * P} CPDs in {t_label:.1f}s, trained {len(losses)} steps "
         f"in {t_train:.2f}s, loss {losses[0]:.3f} -> {losses[-1]:.3f}")
 
-    def run(prec, warm, fit_every):
+    def run(prec, warm, fit_every, fallback=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         probs, sources = problems, None
@@ -893,15 +948,30 @@ def bench_combined(args):
                 probs.append(dict(pr, init=init))
                 sources.append(src)
         b = CPDBatch(probs, precision=prec, tol=0.0, fit_floor=0.0, fit_every=fit_every, fit_targets=targets)
-        fits = b.sweep(args.comb_cap)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        b.sweep(args.comb_cap)
         last, done, sw = b.states()
         promoted = sum(b.stats(i)["fp64_path"] for i in range(P)) if prec == "mixed" else 0
         b.close()
         reached = [bool(last[i] <= targets[i]) for i in range(P)]
+        t_first = time.perf_counter() - t0
+        redo = [i for i in range(P) if not reached[i]] if fallback else []
+        if redo:
+            # the fallback of the warm start: a CPD that missed its target
+            # within the cap is rerun by the plain method (FP64, random start)
+            fb = CPDBatch([problems[i] for i in redo], precision="fp64", tol=0.0, fit_floor=0.0,
+                          fit_targets=[targets[i] for i in redo])
+            fb.sweep(args.comb_cap)
+            flast, _, fsw = fb.states()
+            fb.close()
+            for j, i in enumerate(redo):
+                last[i] = flast[j]
+                sw[i] += fsw[j]
+                reached[i] = bool(flast[j] <= targets[i])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
         gap = [(last[i] - f_ref[i]) / max(f_ref[i], floor) for i in range(P)]
-        res = {"seconds": dt, "reached": int(sum(reached)), "of": P, "sweeps": [int(x) for x in sw],
+        res = {"seconds": dt, "seconds_before_fallback": t_first, "fallback_reruns": redo,
+               "reached": int(sum(reached)), "of": P, "sweeps": [int(x) for x in sw],
                "sweeps_max": int(max(sw)), "sweeps_total": int(sum(sw)), "fit_gap_vs_fp64_ref": gap,
                "fit_gap_max": float(max(gap)), "not_reached": [i for i in range(P) if not reached[i]]}
         if prec == "mixed":
@@ -914,9 +984,9 @@ def bench_combined(args):
 
     run("fp64", False, 1)  # warm-up of the plan set-up paths
     base = run("fp64", False, 1)
-    comb = run("mixed", True, args.fit_every)
+    comb = run("mixed", True, args.fit_every, fallback=True)
     mixed_rnd = run("mixed", False, args.fit_every)
-    fp64_warm = run("fp64", True, 1)
+    fp64_warm = run("fp64", True, 1, fallback=True)
     ok = comb["reached"] == P
     out = {
         "metric": "batched LT CP-ALS wall time to every CPD's FP64 reference fit x (1+1e-4) (s), "

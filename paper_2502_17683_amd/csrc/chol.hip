@@ -732,16 +732,18 @@ template <>
 struct Bits<float> {
   typedef unsigned int type;
 };
+// (through global-address-space pointers: a generic pointer would make these
+// FLAT accesses, which also count against the LDS wait counter)
 template <typename T>
 __device__ __forceinline__ T coherent_load(const T* p) {
   typedef typename Bits<T>::type U;
-  const U u = __hip_atomic_load((const U*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const U u = __hip_atomic_load((gptr<const U>)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return __builtin_bit_cast(T, u);
 }
 template <typename T>
 __device__ __forceinline__ void coherent_store(T* p, T v) {
   typedef typename Bits<T>::type U;
-  __hip_atomic_store((U*)p, __builtin_bit_cast(U, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((gptr<U>)p, __builtin_bit_cast(U, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // fetch_block / store_acc through device-coherent accesses
 template <typename T>
@@ -819,10 +821,10 @@ __global__ __launch_bounds__(256, 2) void bwd_flow_kernel(const StepProb<T>* pro
   auto wait_ready = [&](int i) -> bool {
     if (tid == 0) {
       int spins = 0, bad = 0;
-      while (__hip_atomic_load(flag + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        if ((__hip_atomic_load(&st->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SOLVE_STALL) ||
+      while (__hip_atomic_load(as_global(flag + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        if ((__hip_atomic_load(as_global(&st->flags), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SOLVE_STALL) ||
             ++spins > spin_limit) {
-          __hip_atomic_fetch_or(&st->flags, (int)FLAG_SOLVE_STALL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_or(as_global(&st->flags), (int)FLAG_SOLVE_STALL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           bad = 1;
           break;
         }
@@ -874,7 +876,7 @@ __global__ __launch_bounds__(256, 2) void bwd_flow_kernel(const StepProb<T>* pro
   store_acc_coherent<T>(f, tile, Tp, nrows, lane, w);
   __builtin_amdgcn_s_waitcnt(0);  // this wave's stores of F_k are acknowledged
   __syncthreads();
-  if (tid == 0) __hip_atomic_store(flag + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (tid == 0) __hip_atomic_store(as_global(flag + k), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ------------------------- dataflow factorisation with the forward solve
@@ -949,10 +951,10 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
   int32_t* const xfl = dfl + nblk;             // [k]: X_k stored
   auto spin = [&](const int32_t* f) -> bool {
     int spins = 0;
-    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-      if ((__hip_atomic_load(&st->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SOLVE_STALL) ||
+    while (__hip_atomic_load(as_global(f), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      if ((__hip_atomic_load(as_global(&st->flags), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SOLVE_STALL) ||
           ++spins > spin_limit) {
-        __hip_atomic_fetch_or(&st->flags, (int)FLAG_SOLVE_STALL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_or(as_global(&st->flags), (int)FLAG_SOLVE_STALL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return false;
       }
       __builtin_amdgcn_s_sleep(1);
@@ -969,7 +971,7 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
   auto publish = [&](int32_t* f) {
     __builtin_amdgcn_s_waitcnt(0);  // this wave's stores are acknowledged
     __syncthreads();
-    if (tid == 0) __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) __hip_atomic_store(as_global(f), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
   auto blk = [&](int i, int j) { return q.V + (size_t)i * TB * Tp + (size_t)j * TB; };
   acc_t acc[4], p[4];

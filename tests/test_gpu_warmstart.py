@@ -217,7 +217,8 @@ def test_warm_start_training_and_gain():
     """Train on converged CPDs of small problems (the 5:4 THC-to-CP rank
     ratio of the warm-start workload), then on held-out problems count the
     sweeps the learned, heuristic and random starts need to reach the
-    random start's best fit (1 + 1e-4)."""
+    random start's best fit (1 + 1e-4): the learned start needs at most
+    half the random start's median, and at most 1.5x the heuristic's."""
     from paper_2502_17683_amd import WarmStartMLP, CPDBatch, training_set, ws_init
     n, r_thc, r_cp = 24, 120, 96
     train = []
@@ -262,3 +263,7 @@ def test_warm_start_training_and_gain():
     say(f"median sweeps to the random start's best fit: {med}")
     reached = sum(v <= budget for v in sweeps["learned"])
     assert reached >= 5 and med["learned"] <= 0.5 * med["random"], (sweeps, med)
+    # against the heuristic score (one of the network's input features):
+    # the network is not expected to beat it -- at the configured size the
+    # two are equal within a few sweeps -- only to keep its gain
+    assert med["learned"] <= 1.5 * med["heuristic"] + 2, (sweeps, med)
