@@ -142,6 +142,11 @@ def main():
                          "per-kernel timing hook of both precisions at the headline shape (a short run for "
                          "hardware counters)")
     ap.add_argument("--lt-sweeps", type=int, default=40)
+    ap.add_argument("--lt-precisions", default="mixed,fp32,fp64",
+                    help="lt workload: the precisions of the batched sweeps (comma-separated)")
+    ap.add_argument("--lt-batched-only", action="store_true",
+                    help="lt workload: only the batched sweeps (no one-by-one runs, no runs to convergence); "
+                         "short enough for hardware counters")
     ap.add_argument("--accuracy-sweeps", type=int, default=100,
                     help="exchange workload: CP-ALS sweep cap for the accuracy comparison (0: skip)")
     ap.add_argument("--ws-train", type=int, default=2000)
@@ -369,7 +374,10 @@ def bench_lt(args):
     K = args.lt_sweeps
     res = {}
     from paper_2502_17683_amd import CpdError
-    for prec in ("mixed", "fp32", "fp64"):
+    precisions = [x for x in args.lt_precisions.split(",") if x]
+    if not args.lt_batched_only and not {"mixed", "fp64"} <= set(precisions):
+        raise SystemExit("--lt-precisions must include mixed and fp64 unless --lt-batched-only is given")
+    for prec in precisions:
         b = CPDBatch(problems, precision=prec, tol=0.0, fit_floor=0.0, autotune=True,
                      fit_every=args.fit_every)
         try:
@@ -400,6 +408,13 @@ def bench_lt(args):
             res[prec]["promoted_to_fp64"] = sum(b.stats(i)["fp64_path"] for i in range(len(problems)))
         b.close()
         log(f"[bench-lt] batched {prec}: {ms:.3f} ms/sweep (asynchronous sweeps {ms_async:.3f})")
+    if args.lt_batched_only:
+        print(json.dumps({"metric": "batched LT CP-ALS sweep time (ms), 1 MI355X",
+                          "value": res.get("mixed", {}).get("ms_per_batched_sweep"), "unit": "ms", "n_gpus": 1,
+                          "steps": K, "higher_is_better": False, "data": "synthetic",
+                          "config": {"workload": "48 LT CPDs, batched sweeps only", "fit_every": args.fit_every},
+                          "per_precision": res}), flush=True)
+        return
     # the same 48 CPDs one after another (one plan each, graph-replayed sweeps)
     for prec in ("mixed", "fp64"):
         plans = [CPD(p["X"], p["Z"], p["r_cp"], p["init"], precision=prec, tol=0.0, fit_floor=0.0,
