@@ -64,6 +64,8 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return __builtin_fma(y, r, y);
 }
 __device__ __forceinline__ float rsqrt_nr(float x) { return 1.0f / sqrtf(x); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 // ------------------------------------------------------ block-4 solves
 // Block-4 layout: thread t owns rows 4g .. 4g+3 (g = t >> 4) and columns
@@ -173,22 +175,96 @@ __device__ __forceinline__ void b4_bwd(T s[16], const T* L, const T* invd, int j
 // block: every thread publishes d[b] = A[r][4b+q0] (updated by all earlier
 // blocks) to cb[b & 1][r][q0] (row-major, so a row's four values are one
 // 32-byte read); one barrier (the two buffers alternate); every thread then
-// factors the 4 x 4 diagonal block D = Ld Ld^T from cb (redundantly), forms
-// y = a_r Ld^{-T} (row r of the block column of L, a_r = A[r][4b..4b+3]
-// gathered inside the quad) and w = y Ld^{-1} = a_r D^{-1}, and updates its
-// trailing columns k = q0 + 4u, u > b, by d[u] -= w . A[k][4b..4b+3], the
-// reads of A[k][.] running two columns ahead of the updates.  On return L
-// is in LDS (row-major, stride LDT, zero above the diagonal) and invd[c] =
+// factors the 4 x 4 diagonal block D = Ld Ld^T from cb (redundantly), reads
+// its row a_r = A[r][4b..4b+3] back from cb, forms y = a_r Ld^{-T} (row r of
+// the block column of L) and w = y Ld^{-1} = a_r D^{-1}, and updates its
+// trailing columns k = q0 + 4u, u > b, by d[u] -= w . A[k][4b..4b+3] (four
+// fused multiply-adds, in the order of the four columns), the reads of
+// A[k][.] running two columns ahead of the updates.  On return L is in LDS
+// (row-major, stride LDT, zero above the diagonal) and invd[c] =
 // 1 / L[c][c].  Returns false if a pivot was not positive (the factor is
 // then finite garbage).
 // PANEL: the thread also carries row r of a tile below the block in e[16]
-// (same layout) through every column step, which solves it against L^T.
+// (same layout, published to cb[2 + (b & 1)]) through every column step,
+// which solves it against L^T; the block's own L is then not kept (the
+// values that the trailing updates use are the published A[k][.], so the
+// tile comes out bitwise as it would beside the full factorisation).
+// Updates of the trailing columns u = U0 .. 15 of this thread's row(s) with
+// the block column whose published values are in c (A[k][c0..c0+3] =
+// c[k][0..3]) and whose w is wv (and wt for the tile row): four fused
+// multiply-adds per entry, in the order of the four columns, the reads of
+// c running two columns ahead of the updates.
+template <typename T, int U0, bool PANEL>
+__device__ __forceinline__ void strip_trail(T d[16], T e[16], const T* c, const T wv[4], const T wt[4], int q0) {
+  if constexpr (U0 < 16) {
+    T ca[4], cn[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ca[q] = c[(q0 + 4 * U0) * 4 + q];
+    if constexpr (U0 + 1 < 16) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cn[q] = c[(q0 + 4 * (U0 + 1)) * 4 + q];
+    }
+#pragma unroll
+    for (int u = U0; u < 16; ++u) {
+      T cf[4];
+      if (u + 2 < 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cf[q] = c[(q0 + 4 * (u + 2)) * 4 + q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d[u] = fma_t(-wv[q], ca[q], d[u]);
+      // keep the updates in order: otherwise every column's reads are
+      // hoisted at once and the tile spills
+      if constexpr (sizeof(T) == 8) __asm__ volatile("" : "+v"(d[u]));
+      if constexpr (PANEL) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e[u] = fma_t(-wt[q], ca[q], e[u]);
+        if constexpr (sizeof(T) == 8) __asm__ volatile("" : "+v"(e[u]));
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ca[q] = cn[q];
+        cn[q] = cf[q];
+      }
+    }
+  }
+}
+
+// Cholesky of the 64 x 64 block held in strip layout d (lower part used),
+// four columns per barrier.  Column block b (columns 4b .. 4b+3) is exactly
+// register d[b] of the four threads of a row (column offset q0).  Per
+// block: every thread publishes d[b] = A[r][4b+q0] (updated by all earlier
+// blocks) to c_b = cb[b % 3][r][q0] (row-major, so a row's four values are
+// one 32-byte read); one barrier; every thread then factors the 4 x 4
+// diagonal block D = Ld Ld^T from c_b (redundantly), reads its row
+// a_r = A[r][4b..4b+3] back from c_b, forms y = a_r Ld^{-T} (row r of the
+// block column of L) and w = y Ld^{-1} = a_r D^{-1}, and updates its
+// trailing columns k = q0 + 4u, u > b, by d[u] -= w . A[k][4b..4b+3] (four
+// fused multiply-adds, in the order of the four columns).  Only column
+// b + 1, which the next block publishes, is updated at once; the updates of
+// u >= b + 2 wait for the next block's barrier and run while its 4 x 4
+// factorisation is on the dependent chain, so they fill its latency.  Each
+// entry still takes its updates in block order, so the values are those of
+// the plain order bit for bit.  Three published buffers rotate: c_b is
+// read until the end of block b + 1, and the first write to it again
+// (block b + 3) follows the barrier of block b + 2.  On return L is in LDS
+// (row-major, stride LDT, zero above the diagonal) and invd[c] =
+// 1 / L[c][c].  Returns false if a pivot was not positive (the factor is
+// then finite garbage).
+// PANEL: the thread also carries row r of a tile below the block in e[16]
+// (same layout, published to cb[3 + (b & 1)]) through every column step,
+// which solves it against L^T; the block's own L is then not kept (the
+// values that the trailing updates use are the published A[k][.], so the
+// tile comes out bitwise as it would beside the full factorisation).
 template <typename T, int B, bool PANEL = false>
 struct Potrf4 {
-  __device__ __forceinline__ static void run(T d[16], T e[16], T* cb, T* invd, int r, int q0, bool& ok) {
+  __device__ __forceinline__ static void run(T d[16], T e[16], T* cb, T* invd, int r, int q0, bool& ok,
+                                             const T wp[4], const T wtp[4]) {
     if constexpr (B < 16) {
-      T* c = cb + (B & 1) * 4 * TB;
+      T* c = cb + (B % 3) * 4 * TB;
+      T* ce = cb + (3 + (B & 1)) * 4 * TB;
       c[r * 4 + q0] = d[B];
+      if constexpr (PANEL) ce[r * 4 + q0] = e[B];
       __syncthreads();
       constexpr int c0 = 4 * B;
       // 4 x 4 diagonal block, lower part: D[p][q] = A[c0+p][c0+q] = c[c0+p][q]
@@ -197,6 +273,15 @@ struct Potrf4 {
       for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int q = 0; q <= p; ++q) D[p][q] = c[(c0 + p) * 4 + q];
+      T a[4], at[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = c[r * 4 + q];
+      if constexpr (PANEL) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) at[q] = ce[r * 4 + q];
+      }
+      // the previous block's deferred updates (columns u >= B + 1)
+      if constexpr (B >= 1) strip_trail<T, B + 1, PANEL>(d, e, cb + ((B + 2) % 3) * 4 * TB, wp, wtp, q0);
       T Ld[4][4], il[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -217,16 +302,12 @@ struct Potrf4 {
           Ld[p][q] = v * il[q];
         }
       }
-      if (r == 0 && q0 == 0) {
+      if (!PANEL && r == 0 && q0 == 0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) invd[c0 + q] = il[q];
       }
-      // row r of the block column: a_r inside the quad, y = a_r Ld^{-T}
-      T a[4], y[4], wv[4];
-      a[0] = qb<0>(d[B]);
-      a[1] = qb<1>(d[B]);
-      a[2] = qb<2>(d[B]);
-      a[3] = qb<3>(d[B]);
+      // row r of the block column: y = a_r Ld^{-T}, w = y Ld^{-1}
+      T y[4], wv[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         T v = a[q];
@@ -244,11 +325,6 @@ struct Potrf4 {
       // the tile row: yt = its 4 entries solved against Ld^T, wt = yt Ld^{-1}
       T yt[4], wt[4];
       if constexpr (PANEL) {
-        T at[4];
-        at[0] = qb<0>(e[B]);
-        at[1] = qb<1>(e[B]);
-        at[2] = qb<2>(e[B]);
-        at[3] = qb<3>(e[B]);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           T v = at[q];
@@ -264,49 +340,30 @@ struct Potrf4 {
           wt[q] = v * il[q];
         }
       }
-      // trailing columns of this thread, A[k][c0..c0+3] = c[k][0..3] read
-      // two columns ahead
-      T ca[4], cn[4];
+      // column B + 1 now (the next block publishes it), the rest deferred
       if constexpr (B + 1 < 16) {
+        T ca[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) ca[q] = c[(q0 + 4 * (B + 1)) * 4 + q];
-      }
-      if constexpr (B + 2 < 16) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cn[q] = c[(q0 + 4 * (B + 2)) * 4 + q];
-      }
-#pragma unroll
-      for (int u = B + 1; u < 16; ++u) {
-        T cf[4];
-        if (u + 2 < 16) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) cf[q] = c[(q0 + 4 * (u + 2)) * 4 + q];
-        }
-        d[u] -= wv[0] * ca[0] + wv[1] * ca[1] + wv[2] * ca[2] + wv[3] * ca[3];
-        // keep the updates in order: otherwise every column's reads are
-        // hoisted at once and the tile spills
-        if constexpr (sizeof(T) == 8) __asm__ volatile("" : "+v"(d[u]));
+        for (int q = 0; q < 4; ++q) d[B + 1] = fma_t(-wv[q], ca[q], d[B + 1]);
         if constexpr (PANEL) {
-          e[u] -= wt[0] * ca[0] + wt[1] * ca[1] + wt[2] * ca[2] + wt[3] * ca[3];
-          if constexpr (sizeof(T) == 8) __asm__ volatile("" : "+v"(e[u]));
-        }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          ca[q] = cn[q];
-          cn[q] = cf[q];
+          for (int q = 0; q < 4; ++q) e[B + 1] = fma_t(-wt[q], ca[q], e[B + 1]);
         }
       }
       // own entry of the block column: L[r][c0 + q0] = y[q0]
-      d[B] = q0 == 0 ? y[0] : q0 == 1 ? y[1] : q0 == 2 ? y[2] : y[3];
+      if constexpr (!PANEL) d[B] = q0 == 0 ? y[0] : q0 == 1 ? y[1] : q0 == 2 ? y[2] : y[3];
       if constexpr (PANEL) e[B] = q0 == 0 ? yt[0] : q0 == 1 ? yt[1] : q0 == 2 ? yt[2] : yt[3];
-      Potrf4<T, B + 1, PANEL>::run(d, e, cb, invd, r, q0, ok);
+      Potrf4<T, B + 1, PANEL>::run(d, e, cb, invd, r, q0, ok, wv, wt);
     }
   }
 };
 template <typename T>
-__device__ __forceinline__ bool strip_potrf4(T d[16], T* L, T* invd, T* cb /* 2 x 64 x 4 */, int r, int q0) {
+__device__ __forceinline__ bool strip_potrf4(T d[16], T* L, T* invd, T* cb /* 3 x 64 x 4 */, int r, int q0) {
   bool ok = true;
-  Potrf4<T, 0>::run(d, d, cb, invd, r, q0, ok);
+  const T z[4] = {T(0), T(0), T(0), T(0)};
+  Potrf4<T, 0>::run(d, d, cb, invd, r, q0, ok, z, z);
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int q = q0 + 4 * u;
@@ -324,7 +381,8 @@ __device__ __forceinline__ bool strip_potrf4(T d[16], T* L, T* invd, T* cb /* 2 
 template <typename T>
 __device__ __forceinline__ bool strip_potrf4_panel(T d[16], T e[16], T* invd, T* cb, int r, int q0) {
   bool ok = true;
-  Potrf4<T, 0, true>::run(d, e, cb, invd, r, q0, ok);
+  const T z[4] = {T(0), T(0), T(0), T(0)};
+  Potrf4<T, 0, true>::run(d, e, cb, invd, r, q0, ok, z, z);
   return ok;
 }
 
@@ -491,7 +549,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
   typedef typename Acc4<T>::type acc_t;
   __shared__ T S0[TB * LDT];
   __shared__ T S1[TB * LDT];
-  __shared__ __attribute__((aligned(16))) T colbuf[8 * TB];
+  __shared__ __attribute__((aligned(16))) T colbuf[12 * TB];  // 3 published column blocks
   __shared__ T invd[TB];
   int pid = 0;
   while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
@@ -930,7 +988,7 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
   typedef typename Acc4<T>::type acc_t;
   __shared__ T S0[TB * LDT];
   __shared__ T S1[TB * LDT];
-  __shared__ __attribute__((aligned(16))) T colbuf[8 * TB];
+  __shared__ __attribute__((aligned(16))) T colbuf[20 * TB];  // 3 published column blocks, 2 tile blocks
   __shared__ T invd[TB];
   __shared__ int stalled;
   int pid, k, bid;
