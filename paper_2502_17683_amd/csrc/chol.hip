@@ -52,18 +52,6 @@ __device__ __forceinline__ float qb(float v) {
   return __int_as_float(qb_int<K>(__float_as_int(v)));
 }
 
-// 1/sqrt(x) to working precision: hardware estimate and two Newton steps
-// (y <- y (3/2 - x y^2 / 2)); sqrt(x) = x (1/sqrt(x)).  Far shorter than the
-// correctly rounded square root on the factorisation's critical path.
-__device__ __forceinline__ double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-  double r = __builtin_fma(-h * y, y, 0.5);
-  y = __builtin_fma(y, r, y);
-  r = __builtin_fma(-h * y, y, 0.5);
-  return __builtin_fma(y, r, y);
-}
-__device__ __forceinline__ float rsqrt_nr(float x) { return 1.0f / sqrtf(x); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -189,68 +177,105 @@ __device__ __forceinline__ void b4_bwd(T s[16], const T* L, const T* invd, int j
 // which solves it against L^T; the block's own L is then not kept (the
 // values that the trailing updates use are the published A[k][.], so the
 // tile comes out bitwise as it would beside the full factorisation).
-// Updates of the trailing columns u = U0 .. 15 of this thread's row(s) with
-// the block column whose published values are in c (A[k][c0..c0+3] =
-// c[k][0..3]) and whose w is wv (and wt for the tile row): four fused
-// multiply-adds per entry, in the order of the four columns, the reads of
-// c running two columns ahead of the updates.
-template <typename T, int U0, bool PANEL>
-__device__ __forceinline__ void strip_trail(T d[16], T e[16], const T* c, const T wv[4], const T wt[4], int q0) {
-  if constexpr (U0 < 16) {
-    T ca[4], cn[4];
+// Keeps a value's computation at this point of the instruction stream (an
+// empty asm statement that reads and writes it; such statements keep their
+// source order).
+template <typename T>
+__device__ __forceinline__ void pin(T& x) {
+  __asm__ volatile("" : "+v"(x));
+}
+
+// The deferred trailing updates of one column block, as a flat list of
+// (column u, column q of the block) pairs, u = U0 .. 15 and q = 3 .. 0:
+// pair i updates d[u] -= wp[q] A[k][c0 + q] (and e[u] with wtp), with
+// k = q0 + 4u and A[k][.] the row k of the published buffer c, which is
+// loaded into cr two columns ahead of its first pair.  The row offsets and
+// the updated entries are pinned, so the loads and the updates stay in the
+// gap of the chain they were placed in.
+template <typename T, int U0, bool PANEL, int I0, int I1>
+__device__ __forceinline__ void defer_pairs(T d[16], T e[16], T cr[16][4], const T* c, const T wp[4],
+                                            const T wtp[4], int q0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) ca[q] = c[(q0 + 4 * U0) * 4 + q];
-    if constexpr (U0 + 1 < 16) {
+  for (int i = I0; i < I1; ++i) {
+    const int u = U0 + i / 4, q = 3 - i % 4;
+    if (i % 4 == 0 && u + 2 < 16) {
+      int off = (q0 + 4 * (u + 2)) * 4;
+      pin(off);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) cn[q] = c[(q0 + 4 * (U0 + 1)) * 4 + q];
+      for (int m = 0; m < 4; ++m) cr[u + 2][m] = c[off + m];
     }
-#pragma unroll
-    for (int u = U0; u < 16; ++u) {
-      T cf[4];
-      if (u + 2 < 16) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) cf[q] = c[(q0 + 4 * (u + 2)) * 4 + q];
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) d[u] = fma_t(-wv[q], ca[q], d[u]);
-      // keep the updates in order: otherwise every column's reads are
-      // hoisted at once and the tile spills
-      if constexpr (sizeof(T) == 8) __asm__ volatile("" : "+v"(d[u]));
-      if constexpr (PANEL) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) e[u] = fma_t(-wt[q], ca[q], e[u]);
-        if constexpr (sizeof(T) == 8) __asm__ volatile("" : "+v"(e[u]));
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        ca[q] = cn[q];
-        cn[q] = cf[q];
-      }
+    d[u] = fma_t(-wp[q], cr[u][q], d[u]);
+    pin(d[u]);
+    if constexpr (PANEL) {
+      e[u] = fma_t(-wtp[q], cr[u][q], e[u]);
+      pin(e[u]);
     }
   }
 }
 
+// 1/sqrt of a pivot, one dependent step per call (so that the deferred
+// updates can be placed between the steps): the hardware estimate
+// (relative error below 2^-24 on gfx950) and one third-order correction,
+// y (1 + e/2 + 3e^2/8) with e = 1 - x y^2, which leaves about one unit in
+// the last place.  A pivot that is not positive and finite gives 1 and
+// clears ok; that test runs beside the estimate, off the chain.
+template <typename T>
+struct PivotRsqrt {
+  T x, y, t, e, p, qv;
+  bool bad;
+  __device__ __forceinline__ void s0(T xin, bool& ok) {
+    x = xin;
+    bad = !(x > T(0)) || !__builtin_isfinite(x);
+    if (bad) ok = false;
+    if constexpr (sizeof(T) == 8) y = __builtin_amdgcn_rsq(x);
+    else y = T(1) / sqrtf(x);
+    pin(y);
+  }
+  __device__ __forceinline__ void s1() {
+    t = y * y;
+    pin(t);
+  }
+  __device__ __forceinline__ void s2() {
+    e = fma_t(-x, t, T(1));
+    pin(e);
+  }
+  __device__ __forceinline__ void s3() {
+    p = fma_t(e, T(0.375), T(0.5));
+    qv = y * e;
+    pin(p);
+    pin(qv);
+  }
+  __device__ __forceinline__ T s4() {
+    T r = fma_t(qv, p, y);
+    r = bad ? T(1) : r;
+    pin(r);
+    return r;
+  }
+};
+
 // Cholesky of the 64 x 64 block held in strip layout d (lower part used),
-// four columns per barrier.  Column block b (columns 4b .. 4b+3) is exactly
-// register d[b] of the four threads of a row (column offset q0).  Per
-// block: every thread publishes d[b] = A[r][4b+q0] (updated by all earlier
-// blocks) to c_b = cb[b % 3][r][q0] (row-major, so a row's four values are
-// one 32-byte read); one barrier; every thread then factors the 4 x 4
-// diagonal block D = Ld Ld^T from c_b (redundantly), reads its row
-// a_r = A[r][4b..4b+3] back from c_b, forms y = a_r Ld^{-T} (row r of the
+// four columns per barrier.  Column block b (columns c0 = 4b .. 4b+3) is
+// exactly register d[b] of the four threads of a row (column offset q0).
+// Per block: every thread publishes d[b] = A[r][c0+q0] (updated by all
+// earlier blocks) to c_b = cb[b % 3][r][q0] (row-major, so a row's four
+// values are one 32-byte read); one barrier; every thread then factors the
+// 4 x 4 diagonal block D = Ld Ld^T from c_b (redundantly), reads its row
+// a_r = A[r][c0..c0+3] back from c_b, forms y = a_r Ld^{-T} (row r of the
 // block column of L) and w = y Ld^{-1} = a_r D^{-1}, and updates its
-// trailing columns k = q0 + 4u, u > b, by d[u] -= w . A[k][4b..4b+3] (four
-// fused multiply-adds, in the order of the four columns).  Only column
-// b + 1, which the next block publishes, is updated at once; the updates of
-// u >= b + 2 wait for the next block's barrier and run while its 4 x 4
-// factorisation is on the dependent chain, so they fill its latency.  Each
-// entry still takes its updates in block order, so the values are those of
-// the plain order bit for bit.  Three published buffers rotate: c_b is
-// read until the end of block b + 1, and the first write to it again
-// (block b + 3) follows the barrier of block b + 2.  On return L is in LDS
-// (row-major, stride LDT, zero above the diagonal) and invd[c] =
-// 1 / L[c][c].  Returns false if a pivot was not positive (the factor is
-// then finite garbage).
+// trailing columns k = q0 + 4u, u > b, by d[u] -= w . A[k][c0..c0+3]
+// (four fused multiply-adds, columns c0+3 down to c0).
+// The chain from one barrier to the next is: the reads of D, the four
+// pivots, the last substitution steps and the update of column b + 1,
+// which the next block publishes.  It is written out one dependent step at
+// a time (34 steps), and the updates of columns u >= b + 2 by the previous
+// block, deferred to this block's window, are spread over the steps, a
+// fixed share in each gap, so that they issue while a step waits for its
+// operands.  Each entry takes its updates in block order.  Three published
+// buffers rotate: c_b is read until the end of block b + 1, and the first
+// write to it again (block b + 3) follows the barrier of block b + 2.  On
+// return L is in LDS (row-major, stride LDT, zero above the diagonal) and
+// invd[c] = 1 / L[c][c].  Returns false if a pivot was not positive (the
+// factor is then finite garbage).
 // PANEL: the thread also carries row r of a tile below the block in e[16]
 // (same layout, published to cb[3 + (b & 1)]) through every column step,
 // which solves it against L^T; the block's own L is then not kept (the
@@ -263,98 +288,230 @@ struct Potrf4 {
     if constexpr (B < 16) {
       T* c = cb + (B % 3) * 4 * TB;
       T* ce = cb + (3 + (B & 1)) * 4 * TB;
+      const T* cp = cb + ((B + 2) % 3) * 4 * TB;  // the previous block's values
       c[r * 4 + q0] = d[B];
       if constexpr (PANEL) ce[r * 4 + q0] = e[B];
       __syncthreads();
       constexpr int c0 = 4 * B;
-      // 4 x 4 diagonal block, lower part: D[p][q] = A[c0+p][c0+q] = c[c0+p][q]
-      T D[4][4];
+      // deferred pairs of the previous block, spread over NG gaps
+      constexpr int NP = B >= 1 ? (15 - B) * 4 : 0, NG = 34;
+      T cr[16][4];
+      T D[4][4], a[4], at[4], c1[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int q = 0; q <= p; ++q) D[p][q] = c[(c0 + p) * 4 + q];
-      T a[4], at[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) a[q] = c[r * 4 + q];
       if constexpr (PANEL) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) at[q] = ce[r * 4 + q];
       }
-      // the previous block's deferred updates (columns u >= B + 1)
-      if constexpr (B >= 1) strip_trail<T, B + 1, PANEL>(d, e, cb + ((B + 2) % 3) * 4 * TB, wp, wtp, q0);
-      T Ld[4][4], il[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        T piv = D[q][q];
-#pragma unroll
-        for (int m = 0; m < q; ++m) piv -= Ld[q][m] * Ld[q][m];
-        if (!(piv > T(0)) || !isfinite((double)piv)) {
-          ok = false;
-          piv = T(1);
-        }
-        il[q] = rsqrt_nr(piv);
-        Ld[q][q] = piv * il[q];
-#pragma unroll
-        for (int p = q + 1; p < 4; ++p) {
-          T v = D[p][q];
-#pragma unroll
-          for (int m = 0; m < q; ++m) v -= Ld[p][m] * Ld[q][m];
-          Ld[p][q] = v * il[q];
-        }
-      }
-      if (!PANEL && r == 0 && q0 == 0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) invd[c0 + q] = il[q];
-      }
-      // row r of the block column: y = a_r Ld^{-T}, w = y Ld^{-1}
-      T y[4], wv[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        T v = a[q];
-#pragma unroll
-        for (int m = 0; m < q; ++m) v -= y[m] * Ld[q][m];
-        y[q] = v * il[q];
-      }
-#pragma unroll
-      for (int q = 3; q >= 0; --q) {
-        T v = y[q];
-#pragma unroll
-        for (int m = q + 1; m < 4; ++m) v -= wv[m] * Ld[m][q];
-        wv[q] = v * il[q];
-      }
-      // the tile row: yt = its 4 entries solved against Ld^T, wt = yt Ld^{-1}
-      T yt[4], wt[4];
-      if constexpr (PANEL) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          T v = at[q];
-#pragma unroll
-          for (int m = 0; m < q; ++m) v -= yt[m] * Ld[q][m];
-          yt[q] = v * il[q];
-        }
-#pragma unroll
-        for (int q = 3; q >= 0; --q) {
-          T v = yt[q];
-#pragma unroll
-          for (int m = q + 1; m < 4; ++m) v -= wt[m] * Ld[m][q];
-          wt[q] = v * il[q];
-        }
-      }
-      // column B + 1 now (the next block publishes it), the rest deferred
       if constexpr (B + 1 < 16) {
-        T ca[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ca[q] = c[(q0 + 4 * (B + 1)) * 4 + q];
+        for (int q = 0; q < 4; ++q) c1[q] = c[(q0 + 4 * (B + 1)) * 4 + q];
+      }
+      if constexpr (NP > 0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) d[B + 1] = fma_t(-wv[q], ca[q], d[B + 1]);
-        if constexpr (PANEL) {
+        for (int q = 0; q < 4; ++q) cr[B + 1][q] = cp[(q0 + 4 * (B + 1)) * 4 + q];
+        if constexpr (B + 2 < 16) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) e[B + 1] = fma_t(-wt[q], ca[q], e[B + 1]);
+          for (int q = 0; q < 4; ++q) cr[B + 2][q] = cp[(q0 + 4 * (B + 2)) * 4 + q];
         }
+      }
+#define THCCP_GAP(g)                                                                               \
+  do {                                                                                             \
+    if constexpr (NP > 0)                                                                          \
+      defer_pairs<T, B + 1, PANEL, (g) * NP / NG, ((g) + 1) * NP / NG>(d, e, cr, cp, wp, wtp, q0); \
+  } while (0)
+      PivotRsqrt<T> pv;
+      // pivot 0
+      pv.s0(D[0][0], ok);
+      THCCP_GAP(0);
+      pv.s1();
+      THCCP_GAP(1);
+      pv.s2();
+      THCCP_GAP(2);
+      pv.s3();
+      THCCP_GAP(3);
+      const T il0 = pv.s4();
+      THCCP_GAP(4);
+      T L10 = D[1][0] * il0, L20 = D[2][0] * il0, L30 = D[3][0] * il0;
+      T y0 = a[0] * il0, yt0 = T(0);
+      pin(L10);
+      pin(L20);
+      pin(L30);
+      if constexpr (PANEL) yt0 = at[0] * il0;
+      THCCP_GAP(5);
+      T x1 = fma_t(-L10, L10, D[1][1]);
+      T m21 = fma_t(-L20, L10, D[2][1]), m31 = fma_t(-L30, L10, D[3][1]);
+      T m22 = fma_t(-L20, L20, D[2][2]), m32 = fma_t(-L30, L20, D[3][2]);
+      T m33 = fma_t(-L30, L30, D[3][3]);
+      T v1 = fma_t(-y0, L10, a[1]), v2 = fma_t(-y0, L20, a[2]), v3 = fma_t(-y0, L30, a[3]);
+      T vt1 = T(0), vt2 = T(0), vt3 = T(0);
+      if constexpr (PANEL) {
+        vt1 = fma_t(-yt0, L10, at[1]);
+        vt2 = fma_t(-yt0, L20, at[2]);
+        vt3 = fma_t(-yt0, L30, at[3]);
+      }
+      pin(x1);
+      // pivot 1
+      pv.s0(x1, ok);
+      THCCP_GAP(6);
+      pv.s1();
+      THCCP_GAP(7);
+      pv.s2();
+      THCCP_GAP(8);
+      pv.s3();
+      THCCP_GAP(9);
+      const T il1 = pv.s4();
+      THCCP_GAP(10);
+      T L21 = m21 * il1, L31 = m31 * il1, y1 = v1 * il1, yt1 = T(0);
+      pin(L21);
+      pin(L31);
+      if constexpr (PANEL) yt1 = vt1 * il1;
+      THCCP_GAP(11);
+      T x2 = fma_t(-L21, L21, m22);
+      T m32b = fma_t(-L31, L21, m32), m33b = fma_t(-L31, L31, m33);
+      T v2b = fma_t(-y1, L21, v2), v3b = fma_t(-y1, L31, v3);
+      T vt2b = T(0), vt3b = T(0);
+      if constexpr (PANEL) {
+        vt2b = fma_t(-yt1, L21, vt2);
+        vt3b = fma_t(-yt1, L31, vt3);
+      }
+      pin(x2);
+      // pivot 2
+      pv.s0(x2, ok);
+      THCCP_GAP(12);
+      pv.s1();
+      THCCP_GAP(13);
+      pv.s2();
+      THCCP_GAP(14);
+      pv.s3();
+      THCCP_GAP(15);
+      const T il2 = pv.s4();
+      THCCP_GAP(16);
+      T L32 = m32b * il2, y2 = v2b * il2, yt2 = T(0);
+      pin(L32);
+      if constexpr (PANEL) yt2 = vt2b * il2;
+      THCCP_GAP(17);
+      T x3 = fma_t(-L32, L32, m33b);
+      T v3c = fma_t(-y2, L32, v3b), vt3c = T(0);
+      if constexpr (PANEL) vt3c = fma_t(-yt2, L32, vt3b);
+      pin(x3);
+      // pivot 3
+      pv.s0(x3, ok);
+      THCCP_GAP(18);
+      pv.s1();
+      THCCP_GAP(19);
+      pv.s2();
+      THCCP_GAP(20);
+      pv.s3();
+      THCCP_GAP(21);
+      const T il3 = pv.s4();
+      THCCP_GAP(22);
+      if (!PANEL && r == 0 && q0 == 0) {
+        invd[c0] = il0;
+        invd[c0 + 1] = il1;
+        invd[c0 + 2] = il2;
+        invd[c0 + 3] = il3;
+      }
+      T y3 = v3c * il3, yt3 = T(0);
+      pin(y3);
+      if constexpr (PANEL) {
+        yt3 = vt3c * il3;
+        pin(yt3);
       }
       // own entry of the block column: L[r][c0 + q0] = y[q0]
-      if constexpr (!PANEL) d[B] = q0 == 0 ? y[0] : q0 == 1 ? y[1] : q0 == 2 ? y[2] : y[3];
-      if constexpr (PANEL) e[B] = q0 == 0 ? yt[0] : q0 == 1 ? yt[1] : q0 == 2 ? yt[2] : yt[3];
+      if constexpr (!PANEL) d[B] = q0 == 0 ? y0 : q0 == 1 ? y1 : q0 == 2 ? y2 : y3;
+      if constexpr (PANEL) e[B] = q0 == 0 ? yt0 : q0 == 1 ? yt1 : q0 == 2 ? yt2 : yt3;
+      THCCP_GAP(23);
+      // w = y Ld^{-1} from the last column back; column B + 1 is updated
+      // with each w as it comes
+      T wv[4], wt[4] = {T(0), T(0), T(0), T(0)};
+      wv[3] = y3 * il3;
+      pin(wv[3]);
+      if constexpr (PANEL) {
+        wt[3] = yt3 * il3;
+        pin(wt[3]);
+      }
+      THCCP_GAP(24);
+      T h2 = fma_t(-wv[3], L32, y2), h1 = fma_t(-wv[3], L31, y1), h0 = fma_t(-wv[3], L30, y0);
+      T ht2 = T(0), ht1 = T(0), ht0 = T(0);
+      if constexpr (B + 1 < 16) {
+        d[B + 1] = fma_t(-wv[3], c1[3], d[B + 1]);
+        pin(d[B + 1]);
+      }
+      if constexpr (PANEL) {
+        ht2 = fma_t(-wt[3], L32, yt2);
+        ht1 = fma_t(-wt[3], L31, yt1);
+        ht0 = fma_t(-wt[3], L30, yt0);
+        if constexpr (B + 1 < 16) {
+          e[B + 1] = fma_t(-wt[3], c1[3], e[B + 1]);
+          pin(e[B + 1]);
+        }
+      }
+      pin(h2);
+      THCCP_GAP(25);
+      wv[2] = h2 * il2;
+      pin(wv[2]);
+      if constexpr (PANEL) {
+        wt[2] = ht2 * il2;
+        pin(wt[2]);
+      }
+      THCCP_GAP(26);
+      h1 = fma_t(-wv[2], L21, h1);
+      h0 = fma_t(-wv[2], L20, h0);
+      if constexpr (B + 1 < 16) {
+        d[B + 1] = fma_t(-wv[2], c1[2], d[B + 1]);
+        pin(d[B + 1]);
+      }
+      if constexpr (PANEL) {
+        ht1 = fma_t(-wt[2], L21, ht1);
+        ht0 = fma_t(-wt[2], L20, ht0);
+        if constexpr (B + 1 < 16) {
+          e[B + 1] = fma_t(-wt[2], c1[2], e[B + 1]);
+          pin(e[B + 1]);
+        }
+      }
+      pin(h1);
+      THCCP_GAP(27);
+      wv[1] = h1 * il1;
+      pin(wv[1]);
+      if constexpr (PANEL) {
+        wt[1] = ht1 * il1;
+        pin(wt[1]);
+      }
+      THCCP_GAP(28);
+      h0 = fma_t(-wv[1], L10, h0);
+      if constexpr (B + 1 < 16) {
+        d[B + 1] = fma_t(-wv[1], c1[1], d[B + 1]);
+        pin(d[B + 1]);
+      }
+      if constexpr (PANEL) {
+        ht0 = fma_t(-wt[1], L10, ht0);
+        if constexpr (B + 1 < 16) {
+          e[B + 1] = fma_t(-wt[1], c1[1], e[B + 1]);
+          pin(e[B + 1]);
+        }
+      }
+      pin(h0);
+      THCCP_GAP(29);
+      wv[0] = h0 * il0;
+      pin(wv[0]);
+      if constexpr (PANEL) {
+        wt[0] = ht0 * il0;
+        pin(wt[0]);
+      }
+      THCCP_GAP(30);
+      if constexpr (B + 1 < 16) {
+        d[B + 1] = fma_t(-wv[0], c1[0], d[B + 1]);
+        if constexpr (PANEL) e[B + 1] = fma_t(-wt[0], c1[0], e[B + 1]);
+      }
+      THCCP_GAP(31);
+      THCCP_GAP(32);
+      THCCP_GAP(33);
+#undef THCCP_GAP
       Potrf4<T, B + 1, PANEL>::run(d, e, cb, invd, r, q0, ok, wv, wt);
     }
   }
