@@ -237,7 +237,8 @@ cpd_status cpd_batch_stats(cpd_plan p, int32_t idx, cpd_stats_t* out);
 /* Autotuner decisions of the plan as "kind,M,N,K,...=shape" lines into buf
  * (NUL-terminated, truncated to len); returns the full length.  FP64/FP32
  * kinds: shape = tile edge; split-BF16 kinds (bf16core, bf16back, bf16proj):
- * shape = bm + 1000 (bm x 256 tiles) + 10000 kparts. */
+ * shape = bm + 1000 (bm x 256 tiles) + 10000 kparts, or 100000 + 10000 kparts
+ * for the 256 x 256 direct-load tiles of blocked operands. */
 int32_t cpd_autotune_log(cpd_plan p, char* buf, int32_t len);
 /* Laplace-transform row scaling of THC factors (eq. mp1_t and the THC-LT
  * amplitude after it): out[p, :] = exp(sign * eps[p] * t) * X[p, :] for
@@ -493,7 +494,10 @@ cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, con
  *   FP32 product A o A2 (B o B2), split on the fly.  Launch shape: wide = 0:
  *   128-column tiles with bm = 64 or 128 rows (0: the heuristic the sweep
  *   uses), kparts = 1; wide = 1: bm x 256 tiles, bm = 128 or 256, with
- *   kparts = 1..4 K slices (split-K, summed in order by a second launch).
+ *   kparts = 1..4 K slices (split-K, summed in order by a second launch);
+ *   wide = 2: 256 x 256 tiles loaded straight into LDS from pre-split
+ *   operands (an operand pair is multiplied and split by a separate pass
+ *   first), kparts = 1..4, bm ignored.
  *   Other values return CPD_ERR_INVALID_ARG.  Uploads a one-entry argument
  *   table and synchronises before the launch. */
 size_t cpd_test_split_workspace(int32_t M, int32_t N, int32_t K);

@@ -364,15 +364,17 @@ def test_solve(V, M, panel=0):
 def test_gemm_split(A, B, A2=None, bm=0, B2=None, wide=False, kparts=1):
     """C = A B^T through the split-BF16 GEMM, with A (B) replaced by the
     FP32 product A o A2 (B o B2) when given.  Launch shape: 128-column tiles
-    with bm = 64 or 128 rows (0: the sweep's heuristic), or with wide=True
-    bm x 256 tiles (bm = 128 or 256) and kparts K slices."""
+    with bm = 64 or 128 rows (0: the sweep's heuristic), with wide=True
+    bm x 256 tiles (bm = 128 or 256) and kparts K slices, or with wide=2
+    256 x 256 direct-load tiles of pre-split operands and kparts K slices."""
     lib = _lib.load()
     M, K = A.shape
     N = B.shape[0]
     ws = torch.empty(lib.cpd_test_split_workspace(M, N, K), dtype=torch.uint8, device=A.device)
     C = torch.empty(M, N, dtype=torch.float64, device=A.device)
     check(lib.cpd_test_gemm_split(M, N, K, _ptr(A), _ptr(A2), _ptr(B), _ptr(B2), _ptr(C), _ptr(ws), ws.numel(),
-                                  _stream(A.device), int(bm), int(bool(wide)), int(kparts)), "cpd_test_gemm_split")
+                                  _stream(A.device), int(bm), 2 if wide == 2 else int(bool(wide)), int(kparts)),
+          "cpd_test_gemm_split")
     torch.cuda.current_stream(A.device).synchronize()
     return C
 

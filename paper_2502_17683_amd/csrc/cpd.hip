@@ -87,6 +87,12 @@ struct GroupOp {
   bool wide = false;     // split BF16: bm x 256 tiles (gemm_split_wide_group)
   int kparts = 1;        // split BF16, wide tiles: K slices (split-K) summed by a reduce launch
   int maxm = 0, maxn = 0;
+  // split BF16, direct-load 256 x 256 tiles of blocked operands: their own
+  // argument table, and the pair splits that form a pair operand first
+  bool dma = false;
+  void* dtab = nullptr;  // device SplitArgs[] with the blocked operands (null: not available)
+  void* ptab = nullptr;  // device PairJob[] (one per problem) or null
+  size_t pchunks = 0;    // largest pair split, in 8-element chunks
 };
 
 // One launch of a blocked solve: a step launch or a grouped panel GEMM.
@@ -230,7 +236,7 @@ void carve_typed(Layout& L, Prob& q, Bufs<T>& b, bool own_inputs) {
 // modes) that pass the same input pointer.
 typedef std::map<const double*, std::pair<__bf16*, __bf16*>> SplitMap;
 struct SplitShare {
-  SplitMap x, xt, z, zt;
+  SplitMap x, xt, z, zt, xb, zb, ztb;
 };
 
 void carve_mixed(Layout& L, Prob& q, SplitShare& sh) {
@@ -267,6 +273,19 @@ void carve_mixed(Layout& L, Prob& q, SplitShare& sh) {
   mx.YT = (float*)L.take(4 * (size_t)Rc * mx.Rtp);
   mx.FTh = (__bf16*)L.take(2 * (size_t)Rc * mx.npad_max);
   mx.FTl = (__bf16*)L.take(2 * (size_t)Rc * mx.npad_max);
+  for (int m = 0; m < 4; ++m) {
+    auto xb = pair_for(sh.xb, q.d.X[m], blk_elems(q.n[m], mx.Rtp));
+    mx.XBh[m] = xb.first;
+    mx.XBl[m] = xb.second;
+  }
+  auto zb = pair_for(sh.zb, q.d.Z, blk_elems(Rt, mx.Rtp));
+  auto ztb = pair_for(sh.ztb, q.d.Z, blk_elems(Rt, mx.Rtp));
+  mx.ZBh = zb.first;
+  mx.ZBl = zb.second;
+  mx.ZTBh = ztb.first;
+  mx.ZTBl = ztb.second;
+  mx.PWh = (__bf16*)L.take(2 * blk_elems(Rc, mx.Rtp));
+  mx.PWl = (__bf16*)L.take(2 * blk_elems(Rc, mx.Rtp));
   q.spart = (float*)L.take(4 * (size_t)SPLIT_KPARTS_MAX * q.nmax * q.Tp);
 }
 
@@ -364,34 +383,45 @@ struct SplitCfg {
   int bm = 128;
   bool wide = false;
   int kparts = 1;
-  int code() const { return bm + (wide ? 1000 : 0) + 10000 * kparts; }
+  bool dma = false;  // direct-load 256 x 256 tiles (bm, wide unused)
+  int code() const { return dma ? 100000 + 10000 * kparts : bm + (wide ? 1000 : 0) + 10000 * kparts; }
   static SplitCfg of(int c) {
     SplitCfg g;
+    g.dma = c >= 100000;
+    c %= 100000;
     g.kparts = c / 10000;
     c %= 10000;
     g.wide = c >= 1000;
-    g.bm = c % 1000;
+    g.bm = g.dma ? 256 : c % 1000;
     if (g.kparts < 1) g.kparts = 1;
     return g;
   }
 };
 
+int split_cfg_count(const SplitArgs& g, const SplitCfg& c) {
+  if (c.dma) return split_dma_tile_count(g.M, g.N) * c.kparts;
+  return c.wide ? split_wide_tile_count(g.M, g.N, c.bm) * c.kparts : split_tile_count(g.M, g.N, c.bm);
+}
 long split_cfg_tiles(const std::vector<SplitArgs>& v, const SplitCfg& c) {
   long t = 0;
-  for (auto& g : v)
-    t += (long)(c.wide ? split_wide_tile_count(g.M, g.N, c.bm) * c.kparts : split_tile_count(g.M, g.N, c.bm));
+  for (auto& g : v) t += split_cfg_count(g, c);
   return t;
 }
 
 // Candidate launch shapes of a product; split-K only where a partial buffer
 // exists (the back-projection).
-std::vector<SplitCfg> split_candidates(bool splitk) {
+std::vector<SplitCfg> split_candidates(bool splitk, bool dma) {
   std::vector<SplitCfg> c;
   for (int bm : {64, 128}) c.push_back({bm, false, 1});
   for (int bm : {128, 256}) {
     c.push_back({bm, true, 1});
     if (splitk)
       for (int k = 2; k <= SPLIT_KPARTS_MAX; k *= 2) c.push_back({bm, true, k});
+  }
+  if (dma) {
+    c.push_back({256, false, 1, true});
+    if (splitk)
+      for (int k = 2; k <= SPLIT_KPARTS_MAX; k *= 2) c.push_back({256, false, k, true});
   }
   return c;
 }
@@ -401,12 +431,15 @@ std::vector<SplitCfg> split_candidates(bool splitk) {
 // enough K slices to do so; otherwise the 128-column kernel with 64- or 128-row tiles (64 when
 // 128-row tiles would pad a quarter more rows, as in the Laplace batch, or
 // leave most compute units idle).
-SplitCfg split_default(const std::vector<SplitArgs>& v, bool splitk) {
+SplitCfg split_default(const std::vector<SplitArgs>& v, bool splitk, bool dma) {
   const long w256 = split_cfg_tiles(v, {256, true, 1});
   int kmin = 1 << 30;
   for (auto& g : v) kmin = g.K < kmin ? g.K : kmin;
   // long contractions only: with K = n (the projection) the 128-column
-  // kernel was measured faster
+  // kernel was measured faster; the direct-load tiles where the blocked
+  // operands exist and they cover the compute units
+  if (dma && !splitk && split_cfg_tiles(v, {256, false, 1, true}) >= 192 && kmin >= 2048)
+    return {256, false, 1, true};
   if (w256 >= 192 && kmin >= 2048) return {256, true, 1};
   if (splitk) {
     for (int k = 2; k <= SPLIT_KPARTS_MAX; k *= 2)
@@ -435,16 +468,17 @@ void split_apply(GroupOp& op, const std::vector<SplitArgs>& v, const SplitCfg& c
   op.bm = c.bm;
   op.wide = c.wide;
   op.kparts = c.kparts;
+  op.dma = c.dma;
   std::vector<int> offs(1, 0);
-  for (auto& g : v)
-    offs.push_back(offs.back() + (c.wide ? split_wide_tile_count(g.M, g.N, c.bm) * c.kparts
-                                         : split_tile_count(g.M, g.N, c.bm)));
+  for (auto& g : v) offs.push_back(offs.back() + split_cfg_count(g, c));
   op.total = offs.back();
   if (offs_out) *offs_out = offs;
 }
 
+// vd (optional): the same products with blocked operands for the
+// direct-load tiles, pj: the pair splits they need first.
 GroupOp split_op(TableBuilder& tb, const std::vector<SplitArgs>& v, bool apair, bool bpair, const std::string& kind,
-                 bool splitk) {
+                 bool splitk, const std::vector<SplitArgs>* vd = nullptr, const std::vector<PairJob>* pj = nullptr) {
   GroupOp op;
   op.apair = apair;
   op.bpair = bpair;
@@ -453,12 +487,23 @@ GroupOp split_op(TableBuilder& tb, const std::vector<SplitArgs>& v, bool apair, 
     if (g.M > op.maxm) op.maxm = g.M;
     if (g.N > op.maxn) op.maxn = g.N;
   }
-  SplitCfg c = split_default(v, splitk);
+  if (vd) {
+    op.dtab = tb.put(*vd);
+    if (pj && !pj->empty()) {
+      op.ptab = tb.put(*pj);
+      for (auto& j : *pj) {
+        const size_t ch = (size_t)blk_rows(j.rows) * (j.Kp / 8);
+        if (ch > op.pchunks) op.pchunks = ch;
+      }
+    }
+  }
+  SplitCfg c = split_default(v, splitk, vd != nullptr);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(split_key(kind, v));
     if (it != g_tune.end()) c = SplitCfg::of(it->second);
   }
+  if (c.dma && !vd) c = split_default(v, splitk, false);
   std::vector<int> offs;
   split_apply(op, v, c, &offs);
   // room for the prefix sums of any candidate shape (the autotuner rewrites them)
@@ -663,7 +708,8 @@ void build_typed(TableBuilder& tb, cpd_plan_s* p, Bufs<T> Prob::*bufs, bool gate
 void build_mixed(TableBuilder& tb, cpd_plan_s* p) {
   const int np = p->count;
   for (int n = 0; n < 4; ++n) {
-    std::vector<SplitArgs> core, back, proj;
+    std::vector<SplitArgs> core, back, proj, cored, backd;
+    std::vector<PairJob> corej, backj;
     std::vector<SplitTArgs> ftt;
     for (int i = 0; i < np; ++i) {
       Prob& q = p->P[i];
@@ -676,18 +722,29 @@ void build_mixed(TableBuilder& tb, cpd_plan_s* p) {
         SplitOperand B = n == 0 ? SplitOperand{mx.Zh, mx.Zl, nullptr, nullptr, mx.Rtp}
                                 : SplitOperand{mx.ZTh, mx.ZTl, nullptr, nullptr, mx.Rtp};
         core.push_back({Rc, Rt, mx.Rtp, A, B, mx.YT, nullptr, nullptr, mx.Rtp, done, &q.st->path, 0, nullptr});
+        // direct-load form: the pair product split into PW first
+        SplitOperand Ad{mx.PWh, mx.PWl, nullptr, nullptr, mx.Rtp};
+        SplitOperand Bd = n == 0 ? SplitOperand{mx.ZBh, mx.ZBl, nullptr, nullptr, mx.Rtp}
+                                 : SplitOperand{mx.ZTBh, mx.ZTBl, nullptr, nullptr, mx.Rtp};
+        cored.push_back({Rc, Rt, mx.Rtp, Ad, Bd, mx.YT, nullptr, nullptr, mx.Rtp, done, &q.st->path, 0, nullptr});
+        corej.push_back({mx.WT[a], mx.WT[b], mx.Rtp, Rc, Rt, mx.PWh, mx.PWl, mx.Rtp, done, &q.st->path, 0});
       }
       SplitOperand A{mx.Xh[n], mx.Xl[n], nullptr, nullptr, mx.Rtp};
       SplitOperand B{nullptr, nullptr, mx.WT[partner_of[n]], mx.YT, mx.Rtp};
       back.push_back({q.n[n], Rc, mx.Rtp, A, B, nullptr, q.b64.Msol, nullptr, q.Tp, done, &q.st->path, 0, q.spart});
+      SplitOperand Axd{mx.XBh[n], mx.XBl[n], nullptr, nullptr, mx.Rtp};
+      SplitOperand Bpd{mx.PWh, mx.PWl, nullptr, nullptr, mx.Rtp};
+      backd.push_back({q.n[n], Rc, mx.Rtp, Axd, Bpd, nullptr, q.b64.Msol, nullptr, q.Tp, done, &q.st->path, 0,
+                       q.spart});
+      backj.push_back({mx.WT[partner_of[n]], mx.YT, mx.Rtp, Rc, Rt, mx.PWh, mx.PWl, mx.Rtp, done, &q.st->path, 0});
       SplitOperand PA{mx.FTh, mx.FTl, nullptr, nullptr, mx.npad_max};
       SplitOperand PB{mx.XTh[n], mx.XTl[n], nullptr, nullptr, mx.npad[n]};
       proj.push_back({Rc, Rt, mx.npad[n], PA, PB, mx.WT[n], nullptr, nullptr, mx.Rtp, done, &q.st->path, 0,
                       nullptr});
       ftt.push_back({q.b64.F[n], mx.FTh, mx.FTl, done, &q.st->path, q.n[n], Rc, q.Tp, mx.npad_max, mx.npad[n]});
     }
-    if (n == 0 || n == 2) p->score[n] = split_op(tb, core, true, false, "bf16core", false);
-    p->sback[n] = split_op(tb, back, false, true, "bf16back", true);
+    if (n == 0 || n == 2) p->score[n] = split_op(tb, core, true, false, "bf16core", false, &cored, &corej);
+    p->sback[n] = split_op(tb, back, false, true, "bf16back", true, &backd, &backj);
     p->sproj[n] = split_op(tb, proj, false, false, "bf16proj", false);
     p->ftt[n] = tb.put(ftt);
   }
@@ -832,11 +889,14 @@ void split_inputs(Prob& q, hipStream_t s, std::map<const void*, int>& done_split
     done_split[mx.Xh[m]] = 1;
     split_rows_f64(s, q.d.X[m], q.n[m], q.Rt, q.Rt, mx.Xh[m], mx.Xl[m], mx.Rtp, mx.Rtp);
     split_transpose_f64(s, q.d.X[m], q.n[m], q.Rt, q.Rt, mx.XTh[m], mx.XTl[m], mx.npad[m], mx.npad[m]);
+    split_blocked_f64(s, q.d.X[m], q.n[m], q.Rt, q.Rt, mx.XBh[m], mx.XBl[m], mx.Rtp);
   }
   if (!done_split.count(mx.Zh)) {
     done_split[mx.Zh] = 1;
     split_rows_f64(s, q.d.Z, q.Rt, q.Rt, q.Rt, mx.Zh, mx.Zl, mx.Rtp, mx.Rtp);
     split_transpose_f64(s, q.d.Z, q.Rt, q.Rt, q.Rt, mx.ZTh, mx.ZTl, mx.Rtp, mx.Rtp);
+    split_blocked_f64(s, q.d.Z, q.Rt, q.Rt, q.Rt, mx.ZBh, mx.ZBl, mx.Rtp, false);
+    split_blocked_f64(s, q.d.Z, q.Rt, q.Rt, q.Rt, mx.ZTBh, mx.ZTBl, mx.Rtp, true);
   }
 }
 
@@ -849,6 +909,13 @@ void run_gemm(cpd_plan_s* p, hipStream_t s, const GroupOp& op) {
 void run_split(cpd_plan_s* p, hipStream_t s, const GroupOp& op) {
   (void)p;
   const SplitArgs* tab = (const SplitArgs*)op.tab;
+  if (op.dma) {
+    const SplitArgs* dtab = (const SplitArgs*)op.dtab;
+    if (op.ptab) pair_split_group(s, (const PairJob*)op.ptab, op.count, op.pchunks);
+    gemm_split_dma_group(s, dtab, op.offs, op.count, op.total, op.kparts);
+    if (op.kparts > 1) gemm_split_reduce_group(s, dtab, op.count, op.kparts, op.maxm, op.maxn);
+    return;
+  }
   if (!op.wide) {
     gemm_split_group(s, tab, op.offs, op.count, op.total, op.apair, op.bpair, op.bm);
     return;
@@ -1232,8 +1299,12 @@ void autotune_split(cpd_plan_s* p, hipStream_t s) {
       }
     }
     float best = 1e30f;
-    SplitCfg best_c = SplitCfg::of(op.bm + (op.wide ? 1000 : 0) + 10000 * op.kparts);
-    for (const SplitCfg& c : split_candidates(splitk)) {
+    SplitCfg best_c;
+    best_c.bm = op.bm;
+    best_c.wide = op.wide;
+    best_c.kparts = op.kparts;
+    best_c.dma = op.dma;
+    for (const SplitCfg& c : split_candidates(splitk, op.dtab != nullptr)) {
       GroupOp t = op;
       std::vector<int> offs;
       split_apply(t, host, c, &offs);

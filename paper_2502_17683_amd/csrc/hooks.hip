@@ -165,7 +165,8 @@ cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, con
 size_t cpd_test_split_workspace(int32_t M, int32_t N, int32_t K) {
   if (M <= 0 || N <= 0 || K <= 0) return 0;
   const size_t Kp = (K + 31) / 32 * 32;
-  return 2 * al(2 * (size_t)M * Kp) + 2 * al(2 * (size_t)N * Kp) + 2 * al(4 * (size_t)M * Kp) +
+  // the hi / lo buffers hold the blocked layout's padded rows
+  return 2 * al(2 * blk_elems(M, (int)Kp)) + 2 * al(2 * blk_elems(N, (int)Kp)) + 2 * al(4 * (size_t)M * Kp) +
          2 * al(4 * (size_t)N * Kp) + al(4 * (size_t)4 * M * N) + al(sizeof(SplitArgs)) + al(2 * sizeof(int));
 }
 
@@ -177,7 +178,9 @@ cpd_status cpd_test_gemm_split(int32_t M, int32_t N, int32_t K, const double* A,
                                const double* B, const double* B2, double* C, void* workspace, size_t ws_bytes,
                                void* stream, int32_t bm, int32_t wide, int32_t kparts) {
   if (M <= 0 || N <= 0 || K <= 0 || !A || !B || !C) return CPD_ERR_INVALID_ARG;
-  if (wide) {
+  if (wide == 2) {
+    if (kparts < 1 || kparts > 4) return CPD_ERR_INVALID_ARG;
+  } else if (wide) {
     if ((bm != 128 && bm != 256) || kparts < 1 || kparts > 4) return CPD_ERR_INVALID_ARG;
   } else {
     if (bm == 0) bm = split_default_bm(M, N);
@@ -187,10 +190,10 @@ cpd_status cpd_test_gemm_split(int32_t M, int32_t N, int32_t K, const double* A,
   hipStream_t s = (hipStream_t)stream;
   const int Kp = (K + 31) / 32 * 32;
   char* b = (char*)workspace;
-  __bf16* Ah = (__bf16*)b; b += al(2 * (size_t)M * Kp);
-  __bf16* Al = (__bf16*)b; b += al(2 * (size_t)M * Kp);
-  __bf16* Bh = (__bf16*)b; b += al(2 * (size_t)N * Kp);
-  __bf16* Bl = (__bf16*)b; b += al(2 * (size_t)N * Kp);
+  __bf16* Ah = (__bf16*)b; b += al(2 * blk_elems(M, Kp));
+  __bf16* Al = (__bf16*)b; b += al(2 * blk_elems(M, Kp));
+  __bf16* Bh = (__bf16*)b; b += al(2 * blk_elems(N, Kp));
+  __bf16* Bl = (__bf16*)b; b += al(2 * blk_elems(N, Kp));
   float* Ap = (float*)b; b += al(4 * (size_t)M * Kp);
   float* Aq = (float*)b; b += al(4 * (size_t)M * Kp);
   float* Bp = (float*)b; b += al(4 * (size_t)N * Kp);
@@ -207,15 +210,34 @@ cpd_status cpd_test_gemm_split(int32_t M, int32_t N, int32_t K, const double* A,
     split_rows_f64(s, X, rows, K, K, h, l, Kp, Kp);
     return SplitOperand{h, l, nullptr, nullptr, Kp};
   };
-  const SplitOperand opA = operand(A, A2, M, Ah, Al, Ap, Aq);
-  const SplitOperand opB = operand(B, B2, N, Bh, Bl, Bp, Bq);
+  SplitOperand opA = operand(A, A2, M, Ah, Al, Ap, Aq);
+  SplitOperand opB = operand(B, B2, N, Bh, Bl, Bp, Bq);
+  if (wide == 2) {
+    // direct-load tiles take operands in the blocked split layout
+    if (A2) {
+      pair_split_blocked(s, Ap, Aq, Kp, M, Kp, Ah, Al, Kp);
+    } else {
+      split_blocked_f64(s, A, M, K, K, Ah, Al, Kp);
+    }
+    if (B2) {
+      pair_split_blocked(s, Bp, Bq, Kp, N, Kp, Bh, Bl, Kp);
+    } else {
+      split_blocked_f64(s, B, N, K, K, Bh, Bl, Kp);
+    }
+    opA = SplitOperand{Ah, Al, nullptr, nullptr, Kp};
+    opB = SplitOperand{Bh, Bl, nullptr, nullptr, Kp};
+  }
   const SplitArgs ha{M, N, Kp, opA, opB, nullptr, C, nullptr, N, nullptr, nullptr, 0, part};
-  const int tiles = wide ? split_wide_tile_count(M, N, bm) * kparts : split_tile_count(M, N, bm);
+  const int tiles = wide == 2 ? split_dma_tile_count(M, N) * kparts
+                    : wide ? split_wide_tile_count(M, N, bm) * kparts : split_tile_count(M, N, bm);
   const int ho[2] = {0, tiles};
   if (hipMemcpyAsync(tab, &ha, sizeof(ha), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
   if (hipMemcpyAsync(offs, ho, sizeof(ho), hipMemcpyHostToDevice, s) != hipSuccess) return CPD_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return CPD_ERR_HIP;  // host copies of ha/ho go out of scope
-  if (wide) {
+  if (wide == 2) {
+    gemm_split_dma_group(s, tab, offs, 1, tiles, kparts);
+    gemm_split_reduce_group(s, tab, 1, kparts, M, N);
+  } else if (wide) {
     gemm_split_wide_group(s, tab, offs, 1, tiles, A2 != nullptr, B2 != nullptr, bm, kparts);
     gemm_split_reduce_group(s, tab, 1, kparts, M, N);
   } else {

@@ -25,6 +25,11 @@ struct MixedBufs {
   float* WT[4];             // R_cp x Rtp    (W_m^T, FP32)
   float* YT;                // R_cp x Rtp    (Y^T, FP32)
   __bf16 *FTh, *FTl;        // R_cp x npad_max (current factor, transposed, split)
+  // blocked split layout (direct-load products)
+  __bf16 *XBh[4], *XBl[4];  // n_m rows x Rtp
+  __bf16 *ZBh, *ZBl;        // Z,   R_thc rows x Rtp
+  __bf16 *ZTBh, *ZTBl;      // Z^T, R_thc rows x Rtp
+  __bf16 *PWh, *PWl;        // pair product of the current product, R_cp rows x Rtp
 };
 
 // One operand: a pre-split (hi, lo) pair, or a pair of FP32 matrices whose
@@ -68,6 +73,45 @@ int split_wide_tile_count(int M, int N, int bm);
 void gemm_split_wide_group(hipStream_t s, const SplitArgs* tab, const int* offs, int nprob, int total_tiles,
                            bool apair, bool bpair, int bm, int kparts);
 void gemm_split_reduce_group(hipStream_t s, const SplitArgs* tab, int nprob, int kparts, int max_m, int max_n);
+
+// Blocked split layout of an operand half (hi or lo) with rows r and
+// contraction index k (K padded to Kp, a multiple of 32; rows padded to
+// blk_rows, a multiple of 256, with zeros): element (r, k) at
+//   ((r / 16) * (Kp / 32) + k / 32) * 512 + ((k / 8) % 4) * 128 + (r % 16) * 8 + k % 8,
+// so that a 16-row x 32-k block is one contiguous kilobyte in the lane
+// order of a matrix-core fragment.
+__host__ __device__ inline int blk_rows(int rows) { return (rows + 255) / 256 * 256; }
+inline size_t blk_elems(int rows, int Kp) { return (size_t)blk_rows(rows) * Kp; }
+// hi / lo (blocked) = split of an FP64 row-major matrix (rows x cols, row
+// stride lds), zero beyond it; with trans, of its transpose (src is then
+// cols x rows with row stride lds).
+void split_blocked_f64(hipStream_t s, const double* src, int rows, int cols, int lds, __bf16* hi, __bf16* lo,
+                       int Kp, bool trans = false);
+// hi / lo (blocked) = split(p o q) of two FP32 row-major matrices (rows x
+// cols, row stride ld), zero beyond them.
+void pair_split_blocked(hipStream_t s, const float* p, const float* q, int ld, int rows, int cols, __bf16* hi,
+                        __bf16* lo, int Kp);
+// One pair split of a grouped launch: hi / lo (blocked, Kp) = split(p o q)
+// for FP32 p, q (rows x cols, row stride ld a multiple of 4, 16-byte
+// aligned), skipped when *done or when gate is set and *gate != want.
+struct PairJob {
+  const float* p;
+  const float* q;
+  int ld, rows, cols;
+  __bf16* hi;
+  __bf16* lo;
+  int Kp;
+  const int32_t* done;
+  const int32_t* gate;
+  int32_t want;
+};
+void pair_split_group(hipStream_t s, const PairJob* jobs, int njobs, size_t max_chunks);
+// Direct-load tiles: 256 x 256 per workgroup from operands in the blocked
+// split layout (SplitOperand hi, lo; ld = Kp; p, q unused; K = Kp), with
+// split-K as above.
+int split_dma_tile_count(int M, int N);
+void gemm_split_dma_group(hipStream_t s, const SplitArgs* tab, const int* offs, int nprob, int total_tiles,
+                          int kparts);
 
 // dst (cols x ldd) = split(src^T): dst[c][r] for c < cols, r < dcols
 // (r >= rows written as 0).

@@ -476,6 +476,280 @@ void gemm_split_reduce_group(hipStream_t s, const SplitArgs* tab, int nprob, int
   hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)blocks, nprob), dim3(256), 0, s, tab, kparts);
 }
 
+// ------------------------------------------------- direct-to-LDS tiles
+// 256 x 256 tiles of pre-split operands loaded straight into LDS
+// (global_load_lds_dwordx4): no staging registers and no conversion in
+// the loop, so the wave's instruction stream is the fragment reads and the
+// matrix-core products.  The operands are stored in the blocked split
+// layout (mixed.h): a 16-row x 32-k block is one contiguous kilobyte in
+// fragment order (lane l of a fragment read: row l % 16, k chunk l / 16),
+// so one direct-load instruction of a wave copies one block from memory to
+// LDS unchanged and a fragment read is one contiguous kilobyte of LDS.
+// Two stages (64 KB each): the next k-tile is in flight while the current
+// one is multiplied; one barrier per k-tile.  Rows are padded to the tile
+// with zeros, so no row is clamped.
+namespace {
+typedef __attribute__((address_space(3))) void* lds_vptr_t;
+typedef const __attribute__((address_space(1))) void* glb_cvptr_t;
+constexpr int DT = 256;              // tile edge
+constexpr int DHALF = DT * SBK;      // bf16 per operand half per k-tile
+constexpr int DSTAGE = 4 * DHALF;    // A hi, A lo, B hi, B lo
+
+// this wave's 4 of the tile's 16 row blocks of one operand half, k-tile kt
+__device__ __forceinline__ void dma_blocks(const __bf16* base, int rb0, int KT, int kt, __bf16* dst, int w, int lane) {
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int rb = w * 4 + b;
+    const __bf16* g = base + ((size_t)(rb0 + rb) * KT + kt) * 512 + lane * 8;
+    __builtin_amdgcn_global_load_lds((glb_cvptr_t)g, (lds_vptr_t)(dst + rb * 512), 16, 0, 0);
+  }
+}
+}  // namespace
+
+__global__ __launch_bounds__(256, 1) void gemm_split_dma_kernel(const SplitArgs* tab, const int* offs, int nprob,
+                                                                 int kparts) {
+  __shared__ __attribute__((aligned(1024))) __bf16 lds[2 * DSTAGE];
+  int pid = 0;
+  while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
+  const SplitArgs a = tab[pid];
+  if (a.done && *a.done) return;
+  if (a.gate && *a.gate != a.want) return;
+  const int tiles_n = (a.N + DT - 1) / DT, tiles_m = (a.M + DT - 1) / DT;
+  const int ntiles = tiles_m * tiles_n;
+  const int local = blockIdx.x - offs[pid];
+  const int kp = local / ntiles;
+  const int bid = xcd_remap(local - kp * ntiles, ntiles);
+  int tm, tn;
+  grouped_tile(bid, tiles_m, tiles_n, 4, tm, tn);
+  const int m0 = tm * DT, n0 = tn * DT;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  const int wm = wid >> 1, wn = wid & 1;
+  const int KT = a.K / SBK;
+  const int kt0 = (int)((long)KT * kp / kparts), kt1 = (int)((long)KT * (kp + 1) / kparts);
+
+  f4_t acc[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+  auto issue = [&](int kt, int st) {
+    __bf16* base = lds + st * DSTAGE;
+    dma_blocks(a.A.hi, m0 / 16, KT, kt, base, wid, lane);
+    dma_blocks(a.A.lo, m0 / 16, KT, kt, base + DHALF, wid, lane);
+    dma_blocks(a.B.hi, n0 / 16, KT, kt, base + 2 * DHALF, wid, lane);
+    dma_blocks(a.B.lo, n0 / 16, KT, kt, base + 3 * DHALF, wid, lane);
+  };
+  if (kt0 < kt1) issue(kt0, 0);
+  for (int kt = kt0; kt < kt1; ++kt) {
+    // this wave's loads of k-tile kt have landed; the barrier makes every
+    // wave's visible and ends all reads of the other stage
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    const __bf16* st = lds + ((kt - kt0) & 1) * DSTAGE;
+    const __bf16* Ah = st + (wm * 8) * 512 + lane * 8;
+    const __bf16* Bh = st + 2 * DHALF + (wn * 8) * 512 + lane * 8;
+    // Fragment reads.  While direct loads are in flight, a wait for an LDS
+    // read can only be a wait for all outstanding reads, so every read is
+    // issued right after the wait before it: the first column tile's and
+    // the first four row fragments, then the other row fragments four
+    // products ahead (at most 12 reads in flight before the direct loads
+    // are issued, so those waits are per read), and each later column
+    // tile's fragments right after the first products of the tile before.
+    bf16x8_t ah[8], al[8];
+    bf16x8_t bh = *(const bf16x8_t*)Bh, bl = *(const bf16x8_t*)(Bh + DHALF);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ah[i] = *(const bf16x8_t*)(Ah + i * 512);
+      al[i] = *(const bf16x8_t*)(Ah + DHALF + i * 512);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      bf16x8_t nh, nl;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        if (j == 0 && i + 4 < 8) {
+          ah[i + 4] = *(const bf16x8_t*)(Ah + (i + 4) * 512);
+          al[i + 4] = *(const bf16x8_t*)(Ah + DHALF + (i + 4) * 512);
+        }
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+        if (j == 0 || i == 0) __builtin_amdgcn_sched_barrier(0);
+        if (j == 0 && i == 3 && kt + 1 < kt1) {
+          issue(kt + 1, (kt + 1 - kt0) & 1);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (i == (j == 0 ? 4 : 0) && j + 1 < 8) {
+          nh = *(const bf16x8_t*)(Bh + (j + 1) * 512);
+          nl = *(const bf16x8_t*)(Bh + DHALF + (j + 1) * 512);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (j + 1 < 8) {
+        bh = nh;
+        bl = nl;
+      }
+    }
+  }
+
+  const bool partial = kparts > 1;
+  // the result's row and column bases are formed here, after the loop, so
+  // that no address of the stores is held through it
+  int row0 = m0 + wm * 128 + 4 * (lane >> 4), col0 = n0 + wn * 128 + (lane & 15);
+  __asm__ volatile("" : "+v"(row0), "+v"(col0));
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + i * 16 + r;
+        const int col = col0 + j * 16;
+        if (row < a.M && col < a.N) {
+          const size_t off = (size_t)row * a.ldc + col;
+          if (partial) {
+            as_global(a.part)[(size_t)kp * a.M * a.ldc + off] = acc[i][j][r];
+          } else {
+            if (a.C32) as_global(a.C32)[off] = acc[i][j][r];
+            if (a.C64) as_global(a.C64)[off] = (double)acc[i][j][r];
+            if (a.C64b) as_global(a.C64b)[off] = (double)acc[i][j][r];
+          }
+        }
+      }
+}
+
+int split_dma_tile_count(int M, int N) { return ((M + DT - 1) / DT) * ((N + DT - 1) / DT); }
+
+void gemm_split_dma_group(hipStream_t s, const SplitArgs* tab, const int* offs, int nprob, int total_tiles,
+                          int kparts) {
+  if (total_tiles <= 0) return;
+  if (kparts < 1) kparts = 1;
+  hipLaunchKernelGGL(gemm_split_dma_kernel, dim3(total_tiles), dim3(256), 0, s, tab, offs, nprob, kparts);
+}
+
+// ---------------------------------------------- blocked split layout
+// One thread per 8-element chunk of the padded operand, taken in the
+// blocked (output) order, so that a wave writes one contiguous kilobyte of
+// hi and of lo; its lanes read 16 rows x 4 chunks, 128 contiguous bytes per
+// row of each source.  Chunk e: block b = e / 64 (row block b / KT, k-tile
+// b % KT), k chunk (e / 16) % 4 of the k-tile, row (e % 16) of the block.
+__device__ __forceinline__ void blk_coords(size_t e, int KT, int& r, int& k) {
+  const size_t b = e >> 6;
+  const int w = (int)(e & 63);
+  r = (int)(b / KT) * 16 + (w & 15);
+  k = (int)(b % KT) * 32 + (w >> 4) * 8;
+}
+__global__ __launch_bounds__(256) void split_blocked_f64_kernel(const double* src, int rows, int cols, int lds,
+                                                                __bf16* hi, __bf16* lo, int rows_p, int Kp,
+                                                                bool trans) {
+  const int KT = Kp / 32;
+  const size_t total = (size_t)rows_p * (Kp / 8);
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    int r, k0;
+    blk_coords(e, KT, r, k0);
+    Pack8 ph, pl;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + j;
+      const double x = (r < rows && k < cols) ? (trans ? src[(size_t)k * lds + r] : src[(size_t)r * lds + k]) : 0.0;
+      split_d(x, ph.b[j], pl.b[j]);
+    }
+    as_global((u4_t*)hi)[e] = u4_t{ph.u.x, ph.u.y, ph.u.z, ph.u.w};
+    as_global((u4_t*)lo)[e] = u4_t{pl.u.x, pl.u.y, pl.u.z, pl.u.w};
+  }
+}
+__global__ __launch_bounds__(256) void pair_split_blocked_kernel(const float* p, const float* q, int ld, int rows,
+                                                                 int cols, __bf16* hi, __bf16* lo, int rows_p,
+                                                                 int Kp) {
+  const int KT = Kp / 32;
+  const size_t total = (size_t)rows_p * (Kp / 8);
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    int r, k0;
+    blk_coords(e, KT, r, k0);
+    Pack8 ph, pl;
+    if (r < rows && k0 + 8 <= cols) {
+      const gptr<const f4_t> P = as_global((const f4_t*)(p + (size_t)r * ld + k0));
+      const gptr<const f4_t> Q = as_global((const f4_t*)(q + (size_t)r * ld + k0));
+      const f4_t x0 = P[0] * Q[0], x1 = P[1] * Q[1];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        split_f(x0[j], ph.b[j], pl.b[j]);
+        split_f(x1[j], ph.b[4 + j], pl.b[4 + j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + j;
+        const float x = (r < rows && k < cols) ? p[(size_t)r * ld + k] * q[(size_t)r * ld + k] : 0.f;
+        split_f(x, ph.b[j], pl.b[j]);
+      }
+    }
+    as_global((u4_t*)hi)[e] = u4_t{ph.u.x, ph.u.y, ph.u.z, ph.u.w};
+    as_global((u4_t*)lo)[e] = u4_t{pl.u.x, pl.u.y, pl.u.z, pl.u.w};
+  }
+}
+static int blk_grid(size_t n) {
+  size_t g = (n + 255) / 256;
+  return (int)(g > 16384 ? 16384 : (g < 1 ? 1 : g));
+}
+void split_blocked_f64(hipStream_t s, const double* src, int rows, int cols, int lds, __bf16* hi, __bf16* lo,
+                       int Kp, bool trans) {
+  const int rows_p = blk_rows(rows);
+  hipLaunchKernelGGL(split_blocked_f64_kernel, dim3(blk_grid((size_t)rows_p * (Kp / 8))), dim3(256), 0, s, src, rows,
+                     cols, lds, hi, lo, rows_p, Kp, trans);
+}
+// Grouped form: one job per blockIdx.y, skipped for a problem that is done
+// or not on the path the job is for.
+__global__ __launch_bounds__(256) void pair_split_group_kernel(const PairJob* jobs) {
+  const PairJob jb = jobs[blockIdx.y];
+  if (jb.done && *jb.done) return;
+  if (jb.gate && *jb.gate != jb.want) return;
+  const int KT = jb.Kp / 32;
+  const size_t total = (size_t)blk_rows(jb.rows) * (jb.Kp / 8);
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    int r, k0;
+    blk_coords(e, KT, r, k0);
+    Pack8 ph, pl;
+    if (r < jb.rows && k0 + 8 <= jb.cols) {
+      const gptr<const f4_t> P = as_global((const f4_t*)(jb.p + (size_t)r * jb.ld + k0));
+      const gptr<const f4_t> Q = as_global((const f4_t*)(jb.q + (size_t)r * jb.ld + k0));
+      const f4_t x0 = P[0] * Q[0], x1 = P[1] * Q[1];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        split_f(x0[j], ph.b[j], pl.b[j]);
+        split_f(x1[j], ph.b[4 + j], pl.b[4 + j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + j;
+        const float x = (r < jb.rows && k < jb.cols) ? jb.p[(size_t)r * jb.ld + k] * jb.q[(size_t)r * jb.ld + k] : 0.f;
+        split_f(x, ph.b[j], pl.b[j]);
+      }
+    }
+    as_global((u4_t*)jb.hi)[e] = u4_t{ph.u.x, ph.u.y, ph.u.z, ph.u.w};
+    as_global((u4_t*)jb.lo)[e] = u4_t{pl.u.x, pl.u.y, pl.u.z, pl.u.w};
+  }
+}
+void pair_split_group(hipStream_t s, const PairJob* jobs, int njobs, size_t max_chunks) {
+  if (njobs <= 0) return;
+  size_t g = (max_chunks + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(pair_split_group_kernel, dim3((unsigned)g, njobs), dim3(256), 0, s, jobs);
+}
+
+void pair_split_blocked(hipStream_t s, const float* p, const float* q, int ld, int rows, int cols, __bf16* hi,
+                        __bf16* lo, int Kp) {
+  const int rows_p = blk_rows(rows);
+  hipLaunchKernelGGL(pair_split_blocked_kernel, dim3(blk_grid((size_t)rows_p * (Kp / 8))), dim3(256), 0, s, p, q, ld,
+                     rows, cols, hi, lo, rows_p, Kp);
+}
+
 // ------------------------------------------------------------- splitting
 __global__ void split_rows_kernel(const double* src, int rows, int cols, int lds, __bf16* hi, __bf16* lo,
                                   int ldd, int dcols) {

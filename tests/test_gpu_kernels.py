@@ -144,7 +144,8 @@ def test_dataflow_wait_gives_up_and_recovers():
     assert not failed and rel_err(F.cpu().numpy(), ref) <= 1e-9
 
 
-SPLIT_SHAPES = [(64, False, 1), (128, False, 1), (128, True, 1), (256, True, 1), (256, True, 2), (128, True, 4)]
+SPLIT_SHAPES = [(64, False, 1), (128, False, 1), (128, True, 1), (256, True, 1), (256, True, 2), (128, True, 4),
+                (0, 2, 1), (0, 2, 3)]
 
 
 @pytest.mark.parametrize("M,N,K", [(37, 29, 50), (256, 130, 300), (800, 1000, 1024), (300, 520, 4000)])
@@ -154,9 +155,9 @@ def test_gemm_split_error_bound(M, N, K, pair, bm, wide, kparts):
     """Split-BF16 product: every element within the bound of one correction
     pass (dropped lo*lo term and the two bf16 roundings, ~3 * 2^-16 of
     sum |a||b|) plus FP32 accumulation (K * 2^-24 of sum |a||b|), in every
-    launch shape (128-column tiles; bm x 256 tiles; K slices summed in
-    FP32, still within K * 2^-24), with the FP32 pair product on either
-    operand."""
+    launch shape (128-column tiles; bm x 256 tiles; 256 x 256 direct-load
+    tiles of pre-split operands; K slices summed in FP32, still within
+    K * 2^-24), with the FP32 pair product on either operand."""
     from paper_2502_17683_amd import test_gemm_split
     if (M, N, K) == (300, 520, 4000) and pair == "none" and not (wide and kparts > 1):
         pytest.skip("long-K case: run with split-K shapes and pair operands")
