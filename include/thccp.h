@@ -486,6 +486,14 @@ size_t cpd_test_solve_workspace(int32_t fp32, int32_t R, int32_t n);
  *   needs cpd_init again).  For failure-path tests only: the default never
  *   gives up on a working device.  Not thread-safe. */
 int32_t cpd_test_flow_spin_limit(int32_t polls);
+/* cpd_test_split_force: forces the launch shape of every split-BF16
+ *   product of plans created afterwards in this process to the given shape
+ *   code (the encoding of cpd_autotune_log; 0 or negative: off, the
+ *   heuristic and the autotuner decide again) wherever that shape is
+ *   available for the product (direct-load tiles: core product,
+ *   back-projection and projection; split-K: back-projection); returns the
+ *   previous code.  For tests only.  Not thread-safe with plan creation. */
+int32_t cpd_test_split_force(int32_t code);
 cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, const void* M, void* F,
                           void* workspace, size_t ws_bytes, void* stream, int32_t* failed, int32_t panel);
 /* cpd_test_gemm_split: C (M x N, FP64) = A B^T from FP64 A (M x K) and

@@ -345,6 +345,12 @@ def test_flow_spin_limit(polls):
     return int(_lib.load().cpd_test_flow_spin_limit(int(polls)))
 
 
+def test_split_force(code):
+    """Forces the split-BF16 launch shape of plans created afterwards (the
+    cpd_autotune_log shape code; 0: off); returns the previous code."""
+    return int(_lib.load().cpd_test_split_force(int(code)))
+
+
 def test_solve(V, M, panel=0):
     """F = M V^{-1} through the library's blocked Cholesky and solves
     (panels of `panel` 64-wide blocks; 0: one level)."""

@@ -93,6 +93,8 @@ struct GroupOp {
   void* dtab = nullptr;  // device SplitArgs[] with the blocked operands (null: not available)
   void* ptab = nullptr;  // device PairJob[] (one per problem) or null
   size_t pchunks = 0;    // largest pair split, in 8-element chunks
+  void* ttab = nullptr;  // device SplitTArgs[] (blocked transposes, one per problem) or null
+  size_t tchunks = 0;
 };
 
 // One launch of a blocked solve: a step launch or a grouped panel GEMM.
@@ -117,6 +119,10 @@ struct StepOps {
 
 // Process-wide autotune cache: (kind, shapes) -> tile edge.
 static std::mutex g_tune_mu;
+// Test override of the split-BF16 launch shape (a SplitCfg code, 0: off);
+// applied to every split product of plans built afterwards where that shape
+// is available (split-K only where the product allows it).
+static int g_split_force = 0;
 static std::map<std::string, int> g_tune;
 
 }  // namespace thccp
@@ -236,7 +242,7 @@ void carve_typed(Layout& L, Prob& q, Bufs<T>& b, bool own_inputs) {
 // modes) that pass the same input pointer.
 typedef std::map<const double*, std::pair<__bf16*, __bf16*>> SplitMap;
 struct SplitShare {
-  SplitMap x, xt, z, zt, xb, zb, ztb;
+  SplitMap x, xt, z, zt, xb, zb, ztb, xtb;
 };
 
 void carve_mixed(Layout& L, Prob& q, SplitShare& sh) {
@@ -277,7 +283,12 @@ void carve_mixed(Layout& L, Prob& q, SplitShare& sh) {
     auto xb = pair_for(sh.xb, q.d.X[m], blk_elems(q.n[m], mx.Rtp));
     mx.XBh[m] = xb.first;
     mx.XBl[m] = xb.second;
+    auto xtb = pair_for(sh.xtb, q.d.X[m], blk_elems(Rt, mx.npad[m]));
+    mx.XTBh[m] = xtb.first;
+    mx.XTBl[m] = xtb.second;
   }
+  mx.FTBh = (__bf16*)L.take(2 * blk_elems(Rc, mx.npad_max));
+  mx.FTBl = (__bf16*)L.take(2 * blk_elems(Rc, mx.npad_max));
   auto zb = pair_for(sh.zb, q.d.Z, blk_elems(Rt, mx.Rtp));
   auto ztb = pair_for(sh.ztb, q.d.Z, blk_elems(Rt, mx.Rtp));
   mx.ZBh = zb.first;
@@ -478,7 +489,8 @@ void split_apply(GroupOp& op, const std::vector<SplitArgs>& v, const SplitCfg& c
 // vd (optional): the same products with blocked operands for the
 // direct-load tiles, pj: the pair splits they need first.
 GroupOp split_op(TableBuilder& tb, const std::vector<SplitArgs>& v, bool apair, bool bpair, const std::string& kind,
-                 bool splitk, const std::vector<SplitArgs>* vd = nullptr, const std::vector<PairJob>* pj = nullptr) {
+                 bool splitk, const std::vector<SplitArgs>* vd = nullptr, const std::vector<PairJob>* pj = nullptr,
+                 const std::vector<SplitTArgs>* tj = nullptr) {
   GroupOp op;
   op.apair = apair;
   op.bpair = bpair;
@@ -496,12 +508,26 @@ GroupOp split_op(TableBuilder& tb, const std::vector<SplitArgs>& v, bool apair, 
         if (ch > op.pchunks) op.pchunks = ch;
       }
     }
+    if (tj && !tj->empty()) {
+      op.ttab = tb.put(*tj);
+      for (auto& j : *tj) {
+        const size_t ch = (size_t)blk_rows(j.cols) * (j.dcols / 8);
+        if (ch > op.tchunks) op.tchunks = ch;
+      }
+    }
   }
   SplitCfg c = split_default(v, splitk, vd != nullptr);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(split_key(kind, v));
     if (it != g_tune.end()) c = SplitCfg::of(it->second);
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_split_force) {
+      const SplitCfg f = SplitCfg::of(g_split_force);
+      if ((!f.dma || vd) && (f.kparts == 1 || splitk)) c = f;
+    }
   }
   if (c.dma && !vd) c = split_default(v, splitk, false);
   std::vector<int> offs;
@@ -708,9 +734,9 @@ void build_typed(TableBuilder& tb, cpd_plan_s* p, Bufs<T> Prob::*bufs, bool gate
 void build_mixed(TableBuilder& tb, cpd_plan_s* p) {
   const int np = p->count;
   for (int n = 0; n < 4; ++n) {
-    std::vector<SplitArgs> core, back, proj, cored, backd;
+    std::vector<SplitArgs> core, back, proj, cored, backd, projd;
     std::vector<PairJob> corej, backj;
-    std::vector<SplitTArgs> ftt;
+    std::vector<SplitTArgs> ftt, fttb;
     for (int i = 0; i < np; ++i) {
       Prob& q = p->P[i];
       MixedBufs& mx = q.mx;
@@ -742,10 +768,15 @@ void build_mixed(TableBuilder& tb, cpd_plan_s* p) {
       proj.push_back({Rc, Rt, mx.npad[n], PA, PB, mx.WT[n], nullptr, nullptr, mx.Rtp, done, &q.st->path, 0,
                       nullptr});
       ftt.push_back({q.b64.F[n], mx.FTh, mx.FTl, done, &q.st->path, q.n[n], Rc, q.Tp, mx.npad_max, mx.npad[n]});
+      SplitOperand PAd{mx.FTBh, mx.FTBl, nullptr, nullptr, mx.npad[n]};
+      SplitOperand PBd{mx.XTBh[n], mx.XTBl[n], nullptr, nullptr, mx.npad[n]};
+      projd.push_back({Rc, Rt, mx.npad[n], PAd, PBd, mx.WT[n], nullptr, nullptr, mx.Rtp, done, &q.st->path, 0,
+                       nullptr});
+      fttb.push_back({q.b64.F[n], mx.FTBh, mx.FTBl, done, &q.st->path, q.n[n], Rc, q.Tp, mx.npad[n], mx.npad[n]});
     }
     if (n == 0 || n == 2) p->score[n] = split_op(tb, core, true, false, "bf16core", false, &cored, &corej);
     p->sback[n] = split_op(tb, back, false, true, "bf16back", true, &backd, &backj);
-    p->sproj[n] = split_op(tb, proj, false, false, "bf16proj", false);
+    p->sproj[n] = split_op(tb, proj, false, false, "bf16proj", false, &projd, nullptr, &fttb);
     p->ftt[n] = tb.put(ftt);
   }
   // FP64 mode-3 MTTKRP for the fit of fit sweeps (split-path problems; a
@@ -890,6 +921,7 @@ void split_inputs(Prob& q, hipStream_t s, std::map<const void*, int>& done_split
     split_rows_f64(s, q.d.X[m], q.n[m], q.Rt, q.Rt, mx.Xh[m], mx.Xl[m], mx.Rtp, mx.Rtp);
     split_transpose_f64(s, q.d.X[m], q.n[m], q.Rt, q.Rt, mx.XTh[m], mx.XTl[m], mx.npad[m], mx.npad[m]);
     split_blocked_f64(s, q.d.X[m], q.n[m], q.Rt, q.Rt, mx.XBh[m], mx.XBl[m], mx.Rtp);
+    split_blocked_f64(s, q.d.X[m], q.Rt, q.n[m], q.Rt, mx.XTBh[m], mx.XTBl[m], mx.npad[m], true);
   }
   if (!done_split.count(mx.Zh)) {
     done_split[mx.Zh] = 1;
@@ -912,6 +944,7 @@ void run_split(cpd_plan_s* p, hipStream_t s, const GroupOp& op) {
   if (op.dma) {
     const SplitArgs* dtab = (const SplitArgs*)op.dtab;
     if (op.ptab) pair_split_group(s, (const PairJob*)op.ptab, op.count, op.pchunks);
+    if (op.ttab) split_transpose_blocked_group(s, (const SplitTArgs*)op.ttab, op.count, op.tchunks);
     gemm_split_dma_group(s, dtab, op.offs, op.count, op.total, op.kparts);
     if (op.kparts > 1) gemm_split_reduce_group(s, dtab, op.count, op.kparts, op.maxm, op.maxn);
     return;
@@ -1010,7 +1043,8 @@ void mixed_refresh_mode(cpd_plan_s* p, hipStream_t s, int n, bool with_gram = tr
     if (q.Rc > maxc) maxc = q.Rc;
     if (q.mx.npad[n] > maxd) maxd = q.mx.npad[n];
   }
-  split_transpose_group(s, (const SplitTArgs*)p->ftt[n], p->count, maxc, maxd);
+  // (the direct-load projection splits its own blocked transpose)
+  if (!p->sproj[n].dma) split_transpose_group(s, (const SplitTArgs*)p->ftt[n], p->count, maxc, maxd);
   run_split(p, s, p->sproj[n]);
 }
 
@@ -1728,6 +1762,13 @@ cpd_status cpd_kernel_times(cpd_plan p, int32_t reps, double* ms_out) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return CPD_OK;
+}
+
+int32_t cpd_test_split_force(int32_t code) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const int prev = g_split_force;
+  g_split_force = code < 0 ? 0 : code;
+  return prev;
 }
 
 int32_t cpd_autotune_log(cpd_plan p, char* buf, int32_t len) {

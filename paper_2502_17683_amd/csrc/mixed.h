@@ -30,6 +30,8 @@ struct MixedBufs {
   __bf16 *ZBh, *ZBl;        // Z,   R_thc rows x Rtp
   __bf16 *ZTBh, *ZTBl;      // Z^T, R_thc rows x Rtp
   __bf16 *PWh, *PWl;        // pair product of the current product, R_cp rows x Rtp
+  __bf16 *XTBh[4], *XTBl[4];  // X_m^T, R_thc rows x npad_m
+  __bf16 *FTBh, *FTBl;      // current factor transposed, R_cp rows x npad_m (blocked, per mode)
 };
 
 // One operand: a pre-split (hi, lo) pair, or a pair of FP32 matrices whose
@@ -124,6 +126,10 @@ struct SplitTArgs {
   int rows, cols, lds, ldd, dcols;
 };
 void split_transpose_group(hipStream_t s, const SplitTArgs* tab, int nprob, int max_cols, int max_dcols);
+// The same transposes into the blocked split layout (hi / lo: cols rows,
+// Kp = dcols, a multiple of 32); max_chunks = the largest
+// blk_rows(cols) * dcols / 8.
+void split_transpose_blocked_group(hipStream_t s, const SplitTArgs* tab, int nprob, size_t max_chunks);
 void split_rows_f64(hipStream_t s, const double* src, int rows, int cols, int lds, __bf16* hi, __bf16* lo,
                     int ldd, int dcols);
 void split_transpose_f64(hipStream_t s, const double* src, int rows, int cols, int lds, __bf16* hi,

@@ -743,6 +743,38 @@ void pair_split_group(hipStream_t s, const PairJob* jobs, int njobs, size_t max_
   hipLaunchKernelGGL(pair_split_group_kernel, dim3((unsigned)g, njobs), dim3(256), 0, s, jobs);
 }
 
+// Grouped blocked split of transposes: job blockIdx.y writes hi / lo
+// (blocked, rows = its cols, Kp = its dcols) = split(src^T), zero for
+// k >= rows (the padding); skipped as split_transpose_group_kernel.  In the
+// blocked order the lanes of a wave read consecutive source columns.
+__global__ __launch_bounds__(256) void split_transpose_blocked_group_kernel(const SplitTArgs* tab) {
+  const SplitTArgs a = tab[blockIdx.y];
+  if (a.done && *a.done) return;
+  if (a.gate && *a.gate != 0) return;
+  const int KT = a.dcols / 32;
+  const size_t total = (size_t)blk_rows(a.cols) * (a.dcols / 8);
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    int r, k0;
+    blk_coords(e, KT, r, k0);
+    Pack8 ph, pl;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + j;
+      const double x = (r < a.cols && k < a.rows) ? a.src[(size_t)k * a.lds + r] : 0.0;
+      split_d(x, ph.b[j], pl.b[j]);
+    }
+    as_global((u4_t*)a.hi)[e] = u4_t{ph.u.x, ph.u.y, ph.u.z, ph.u.w};
+    as_global((u4_t*)a.lo)[e] = u4_t{pl.u.x, pl.u.y, pl.u.z, pl.u.w};
+  }
+}
+void split_transpose_blocked_group(hipStream_t s, const SplitTArgs* tab, int nprob, size_t max_chunks) {
+  if (nprob <= 0) return;
+  size_t g = (max_chunks + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(split_transpose_blocked_group_kernel, dim3((unsigned)g, nprob), dim3(256), 0, s, tab);
+}
+
 void pair_split_blocked(hipStream_t s, const float* p, const float* q, int ld, int rows, int cols, __bf16* hi,
                         __bf16* lo, int Kp) {
   const int rows_p = blk_rows(rows);

@@ -54,6 +54,37 @@ def test_mttkrp_general_modes(precision, tol):
         assert err <= tol
 
 
+@pytest.mark.parametrize("code", [100000, 120000, 140000])
+def test_mttkrp_split_direct_load_shapes(code):
+    """Split-BF16 MTTKRP of every mode with the direct-load 256 x 256 tiles
+    forced for all three products (split-K slices on the back-projection for
+    codes above 100000), distinct X_m and a non-symmetric Z, ragged sizes
+    that leave partial tiles: element by element against the oracle, within
+    the split bound of the products' contraction lengths times the oracle's
+    MTTKRP of absolute values."""
+    from paper_2502_17683_amd import test_split_force
+    dims, r_thc, r_cp = (300, 281, 260, 290), 600, 520
+    X, Z, init = _general(4, dims, r_thc, r_cp)
+    F = [_norm_cols(f) for f in init]
+    u = lambda K: 3 * 2.0 ** -16 + K * 2.0 ** -24
+    k = 1.001 * (3 * u(max(dims)) + 2 * u(r_thc) + 6 * 2.0 ** -24)
+    prev = test_split_force(code)
+    try:
+        cpd = _plan(X, Z, init, r_cp, precision="mixed")
+        log = cpd.autotune_log()
+        for n in range(4):
+            ref = matfree.mttkrp(X, Z, F, n)
+            A = matfree.mttkrp([np.abs(x) for x in X], np.abs(Z), [np.abs(f) for f in F], n)
+            got = cpd.mttkrp(n).cpu().numpy()
+            ratio = float(np.max(np.abs(got - ref) / (A + 1e-300)))
+            say(f"  forced {code} mode {n}: max |err| / |.|-MTTKRP {ratio:.2e} (bound {k:.2e})")
+            assert np.all(np.abs(got - ref) <= k * A)
+        cpd.close()
+    finally:
+        test_split_force(prev)
+    say(f"  autotune log: {log!r}")
+
+
 def test_mttkrp_matches_dense_bruteforce():
     """Small molecule-like input: GPU MTTKRP == G_(n) KR(others) of the
     explicitly formed tensor."""
