@@ -508,7 +508,7 @@ __device__ __forceinline__ void dma_blocks(const __bf16* base, int rb0, int KT, 
 
 __global__ __launch_bounds__(256, 1) void gemm_split_dma_kernel(const SplitArgs* tab, const int* offs, int nprob,
                                                                  int kparts) {
-  __shared__ __attribute__((aligned(1024))) __bf16 lds[2 * DSTAGE];
+  __shared__ __attribute__((aligned(1024))) __bf16 lds[10 * DHALF];
   int pid = 0;
   while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
   const SplitArgs a = tab[pid];
@@ -534,29 +534,55 @@ __global__ __launch_bounds__(256, 1) void gemm_split_dma_kernel(const SplitArgs*
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-  auto issue = [&](int kt, int st) {
-    __bf16* base = lds + st * DSTAGE;
-    dma_blocks(a.A.hi, m0 / 16, KT, kt, base, wid, lane);
-    dma_blocks(a.A.lo, m0 / 16, KT, kt, base + DHALF, wid, lane);
-    dma_blocks(a.B.hi, n0 / 16, KT, kt, base + 2 * DHALF, wid, lane);
-    dma_blocks(a.B.lo, n0 / 16, KT, kt, base + 3 * DHALF, wid, lane);
+  // Two k-tiles in flight: the row operand has two LDS stages, the column
+  // operand three.  The column operand's k-tile t + 2 is loaded during the
+  // first column tile of step t (its stage held k-tile t - 1); the row
+  // operand's k-tile t + 2 during the second, after every wave has read its
+  // fragments of k-tile t (they are all read during the first).  One load
+  // instruction follows each row's products, so that no wave stalls on a
+  // burst of loads.  Past the last k-tile the loads fetch the last k-tile
+  // again into a stage that is not read any more: the loop body stays one
+  // block and the wait counts are constants.
+  const int n = kt1 - kt0;
+  // load b of 8 (hi blocks, then lo blocks) of this wave's share of k-tile t
+  auto dma_a = [&](int t, int b) {
+    const int kt = kt0 + min(t, n - 1), rb = wid * 4 + (b & 3);
+    const __bf16* g = (b < 4 ? a.A.hi : a.A.lo) + ((size_t)(m0 / 16 + rb) * KT + kt) * 512 + lane * 8;
+    __bf16* d = lds + (t & 1) * 2 * DHALF + (b < 4 ? 0 : DHALF) + rb * 512;
+    __builtin_amdgcn_global_load_lds((glb_cvptr_t)g, (lds_vptr_t)d, 16, 0, 0);
   };
-  if (kt0 < kt1) issue(kt0, 0);
-  for (int kt = kt0; kt < kt1; ++kt) {
-    // this wave's loads of k-tile kt have landed; the barrier makes every
-    // wave's visible and ends all reads of the other stage
-    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    const __bf16* st = lds + ((kt - kt0) & 1) * DSTAGE;
-    const __bf16* Ah = st + (wm * 8) * 512 + lane * 8;
-    const __bf16* Bh = st + 2 * DHALF + (wn * 8) * 512 + lane * 8;
-    // Fragment reads.  While direct loads are in flight, a wait for an LDS
-    // read can only be a wait for all outstanding reads, so every read is
-    // issued right after the wait before it: the first column tile's and
-    // the first four row fragments, then the other row fragments four
-    // products ahead (at most 12 reads in flight before the direct loads
-    // are issued, so those waits are per read), and each later column
-    // tile's fragments right after the first products of the tile before.
+  auto dma_b = [&](int t, int st, int b) {
+    const int kt = kt0 + min(t, n - 1), rb = wid * 4 + (b & 3);
+    const __bf16* g = (b < 4 ? a.B.hi : a.B.lo) + ((size_t)(n0 / 16 + rb) * KT + kt) * 512 + lane * 8;
+    __bf16* d = lds + (4 + 2 * st) * DHALF + (b < 4 ? 0 : DHALF) + rb * 512;
+    __builtin_amdgcn_global_load_lds((glb_cvptr_t)g, (lds_vptr_t)d, 16, 0, 0);
+  };
+  if (n > 0) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) dma_a(0, b);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) dma_b(0, 0, b);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) dma_a(1, b);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) dma_b(1, 1, b);
+  }
+  int bs = 0;  // t % 3
+  for (int t = 0; t < n; ++t) {
+    // This wave's loads of k-tile t have landed (those of k-tile t + 1, 16
+    // per wave, issued after them, may still be in flight); the barrier
+    // makes every wave's visible and ends every read of step t - 1.  A
+    // plain barrier: a fenced one would wait for all loads.
+    __asm__ volatile("s_waitcnt vmcnt(16)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+    const int bs2 = bs == 0 ? 2 : bs - 1;  // (t + 2) % 3
+    const __bf16* Ah = lds + (t & 1) * 2 * DHALF + (wm * 8) * 512 + lane * 8;
+    const __bf16* Bh = lds + (4 + 2 * bs) * DHALF + (wn * 8) * 512 + lane * 8;
+    // fragment reads: the first column tile's and the first four row
+    // fragments, the other row fragments four products ahead of their use,
+    // each later column tile's right after the first products of the tile
+    // before
     bf16x8_t ah[8], al[8];
     bf16x8_t bh = *(const bf16x8_t*)Bh, bl = *(const bf16x8_t*)(Bh + DHALF);
 #pragma unroll
@@ -578,8 +604,11 @@ __global__ __launch_bounds__(256, 1) void gemm_split_dma_kernel(const SplitArgs*
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
         if (j == 0 || i == 0) __builtin_amdgcn_sched_barrier(0);
-        if (j == 0 && i == 3 && kt + 1 < kt1) {
-          issue(kt + 1, (kt + 1 - kt0) & 1);
+        if (j == 0) {
+          dma_b(t + 2, bs2, i);
+          __builtin_amdgcn_sched_barrier(0);
+        } else if (j == 1) {
+          dma_a(t + 2, i);
           __builtin_amdgcn_sched_barrier(0);
         }
         if (i == (j == 0 ? 4 : 0) && j + 1 < 8) {
@@ -588,13 +617,22 @@ __global__ __launch_bounds__(256, 1) void gemm_split_dma_kernel(const SplitArgs*
           __builtin_amdgcn_sched_barrier(0);
         }
       }
+      if (j == 0) {
+        // every wave's row fragments of k-tile t are in registers: its
+        // stage takes k-tile t + 2 from here on
+        __builtin_amdgcn_s_barrier();
+        __asm__ volatile("" ::: "memory");
+      }
       __builtin_amdgcn_sched_barrier(0);
       if (j + 1 < 8) {
         bh = nh;
         bl = nl;
       }
     }
+    bs = bs == 2 ? 0 : bs + 1;
   }
+  // no load into LDS may outlive the workgroup
+  __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
 
   const bool partial = kparts > 1;
   // the result's row and column bases are formed here, after the loop, so
