@@ -446,11 +446,16 @@ SplitCfg split_default(const std::vector<SplitArgs>& v, bool splitk, bool dma) {
   const long w256 = split_cfg_tiles(v, {256, true, 1});
   int kmin = 1 << 30;
   for (auto& g : v) kmin = g.K < kmin ? g.K : kmin;
-  // long contractions only: with K = n (the projection) the 128-column
-  // kernel was measured faster; the direct-load tiles where the blocked
-  // operands exist and they cover the compute units
-  if (dma && !splitk && split_cfg_tiles(v, {256, false, 1, true}) >= 192 && kmin >= 2048)
-    return {256, false, 1, true};
+  // The direct-load tiles wherever the blocked operands exist and the
+  // tiles (times the K slices, for a split-K product) cover the compute
+  // units with at least 256 of K per slice: measured faster than the other
+  // shapes for the core product, the projection (K = n) and the
+  // back-projection (4 K slices) alike.
+  if (dma) {
+    const long wd = split_cfg_tiles(v, {256, false, 1, true});
+    for (int k = 1; k <= (splitk ? SPLIT_KPARTS_MAX : 1); k *= 2)
+      if (wd * k >= 192 && kmin >= 256 * k) return {256, false, k, true};
+  }
   if (w256 >= 192 && kmin >= 2048) return {256, true, 1};
   if (splitk) {
     for (int k = 2; k <= SPLIT_KPARTS_MAX; k *= 2)
