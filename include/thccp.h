@@ -486,6 +486,13 @@ size_t cpd_test_solve_workspace(int32_t fp32, int32_t R, int32_t n);
  *   needs cpd_init again).  For failure-path tests only: the default never
  *   gives up on a working device.  Not thread-safe. */
 int32_t cpd_test_flow_spin_limit(int32_t polls);
+/* cpd_test_bwd_form: form of the one-level backward solve for plans and
+ *   test solves created afterwards in this process: 0 (default) two block
+ *   columns per dependency hop (a set-up launch forms the products of L it
+ *   needs into the unused upper blocks of V), 1 one block column per hop.
+ *   Any other value selects 0.  Returns the previous value.  For testing
+ *   both forms against the same reference.  Not thread-safe. */
+int32_t cpd_test_bwd_form(int32_t form);
 /* cpd_test_split_force: forces the launch shape of every split-BF16
  *   product of plans created afterwards in this process to the given shape
  *   code (the encoding of cpd_autotune_log; 0 or negative: off, the

@@ -8,6 +8,7 @@ arguments and owns the torch tensors that back the library's workspace.
 from ._lib import CpdError, load, LIB_PATH  # noqa: F401
 from .cpd import CPD, CPDBatch, lt_scale_rows, test_gemm, test_solve, test_gemm_split, df_to_thc  # noqa: F401
 from .cpd import test_flow_spin_limit  # noqa: F401
+from .cpd import test_bwd_form  # noqa: F401
 from .cpd import test_split_force  # noqa: F401
 from .lt import (lt_batch_problems, lt_exchange, lt_exchange_workspace_bytes, lt_mp2,  # noqa: F401
                  lt_mp2_workspace_bytes)

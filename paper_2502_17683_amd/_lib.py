@@ -102,6 +102,7 @@ EXPORTS = {
     "cpd_test_solve_workspace": (ctypes.c_size_t, [i32, i32, i32]),
     "cpd_test_solve": (i32, [i32, i32, i32, vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(i32), i32]),
     "cpd_test_flow_spin_limit": (i32, [i32]),
+    "cpd_test_bwd_form": (i32, [i32]),
     "cpd_test_split_force": (i32, [i32]),
     "cpd_test_split_workspace": (ctypes.c_size_t, [i32, i32, i32]),
     "cpd_test_gemm_split": (i32, [i32, i32, i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp, i32, i32, i32]),

@@ -345,6 +345,13 @@ def test_flow_spin_limit(polls):
     return int(_lib.load().cpd_test_flow_spin_limit(int(polls)))
 
 
+def test_bwd_form(form):
+    """Form of the one-level backward solve of plans and test solves
+    created afterwards: 0 (default) two block columns per dependency hop,
+    1 one per hop; returns the previous form."""
+    return int(_lib.load().cpd_test_bwd_form(int(form)))
+
+
 def test_split_force(code):
     """Forces the split-BF16 launch shape of plans created afterwards (the
     cpd_autotune_log shape code; 0: off); returns the previous code."""

@@ -11,7 +11,8 @@
 // waits on another -- and solves its own tile of the column.  In the
 // one-level form the blocks beyond column j+2 take their updates in pairs
 // (rank 128, every other step), and the backward solve is one dataflow
-// launch (STEP_BWD_FLOW, below).  After a panel, one GEMM applies its
+// launch (STEP_BWD_PAIR, two block columns per dependency hop, after its
+// set-up launch STEP_BWD_PREP; or STEP_BWD_FLOW, one per hop; below).  After a panel, one GEMM applies its
 // rank-(64 pw) update to the trailing matrix (and, in the forward
 // solve, to the right-hand sides): the trailing matrix is read and written
 // once per panel instead of once per block column.  The diagonal blocks of
@@ -931,6 +932,12 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
 // reads are issued after it has seen the flag.
 constexpr int FLOW_SPIN_LIMIT = 1 << 20;
 static int g_flow_spin_limit = FLOW_SPIN_LIMIT;  // host side, lowered only by a test hook
+static int g_bwd_form = 0;  // host side: 0 block pairs, 1 one block column per hop
+int set_bwd_form(int form) {
+  const int prev = g_bwd_form;
+  g_bwd_form = form == 1 ? 1 : 0;
+  return prev;
+}
 int set_flow_spin_limit(int polls) {
   const int prev = g_flow_spin_limit;
   g_flow_spin_limit = polls < 0 ? FLOW_SPIN_LIMIT : polls;
@@ -1092,6 +1099,245 @@ __global__ __launch_bounds__(256, 2) void bwd_flow_kernel(const StepProb<T>* pro
   __builtin_amdgcn_s_waitcnt(0);  // this wave's stores of F_k are acknowledged
   __syncthreads();
   if (tid == 0) __hip_atomic_store(as_global(flag + k), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------- backward solve in block pairs
+// The recurrence F_k = (G_k - sum_{i>k} F_i L_ik) X_k^T (X_k = L_kk^{-T})
+// taken two block columns per step: pair j holds b = nblk - 1 - 2j and
+// a = b - 1 (none when b = 0), and depends on the pair before it, c = b + 1
+// and d = b + 2, only through
+//
+//   F_b = -(R_b + F_c P_cb + F_d P_db),        R_b = acc_b X_b^T,
+//   F_a = -(acc_a X_a^T - acc_b U + F_c Q_c + F_d Q_d),
+//
+// with acc_x = -G_x + sum_{i>=b+3} F_i L_ix (the columns beyond c and d),
+// P_xb = L_xb X_b^T, S = L_ba X_a^T, U = X_b^T S and Q_x = L_xa X_a^T -
+// P_xb S (substituting F_b into the equation of F_a).  P, U and Q depend on
+// L alone: one launch forms them per pair into blocks of V's upper
+// triangle, which the factorisation leaves unused ((b, c), (b, d), (a, b),
+// (a, c), (a, d)).  The backward launch then has one workgroup per (pair,
+// row tile, block): after the last wait each applies two products (F_c
+// and F_d against its own P or Q), so the chain crosses a dependency hop
+// once per two block columns.  The a workgroup needs acc_b: the b workgroup
+// stores it in the a tile (which the a workgroup has read by then) and
+// flags it.  Ready-flag values per (row tile, block): FL_GLOADED the a
+// tile's G has been read, FL_ACCB acc_b is stored there, FL_F the block's
+// F is stored.
+constexpr int32_t FL_GLOADED = 1, FL_ACCB = 2, FL_F = 3;
+__host__ __device__ inline int bwd_pair_count(int nblk) { return (nblk + 1) / 2; }
+__host__ __device__ inline int bwd_prep_tiles(int nblk) { return 5 * bwd_pair_count(nblk); }
+
+// acc += A B with A given as register fragments: a[m] = A[16 w + lane % 16][4 m + lane / 16]
+template <typename T>
+__device__ __forceinline__ void tile_mma64_ra(typename Acc4<T>::type acc[4], const T a[16], const T* Bk, int lane) {
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int k = 4 * m + (lane >> 4);
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[tj] = mfma4(a[m], Bk[k * LDT + 16 * tj + (lane & 15)], acc[tj]);
+  }
+}
+// the A fragments of rows 16 w.. of a row-major block written in this launch
+template <typename T>
+__device__ __forceinline__ void fetch_afrag_coherent(T a[16], const T* g, size_t ld, int nrows, int lane, int w) {
+  const int row = 16 * w + (lane & 15);
+#pragma unroll
+  for (int m = 0; m < 16; ++m)
+    a[m] = row < nrows ? coherent_load<T>(g + (size_t)row * ld + 4 * m + (lane >> 4)) : T(0);
+}
+
+// One product of the pair set-up per workgroup (output o of pair j): the
+// result goes to an upper block of V.
+template <typename T>
+__global__ __launch_bounds__(256) void bwd_prep_kernel(const StepProb<T>* probs, const int* offs, int nprob) {
+  typedef typename Acc4<T>::type acc_t;
+  __shared__ T S0[TB * LDT];
+  __shared__ T S1[TB * LDT];
+  int pid = 0;
+  while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
+  const StepProb<T> q = probs[pid];
+  if (q.st->done) return;  // as the backward launch that reads the results
+  const int local = blockIdx.x - offs[pid], j = local / 5, o = local % 5;
+  const int nblk = q.nblk, Tp = nblk * TB;
+  const int b = nblk - 1 - 2 * j, a = b - 1, c = b + 1, d = b + 2;
+  const bool has_a = a >= 0, has_q = j >= 1;
+  if ((o < 2 && !has_q) || (o == 2 && !has_a) || (o > 2 && !(has_a && has_q))) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  auto blk = [&](int x, int y) { return q.V + (size_t)x * TB * Tp + (size_t)y * TB; };
+  auto xk = [&](int k) { return q.ldiag + (size_t)k * TB * TB; };
+  T ra[16], rb[16];
+  acc_t acc[4], t[4], u[4];
+  auto zero = [&](acc_t* x) {
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) x[tj] = acc_t{0, 0, 0, 0};
+  };
+  // x += L_{r,k} X_k^T
+  auto l_xt = [&](acc_t* x, int r, int k) {
+    fetch_block<T>(ra, blk(r, k), Tp, TB, tid);
+    fetch_block<T>(rb, xk(k), TB, TB, tid);
+    __syncthreads();  // every wave is past its reads of S0 / S1
+    put_block<T, true>(S0, ra, tid);  // A = L_rk
+    put_block<T, true>(S1, rb, tid);  // B = X_k^T
+    __syncthreads();
+    tile_mma64<T>(x, S0, S1, lane, w);
+  };
+  // x += y z (both accumulator tiles of this workgroup)
+  auto prod = [&](acc_t* x, const acc_t* y, const acc_t* z) {
+    __syncthreads();
+    acc_to_lds_t<T>(y, S0, lane, w);
+    acc_to_lds<T>(z, S1, lane, w);
+    __syncthreads();
+    tile_mma64<T>(x, S0, S1, lane, w);
+  };
+  zero(acc);
+  T* dst;
+  if (o < 2) {  // P_cb or P_db
+    const int x = o == 0 ? c : d;
+    l_xt(acc, x, b);
+    dst = blk(b, x);
+  } else {
+    zero(t);
+    l_xt(t, b, a);  // S
+    if (o == 2) {  // U = X_b^T S
+      fetch_block<T>(ra, xk(b), TB, TB, tid);
+      __syncthreads();
+      put_block<T, false>(S0, ra, tid);  // A = X_b^T
+      acc_to_lds<T>(t, S1, lane, w);     // B = S
+      __syncthreads();
+      tile_mma64<T>(acc, S0, S1, lane, w);
+      dst = blk(a, b);
+    } else {  // Q_x = L_xa X_a^T - P_xb S
+      const int x = o == 3 ? c : d;
+      zero(u);
+      l_xt(u, x, b);     // P_xb
+      prod(acc, u, t);   // P_xb S
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) acc[tj] = -acc[tj];
+      l_xt(acc, x, a);
+      dst = blk(a, x);
+    }
+  }
+  store_acc<T>(acc, dst, Tp, TB, lane, w);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void bwd_pair_kernel(const StepProb<T>* probs, const int* seg, int nseg,
+                                                       int spin_limit) {
+  typedef typename Acc4<T>::type acc_t;
+  __shared__ T S0[TB * LDT];
+  __shared__ T S1[TB * LDT];
+  __shared__ int stalled;
+  int pid, j, bid;  // no XCD remap: the id order is the dependency order
+  flow_segment(seg, nseg, blockIdx.x, pid, j, bid);
+  const StepProb<T> q = probs[pid];
+  DevState* const st = q.st;
+  // uniform per problem and unchanged during the launch: all or none of a
+  // problem's workgroups take part
+  if (st->done) return;
+  const int nblk = q.nblk, Tp = nblk * TB;
+  const int hb = nblk - 1 - 2 * j, ha = hb - 1, c = hb + 1, d = hb + 2;
+  const bool has_a = ha >= 0, has_q = j >= 1;
+  const int per = has_a ? 2 : 1, rt = bid / per;
+  const bool role_a = bid % per == 1;  // the b workgroup of a row tile comes first
+  const int k = role_a ? ha : hb;
+  const int r0 = rt * TB, nrows = min(TB, q.n - r0);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int32_t* const flag = q.flow + (size_t)rt * nblk;
+  T* const rowp = q.M + (size_t)r0 * Tp;
+  auto tile = [&](int x) { return rowp + (size_t)x * TB; };
+  auto vblk = [&](int x, int y) { return q.V + (size_t)x * TB * Tp + (size_t)y * TB; };
+  acc_t acc[4], f[4];
+  T rf[16], rl[16], rx[16];
+  // waits until flag i reaches want; false (for every wave) once a wait of
+  // the problem has stalled.  The barrier also means every wave is past its
+  // reads of S0 / S1.
+  auto wait_flag = [&](int i, int32_t want) -> bool {
+    if (tid == 0) {
+      int spins = 0, bad = 0;
+      while (__hip_atomic_load(as_global(flag + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+        if ((__hip_atomic_load(as_global(&st->flags), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SOLVE_STALL) ||
+            ++spins > spin_limit) {
+          __hip_atomic_fetch_or(as_global(&st->flags), (int)FLAG_SOLVE_STALL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          bad = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      stalled = bad;
+    }
+    __syncthreads();
+    return !stalled;
+  };
+  auto set_flag = [&](int i, int32_t v) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores (and loads) are complete
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(as_global(flag + i), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  // the accumulators hold -G_k so that every product adds in place
+  load_acc<T>(acc, tile(k), Tp, nrows, lane, w);
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) acc[tj] = -acc[tj];
+  if (role_a) set_flag(ha, FL_GLOADED);  // the tile may now take acc_b
+  fetch_block<T>(rx, q.ldiag + (size_t)k * TB * TB, TB, TB, tid);
+  // acc += F_i L_ik for the columns beyond the previous pair
+  const int ilo = has_q ? d + 1 : nblk;
+  if (ilo < nblk) fetch_block<T>(rl, vblk(nblk - 1, k), Tp, TB, tid);
+  for (int i = nblk - 1; i >= ilo; --i) {
+    if (!wait_flag(i, FL_F)) return;
+    fetch_block_coherent<T>(rf, tile(i), Tp, nrows, tid);
+    put_block<T, false>(S1, rl, tid);  // L_ik
+    if (i > ilo) fetch_block<T>(rl, vblk(i - 1, k), Tp, TB, tid);
+    put_block<T, true>(S0, rf, tid);  // F_i^T
+    __syncthreads();
+    tile_mma64<T>(acc, S0, S1, lane, w);
+  }
+  if (!role_a && has_a) {
+    // acc_b for the a workgroup, in its tile once its G has been read
+    if (!wait_flag(ha, FL_GLOADED)) return;
+    store_acc_coherent<T>(acc, tile(ha), Tp, nrows, lane, w);
+    set_flag(ha, FL_ACCB);
+  }
+  // f = acc X_k^T
+  __syncthreads();  // every wave is past its reads of S0 / S1
+  acc_to_lds_t<T>(acc, S0, lane, w);
+  put_block<T, true>(S1, rx, tid);  // X_k^T
+  __syncthreads();
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) f[tj] = acc_t{0, 0, 0, 0};
+  tile_mma64<T>(f, S0, S1, lane, w);
+  if (role_a) {
+    // f -= acc_b U
+    fetch_block<T>(rl, vblk(ha, hb), Tp, TB, tid);  // U
+    if (!wait_flag(ha, FL_ACCB)) return;
+    fetch_block_coherent<T>(rf, tile(ha), Tp, nrows, tid);  // acc_b
+    put_block<T, false>(S1, rl, tid);
+    put_block<T, true>(S0, rf, tid);
+    __syncthreads();
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[tj] = acc_t{0, 0, 0, 0};
+    tile_mma64<T>(acc, S0, S1, lane, w);
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) f[tj] -= acc[tj];
+  }
+  if (has_q) {
+    // f += F_c B_c + F_d B_d with B = P_cb, P_db (b) or Q_c, Q_d (a)
+    fetch_block<T>(rl, role_a ? vblk(ha, c) : vblk(hb, c), Tp, TB, tid);
+    fetch_block<T>(rx, role_a ? vblk(ha, d) : vblk(hb, d), Tp, TB, tid);
+    __syncthreads();  // every wave is past its reads of S0 / S1
+    put_block<T, false>(S0, rl, tid);
+    put_block<T, false>(S1, rx, tid);
+    if (!wait_flag(c, FL_F) || !wait_flag(d, FL_F)) return;
+    __builtin_amdgcn_s_setprio(3);  // the chain
+    T fc[16], fd[16];
+    fetch_afrag_coherent<T>(fc, tile(c), Tp, nrows, lane, w);
+    fetch_afrag_coherent<T>(fd, tile(d), Tp, nrows, lane, w);
+    tile_mma64_ra<T>(f, fc, S0, lane);
+    tile_mma64_ra<T>(f, fd, S1, lane);
+  }
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) f[tj] = -f[tj];
+  store_acc_coherent<T>(f, tile(k), Tp, nrows, lane, w);
+  set_flag(k, FL_F);
 }
 
 // ------------------------- dataflow factorisation with the forward solve
@@ -1330,6 +1576,16 @@ std::vector<int> flow_segments(int mode, const std::vector<int>& nblk, const std
     for (size_t p = 0; p < nblk.size(); ++p) {
       if (c >= nblk[p]) continue;
       const int nrt = (n[p] + TB - 1) / TB;
+      if (mode == STEP_BWD_PAIR) {
+        // segment (problem, pair c): per row tile the b workgroup, then the
+        // a workgroup (the pair's lower block, if any)
+        if (c >= bwd_pair_count(nblk[p])) continue;
+        seg.push_back(start);
+        seg.push_back((int)p);
+        seg.push_back(c);
+        start += nrt * (nblk[p] - 1 - 2 * c >= 1 ? 2 : 1);
+        continue;
+      }
       const int k = mode == STEP_BWD_FLOW ? nblk[p] - 1 - c : c;
       seg.push_back(start);
       seg.push_back((int)p);
@@ -1352,6 +1608,8 @@ int step_tiles(int mode, int nblk, int n, StepCfg c) {
     case STEP_BWD_FLOW: return nrt * nblk;
     case STEP_CFLOW_RESET: return 1;
     case STEP_CHOL_FWD_FLOW: return chol_fwd_flow_tiles(nblk, nrt);
+    case STEP_BWD_PREP: return bwd_prep_tiles(nblk);
+    case STEP_BWD_PAIR: return nrt * nblk;
     default: return bwd_tiles(nblk, nrt, c.pw, c.pf, c.tf);
   }
 }
@@ -1382,6 +1640,12 @@ void step_group(hipStream_t s, int mode, const StepProb<T>* probs, const int* of
       break;
     case STEP_CHOL_FWD_FLOW:  // offs: segment table, nprob: its segment count
       hipLaunchKernelGGL((chol_fwd_flow_kernel<T>), grid, block, 0, s, probs, offs, nprob, g_flow_spin_limit);
+      break;
+    case STEP_BWD_PREP:
+      hipLaunchKernelGGL((bwd_prep_kernel<T>), grid, block, 0, s, probs, offs, nprob);
+      break;
+    case STEP_BWD_PAIR:  // offs: segment table, nprob: its segment count
+      hipLaunchKernelGGL((bwd_pair_kernel<T>), grid, block, 0, s, probs, offs, nprob, g_flow_spin_limit);
       break;
     default:
       hipLaunchKernelGGL((step_kernel<T, STEP_CHOL_FWD>), grid, block, 0, s, probs, offs, nprob, cfg,
@@ -1458,9 +1722,15 @@ std::vector<SolveItem> solve_schedule(int sched, int max_nblk, int pw) {
       break;
     default:
       if (P == 1) {
-        // one level: the whole solve as one dataflow launch
+        // one level: the whole solve as one dataflow launch, in block pairs
+        // after their set-up launch, or one block column per hop
         step(STEP_FLOW_RESET, -1, 0, 0, 0);
-        step(STEP_BWD_FLOW, -1, 0, 0, 0);
+        if (g_bwd_form == 0) {
+          step(STEP_BWD_PREP, -1, 0, 0, 0);
+          step(STEP_BWD_PAIR, -1, 0, 0, 0);
+        } else {
+          step(STEP_BWD_FLOW, -1, 0, 0, 0);
+        }
         break;
       }
       for (int p = P - 1; p >= 0; --p) {

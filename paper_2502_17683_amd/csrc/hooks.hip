@@ -150,6 +150,7 @@ size_t cpd_test_solve_workspace(int32_t fp32, int32_t R, int32_t n) {
 }
 
 int32_t cpd_test_flow_spin_limit(int32_t polls) { return set_flow_spin_limit(polls); }
+int32_t cpd_test_bwd_form(int32_t form) { return set_bwd_form(form); }
 
 cpd_status cpd_test_solve(int32_t fp32, int32_t R, int32_t n, const void* V, const void* M, void* F,
                           void* workspace, size_t ws_bytes, void* stream, int32_t* failed, int32_t panel) {

@@ -106,7 +106,9 @@ enum StepMode {
   STEP_FLOW_RESET = 4,     // clears the solve's ready flags (one workgroup per problem)
   STEP_BWD_FLOW = 5,       // the whole one-level backward solve as one dataflow launch
   STEP_CFLOW_RESET = 6,    // clears the factorisation's and the solve's ready flags
-  STEP_CHOL_FWD_FLOW = 7   // one-level factorisation + forward solve as one dataflow launch
+  STEP_CHOL_FWD_FLOW = 7,  // one-level factorisation + forward solve as one dataflow launch
+  STEP_BWD_PREP = 8,       // per pair of block columns, the products of L the paired solve needs
+  STEP_BWD_PAIR = 9        // the one-level backward solve as one dataflow launch, in block pairs
 };
 
 // Two-level blocking: the 64-wide block columns are grouped into panels of
@@ -131,17 +133,29 @@ inline int panel_count(int nblk, int pw) { return (nblk + pw - 1) / pw; }
 // Workgroups of problem (nblk, n) in a launch of `mode` with `cfg`.
 int step_tiles(int mode, int nblk, int n, StepCfg cfg);
 // Workgroup order of a grouped dataflow launch (STEP_CHOL_FWD_FLOW,
-// STEP_BWD_FLOW) over problems of nblk[p] blocks and n[p] rows: segments of
-// one (problem, block column), block column by block column across the
-// problems (ascending for the factorisation, from each problem's last
-// column down for the backward solve), so every problem advances at the
-// same pace and every wait is on a lower workgroup id.  Int triples
-// (first workgroup, problem, column), then (total workgroups, -1, -1).
+// STEP_BWD_FLOW, STEP_BWD_PAIR) over problems of nblk[p] blocks and n[p]
+// rows: segments of one (problem, block column), block column by block
+// column across the problems (ascending for the factorisation, from each
+// problem's last column down for the backward solve), so every problem
+// advances at the same pace and every wait is on a lower workgroup id.
+// STEP_BWD_PAIR: segments of one (problem, pair of block columns), pairs
+// from the last column down; per row tile the workgroup of the pair's upper
+// block, then that of its lower block.  The one wait on a higher id is the
+// upper block's wait for the lower block's first action (its right-hand
+// side read), which waits on nothing.  Int triples (first workgroup,
+// problem, column or pair), then (total workgroups, -1, -1).
 std::vector<int> flow_segments(int mode, const std::vector<int>& nblk, const std::vector<int>& n);
-inline bool is_flow_mode(int mode) { return mode == STEP_CHOL_FWD_FLOW || mode == STEP_BWD_FLOW; }
+inline bool is_flow_mode(int mode) {
+  return mode == STEP_CHOL_FWD_FLOW || mode == STEP_BWD_FLOW || mode == STEP_BWD_PAIR;
+}
 // Polls a dataflow wait makes before it gives up (negative: the default);
 // returns the previous value.  Applies to launches enqueued afterwards.
 int set_flow_spin_limit(int polls);
+// Form of the one-level backward solve for schedules built afterwards:
+// 0 (default) two block columns per dependency hop (STEP_BWD_PREP +
+// STEP_BWD_PAIR), 1 one block column per hop (STEP_BWD_FLOW); returns the
+// previous value.
+int set_bwd_form(int form);
 // Launches one step of `mode`.  offs: nprob + 1 prefix sums of the
 // problems' workgroups, or for a dataflow mode the segment table, with
 // nprob its segment count.
@@ -169,8 +183,9 @@ bool panel_gemm(int kind, const StepProb<T>& q, int pw, int p, GemmArgs<T>& g);
 //                   forward update of panel p - 1.  One-level (pw >=
 //                   max_nblk): one block column behind.
 //   SCHED_FWD       forward solve alone;  SCHED_BWD  backward solve (panels
-//                   from the last one down; one level: a flag reset and one
-//                   dataflow launch, STEP_BWD_FLOW).
+//                   from the last one down; one level: a flag reset, then
+//                   STEP_BWD_PREP and the dataflow launch STEP_BWD_PAIR, or
+//                   the dataflow launch STEP_BWD_FLOW; set_bwd_form).
 enum SolveSched { SCHED_CHOL = 0, SCHED_CHOL_FWD = 1, SCHED_FWD = 2, SCHED_BWD = 3 };
 struct SolveItem {
   int mode;

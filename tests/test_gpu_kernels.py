@@ -83,6 +83,33 @@ def test_spd_solve(R, n, panel, fp32):
     assert rel_err(F, ref) <= 50 * R * cond * eps
 
 
+@pytest.mark.parametrize("R,n", [(60, 20), (100, 45), (150, 64), (250, 130), (300, 200), (1000, 70), (1030, 130)])
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_spd_solve_bwd_forms(R, n, form, fp32):
+    """The one-level backward solve in block pairs (form 0) and one block
+    column per hop (form 1): block counts 1 to 17, odd and even (an odd
+    count leaves the first block column unpaired), ragged row tiles."""
+    from paper_2502_17683_amd import test_bwd_form, test_solve
+    say(f"solve bwd form={form} R={R} n={n} fp32={fp32}")
+    rng = np.random.default_rng(R + 7 * n)
+    A = rng.standard_normal((R, R + 5))
+    V = A @ A.T / R + 0.5 * np.eye(R)
+    M = rng.standard_normal((n, R))
+    dt = torch.float32 if fp32 else torch.float64
+    prev = test_bwd_form(form)
+    try:
+        F, failed = test_solve(to_dev(V, dt), to_dev(M, dt))
+    finally:
+        test_bwd_form(prev)
+    assert not failed
+    F = F.cpu().numpy()
+    ref = np.linalg.solve(V, M.T).T
+    cond = np.linalg.cond(V)
+    eps = 6e-8 if fp32 else 1.1e-16
+    assert rel_err(F, ref) <= 50 * R * cond * eps
+
+
 def test_spd_solve_detects_indefinite():
     from paper_2502_17683_amd import test_solve
     R = 100
