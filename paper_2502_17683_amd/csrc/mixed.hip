@@ -485,25 +485,15 @@ void gemm_split_reduce_group(hipStream_t s, const SplitArgs* tab, int nprob, int
 // fragment order (lane l of a fragment read: row l % 16, k chunk l / 16),
 // so one direct-load instruction of a wave copies one block from memory to
 // LDS unchanged and a fragment read is one contiguous kilobyte of LDS.
-// Two stages (64 KB each): the next k-tile is in flight while the current
-// one is multiplied; one barrier per k-tile.  Rows are padded to the tile
-// with zeros, so no row is clamped.
+// The 160 KB of LDS hold five operand stages of 32 KB (hi and lo of 256
+// rows x 32 k): two of the row operand and three of the column operand,
+// so that two k-tiles are in flight while one is multiplied.  Rows are padded to the tile with zeros, so no row is
+// clamped.
 namespace {
 typedef __attribute__((address_space(3))) void* lds_vptr_t;
 typedef const __attribute__((address_space(1))) void* glb_cvptr_t;
-constexpr int DT = 256;              // tile edge
-constexpr int DHALF = DT * SBK;      // bf16 per operand half per k-tile
-constexpr int DSTAGE = 4 * DHALF;    // A hi, A lo, B hi, B lo
-
-// this wave's 4 of the tile's 16 row blocks of one operand half, k-tile kt
-__device__ __forceinline__ void dma_blocks(const __bf16* base, int rb0, int KT, int kt, __bf16* dst, int w, int lane) {
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int rb = w * 4 + b;
-    const __bf16* g = base + ((size_t)(rb0 + rb) * KT + kt) * 512 + lane * 8;
-    __builtin_amdgcn_global_load_lds((glb_cvptr_t)g, (lds_vptr_t)(dst + rb * 512), 16, 0, 0);
-  }
-}
+constexpr int DT = 256;          // tile edge
+constexpr int DHALF = DT * SBK;  // bf16 per operand half per k-tile
 }  // namespace
 
 __global__ __launch_bounds__(256, 1) void gemm_split_dma_kernel(const SplitArgs* tab, const int* offs, int nprob,
