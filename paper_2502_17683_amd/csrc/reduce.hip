@@ -13,36 +13,59 @@ namespace thccp {
 // on the retry pass.  blockIdx.y selects the problem.  V is symmetric and
 // the factorisation reads only its lower 64 x 64 blocks (diagonal blocks
 // whole), so only those are formed; the Grams are computed on the lower
-// tiles only, which cover them.
+// tiles only, which cover them.  One workgroup per lower block (row-major
+// order: block row r holds r + 1 blocks), two adjacent elements per thread
+// and step.
 template <typename T>
 __global__ __launch_bounds__(256) void form_V_kernel(const FormVArgs<T>* tab, int retry_pass) {
   const FormVArgs<T> a = tab[blockIdx.y];
   DevState* st = a.st;
   if (st->done) return;
   if (retry_pass && !st->retry_active) return;
+  const int nb = a.Tp / 64, b = blockIdx.x;
+  if (b >= nb * (nb + 1) / 2) return;
+  int r = (int)((sqrtf(8.f * (float)b + 1.f) - 1.f) * 0.5f);
+  while ((r + 1) * (r + 2) / 2 <= b) ++r;
+  while (r * (r + 1) / 2 > b) --r;
+  const int c = b - r * (r + 1) / 2;
   const T mu = retry_pass ? (T)st->mu : T(0);
-  const int Tp = a.Tp, R = a.R;
-  const size_t total = (size_t)Tp * Tp;
-  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
-    const int i = (int)(e / Tp), j = (int)(e % Tp);
-    if ((j >> 6) > (i >> 6)) continue;
-    T v;
-    if (i < R && j < R) {
-      v = as_global(a.g0)[e] * as_global(a.g1)[e] * as_global(a.g2)[e];
-      if (i == j) v += mu;
+  const int R = a.R;
+  typedef T v2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int idx = threadIdx.x + 256 * e;
+    const int i = 64 * r + (idx >> 5), j = 64 * c + 2 * (idx & 31);
+    const size_t off = (size_t)i * a.Tp + j;
+    v2 v;
+    if (i < R && j + 1 < R) {
+      const v2 x = *(const gptr<const v2>)(as_global(a.g0) + off);
+      const v2 y = *(const gptr<const v2>)(as_global(a.g1) + off);
+      const v2 z = *(const gptr<const v2>)(as_global(a.g2) + off);
+      v = x * y * z;
+      if (i == j) v.x += mu;
+      if (i == j + 1) v.y += mu;
     } else {
-      v = (i == j) ? T(1) : T(0);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int jj = j + h;
+        T t;
+        if (i < R && jj < R) {
+          t = as_global(a.g0)[off + h] * as_global(a.g1)[off + h] * as_global(a.g2)[off + h];
+          if (i == jj) t += mu;
+        } else {
+          t = (i == jj) ? T(1) : T(0);
+        }
+        v[h] = t;
+      }
     }
-    as_global(a.V)[e] = v;
+    *(gptr<v2>)(as_global(a.V) + off) = v;
   }
 }
 
 template <typename T>
 void form_v_group(hipStream_t s, const FormVArgs<T>* tab, int nprob, int max_Tp, int retry_pass) {
-  const size_t total = (size_t)max_Tp * max_Tp;
-  int grid = (int)((total + 255) / 256);
-  if (grid > 2048) grid = 2048;
-  hipLaunchKernelGGL((form_V_kernel<T>), dim3(grid, nprob), dim3(256), 0, s, tab, retry_pass);
+  const int nb = max_Tp / 64;
+  hipLaunchKernelGGL((form_V_kernel<T>), dim3(nb * (nb + 1) / 2, nprob), dim3(256), 0, s, tab, retry_pass);
 }
 
 // After the first factorisation pass: arm the damped retry (mu = 1e-12
