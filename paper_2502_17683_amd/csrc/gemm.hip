@@ -189,11 +189,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> p) {
 }
 
 // Grouped form: workgroup -> (problem, local tile) through the prefix sums.
-// The FP64 64-tiles without a Hadamard operand fit four workgroups per
-// compute unit (<= 128 registers, the accumulators in VGPRs): the
-// lower-triangle Gram at R = 4000 is then ~2 rounds of its 2016 tiles.
+// The FP64 64-tiles fit four workgroups per compute unit (<= 128
+// registers, the accumulators in VGPRs; with a Hadamard operand a few
+// values spill): the lower-triangle Gram at R = 4000 is then ~2 rounds of
+// its 2016 tiles, and the back-projection's 819 tiles at n = 800 all
+// resident at once.
 template <typename T, int BM, int BN, bool AT, bool BT, bool HAD>
-__global__ __launch_bounds__(256, (BM == 64 && sizeof(T) == 8 && !HAD) ? 4 : 1) void gemm_group_kernel(
+__global__ __launch_bounds__(256, (BM == 64 && sizeof(T) == 8) ? 4 : 1) void gemm_group_kernel(
     const GemmArgs<T>* tab, const int* offs, int nprob) {
   int pid = 0;
   while (pid + 1 < nprob && (int)blockIdx.x >= offs[pid + 1]) ++pid;
