@@ -203,25 +203,29 @@ def test_checkpoint_resume_bitwise():
 
 
 def test_fp32_error_report():
-    """Plain FP32 (Cholesky included): per-sweep fit error vs FP64 stated."""
+    """Plain FP32 (Cholesky included): per-sweep fit error vs FP64 stated,
+    within the 1e-4 'same fit' tolerance over the first 10 sweeps (measured
+    on one MI355X: <= 5.5e-6)."""
     X, Z = make_thc(200, 1000, 0)
     init = init_factors([200] * 4, 1000, 1000)
     f64 = np.array(_plan(X, Z, init, 1000, tol=0.0).sweep(10))
     f32 = np.array(_plan(X, Z, init, 1000, tol=0.0, precision="fp32").sweep(10))
     err = np.abs(f32 - f64) / f64
     say(f"fp32 per-sweep fit error vs fp64: {err}")
-    assert np.all(err <= 1e-3)
+    assert np.all(err <= 1e-4)
 
 
 def test_mixed_error_report():
-    """Split BF16: fit (evaluated in FP64) per sweep vs the FP64 run."""
+    """Split BF16: fit (evaluated in FP64) per sweep vs the FP64 run, within
+    the 1e-4 'same fit' tolerance over the first 10 sweeps (measured: <=
+    2.3e-6)."""
     X, Z = make_thc(200, 1000, 0)
     init = init_factors([200] * 4, 1000, 1000)
     f64 = np.array(_plan(X, Z, init, 1000, tol=0.0).sweep(10))
     fmx = np.array(_plan(X, Z, init, 1000, tol=0.0, precision="mixed").sweep(10))
     err = np.abs(fmx - f64) / f64
     say(f"mixed per-sweep fit error vs fp64: {err}")
-    assert np.all(err <= 1e-3)
+    assert np.all(err <= 1e-4)
 
 
 def test_mixed_fit_every():
