@@ -111,7 +111,9 @@ void retry_prepare_group(hipStream_t s, const FormVArgs<T>* tab, int nprob, int 
 // Column norms lambda_k of the solved factor, F = Msol / lambda, and (for
 // the fit) the per-column partial sums of Msol o Msave.  One workgroup per
 // 16 columns (~R/16 workgroups, enough to keep HBM busy); 16 row groups
-// reduced in a fixed order.
+// reduced in a fixed order.  A thread's rows are read 16 at a time before
+// they are summed (in row order), so that each thread has 16 loads in
+// flight instead of waiting on one load per row.
 template <typename T>
 __global__ __launch_bounds__(256) void normalise_kernel(const NormArgs<T>* tab) {
   __shared__ double ss[16][16];
@@ -123,13 +125,23 @@ __global__ __launch_bounds__(256) void normalise_kernel(const NormArgs<T>* tab) 
   if (blockIdx.x * 16 >= a.R) return;
   const int n = a.n, R = a.R, ld = a.ld;
   const gptr<const T> Msol = as_global(a.Msol), Msave = as_global(a.Msave);
+  constexpr int NB = 16;
   double x = 0.0, y = 0.0;
   if (col < R) {
-#pragma unroll 4
-    for (int s = g; s < n; s += 16) {
-      const double v = (double)Msol[(size_t)s * ld + col];
-      x += v * v;
-      if (a.Msave) y += v * (double)Msave[(size_t)s * ld + col];
+    for (int s0 = g; s0 < n; s0 += 16 * NB) {
+      T v[NB], m[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int s = s0 + 16 * u;
+        v[u] = s < n ? Msol[(size_t)s * ld + col] : T(0);
+        m[u] = (a.Msave && s < n) ? Msave[(size_t)s * ld + col] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const double dv = (double)v[u];
+        x += dv * dv;
+        if (a.Msave) y += dv * (double)m[u];
+      }
     }
   }
   ss[g][c] = x;
@@ -144,10 +156,18 @@ __global__ __launch_bounds__(256) void normalise_kernel(const NormArgs<T>* tab) 
   const double nrm = sqrt(n2);
   if (col < R) {
     const double scale = nrm > 0.0 ? 1.0 / nrm : 1.0;
-#pragma unroll 4
-    for (int s = g; s < n; s += 16) {
-      const size_t off = (size_t)s * ld + col;
-      as_global(a.F)[off] = (T)((double)Msol[off] * scale);
+    for (int s0 = g; s0 < n; s0 += 16 * NB) {
+      T v[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int s = s0 + 16 * u;
+        v[u] = s < n ? Msol[(size_t)s * ld + col] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int s = s0 + 16 * u;
+        if (s < n) as_global(a.F)[(size_t)s * ld + col] = (T)((double)v[u] * scale);
+      }
     }
     if (g == 0) {
       a.lam[col] = (T)nrm;
