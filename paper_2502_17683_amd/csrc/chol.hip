@@ -1379,7 +1379,7 @@ __host__ __device__ inline int chol_fwd_flow_tiles(int nblk, int nrt) { return n
 template <typename T>
 __global__ __launch_bounds__(256) void cflow_reset_kernel(const StepProb<T>* probs) {
   const StepProb<T>& q = probs[blockIdx.x];
-  const int nf = ((q.n + TB - 1) / TB) * q.nblk, nc = (q.nblk + 2) * q.nblk;
+  const int nf = ((q.n + TB - 1) / TB) * q.nblk, nc = (q.nblk + 2) * q.nblk + CU_SLOTS;
   const gptr<int32_t> f = as_global(q.flow), c = as_global(q.cflow);
   for (int e = threadIdx.x; e < nf; e += 256) f[e] = 0;
   for (int e = threadIdx.x; e < nc; e += 256) c[e] = 0;
@@ -1429,6 +1429,35 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
     __syncthreads();
     return !stalled;
   };
+  // The compute unit this workgroup runs on, and its counter of the
+  // chain's workgroups (a tile of the current block column between its
+  // last wait and its publication) running there: their dependent FP64
+  // steps slow down several times beside another wave's matrix
+  // instructions on the same SIMD, so accumulating workgroups hold back
+  // their next product while the counter is set (bounded).
+  const unsigned hw_id = __builtin_amdgcn_s_getreg((31 << 11) | 4);    // HW_ID
+  const unsigned xcc_id = __builtin_amdgcn_s_getreg((31 << 11) | 20);  // XCC_ID
+  int32_t* const cu_busy = q.cflow + (nblk + 2) * nblk +
+                           (int)(((xcc_id & 7u) << 8) | (((hw_id >> 13) & 7u) << 5) | (((hw_id >> 12) & 1u) << 4) |
+                                 ((hw_id >> 8) & 15u));
+  // a wait for one or two flags that then holds back while a chain
+  // workgroup runs on this unit
+  auto wait_acc = [&](const int32_t* a, const int32_t* b) -> bool {
+    if (tid == 0) {
+      stalled = !(spin(a) && (b == nullptr || spin(b)));
+      for (int s = 0; s < 32 && __hip_atomic_load(as_global(cu_busy), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0;
+           ++s)
+        __builtin_amdgcn_s_sleep(8);
+    }
+    __syncthreads();
+    return !stalled;
+  };
+  auto chain_begin = [&]() {
+    if (tid == 0) __hip_atomic_fetch_add(as_global(cu_busy), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  auto chain_end = [&]() {
+    if (tid == 0) __hip_atomic_fetch_add(as_global(cu_busy), -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
   auto publish = [&](int32_t* f) {
     __builtin_amdgcn_s_waitcnt(0);  // this wave's stores are acknowledged
     __syncthreads();
@@ -1447,7 +1476,7 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
     for (int j = 0; j + 1 < k; ++j) {  // columns j <= k - 2
-      if (!wait(lfl + i * nblk + j, diag ? nullptr : lfl + k * nblk + j)) return;
+      if (!wait_acc(lfl + i * nblk + j, diag ? nullptr : lfl + k * nblk + j)) return;
       fetch_block_coherent<T>(ra, blk(i, j), Tp, TB, tid);
       if (!diag) fetch_block_coherent<T>(rb, blk(k, j), Tp, TB, tid);
       put_block<T, true>(S0, ra, tid);
@@ -1475,6 +1504,7 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
       // column k - 1: the own tile and D_k
       if (!wait(lfl + i * nblk + k - 1, diag ? nullptr : lfl + k * nblk + k - 1)) return;
       __builtin_amdgcn_s_setprio(3);  // the chain
+      if (!diag) chain_begin();
       fetch_block_coherent<T>(rb, blk(k, k - 1), Tp, TB, tid);
       if (!diag) fetch_block_coherent<T>(ra, blk(i, k - 1), Tp, TB, tid);
       put_block<T, true>(S1, rb, tid);
@@ -1510,6 +1540,7 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
 #pragma unroll
         for (int u = 0; u < 16; ++u) coherent_store<T>(tile + (size_t)sr * Tp + q0 + 4 * u, e[u]);
         publish(lfl + i * nblk + k);
+        if (k >= 1) chain_end();
         return;
       }
     }
@@ -1521,6 +1552,7 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
       b4_fwd<T>(s, S1, invd, bj);
       store_b4_coherent<T>(s, tile, Tp, bg, bj);
       publish(lfl + i * nblk + k);
+      if (k >= 1) chain_end();
       return;
     }
     // the diagonal workgroup: L_kk, and X_k = L_kk^{-T} for the forward solve
@@ -1545,7 +1577,7 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
   for (int j = 0; j < k; ++j) {
-    if (!wait(gfl + j, lfl + k * nblk + j)) return;
+    if (!wait_acc(gfl + j, lfl + k * nblk + j)) return;
     fetch_block_coherent<T>(ra, q.M + (size_t)r0 * Tp + (size_t)j * TB, Tp, nrows, tid);  // G_j
     fetch_block_coherent<T>(rb, blk(k, j), Tp, TB, tid);                                 // L_kj
     put_block<T, true>(S0, ra, tid);

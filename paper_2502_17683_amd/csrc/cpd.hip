@@ -234,7 +234,7 @@ void carve_typed(Layout& L, Prob& q, Bufs<T>& b, bool own_inputs) {
   b.diagL = (T*)L.take(sizeof(T) * (size_t)Tp);
   b.lam = (T*)L.take(sizeof(T) * (size_t)Tp);
   b.flow = (int32_t*)L.take(sizeof(int32_t) * (size_t)((q.nmax + 63) / 64) * q.nblk);
-  b.cflow = (int32_t*)L.take(sizeof(int32_t) * (size_t)(q.nblk + 2) * q.nblk);
+  b.cflow = (int32_t*)L.take(sizeof(int32_t) * ((size_t)(q.nblk + 2) * q.nblk + CU_SLOTS));
   b.dpart = (T*)L.take(sizeof(T) * (size_t)q.nblk * 64 * 64);
 }
 

@@ -57,7 +57,7 @@ size_t solve_ws(int R, int n) {
   return al(sizeof(DevState)) + al(sizeof(T) * (size_t)Tp * Tp) + al(sizeof(T) * (size_t)nblk * 4096) +
          al(sizeof(T) * Tp) + al(sizeof(T) * (size_t)n * Tp) + al(sizeof(StepProb<T>)) + al(sizeof(int) * 3 * (nblk + 1)) +
          al(sizeof(GemmArgs<T>)) + al(sizeof(int32_t) * (size_t)((n + 63) / 64) * nblk) +
-         al(sizeof(int32_t) * (size_t)(nblk + 2) * nblk) + al(sizeof(T) * (size_t)nblk * 4096);
+         al(sizeof(int32_t) * ((size_t)(nblk + 2) * nblk + CU_SLOTS)) + al(sizeof(T) * (size_t)nblk * 4096);
 }
 
 // One-problem run of the blocked factorisation, forward and backward solves
@@ -76,7 +76,7 @@ cpd_status solve_impl(int R, int n, const T* V, const T* M, T* F, void* ws, hipS
   int* offs = (int*)b; b += al(sizeof(int) * 3 * (nblk + 1));
   GemmArgs<T>* gtab = (GemmArgs<T>*)b; b += al(sizeof(GemmArgs<T>));
   int32_t* flow = (int32_t*)b; b += al(sizeof(int32_t) * (size_t)((n + 63) / 64) * nblk);
-  int32_t* cflow = (int32_t*)b; b += al(sizeof(int32_t) * (size_t)(nblk + 2) * nblk);
+  int32_t* cflow = (int32_t*)b; b += al(sizeof(int32_t) * ((size_t)(nblk + 2) * nblk + CU_SLOTS));
   T* dpart = (T*)b;
   hipLaunchKernelGGL(init_state, dim3(1), dim3(64), 0, s, st);
   hipLaunchKernelGGL((pad_square<T>), dim3(grid_of((size_t)Tp * Tp)), dim3(256), 0, s, V, R, Tp, Vp);

@@ -95,9 +95,13 @@ struct StepProb {
   int nblk;
   int n;
   int32_t* flow;   // ready flags of the dataflow solves, ceil(n / 64) x nblk
-  int32_t* cflow;  // ready flags of the dataflow factorisation, nblk^2 + 2 nblk
+  int32_t* cflow;  // ready flags of the dataflow factorisation, nblk^2 + 2 nblk,
+                   // then CU_SLOTS per-compute-unit counters
   T* dpart;        // diagonal blocks updated through column k - 2, nblk x 64 x 64
 };
+// Per-compute-unit counters of the dataflow factorisation (an XCC, shader
+// engine, shader array and CU index from the hardware id registers).
+constexpr int CU_SLOTS = 2048;
 enum StepMode {
   STEP_CHOL = 0,
   STEP_FWD = 1,
