@@ -932,6 +932,29 @@ __global__ __launch_bounds__(256) void step_kernel(const StepProb<T>* probs, con
 // reads are issued after it has seen the flag.
 constexpr int FLOW_SPIN_LIMIT = 1 << 20;
 static int g_flow_spin_limit = FLOW_SPIN_LIMIT;  // host side, lowered only by a test hook
+
+// Polls until *a >= want, and *b >= want when b is given.  Each poll
+// issues the loads of both flags and of the problem's status word
+// together, so it costs one memory round trip, and a second flag that is
+// already set costs nothing more.  Gives up (setting FLAG_SOLVE_STALL, for
+// every other wait of the problem to follow) once the problem has stalled
+// or after spin_limit polls that found a flag unset.
+__device__ __forceinline__ bool poll_flags(const int32_t* a, const int32_t* b, int32_t want, DevState* st,
+                                           int spin_limit) {
+  const auto pa = as_global(a), pb = as_global(b != nullptr ? b : a);
+  const auto ps = as_global(&st->flags);
+  for (int spins = 0;; ++spins) {
+    const int32_t va = __hip_atomic_load(pa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t vb = __hip_atomic_load(pb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t fl = __hip_atomic_load(ps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (va >= want && vb >= want) return true;
+    if ((fl & FLAG_SOLVE_STALL) || spins >= spin_limit) {
+      __hip_atomic_fetch_or(ps, (int)FLAG_SOLVE_STALL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
 static int g_bwd_form = 0;  // host side: 0 block pairs, 1 one block column per hop
 int set_bwd_form(int form) {
   const int prev = g_bwd_form;
@@ -1041,19 +1064,7 @@ __global__ __launch_bounds__(256, 2) void bwd_flow_kernel(const StepProb<T>* pro
   // once a wait of the problem has stalled.  The barrier also means every
   // wave is past its reads of S0 / S1 for the previous product.
   auto wait_ready = [&](int i) -> bool {
-    if (tid == 0) {
-      int spins = 0, bad = 0;
-      while (__hip_atomic_load(as_global(flag + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        if ((__hip_atomic_load(as_global(&st->flags), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SOLVE_STALL) ||
-            ++spins > spin_limit) {
-          __hip_atomic_fetch_or(as_global(&st->flags), (int)FLAG_SOLVE_STALL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          bad = 1;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-      stalled = bad;
-    }
+    if (tid == 0) stalled = !poll_flags(flag + i, nullptr, 1, st, spin_limit);
     __syncthreads();
     return !stalled;
   };
@@ -1252,19 +1263,13 @@ __global__ __launch_bounds__(256, 2) void bwd_pair_kernel(const StepProb<T>* pro
   // the problem has stalled.  The barrier also means every wave is past its
   // reads of S0 / S1.
   auto wait_flag = [&](int i, int32_t want) -> bool {
-    if (tid == 0) {
-      int spins = 0, bad = 0;
-      while (__hip_atomic_load(as_global(flag + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
-        if ((__hip_atomic_load(as_global(&st->flags), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SOLVE_STALL) ||
-            ++spins > spin_limit) {
-          __hip_atomic_fetch_or(as_global(&st->flags), (int)FLAG_SOLVE_STALL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          bad = 1;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-      stalled = bad;
-    }
+    if (tid == 0) stalled = !poll_flags(flag + i, nullptr, want, st, spin_limit);
+    __syncthreads();
+    return !stalled;
+  };
+  // ... for two flags polled together
+  auto wait_flag2 = [&](int i, int i2, int32_t want) -> bool {
+    if (tid == 0) stalled = !poll_flags(flag + i, flag + i2, want, st, spin_limit);
     __syncthreads();
     return !stalled;
   };
@@ -1326,7 +1331,7 @@ __global__ __launch_bounds__(256, 2) void bwd_pair_kernel(const StepProb<T>* pro
     __syncthreads();  // every wave is past its reads of S0 / S1
     put_block<T, false>(S0, rl, tid);
     put_block<T, false>(S1, rx, tid);
-    if (!wait_flag(c, FL_F) || !wait_flag(d, FL_F)) return;
+    if (!wait_flag2(c, d, FL_F)) return;
     __builtin_amdgcn_s_setprio(3);  // the chain
     T fc[16], fd[16];
     fetch_afrag_coherent<T>(fc, tile(c), Tp, nrows, lane, w);
@@ -1385,6 +1390,26 @@ __global__ __launch_bounds__(256) void cflow_reset_kernel(const StepProb<T>* pro
   for (int e = threadIdx.x; e < nc; e += 256) c[e] = 0;
 }
 
+// D -= L L^T on the lower 16 x 16 tiles of a 64 x 64 block only (the
+// factorisation reads no entry above the diagonal), spread over the waves
+// so that none takes more than seven tile products together with the four
+// of its rows of the tile update: wave W forms tiles (W, tj), tj <= W,
+// except (3, 0), which wave 0 forms (into qx) for wave 3.  Lk is the block
+// in k-major form, as tile_mma64 reads it; the products run over k in the
+// same order, so each tile is bitwise the one tile_mma64 forms.
+template <typename T, int W>
+__device__ __forceinline__ void lower_llt(typename Acc4<T>::type q[4], typename Acc4<T>::type& qx, const T* Lk,
+                                          int lane) {
+#pragma unroll 4
+  for (int kk = 0; kk < TB; kk += 4) {
+    const T* row = Lk + (kk + (lane >> 4)) * LDT + (lane & 15);
+    const T a = row[16 * W];
+#pragma unroll
+    for (int tj = (W == 3 ? 1 : 0); tj <= W; ++tj) q[tj] = mfma4(a, row[16 * tj], q[tj]);
+    if constexpr (W == 0) qx = mfma4(row[48], row[0], qx);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>* probs, const int* seg,
                                                                int nseg, int spin_limit) {
@@ -1405,27 +1430,16 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
   if (st->done) return;
   const int nblk = q.nblk, Tp = nblk * TB, nrt = (q.n + TB - 1) / TB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wu = __builtin_amdgcn_readfirstlane(w);  // wave-uniform
   const int sr = tid >> 2, q0 = tid & 3;   // strip layout (diagonal factorisation)
   const int bg = tid >> 4, bj = tid & 15;  // block-4 layout (triangular solves)
   int32_t* const lfl = q.cflow;                // [i nblk + j]: L_ij stored
   int32_t* const dfl = q.cflow + nblk * nblk;  // [k]: D_k through column k - 2 stored
   int32_t* const xfl = dfl + nblk;             // [k]: X_k stored
-  auto spin = [&](const int32_t* f) -> bool {
-    int spins = 0;
-    while (__hip_atomic_load(as_global(f), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-      if ((__hip_atomic_load(as_global(&st->flags), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SOLVE_STALL) ||
-          ++spins > spin_limit) {
-        __hip_atomic_fetch_or(as_global(&st->flags), (int)FLAG_SOLVE_STALL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    return true;
-  };
   // waits for one or two flags; false (for every wave) once the problem has
   // stalled.  The barrier also means every wave is past its reads of S0 / S1.
   auto wait = [&](const int32_t* a, const int32_t* b) -> bool {
-    if (tid == 0) stalled = !(spin(a) && (b == nullptr || spin(b)));
+    if (tid == 0) stalled = !poll_flags(a, b, 1, st, spin_limit);
     __syncthreads();
     return !stalled;
   };
@@ -1446,7 +1460,7 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
   // workgroup runs on this unit
   auto wait_acc = [&](const int32_t* a, const int32_t* b) -> bool {
     if (tid == 0) {
-      stalled = !(spin(a) && (b == nullptr || spin(b)));
+      stalled = !poll_flags(a, b, 1, st, spin_limit);
       for (int s = 0; s < 64 && __hip_atomic_load(as_global(cu_busy), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0;
            ++s)
         __builtin_amdgcn_s_sleep(8);
@@ -1521,11 +1535,30 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
       }
 #pragma unroll
       for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
-      tile_mma64<T>(p, S1, S1, lane, w);
+      if (sizeof(T) == 8 && !diag) {
+        // the chain: the lower tiles of D_k's update only, balanced
+        acc_t qx = acc_t{0, 0, 0, 0};
+        switch (wu) {
+          case 0: lower_llt<T, 0>(p, qx, S1, lane); break;
+          case 1: lower_llt<T, 1>(p, qx, S1, lane); break;
+          case 2: lower_llt<T, 2>(p, qx, S1, lane); break;
+          default: lower_llt<T, 3>(p, qx, S1, lane); break;
+        }
+        if (wu == 0) {
 #pragma unroll
-      for (int tj = 0; tj < 4; ++tj) dd[tj] -= p[tj];
+          for (int r = 0; r < 4; ++r) colbuf[lane * 4 + r] = qx[r];  // tile (3, 0), read after the barrier
+        }
+      } else {
+        tile_mma64<T>(p, S1, S1, lane, w);
+      }
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) dd[tj] -= p[tj];  // zero for the tiles not formed here
     }
     __syncthreads();  // every wave is past its reads of S0 / S1
+    if (sizeof(T) == 8 && !diag && k >= 1 && wu == 3) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dd[0][r] -= colbuf[lane * 4 + r];
+    }
     acc_to_lds<T>(dd, S1, lane, w);
     if (!diag) acc_to_lds<T>(acc, S0, lane, w);
     __syncthreads();
