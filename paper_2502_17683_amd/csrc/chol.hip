@@ -999,6 +999,65 @@ __device__ __forceinline__ void fetch_block_coherent(T v[16], const T* g, size_t
     v[e] = (idx >> 6) < nrows ? coherent_load<T>(g + (size_t)(idx >> 6) * ld + (idx & 63)) : T(0);
   }
 }
+// fetch_block_coherent through device-coherent 16-byte loads (FP64): load e
+// of thread t brings the elements (r, c) and (r, c + 1) of pair p =
+// t + 256 e, r = p / 32, c = 2 (p % 32), into v[2e], v[2e + 1]; rows at or
+// past nrows read zero (the buffer's bound).  put_block2 writes that
+// layout to LDS; other types keep the 8-byte element form.
+template <typename T>
+__device__ __forceinline__ void fetch_block2_coherent(T v[16], const T* g, size_t ld, int nrows, int tid) {
+  if constexpr (sizeof(T) == 8) {
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    constexpr int SC1 = 16;  // cache policy: device-coherent, as the agent-scope loads
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)g, (short)0, (int)((size_t)nrows * ld * sizeof(T)), 0x00020000);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int pr = tid + 256 * e;
+      const u4 x = __builtin_amdgcn_raw_buffer_load_b128(
+          rs, (int)(((pr >> 5) * ld + 2 * (pr & 31)) * sizeof(T)), 0, SC1);
+      v[2 * e] = __builtin_bit_cast(T, (unsigned long long)x.x | ((unsigned long long)x.y << 32));
+      v[2 * e + 1] = __builtin_bit_cast(T, (unsigned long long)x.z | ((unsigned long long)x.w << 32));
+    }
+  } else {
+    fetch_block_coherent<T>(v, g, ld, nrows, tid);
+  }
+}
+template <typename T, bool TRANSPOSE>
+__device__ __forceinline__ void put_block2(T* S, const T v[16], int tid) {
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int pr = tid + 256 * e, r = pr >> 5, c = 2 * (pr & 31);
+      if (TRANSPOSE) {
+        S[c * LDT + r] = v[2 * e];
+        S[(c + 1) * LDT + r] = v[2 * e + 1];
+      } else {
+        S[r * LDT + c] = v[2 * e];
+        S[r * LDT + c + 1] = v[2 * e + 1];
+      }
+    }
+  } else {
+    put_block<T, TRANSPOSE>(S, v, tid);
+  }
+}
+// A 64-column tile held in LDS (row-major, stride LDT) stored through
+// device-coherent 16-byte stores, in the pair layout of fetch_block2_coherent
+// (rows at or past nrows are dropped by the buffer's bound).  FP64 only.
+__device__ __forceinline__ void store_block2_coherent(const double* S, double* g, size_t ld, int nrows, int tid) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  constexpr int SC1 = 16;  // cache policy: device-coherent, as the agent-scope stores
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)g, (short)0, (int)((size_t)nrows * ld * sizeof(double)), 0x00020000);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int pr = tid + 256 * e, r = pr >> 5, c = 2 * (pr & 31);
+    const unsigned long long x0 = __builtin_bit_cast(unsigned long long, S[r * LDT + c]);
+    const unsigned long long x1 = __builtin_bit_cast(unsigned long long, S[r * LDT + c + 1]);
+    const u4 v = {(unsigned)x0, (unsigned)(x0 >> 32), (unsigned)x1, (unsigned)(x1 >> 32)};
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)((r * ld + c) * sizeof(double)), 0, SC1);
+  }
+}
 template <typename T>
 __device__ __forceinline__ void store_acc_coherent(const typename Acc4<T>::type acc[4], T* g, size_t ld, int nrows,
                                                    int lane, int w) {
@@ -1157,6 +1216,35 @@ __device__ __forceinline__ void fetch_afrag_coherent(T a[16], const T* g, size_t
     a[m] = row < nrows ? coherent_load<T>(g + (size_t)row * ld + 4 * m + (lane >> 4)) : T(0);
 }
 
+// The same fragments through device-coherent 16-byte loads (FP64): product
+// m of tile_mma64_ra2 takes k = 8 (m / 2) + 2 (lane / 16) + m % 2, so a
+// lane's values of products 2 m2 and 2 m2 + 1 are adjacent in memory and
+// come in one load.  Rows at or past nrows read zero (the buffer's bound).
+__device__ __forceinline__ void fetch_afrag2_coherent(double a[16], const double* g, size_t ld, int nrows, int lane,
+                                                      int w) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  constexpr int SC1 = 16;  // cache policy: device-coherent, as the agent-scope loads
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)g, (short)0, (int)((size_t)nrows * ld * sizeof(double)), 0x00020000);
+  const int off = (int)(((16 * w + (lane & 15)) * ld + 2 * (lane >> 4)) * sizeof(double));
+#pragma unroll
+  for (int m2 = 0; m2 < 8; ++m2) {
+    const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 64 * m2, 0, SC1);
+    a[2 * m2] = __builtin_bit_cast(double, (unsigned long long)v.x | ((unsigned long long)v.y << 32));
+    a[2 * m2 + 1] = __builtin_bit_cast(double, (unsigned long long)v.z | ((unsigned long long)v.w << 32));
+  }
+}
+// acc += A B for fragments in that order
+template <typename T>
+__device__ __forceinline__ void tile_mma64_ra2(typename Acc4<T>::type acc[4], const T a[16], const T* Bk, int lane) {
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int k = 8 * (m >> 1) + 2 * (lane >> 4) + (m & 1);
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[tj] = mfma4(a[m], Bk[k * LDT + 16 * tj + (lane & 15)], acc[tj]);
+  }
+}
+
 // One product of the pair set-up per workgroup (output o of pair j): the
 // result goes to an upper block of V.
 template <typename T>
@@ -1289,10 +1377,10 @@ __global__ __launch_bounds__(256, 2) void bwd_pair_kernel(const StepProb<T>* pro
   if (ilo < nblk) fetch_block<T>(rl, vblk(nblk - 1, k), Tp, TB, tid);
   for (int i = nblk - 1; i >= ilo; --i) {
     if (!wait_flag(i, FL_F)) return;
-    fetch_block_coherent<T>(rf, tile(i), Tp, nrows, tid);
+    fetch_block2_coherent<T>(rf, tile(i), Tp, nrows, tid);
     put_block<T, false>(S1, rl, tid);  // L_ik
     if (i > ilo) fetch_block<T>(rl, vblk(i - 1, k), Tp, TB, tid);
-    put_block<T, true>(S0, rf, tid);  // F_i^T
+    put_block2<T, true>(S0, rf, tid);  // F_i^T
     __syncthreads();
     tile_mma64<T>(acc, S0, S1, lane, w);
   }
@@ -1334,14 +1422,30 @@ __global__ __launch_bounds__(256, 2) void bwd_pair_kernel(const StepProb<T>* pro
     if (!wait_flag2(c, d, FL_F)) return;
     __builtin_amdgcn_s_setprio(3);  // the chain
     T fc[16], fd[16];
-    fetch_afrag_coherent<T>(fc, tile(c), Tp, nrows, lane, w);
-    fetch_afrag_coherent<T>(fd, tile(d), Tp, nrows, lane, w);
-    tile_mma64_ra<T>(f, fc, S0, lane);
-    tile_mma64_ra<T>(f, fd, S1, lane);
+    if constexpr (sizeof(T) == 8) {
+      fetch_afrag2_coherent(fc, tile(c), Tp, nrows, lane, w);
+      fetch_afrag2_coherent(fd, tile(d), Tp, nrows, lane, w);
+      __builtin_amdgcn_sched_barrier(0);  // every load issued before the first product waits
+      tile_mma64_ra2<T>(f, fc, S0, lane);
+      tile_mma64_ra2<T>(f, fd, S1, lane);
+    } else {
+      fetch_afrag_coherent<T>(fc, tile(c), Tp, nrows, lane, w);
+      fetch_afrag_coherent<T>(fd, tile(d), Tp, nrows, lane, w);
+      tile_mma64_ra<T>(f, fc, S0, lane);
+      tile_mma64_ra<T>(f, fd, S1, lane);
+    }
   }
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj) f[tj] = -f[tj];
-  store_acc_coherent<T>(f, tile(k), Tp, nrows, lane, w);
+  if constexpr (sizeof(T) == 8) {
+    // through LDS into coalesced 16-byte stores
+    __syncthreads();  // every wave is past its reads of S0 / S1
+    acc_to_lds<T>(f, S0, lane, w);
+    __syncthreads();
+    store_block2_coherent(S0, tile(k), Tp, nrows, tid);
+  } else {
+    store_acc_coherent<T>(f, tile(k), Tp, nrows, lane, w);
+  }
   set_flag(k, FL_F);
 }
 
@@ -1493,10 +1597,10 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
     for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
     for (int j = 0; j + 1 < k; ++j) {  // columns j <= k - 2
       if (!wait_acc(lfl + i * nblk + j, diag ? nullptr : lfl + k * nblk + j)) return;
-      fetch_block_coherent<T>(ra, blk(i, j), Tp, TB, tid);
-      if (!diag) fetch_block_coherent<T>(rb, blk(k, j), Tp, TB, tid);
-      put_block<T, true>(S0, ra, tid);
-      if (!diag) put_block<T, true>(S1, rb, tid);
+      fetch_block2_coherent<T>(ra, blk(i, j), Tp, TB, tid);
+      if (!diag) fetch_block2_coherent<T>(rb, blk(k, j), Tp, TB, tid);
+      put_block2<T, true>(S0, ra, tid);
+      if (!diag) put_block2<T, true>(S1, rb, tid);
       __syncthreads();
       tile_mma64<T>(p, S0, diag ? S0 : S1, lane, w);  // += L_ij L_kj^T
     }
@@ -1521,10 +1625,10 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
       if (!wait(lfl + i * nblk + k - 1, diag ? nullptr : lfl + k * nblk + k - 1)) return;
       __builtin_amdgcn_s_setprio(3);  // the chain
       if (!diag) chain_begin();
-      fetch_block_coherent<T>(rb, blk(k, k - 1), Tp, TB, tid);
-      if (!diag) fetch_block_coherent<T>(ra, blk(i, k - 1), Tp, TB, tid);
-      put_block<T, true>(S1, rb, tid);
-      if (!diag) put_block<T, true>(S0, ra, tid);
+      fetch_block2_coherent<T>(rb, blk(k, k - 1), Tp, TB, tid);
+      if (!diag) fetch_block2_coherent<T>(ra, blk(i, k - 1), Tp, TB, tid);
+      put_block2<T, true>(S1, rb, tid);
+      if (!diag) put_block2<T, true>(S0, ra, tid);
       __syncthreads();
       if (!diag) {
 #pragma unroll
@@ -1572,8 +1676,12 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
         T e[16];
         lds_to_strip<T>(S0, e, sr, q0);
         strip_potrf4_panel<T>(d, e, invd, colbuf, sr, q0);
+        // L_ik through LDS (S0 is free: every thread read its strip before
+        // the factorisation's first barrier) into coalesced 16-byte stores
 #pragma unroll
-        for (int u = 0; u < 16; ++u) coherent_store<T>(tile + (size_t)sr * Tp + q0 + 4 * u, e[u]);
+        for (int u = 0; u < 16; ++u) S0[sr * LDT + q0 + 4 * u] = e[u];
+        __syncthreads();
+        store_block2_coherent(S0, tile, Tp, TB, tid);
         publish(lfl + i * nblk + k);
         if (k >= 1) chain_end();
         return;
@@ -1613,10 +1721,10 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
   for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
   for (int j = 0; j < k; ++j) {
     if (!wait_acc(gfl + j, lfl + k * nblk + j)) return;
-    fetch_block_coherent<T>(ra, q.M + (size_t)r0 * Tp + (size_t)j * TB, Tp, nrows, tid);  // G_j
-    fetch_block_coherent<T>(rb, blk(k, j), Tp, TB, tid);                                 // L_kj
-    put_block<T, true>(S0, ra, tid);
-    put_block<T, true>(S1, rb, tid);
+    fetch_block2_coherent<T>(ra, q.M + (size_t)r0 * Tp + (size_t)j * TB, Tp, nrows, tid);  // G_j
+    fetch_block2_coherent<T>(rb, blk(k, j), Tp, TB, tid);                                 // L_kj
+    put_block2<T, true>(S0, ra, tid);
+    put_block2<T, true>(S1, rb, tid);
     __syncthreads();
     tile_mma64<T>(p, S0, S1, lane, w);  // += G_j L_kj^T
   }
