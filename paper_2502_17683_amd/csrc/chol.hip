@@ -1387,7 +1387,13 @@ __global__ __launch_bounds__(256, 2) void bwd_pair_kernel(const StepProb<T>* pro
   if (!role_a && has_a) {
     // acc_b for the a workgroup, in its tile once its G has been read
     if (!wait_flag(ha, FL_GLOADED)) return;
-    store_acc_coherent<T>(acc, tile(ha), Tp, nrows, lane, w);
+    if constexpr (sizeof(T) == 8) {
+      acc_to_lds<T>(acc, S0, lane, w);  // (the wait's barrier: every wave is past its reads of S0)
+      __syncthreads();
+      store_block2_coherent(S0, tile(ha), Tp, nrows, tid);
+    } else {
+      store_acc_coherent<T>(acc, tile(ha), Tp, nrows, lane, w);
+    }
     set_flag(ha, FL_ACCB);
   }
   // f = acc X_k^T
@@ -1402,9 +1408,9 @@ __global__ __launch_bounds__(256, 2) void bwd_pair_kernel(const StepProb<T>* pro
     // f -= acc_b U
     fetch_block<T>(rl, vblk(ha, hb), Tp, TB, tid);  // U
     if (!wait_flag(ha, FL_ACCB)) return;
-    fetch_block_coherent<T>(rf, tile(ha), Tp, nrows, tid);  // acc_b
+    fetch_block2_coherent<T>(rf, tile(ha), Tp, nrows, tid);  // acc_b
     put_block<T, false>(S1, rl, tid);
-    put_block<T, true>(S0, rf, tid);
+    put_block2<T, true>(S0, rf, tid);
     __syncthreads();
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj) acc[tj] = acc_t{0, 0, 0, 0};
@@ -1732,14 +1738,21 @@ __global__ __launch_bounds__(256, 2) void chol_fwd_flow_kernel(const StepProb<T>
   for (int tj = 0; tj < 4; ++tj) acc[tj] -= p[tj];
   if (!wait(xfl + k, nullptr)) return;
   __builtin_amdgcn_s_setprio(3);
-  fetch_block_coherent<T>(ra, q.ldiag + (size_t)k * TB * TB, TB, TB, tid);
+  fetch_block2_coherent<T>(ra, q.ldiag + (size_t)k * TB * TB, TB, TB, tid);
   acc_to_lds_t<T>(acc, S0, lane, w);
-  put_block<T, false>(S1, ra, tid);  // X_k
+  put_block2<T, false>(S1, ra, tid);  // X_k
   __syncthreads();
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj) p[tj] = acc_t{0, 0, 0, 0};
   tile_mma64<T>(p, S0, S1, lane, w);  // G_k
-  store_acc_coherent<T>(p, tile, Tp, nrows, lane, w);
+  if constexpr (sizeof(T) == 8) {
+    __syncthreads();  // every wave is past its reads of S0 / S1
+    acc_to_lds<T>(p, S0, lane, w);
+    __syncthreads();
+    store_block2_coherent(S0, tile, Tp, nrows, tid);
+  } else {
+    store_acc_coherent<T>(p, tile, Tp, nrows, lane, w);
+  }
   publish(gfl + k);
 }
 
